@@ -1,0 +1,368 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+the paper's worked CSR example, dense brute force, exact rational arithmetic,
+IEEE-754 special cases, Krylov theory (termination, manufactured eigenvectors,
+Chebyshev bound) and textbook identities (Jacobi-PCG == CG on the scaled
+system, Lanczos Ritz values)."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import CSR
+
+U = 2.0 ** -53
+
+
+# ------------------------------------------------------------------ helpers --
+
+def dense_to_csr(a):
+    a = np.asarray(a)
+    rp, ci, v = [0], [], []
+    for i in range(a.shape[0]):
+        for j in range(a.shape[1]):
+            if a[i, j] != 0:
+                ci.append(j)
+                v.append(float(a[i, j]))
+        rp.append(len(ci))
+    return CSR(a.shape[0], a.shape[1], np.array(rp, np.int32), np.array(ci, np.int32),
+               np.array(v, np.float64))
+
+
+def exact(v):
+    return Fraction(float(v))
+
+
+def random_csr(rng, n_rows, n_cols, density, integer=False, empty_rows=()):
+    a = np.zeros((n_rows, n_cols))
+    mask = rng.random((n_rows, n_cols)) < density
+    if integer:
+        a[mask] = rng.integers(-9, 10, mask.sum())
+    else:
+        a[mask] = rng.uniform(-1, 1, mask.sum())
+    for r in empty_rows:
+        a[r, :] = 0
+    return a, dense_to_csr(a)
+
+
+# ------------------------------------------------- Table 1 (Section 2.3) --
+
+def test_table1_csr_derivation_and_spmv(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "table1_example.json")))
+    dense = np.array(g["dense"])
+    # CSR by the paper's definition (1-based) == the fixture's arrays
+    A1 = dense_to_csr(dense)
+    rp, ci, v = oracle.from_one_based(g["IA_1based"], g["JA_1based"], g["AA_1based"])
+    assert np.array_equal(rp, A1.row_ptr) and np.array_equal(ci, A1.col_idx)
+    assert np.array_equal(v, A1.val)
+    assert oracle.csr_check(5, 5, rp, ci) == 0
+    A = CSR(5, 5, rp, ci, v)
+    assert np.array_equal(A.to_dense(), dense)
+    # y = A x by integer brute force over the printed matrix
+    x = g["x"]
+    y_exact = [sum(int(dense[i][j]) * x[j] for j in range(5)) for i in range(5)]
+    assert y_exact == [-3, 37, 32, 61, 26]
+    y = oracle.spmv(A, np.array(x, float))
+    assert list(y) == [float(t) for t in y_exact]
+
+
+# ----------------------------------------------------------------- SpMV --
+
+@pytest.mark.parametrize("seed", range(6))
+def test_spmv_integer_bruteforce_exact(seed):
+    rng = np.random.default_rng(seed)
+    n_rows, n_cols = int(rng.integers(1, 65)), int(rng.integers(1, 65))
+    a, A = random_csr(rng, n_rows, n_cols, 0.3, integer=True,
+                      empty_rows=[0] if n_rows > 2 else [])
+    x = rng.integers(-50, 51, n_cols)
+    y_ref = [sum(int(a[i, j]) * int(x[j]) for j in range(n_cols)) for i in range(n_rows)]
+    y = oracle.spmv(A, x.astype(float))
+    assert [float(t) for t in y_ref] == list(y)
+    if n_rows > 2:
+        assert y[0] == 0.0 and math.copysign(1.0, y[0]) == 1.0  # empty row -> +0.0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_spmv_float_within_sequential_error_bound(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 65))
+    a, A = random_csr(rng, n, n, 0.4)
+    x = rng.uniform(-1, 1, n)
+    y = oracle.spmv(A, x)
+    for i in range(n):
+        terms = [exact(a[i, j]) * exact(x[j]) for j in range(n) if a[i, j] != 0]
+        s = sum(terms, Fraction(0))
+        absum = float(sum((abs(t) for t in terms), Fraction(0)))
+        k = len(terms)
+        gamma = k * U / (1 - k * U)
+        assert abs(Fraction(y[i]) - s) <= Fraction(gamma * absum) + Fraction(1e-300)
+
+
+def test_spmv_rejects_malformed_csr():
+    rp = np.array([0, 2, 1], np.int32)
+    assert oracle.csr_check(2, 3, rp, np.array([0, 1], np.int32)) != 0      # decreasing ptr
+    assert oracle.csr_check(1, 3, np.array([0, 2], np.int32), np.array([0, 3], np.int32)) != 0
+    assert oracle.csr_check(1, 3, np.array([0, 2], np.int32), np.array([1, 1], np.int32)) != 0
+    assert oracle.csr_check(1, 3, np.array([1, 2], np.int32), np.array([1, 1], np.int32)) != 0
+    assert oracle.csr_check(3, 3, np.array([0, 0, 2, 2], np.int32),
+                            np.array([2, 0], np.int32)) == 0                 # empty rows, unsorted ok
+
+
+# ---------------------------------------------- add / axpy / xmul (IEEE) --
+
+def _rand_specials(rng, n):
+    v = rng.uniform(-1, 1, n) * np.exp2(rng.integers(-30, 30, n))
+    v[:8] = [0.0, -0.0, 5e-324, -5e-324, 2.2250738585072014e-308, 1e-310, 1.0, -1.0]
+    return v
+
+
+def test_add_xmul_match_exact_rounding():
+    rng = np.random.default_rng(7)
+    x, y = _rand_specials(rng, 2000), _rand_specials(rng, 2000)
+    z_add, z_mul = oracle.add(x, y), oracle.xmul(x, y)
+    for i in range(x.size):
+        assert z_add[i] == float(exact(x[i]) + exact(y[i]))
+        assert z_mul[i] == float(exact(x[i]) * exact(y[i]))
+
+
+def test_axpy_is_single_rounding_fma():
+    rng = np.random.default_rng(8)
+    x, y = rng.uniform(-1, 1, 5000), rng.uniform(-1, 1, 5000)
+    alpha = 0.7390851332151607
+    z = oracle.axpy(alpha, x, y)
+    two_roundings_differ = 0
+    for i in range(x.size):
+        e = exact(alpha) * exact(x[i]) + exact(y[i])
+        assert z[i] == float(e)
+        if float(e) != alpha * x[i] + y[i]:
+            two_roundings_differ += 1
+    assert two_roundings_differ > 50  # the cases discriminate fma from mul+add
+
+
+def test_elementwise_ieee_special_values():
+    inf, nan = float("inf"), float("nan")
+    x = np.array([inf, inf, -inf, 0.0, -0.0, -0.0, nan, 1e308])
+    y = np.array([1.0, -inf, -inf, -0.0, -0.0, 0.0, 1.0, 1e308])
+    z = oracle.add(x, y)
+    assert z[0] == inf and math.isnan(z[1]) and z[2] == -inf
+    assert z[3] == 0 and math.copysign(1, z[3]) == 1     # +0 + -0 = +0 (round to nearest)
+    assert z[4] == 0 and math.copysign(1, z[4]) == -1    # -0 + -0 = -0
+    assert math.isnan(z[6]) and z[7] == inf              # overflow to +inf
+    m = oracle.xmul(np.array([inf, 0.0, -0.0, 1e200, nan]), np.array([0.0, -3.0, -0.0, 1e200, 0.0]))
+    assert math.isnan(m[0]) and math.copysign(1, m[1]) == -1 and math.copysign(1, m[2]) == 1
+    assert m[3] == inf and math.isnan(m[4])
+
+
+# ------------------------------------------------------------------ dot --
+
+@pytest.mark.parametrize("n", [1, 17, 1000, 10000])
+def test_dot_kahan_bound_vs_exact_rational(n):
+    rng = np.random.default_rng(n)
+    x, y = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    s_exact = sum((exact(a) * exact(b) for a, b in zip(x, y)), Fraction(0))
+    absum = float(np.sum(np.abs(x * y)))
+    d = oracle.dot(x, y)
+    # products rounded once (u each) + Kahan's 2u + O(n u^2) summation bound
+    assert abs(Fraction(d) - s_exact) <= Fraction((3 * U + 2 * n * U * U) * absum)
+
+
+def test_dot_cancellation_and_integers():
+    # integer vectors with |sum| < 2^53: exact in any order
+    rng = np.random.default_rng(3)
+    x = rng.integers(-1000, 1000, 5000).astype(float)
+    y = rng.integers(-1000, 1000, 5000).astype(float)
+    assert oracle.dot(x, y) == float(int(np.dot(x.astype(np.int64), y.astype(np.int64))))
+    # many tiny terms after a large one: recursive summation drops all of them,
+    # the compensated sum stays within its 2u * sum|x_i y_i| bound
+    x = np.array([1.0] + [1e-16] * 10000)
+    y = np.ones_like(x)
+    s_exact = Fraction(1) + 10000 * exact(1e-16)
+    d = oracle.dot(x, y)
+    assert abs(Fraction(d) - s_exact) <= Fraction(3 * U * 1.000000000001)
+    assert d != 1.0
+
+
+# ------------------------------------------------------------------- CG --
+
+def fd7_eigs(N):
+    th = [j * math.pi / (N + 1) for j in range(1, N + 1)]
+    l1 = [4 * math.sin(t / 2) ** 2 for t in th]
+    return l1
+
+
+def test_cg_fd7_manufactured_eigenvector_one_iteration():
+    N = 9
+    A = synth.fd7(N)
+    j = (2, 5, 7)
+    i = np.arange(1, N + 1)
+    vs = [np.sin(jj * math.pi * i / (N + 1)) for jj in j]
+    v = np.einsum("k,j,i->kji", vs[2], vs[1], vs[0]).ravel()
+    lam = sum(4 * math.sin(jj * math.pi / (2 * (N + 1))) ** 2 for jj in j)
+    r = oracle.cg(A, lam * v, rtol=1e-12)
+    assert r.status == oracle.OK and r.iters == 1
+    assert np.linalg.norm(r.x - v) / np.linalg.norm(v) < 1e-13
+
+
+def test_cg_q1_manufactured_eigenvector_one_iteration():
+    """Constant-k Q1 on the unit cube: A = S(x)M(x)M + M(x)S(x)M + M(x)M(x)S with
+    1D stiffness S = tridiag(-1,2,-1)/h and mass M = h tridiag(1,4,1)/6, whose
+    sine eigenvectors give lambda = s_a m_b m_c + m_a s_b m_c + m_a m_b s_c."""
+    N = 8
+    A = synth.q1cube(N, sigma=0.0)
+    h = 1.0 / (N + 1)
+    jx, jy, jz = 1, 4, 6
+    i = np.arange(1, N + 1)
+    vx, vy, vz = (np.sin(j * math.pi * i / (N + 1)) for j in (jx, jy, jz))
+    v = np.einsum("k,j,i->kji", vz, vy, vx).ravel()
+
+    def s_m(j):
+        c = math.cos(j * math.pi / (N + 1))
+        return (2 - 2 * c) / h, h * (4 + 2 * c) / 6
+
+    (sx, mx), (sy, my), (sz, mz) = s_m(jx), s_m(jy), s_m(jz)
+    lam = sx * my * mz + mx * sy * mz + mx * my * sz
+    assert np.allclose(oracle.spmv(A, v), lam * v, rtol=0, atol=1e-14 * lam)
+    r = oracle.cg(A, lam * v, rtol=1e-12)
+    assert r.status == oracle.OK and r.iters == 1
+    assert np.linalg.norm(r.x - v) / np.linalg.norm(v) < 1e-13
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_cg_terminates_within_distinct_eigenvalue_count(N):
+    l1 = fd7_eigs(N)
+    sums = sorted({round(a + b + c, 9) for a in l1 for b in l1 for c in l1})
+    m = len(sums)
+    assert m == {2: 4, 3: 7, 4: 16}[N]
+    A = synth.fd7(N)
+    b = synth.uniform(5, N ** 3)
+    r = oracle.cg(A, b, rtol=0.0, maxit=m)
+    assert r.relres_true < 1e-11
+    r_short = oracle.cg(A, b, rtol=0.0, maxit=m - 1)
+    assert r_short.relres_true > 1e-9  # not earlier for a generic right-hand side
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_cg_random_spd_matches_dense_solve(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 65))
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.exp(rng.uniform(0, math.log(100), n))
+    a = (Q * ev) @ Q.T
+    a = (a + a.T) / 2
+    A = dense_to_csr(a)
+    b = rng.uniform(-1, 1, n)
+    r = oracle.cg(A, b, rtol=1e-12, maxit=10 * n)
+    kappa = ev.max() / ev.min()
+    rho = (math.sqrt(kappa) - 1) / (math.sqrt(kappa) + 1)
+    kcheb = math.ceil(math.log(1e-12 / (2 * math.sqrt(kappa))) / math.log(rho))
+    assert r.status == oracle.OK and r.iters <= kcheb
+    xs = np.linalg.solve(a, b)
+    assert np.linalg.norm(r.x - xs) / np.linalg.norm(xs) < 100 * 1e-12 * 10
+
+
+def test_cg_fd7_16_chebyshev_bound_and_ritz_values():
+    """The plain-CG configuration on the 16^3 7-point grid: x* ~ U[-1,1] (seed 0),
+    b = A x*, stop at 1e-10.  Iterations obey the Chebyshev bound
+    ||r_k||/||b|| <= 2 sqrt(kappa) ((sqrt(kappa)-1)/(sqrt(kappa)+1))^k, and the
+    Lanczos Ritz extremes reproduce the analytic spectrum edges."""
+    N = 16
+    A = synth.fd7(N)
+    xs = synth.uniform(synth.SEED_C1_XSTAR, N ** 3)
+    b = oracle.spmv(A, xs)
+    r = oracle.cg(A, b, rtol=1e-10, history=True)
+    l1 = fd7_eigs(N)
+    lmin, lmax = 3 * l1[0], 3 * l1[-1]
+    kappa = lmax / lmin
+    rho = (math.sqrt(kappa) - 1) / (math.sqrt(kappa) + 1)
+    kmax = math.ceil(math.log(1e-10 / (2 * math.sqrt(kappa))) / math.log(rho))
+    assert r.status == oracle.OK and 0 < r.iters <= kmax
+    assert r.relres_true < 2e-10
+    assert np.linalg.norm(r.x - xs) / np.linalg.norm(xs) < kappa * 1e-10
+    emin, emax = oracle.lanczos_extremes(r.alpha, r.beta)
+    assert abs(emin - lmin) / lmin < 1e-8 and abs(emax - lmax) / lmax < 1e-8
+
+
+def test_jacobi_pcg_equals_cg_on_symmetrically_scaled_system():
+    N = 6
+    A = synth.q1cube(N, sigma=1.0, seed=3)
+    a = A.to_dense()
+    d = np.diag(a)
+    s = 1 / np.sqrt(d)
+    As = dense_to_csr(a * s[:, None] * s[None, :])
+    b = synth.uniform(9, N ** 3)
+    for k in (1, 2, 5, 12):
+        rj = oracle.cg(A, b, rtol=0.0, maxit=k, jacobi=True)
+        rs = oracle.cg(As, s * b, rtol=0.0, maxit=k)
+        assert rj.iters == rs.iters == k
+        assert np.linalg.norm(rj.x - s * rs.x) / np.linalg.norm(rj.x) < 1e-12
+
+
+def test_jacobi_pcg_converges_and_helps_on_rough_coefficients():
+    N = 12
+    A = synth.q1cube(N, sigma=1.0, seed=synth.SEED_C2_COEFF)
+    b = synth.blob_rhs(N, synth.SEED_C2_BLOBS)
+    rp = oracle.cg(A, b, rtol=1e-8)
+    rj = oracle.cg(A, b, rtol=1e-8, jacobi=True)
+    assert rp.status == rj.status == oracle.OK
+    assert rj.iters < rp.iters
+    assert rj.relres_true < 2e-8 and rp.relres_true < 2e-8
+
+
+def test_cg_status_codes():
+    A = synth.fd7(3)
+    n = A.n_rows
+    # b = 0 -> x = 0 after 0 iterations, whatever x0
+    r = oracle.cg(A, np.zeros(n), x0=np.ones(n))
+    assert r.status == oracle.OK and r.iters == 0 and not r.x.any()
+    # maxit too small -> NOT_CONVERGED, last iterate kept
+    r = oracle.cg(A, synth.uniform(1, n), rtol=1e-14, maxit=2)
+    assert r.status == oracle.NOT_CONVERGED and r.iters == 2 and r.relres_true < 1
+    # indefinite matrix -> breakdown
+    neg = CSR(n, n, A.row_ptr, A.col_idx, -A.val)
+    r = oracle.cg(neg, synth.uniform(1, n))
+    assert r.status == oracle.BREAKDOWN
+    # non-finite right-hand side
+    bb = synth.uniform(1, n)
+    bb[3] = float("nan")
+    assert oracle.cg(A, bb).status == oracle.NONFINITE
+    # Jacobi with a non-positive diagonal
+    bad = CSR(n, n, A.row_ptr, A.col_idx, np.where(A.col_idx == np.repeat(np.arange(n), np.diff(A.row_ptr)), 0.0, A.val))
+    assert oracle.cg(bad, synth.uniform(1, n), jacobi=True).status == oracle.BREAKDOWN
+
+
+# ------------------------------------------------------- mixed precision --
+
+def test_mixed_ir_reaches_fp64_accuracy():
+    N = 14
+    A = synth.q1cube(N, sigma=1.5, seed=synth.SEED_C3_COEFF)
+    b = synth.uniform(synth.SEED_C3_RHS, N ** 3)
+    v32 = A.val.astype(np.float32)
+    tau = 1e-3
+    r = oracle.mixed_ir(A, v32, b, rtol=1e-10, tau=tau)
+    assert r.status == oracle.OK and r.relres <= 1e-10
+    # each refinement step contracts by about tau (plus the binary32 floor)
+    assert r.outer_iters <= 2 * math.ceil(math.log(1e-10) / math.log(tau)) + 1
+    ref = oracle.cg(A, b, rtol=1e-13)
+    xs = np.linalg.solve(A.to_dense(), b)
+    assert np.linalg.norm(ref.x - xs) / np.linalg.norm(xs) < 1e-9
+    assert np.linalg.norm(r.x - xs) / np.linalg.norm(xs) < 1e-7
+
+
+def test_f32_kernels_are_binary32():
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1, 1, 3000).astype(np.float32)
+    y = rng.uniform(-1, 1, 3000).astype(np.float32)
+    d = oracle.dot_f32(x, y)
+    s = sum((Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x, y)), Fraction(0))
+    absum = float(np.sum(np.abs(x.astype(float) * y.astype(float))))
+    u32 = 2.0 ** -24
+    assert abs(Fraction(d) - s) <= Fraction((3 * u32 + 2 * 3000 * u32 * u32) * absum)
+    assert np.float32(d) == d
+    A = synth.fd7(5)
+    y32 = oracle.spmv_f32(A, A.val.astype(np.float32), np.ones(A.n_rows, np.float32))
+    assert y32.dtype == np.float32
+    assert np.array_equal(y32, oracle.spmv(A, np.ones(A.n_rows)).astype(np.float32))
