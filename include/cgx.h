@@ -1,0 +1,172 @@
+/*
+ * cgx — sparse conjugate-gradient solver for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libcgx.so.  Every entry point takes plain pointers and sizes; no
+ * framework types cross this boundary.  The operations are those the paper
+ * (arXiv 2112.10823, "Fast and Green Computing with GPUs for solving Sparse
+ * Linear Systems") measures: CSR sparse matrix-vector product, addition of
+ * vectors, element-wise product, dot product (Section 5.2) and the conjugate
+ * gradient method built from them (Section 5.3).
+ *
+ * Conventions shared by all calls
+ *  - Pointers named as device pointers must point to device memory of the
+ *    handle's GPU; they stay owned by the caller.  The library never frees
+ *    caller memory and never allocates memory the caller sees.
+ *  - Calls are asynchronous on the handle's stream unless marked (sync).
+ *  - Return value: CGX_OK (0) or a negative CGX_E* / solver status code.  On
+ *    error nothing is launched and cgx_last_error() (per thread) explains.
+ *  - Index arrays are 0-based int32; nnz must be < 2^31.
+ *  - Aliasing: outputs may alias inputs only where a call says so.
+ */
+#ifndef CGX_H
+#define CGX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGX_OK 0
+#define CGX_PENDING 1          /* cgx_poll: request queued or running */
+#define CGX_EINVAL (-1)        /* bad argument: size, pointer, CSR structure, alias */
+#define CGX_ENOMEM (-2)        /* caller workspace / pool too small */
+#define CGX_EHIP (-3)          /* HIP runtime error */
+#define CGX_NOT_CONVERGED (-4) /* maxit reached; x holds the last iterate */
+#define CGX_BREAKDOWN (-5)     /* p.Ap <= 0 or r.z <= 0: matrix not SPD */
+#define CGX_NONFINITE (-6)     /* NaN or Inf met in b, A or the iteration */
+
+typedef struct cgx_context *cgx_handle;
+
+/* Sparse matrix in CSR form (Section 2.3: values row-wise in AA, their
+ * column numbers in JA, IA(i) the start of row i).  All arrays are device
+ * pointers, read-only to the library:
+ *   row_ptr  int32[n_rows + 1], row_ptr[0] = 0, non-decreasing, row_ptr[n_rows] = nnz
+ *   col_idx  int32[nnz], each in [0, n_cols), no column twice in a row (order free)
+ *   val      float64[nnz]  (may be NULL if only the float32 product is used)
+ *   val32    float32[nnz]  values rounded to binary32, same pattern; NULL
+ *            unless the float32 product or mixed precision is used.
+ * Kernels clamp every index they read, so a malformed matrix gives wrong
+ * numbers rather than a memory fault; cgx_csr_validate reports it. */
+typedef struct cgx_csr {
+    int32_t n_rows;
+    int32_t n_cols;
+    int64_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+    const float *val32;
+} cgx_csr;
+
+/* ------------------------------------------------------------- handle -- */
+
+/* Create a handle bound to GPU `device` and HIP stream `stream` (a
+ * hipStream_t; NULL = the null stream).  Allocates the handle's private state:
+ * a small device scratch area for reductions and pinned host status words. */
+int cgx_create(cgx_handle *out, int device, void *stream);
+/* Destroy a handle (sync: waits for its stream). */
+int cgx_destroy(cgx_handle h);
+/* Re-target the handle to another stream of the same device. */
+int cgx_set_stream(cgx_handle h, void *stream);
+/* Message of the last error raised on the calling thread ("" if none). */
+const char *cgx_last_error(void);
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int cgx_version(void);
+
+/* ---------------------------------------------------------- CSR / SpMV -- */
+
+/* (sync) Structural check of a device CSR matrix: row_ptr as above, columns
+ * in range, no duplicate column within a row.  Returns CGX_OK or CGX_EINVAL;
+ * *bad_row (nullable) receives the first offending row, or -1. */
+int cgx_csr_validate(cgx_handle h, const cgx_csr *A, int64_t *bad_row);
+
+/* y = A x (Section 5.2, table "SpMV with CSR format"), float64.
+ * x: float64[n_cols], y: float64[n_rows], device; y must not overlap x.
+ * Row i of y is the sum of val[k] * x[col_idx[k]] over the row, +0.0 for an
+ * empty row; the summation order is unspecified (not bit-reproducible
+ * against a sequential sum, but run-to-run deterministic). */
+int cgx_csr_spmv(cgx_handle h, const cgx_csr *A, const double *x, double *y);
+
+/* y = A32 x in binary32 with binary32 accumulation, using A->val32.
+ * x: float32[n_cols], y: float32[n_rows]; y must not overlap x. */
+int cgx_csr_spmv_f32(cgx_handle h, const cgx_csr *A, const float *x, float *y);
+
+/* --------------------------------------------------------------- BLAS-1 -- */
+
+/* z = x + y elementwise, float64 (Section 5.2, table "Addition of vectors").
+ * One IEEE rounding per element: bit-identical to any correct scalar loop.
+ * z may alias x or y exactly (same pointer); partial overlap is invalid. */
+int cgx_add(cgx_handle h, int64_t n, const double *x, const double *y, double *z);
+
+/* y = alpha * x + y with one rounding per element (fma) — the daxpy named by
+ * the label of the paper's addition table.  x and y must not overlap. */
+int cgx_axpy(cgx_handle h, int64_t n, double alpha, const double *x, double *y);
+
+/* z = x .* y elementwise (Section 5.2, table "Element wise product").
+ * Bit-identical to a scalar loop; z may alias x or y exactly. */
+int cgx_xmul(cgx_handle h, int64_t n, const double *x, const double *y, double *z);
+
+/* *result = sum_i x_i y_i (Section 5.2, table "Dot product"), written to the
+ * DEVICE pointer `result` (one float64).  Accumulates with error-free
+ * transformations (two-product by fma, two-sum) and a fixed reduction tree:
+ * the result is deterministic and within about 2 ulp of the exact sum for
+ * well-conditioned data.  n = 0 gives +0.0. */
+int cgx_dot(cgx_handle h, int64_t n, const double *x, const double *y, double *result);
+
+/* dst[i] = (float)src[i], round to nearest even (e.g. to build val32). */
+int cgx_demote(cgx_handle h, int64_t n, const double *src, float *dst);
+
+/* ------------------------------------------------------------------- CG -- */
+
+#define CGX_PRECOND_NONE 0
+#define CGX_PRECOND_JACOBI 1
+#define CGX_PRECISION_FP64 0
+#define CGX_PRECISION_MIXED 1
+
+typedef struct cgx_opts {
+    double rtol;         /* stop when ||r_k||_2 <= rtol * ||b||_2 */
+    int32_t maxit;       /* iteration cap (inner cap for MIXED); <= 0 means n */
+    int32_t precond;     /* CGX_PRECOND_* */
+    int32_t precision;   /* CGX_PRECISION_* */
+    int32_t check_every; /* iterations between host convergence checks; <= 0 = auto */
+    double inner_rtol;   /* MIXED: inner binary32 CG relative tolerance (<= 0: 1e-3) */
+    int32_t max_outer;   /* MIXED: refinement step cap (<= 0: 100) */
+    int32_t true_residual; /* nonzero: also compute ||b - A x|| / ||b|| at exit */
+    int32_t profile;     /* nonzero: launch the phase kernels one by one (no graph) with
+                          * HIP events around each, and report their mean durations */
+} cgx_opts;
+
+typedef struct cgx_stats {
+    int32_t status;      /* CGX_OK, CGX_NOT_CONVERGED, CGX_BREAKDOWN, CGX_NONFINITE */
+    int32_t iters;       /* CG iterations (binary32 inner iterations for MIXED) */
+    int32_t outer_iters; /* MIXED: refinement steps */
+    int32_t path;        /* kernel path taken: 0 phase kernels, 1 single-workgroup */
+    double relres;       /* recursive ||r|| / ||b|| at exit (outer residual for MIXED) */
+    double relres_true;  /* ||b - A x|| / ||b|| if requested, else -1 */
+    double device_ms;    /* GPU time of the solve, from stream events */
+    double phase_ms[3];  /* profile: mean duration of one launch of phase kernel
+                          * (1) q = A p + p.q, (2) x/r/z update + dots, (3) p update */
+} cgx_stats;
+
+/* Bytes of device workspace cg_solve needs for an n-row system and `opts`
+ * (0 on invalid arguments).  The caller allocates it (256-byte aligned) and
+ * keeps it alive for the duration of the call. */
+size_t cgx_cg_workspace_bytes(int64_t n_rows, int64_t nnz, const cgx_opts *opts);
+
+/* (sync) Solve A x = b, A symmetric positive definite, by conjugate gradient
+ * (Section 5.3: classical CG; Jacobi preconditioning and binary32-inner
+ * iterative refinement are options).  b: float64[n] device; x: float64[n]
+ * device, holds x0 on entry (zeros for the usual start) and the solution on
+ * exit.  workspace: device, >= cgx_cg_workspace_bytes bytes.  The iteration
+ * state stays on the GPU; the host reads one status word every check_every
+ * iterations.  b = 0 gives x = 0.  Returns stats->status (CGX_OK when
+ * converged) or an argument error. */
+int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, void *workspace,
+                 size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGX_H */

@@ -1,0 +1,330 @@
+"""Python binding of libcgx (argument marshalling only).
+
+Each function here forwards to the C entry point of the same name with the
+`cgx_` prefix (`csr_spmv` -> `cgx_csr_spmv`, ...).  Device memory and streams
+come from PyTorch (ROCm build): tensors must live on the handle's GPU; the
+handle follows `torch.cuda.current_stream()` at creation.  All arithmetic runs
+in the library's HIP kernels; if libcgx.so cannot be loaded every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcgx.so")
+
+OK, PENDING, EINVAL, ENOMEM, EHIP, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 1, -1, -2, -3, -4, -5, -6
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
+PRECISION_FP64, PRECISION_MIXED = 0, 1
+STATUS_NAMES = {OK: "OK", PENDING: "PENDING", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP",
+                NOT_CONVERGED: "NOT_CONVERGED", BREAKDOWN: "BREAKDOWN", NONFINITE: "NONFINITE"}
+
+
+class CgxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("val32", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
+                ("max_outer", ctypes.c_int32), ("true_residual", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("outer_iters", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("device_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 3)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["phase_ms"] = list(self.phase_ms)
+        return d
+
+
+EXPORTS = [
+    "cgx_create", "cgx_destroy", "cgx_set_stream", "cgx_last_error", "cgx_version",
+    "cgx_csr_validate", "cgx_csr_spmv", "cgx_csr_spmv_f32", "cgx_add", "cgx_axpy", "cgx_xmul",
+    "cgx_dot", "cgx_demote", "cgx_cg_workspace_bytes", "cgx_cg_solve",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcgx.so and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libcgx.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "cgx_create": ([P(vp), ctypes.c_int, vp], ctypes.c_int),
+        "cgx_destroy": ([vp], ctypes.c_int),
+        "cgx_set_stream": ([vp, vp], ctypes.c_int),
+        "cgx_last_error": ([], ctypes.c_char_p),
+        "cgx_version": ([], ctypes.c_int),
+        "cgx_csr_validate": ([vp, P(_Csr), P(i64)], ctypes.c_int),
+        "cgx_csr_spmv": ([vp, P(_Csr), vp, vp], ctypes.c_int),
+        "cgx_csr_spmv_f32": ([vp, P(_Csr), vp, vp], ctypes.c_int),
+        "cgx_add": ([vp, i64, vp, vp, vp], ctypes.c_int),
+        "cgx_axpy": ([vp, i64, dbl, vp, vp], ctypes.c_int),
+        "cgx_xmul": ([vp, i64, vp, vp, vp], ctypes.c_int),
+        "cgx_dot": ([vp, i64, vp, vp, vp], ctypes.c_int),
+        "cgx_demote": ([vp, i64, vp, vp], ctypes.c_int),
+        "cgx_cg_workspace_bytes": ([i64, i64, P(Opts)], ctypes.c_size_t),
+        "cgx_cg_solve": ([vp, P(_Csr), vp, vp, vp, ctypes.c_size_t, P(Opts), P(Stats)],
+                         ctypes.c_int),
+    }
+    for name, (argt, rest) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = argt
+        fn.restype = rest
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, allow=(OK,)):
+    if rc not in allow:
+        raise CgxError(rc, _lib.cgx_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev_tensor(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Handle:
+    """A libcgx handle bound to a device and a stream."""
+
+    def __init__(self, device: int | None = None, stream=None):
+        lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.cgx_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)))
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.cgx_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_handles: dict = {}
+
+
+def default_handle() -> Handle:
+    dev = torch.cuda.current_device()
+    s = torch.cuda.current_stream(dev)
+    key = (dev, s.cuda_stream)
+    h = _handles.get(key)
+    if h is None:
+        h = Handle(dev, s)
+        _handles[key] = h
+    return h
+
+
+@dataclass
+class DeviceCSR:
+    """CSR matrix resident on the GPU (torch-owned arrays) plus its C descriptor."""
+
+    n_rows: int
+    n_cols: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    val: torch.Tensor | None
+    val32: torch.Tensor | None = None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    def desc(self) -> _Csr:
+        return _Csr(self.n_rows, self.n_cols, self.nnz, self.row_ptr.data_ptr(),
+                    self.col_idx.data_ptr(),
+                    self.val.data_ptr() if self.val is not None else None,
+                    self.val32.data_ptr() if self.val32 is not None else None)
+
+    @classmethod
+    def from_host(cls, A, device="cuda", with_f32=False, validate=True, handle=None):
+        """Upload a host CSR (row_ptr, col_idx, val numpy arrays) and validate it on the GPU."""
+        rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, np.int32)).to(device)
+        ci = torch.from_numpy(np.ascontiguousarray(A.col_idx, np.int32)).to(device)
+        v = torch.from_numpy(np.ascontiguousarray(A.val, np.float64)).to(device)
+        d = cls(int(A.n_rows), int(A.n_cols), rp, ci, v)
+        if with_f32:
+            d.val32 = torch.empty(d.nnz, dtype=torch.float32, device=device)
+            demote(v, d.val32, handle=handle)
+        if validate:
+            csr_validate(d, handle=handle)
+        return d
+
+
+def _h(handle):
+    return (handle or default_handle()).ptr
+
+
+# ------------------------------------------------------------------ calls --
+
+def csr_validate(A: DeviceCSR, handle=None) -> int:
+    bad = ctypes.c_int64(-1)
+    d = A.desc()
+    _check(load_library().cgx_csr_validate(_h(handle), ctypes.byref(d), ctypes.byref(bad)))
+    return bad.value
+
+
+def csr_spmv(A: DeviceCSR, x: torch.Tensor, y: torch.Tensor | None = None, handle=None):
+    _dev_tensor(x, torch.float64, "x")
+    if y is None:
+        y = torch.empty(A.n_rows, dtype=torch.float64, device=x.device)
+    _dev_tensor(y, torch.float64, "y")
+    if x.numel() != A.n_cols or y.numel() != A.n_rows:
+        raise ValueError("x / y length does not match A")
+    d = A.desc()
+    _check(load_library().cgx_csr_spmv(_h(handle), ctypes.byref(d), _ptr(x), _ptr(y)))
+    return y
+
+
+def csr_spmv_f32(A: DeviceCSR, x: torch.Tensor, y: torch.Tensor | None = None, handle=None):
+    _dev_tensor(x, torch.float32, "x")
+    if y is None:
+        y = torch.empty(A.n_rows, dtype=torch.float32, device=x.device)
+    _dev_tensor(y, torch.float32, "y")
+    if x.numel() != A.n_cols or y.numel() != A.n_rows:
+        raise ValueError("x / y length does not match A")
+    d = A.desc()
+    _check(load_library().cgx_csr_spmv_f32(_h(handle), ctypes.byref(d), _ptr(x), _ptr(y)))
+    return y
+
+
+def _vec_args(x, y, z=None):
+    _dev_tensor(x, torch.float64, "x")
+    _dev_tensor(y, torch.float64, "y")
+    if x.numel() != y.numel() or (z is not None and z.numel() != x.numel()):
+        raise ValueError("length mismatch")
+    if z is not None:
+        _dev_tensor(z, torch.float64, "z")
+
+
+def add(x, y, z=None, handle=None):
+    if z is None:
+        z = torch.empty_like(x)
+    _vec_args(x, y, z)
+    _check(load_library().cgx_add(_h(handle), x.numel(), _ptr(x), _ptr(y), _ptr(z)))
+    return z
+
+
+def axpy(alpha: float, x, y, handle=None):
+    """y <- fma(alpha, x, y) in place; returns y."""
+    _vec_args(x, y)
+    _check(load_library().cgx_axpy(_h(handle), x.numel(), float(alpha), _ptr(x), _ptr(y)))
+    return y
+
+
+def xmul(x, y, z=None, handle=None):
+    if z is None:
+        z = torch.empty_like(x)
+    _vec_args(x, y, z)
+    _check(load_library().cgx_xmul(_h(handle), x.numel(), _ptr(x), _ptr(y), _ptr(z)))
+    return z
+
+
+def dot(x, y, out=None, handle=None):
+    """Returns a 1-element float64 GPU tensor holding x . y (asynchronous)."""
+    _vec_args(x, y)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x.device)
+    _dev_tensor(out, torch.float64, "out")
+    _check(load_library().cgx_dot(_h(handle), x.numel(), _ptr(x), _ptr(y), _ptr(out)))
+    return out
+
+
+def demote(src, dst=None, handle=None):
+    _dev_tensor(src, torch.float64, "src")
+    if dst is None:
+        dst = torch.empty(src.numel(), dtype=torch.float32, device=src.device)
+    _dev_tensor(dst, torch.float32, "dst")
+    if dst.numel() != src.numel():
+        raise ValueError("length mismatch")
+    _check(load_library().cgx_demote(_h(handle), src.numel(), _ptr(src), _ptr(dst)))
+    return dst
+
+
+def make_opts(rtol=1e-8, maxit=0, precond=PRECOND_NONE, precision=PRECISION_FP64,
+              check_every=0, inner_rtol=0.0, max_outer=0, true_residual=False,
+              profile=False) -> Opts:
+    return Opts(float(rtol), int(maxit), int(precond), int(precision), int(check_every),
+                float(inner_rtol), int(max_outer), int(bool(true_residual)), int(bool(profile)))
+
+
+def cg_workspace_bytes(n_rows: int, nnz: int, opts: Opts) -> int:
+    return int(load_library().cgx_cg_workspace_bytes(n_rows, nnz, ctypes.byref(opts)))
+
+
+def cg_workspace(A: DeviceCSR, opts: Opts, device=None) -> torch.Tensor:
+    nbytes = cg_workspace_bytes(A.n_rows, A.nnz, opts)
+    # torch's caching allocator returns blocks aligned to at least 512 bytes
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device or A.row_ptr.device)
+
+
+def cg_solve(A: DeviceCSR, b, x, opts: Opts | None = None, workspace=None, handle=None,
+             raise_on_fail=False) -> Stats:
+    """Solve A x = b in place on x (x holds x0 on entry).  Returns Stats."""
+    opts = opts or make_opts()
+    _dev_tensor(b, torch.float64, "b")
+    _dev_tensor(x, torch.float64, "x")
+    if b.numel() != A.n_rows or x.numel() != A.n_rows:
+        raise ValueError("b / x length does not match A")
+    if workspace is None:
+        workspace = cg_workspace(A, opts)
+    st = Stats()
+    d = A.desc()
+    rc = load_library().cgx_cg_solve(_h(handle), ctypes.byref(d), _ptr(b), _ptr(x),
+                                     _ptr(workspace), workspace.numel(), ctypes.byref(opts),
+                                     ctypes.byref(st))
+    if rc in (EINVAL, ENOMEM, EHIP) or (raise_on_fail and rc != OK):
+        _check(rc)
+    return st

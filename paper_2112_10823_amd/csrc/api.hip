@@ -1,0 +1,277 @@
+// extern "C" entry points of libcgx: argument checks, handle lifetime and
+// dispatch to the kernels.  No exception crosses this boundary.
+#include <cstring>
+#include <new>
+
+#include "cgx_internal.h"
+
+namespace cgx {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace cgx
+
+using cgx::Context;
+
+namespace {
+
+Context *ctx_of(cgx_handle h) { return reinterpret_cast<Context *>(h); }
+
+bool overlaps(const void *a, size_t an, const void *b, size_t bn)
+{
+    const char *x = static_cast<const char *>(a), *y = static_cast<const char *>(b);
+    return x < y + bn && y < x + an;
+}
+
+int check_csr(const cgx_csr *A, bool need_val, bool need_val32)
+{
+    CGX_REQUIRE(A != nullptr, "A is NULL");
+    CGX_REQUIRE(A->n_rows >= 0 && A->n_cols >= 0, "negative matrix dimension");
+    CGX_REQUIRE(A->nnz >= 0 && A->nnz < ((int64_t)1 << 31), "nnz must be in [0, 2^31)");
+    CGX_REQUIRE(A->row_ptr != nullptr, "row_ptr is NULL");
+    if (A->nnz > 0) {
+        CGX_REQUIRE(A->col_idx != nullptr, "col_idx is NULL");
+        if (need_val) CGX_REQUIRE(A->val != nullptr, "val is NULL");
+        if (need_val32) CGX_REQUIRE(A->val32 != nullptr, "val32 is NULL");
+    }
+    return CGX_OK;
+}
+
+template <class F>
+int guarded(F &&f)
+{
+    try {
+        cgx::clear_error();
+        return f();
+    } catch (const std::bad_alloc &) {
+        cgx::set_error("host allocation failed");
+        return CGX_ENOMEM;
+    } catch (...) {
+        cgx::set_error("internal error");
+        return CGX_EHIP;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cgx_last_error(void) { return cgx::g_last_error.c_str(); }
+
+int cgx_version(void) { return 100; }
+
+int cgx_create(cgx_handle *out, int device, void *stream)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        int ndev = 0;
+        CGX_HIP_CHECK(hipGetDeviceCount(&ndev));
+        CGX_REQUIRE(device >= 0 && device < ndev, "no such device");
+        CGX_HIP_CHECK(hipSetDevice(device));
+        Context *c = new Context();
+        c->device = device;
+        c->stream = static_cast<hipStream_t>(stream);
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+            c->num_cu = prop.multiProcessorCount;
+        const size_t scratch_bytes = (size_t)2 * cgx::kReduceBlocks * sizeof(double) + 256;
+        hipError_t e = hipMalloc(&c->scratch, scratch_bytes);
+        if (e == hipSuccess) e = hipMalloc(&c->counters, 64 * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemset(c->counters, 0, 64 * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipHostMalloc(&c->host_state, sizeof(cgx::CgState));
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&c->ev0);
+        if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
+        for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev_phase[i]);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            cgx::set_error(std::string("cgx_create: ") + hipGetErrorString(e));
+            cgx_destroy(reinterpret_cast<cgx_handle>(c));
+            return CGX_EHIP;
+        }
+        *out = reinterpret_cast<cgx_handle>(c);
+        return CGX_OK;
+    });
+}
+
+int cgx_destroy(cgx_handle h)
+{
+    Context *c = ctx_of(h);
+    if (!c) return CGX_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    for (int i = 0; i < 4; ++i)
+        if (c->ev_phase[i]) (void)hipEventDestroy(c->ev_phase[i]);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    if (c->host_state) (void)hipHostFree(c->host_state);
+    if (c->counters) (void)hipFree(c->counters);
+    if (c->scratch) (void)hipFree(c->scratch);
+    delete c;
+    return CGX_OK;
+}
+
+int cgx_set_stream(cgx_handle h, void *stream)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        ctx_of(h)->stream = static_cast<hipStream_t>(stream);
+        return CGX_OK;
+    });
+}
+
+int cgx_csr_validate(cgx_handle h, const cgx_csr *A, int64_t *bad_row)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        int rc = check_csr(A, false, false);
+        if (rc) return rc;
+        return cgx::run_csr_validate(ctx_of(h), A, bad_row);
+    });
+}
+
+int cgx_csr_spmv(cgx_handle h, const cgx_csr *A, const double *x, double *y)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        int rc = check_csr(A, true, false);
+        if (rc) return rc;
+        if (A->n_rows == 0) return CGX_OK;
+        CGX_REQUIRE(y != nullptr && (x != nullptr || A->n_cols == 0), "x or y is NULL");
+        CGX_REQUIRE(!overlaps(x, (size_t)A->n_cols * 8, y, (size_t)A->n_rows * 8),
+                    "y overlaps x");
+        return cgx::launch_spmv(ctx_of(h), A, x, y);
+    });
+}
+
+int cgx_csr_spmv_f32(cgx_handle h, const cgx_csr *A, const float *x, float *y)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        int rc = check_csr(A, false, true);
+        if (rc) return rc;
+        if (A->n_rows == 0) return CGX_OK;
+        CGX_REQUIRE(y != nullptr && (x != nullptr || A->n_cols == 0), "x or y is NULL");
+        CGX_REQUIRE(!overlaps(x, (size_t)A->n_cols * 4, y, (size_t)A->n_rows * 4),
+                    "y overlaps x");
+        return cgx::launch_spmv_f32(ctx_of(h), A, x, y);
+    });
+}
+
+static int check_vec3(cgx_handle h, int64_t n, const void *x, const void *y, const void *z,
+                      bool z_may_alias)
+{
+    CGX_REQUIRE(h != nullptr, "handle is NULL");
+    CGX_REQUIRE(n >= 0, "negative length");
+    if (n == 0) return CGX_OK;
+    CGX_REQUIRE(x && y && z, "NULL vector");
+    const size_t nb = (size_t)n * 8;
+    if (z_may_alias) {
+        CGX_REQUIRE(z == x || !overlaps(z, nb, x, nb), "z partially overlaps x");
+        CGX_REQUIRE(z == y || !overlaps(z, nb, y, nb), "z partially overlaps y");
+    } else {
+        CGX_REQUIRE(!overlaps(x, nb, y, nb), "x and y overlap");
+    }
+    return CGX_OK;
+}
+
+int cgx_add(cgx_handle h, int64_t n, const double *x, const double *y, double *z)
+{
+    return guarded([&]() -> int {
+        int rc = check_vec3(h, n, x, y, z, true);
+        if (rc || n == 0) return rc;
+        return cgx::launch_add(ctx_of(h), n, x, y, z);
+    });
+}
+
+int cgx_axpy(cgx_handle h, int64_t n, double alpha, const double *x, double *y)
+{
+    return guarded([&]() -> int {
+        int rc = check_vec3(h, n, x, y, y, false);
+        if (rc || n == 0) return rc;
+        return cgx::launch_axpy(ctx_of(h), n, alpha, x, y);
+    });
+}
+
+int cgx_xmul(cgx_handle h, int64_t n, const double *x, const double *y, double *z)
+{
+    return guarded([&]() -> int {
+        int rc = check_vec3(h, n, x, y, z, true);
+        if (rc || n == 0) return rc;
+        return cgx::launch_xmul(ctx_of(h), n, x, y, z);
+    });
+}
+
+int cgx_dot(cgx_handle h, int64_t n, const double *x, const double *y, double *result)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(n >= 0, "negative length");
+        CGX_REQUIRE(result != nullptr, "result is NULL");
+        CGX_REQUIRE(n == 0 || (x && y), "NULL vector");
+        return cgx::launch_dot(ctx_of(h), n, x, y, result);
+    });
+}
+
+int cgx_demote(cgx_handle h, int64_t n, const double *src, float *dst)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(n >= 0, "negative length");
+        if (n == 0) return CGX_OK;
+        CGX_REQUIRE(src && dst, "NULL vector");
+        CGX_REQUIRE(!overlaps(src, (size_t)n * 8, dst, (size_t)n * 4), "dst overlaps src");
+        return cgx::launch_demote(ctx_of(h), n, src, dst);
+    });
+}
+
+size_t cgx_cg_workspace_bytes(int64_t n_rows, int64_t nnz, const cgx_opts *opts)
+{
+    if (n_rows < 0 || nnz < 0 || opts == nullptr) return 0;
+    try {
+        return cgx::cg_workspace_bytes(n_rows, nnz, opts);
+    } catch (...) {
+        return 0;
+    }
+}
+
+int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, void *workspace,
+                 size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(opts != nullptr && stats != nullptr, "opts or stats is NULL");
+        int rc = check_csr(A, true, opts->precision == CGX_PRECISION_MIXED);
+        if (rc) return rc;
+        CGX_REQUIRE(A->n_rows == A->n_cols, "matrix must be square");
+        CGX_REQUIRE(opts->precond == CGX_PRECOND_NONE || opts->precond == CGX_PRECOND_JACOBI,
+                    "unknown preconditioner");
+        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64 ||
+                        opts->precision == CGX_PRECISION_MIXED,
+                    "unknown precision");
+        CGX_REQUIRE(opts->rtol >= 0.0, "rtol must be >= 0");
+        std::memset(stats, 0, sizeof(*stats));
+        stats->relres_true = -1.0;
+        if (A->n_rows == 0) return CGX_OK;
+        CGX_REQUIRE(b && x && workspace, "NULL b, x or workspace");
+        CGX_REQUIRE(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
+        const size_t nb = (size_t)A->n_rows * 8;
+        CGX_REQUIRE(!overlaps(b, nb, x, nb), "x overlaps b");
+        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64, "mixed precision: not built yet");
+        return cgx::run_cg(ctx_of(h), A, b, x, workspace, workspace_bytes, opts, stats);
+    });
+}
+
+}  // extern "C"

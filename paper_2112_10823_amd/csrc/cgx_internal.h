@@ -1,0 +1,97 @@
+// Internal declarations shared by the libcgx translation units (HIP, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/cgx.h"
+
+namespace cgx {
+
+// ------------------------------------------------------------- errors ----
+
+void set_error(const std::string &msg);
+void clear_error();
+
+#define CGX_HIP_CHECK(expr)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ::cgx::set_error(std::string(#expr " failed: ") + hipGetErrorString(e_));    \
+            return CGX_EHIP;                                                             \
+        }                                                                                \
+    } while (0)
+
+#define CGX_REQUIRE(cond, msg)                                                           \
+    do {                                                                                 \
+        if (!(cond)) {                                                                   \
+            ::cgx::set_error(msg);                                                       \
+            return CGX_EINVAL;                                                           \
+        }                                                                                \
+    } while (0)
+
+// -------------------------------------------------------- launch sizes ----
+
+constexpr int kBlock = 256;         // threads per workgroup for streaming kernels
+constexpr int kReduceBlocks = 1024; // fixed grid of the standalone reductions
+constexpr int kMaxPartials = 65536; // partial sums a grid reduction may hold
+
+// Device-side CG state, stored at the start of the solver workspace.  All
+// fields are written by the single "last" workgroup of a reduction and read
+// by the following kernels.
+struct CgState {
+    double rho;    // r.z of the current iterate (r.r without preconditioner)
+    double alpha;  // rho / p.q
+    double beta;   // rho_new / rho
+    double pq;     // p.Ap
+    double rr;     // r.r of the current iterate
+    double bb;     // b.b
+    double stop2;  // (rtol * ||b||)^2
+    double rr_true;// ||b - A x||^2 when requested
+    int32_t iter;  // completed iterations
+    int32_t maxit;
+    int32_t status;// CGX_* status; CGX_PENDING while iterating
+    int32_t done;  // nonzero once converged or failed: later kernels return at once
+    int32_t bad;   // set by any thread meeting a non-positive / missing diagonal
+    int32_t pad;
+    uint32_t counter[4]; // arrival tickets of the grid reductions
+};
+
+// Handle state.
+struct Context {
+    int device = 0;
+    hipStream_t stream = nullptr;     // caller's stream: all asynchronous calls
+    hipStream_t own_stream = nullptr; // solver stream (graph capture needs a non-null stream)
+    int num_cu = 256;
+    double *scratch = nullptr;     // device: reduction partials
+    uint32_t *counters = nullptr;  // device: arrival tickets (zeroed at creation)
+    CgState *host_state = nullptr; // pinned host copy of the solver state
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;      // timing of a solve
+    hipEvent_t ev_in = nullptr, ev_out = nullptr; // ordering between the two streams
+    hipEvent_t ev_phase[4] = {nullptr, nullptr, nullptr, nullptr}; // profile mode
+    // cached CG graph
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    uint64_t graph_key[12] = {0};
+};
+
+// ----------------------------------------------------------- launchers ----
+
+int launch_add(Context *c, int64_t n, const double *x, const double *y, double *z);
+int launch_axpy(Context *c, int64_t n, double alpha, const double *x, double *y);
+int launch_xmul(Context *c, int64_t n, const double *x, const double *y, double *z);
+int launch_dot(Context *c, int64_t n, const double *x, const double *y, double *result);
+int launch_demote(Context *c, int64_t n, const double *src, float *dst);
+int launch_spmv(Context *c, const cgx_csr *A, const double *x, double *y);
+int launch_spmv_f32(Context *c, const cgx_csr *A, const float *x, float *y);
+int run_csr_validate(Context *c, const cgx_csr *A, int64_t *bad_row);
+int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
+           const cgx_opts *o, cgx_stats *st);
+size_t cg_workspace_bytes(int64_t n, int64_t nnz, const cgx_opts *o);
+
+// Lanes per row for the vector CSR kernel, from the mean row length.
+int lanes_per_row(int64_t n_rows, int64_t nnz);
+
+}  // namespace cgx

@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/cgx.h declares, and its struct layouts match the binding (no GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2112_10823_amd import cgx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cgx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cgx_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cgx.load_library()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in cgx.h but not exported"
+    assert set(names) == set(cgx.EXPORTS)
+
+
+def test_host_only_calls():
+    lib = cgx.load_library()
+    assert lib.cgx_version() == 100
+    o = cgx.make_opts(rtol=1e-8)
+    nb = cgx.cg_workspace_bytes(1000, 27000, o)
+    assert nb >= 3 * 1000 * 8
+    oj = cgx.make_opts(precond=cgx.PRECOND_JACOBI)
+    assert cgx.cg_workspace_bytes(1000, 27000, oj) >= nb + 2 * 1000 * 8
+    assert cgx.cg_workspace_bytes(-1, 0, o) == 0
+    assert lib.cgx_last_error() is not None
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(f"""
+#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+int main(void) {{
+  printf("%zu %zu %zu %zu\\n", sizeof(cgx_csr), offsetof(cgx_csr, row_ptr), offsetof(cgx_csr, val32), offsetof(cgx_csr, nnz));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(cgx_opts), offsetof(cgx_opts, inner_rtol), offsetof(cgx_opts, max_outer), offsetof(cgx_opts, true_residual), offsetof(cgx_opts, profile));
+  printf("%zu %zu %zu %zu\\n", sizeof(cgx_stats), offsetof(cgx_stats, relres), offsetof(cgx_stats, device_ms), offsetof(cgx_stats, phase_ms));
+  return 0;
+}}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    c = [list(map(int, l.split())) for l in out if l.strip()]
+    S, O, T = cgx._Csr, cgx.Opts, cgx.Stats
+    assert c[0] == [ctypes.sizeof(S), S.row_ptr.offset, S.val32.offset, S.nnz.offset]
+    assert c[1] == [ctypes.sizeof(O), O.inner_rtol.offset, O.max_outer.offset, O.true_residual.offset,
+                    O.profile.offset]
+    assert c[2] == [ctypes.sizeof(T), T.relres.offset, T.device_ms.offset, T.phase_ms.offset]
+
+
+def test_binding_refuses_host_tensors():
+    import torch
+    with pytest.raises(TypeError):
+        cgx._dev_tensor(torch.zeros(3, dtype=torch.float64), torch.float64, "x")
