@@ -118,6 +118,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--profile-only", action="store_true",
                     help="warm-up plus a few solves, for profiler runs")
+    ap.add_argument("--calib", action="store_true",
+                    help="with --profile-only: first run cgx_add on 2^26 float64 elements "
+                         "(reads 1 GiB, writes 0.5 GiB) to calibrate byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only; the multi-GPU path is a design "
@@ -132,6 +135,16 @@ def main():
     from paper_2112_10823_amd import cgx
 
     torch.cuda.set_device(0)
+    if args.calib:
+        m = 1 << 26
+        xa = torch.rand(m, dtype=torch.float64, device="cuda")
+        ya = torch.rand(m, dtype=torch.float64, device="cuda")
+        za = torch.empty_like(xa)
+        for _ in range(5):
+            cgx.add(xa, ya, za)
+        torch.cuda.synchronize()
+        del xa, ya, za
+        print("# calibration adds done (5 x 2^26 elements)", file=sys.stderr, flush=True)
     print(f"# building Q1 {N_GRID}^3 lognormal({SIGMA}) system", file=sys.stderr, flush=True)
     A = synth.q1cube(N_GRID, SIGMA, seed=synth.SEED_C2_COEFF)
     b = synth.blob_rhs(N_GRID, synth.SEED_C2_BLOBS)

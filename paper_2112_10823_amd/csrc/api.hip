@@ -80,8 +80,6 @@ int cgx_create(cgx_handle *out, int device, void *stream)
             c->num_cu = prop.multiProcessorCount;
         const size_t scratch_bytes = (size_t)2 * cgx::kReduceBlocks * sizeof(double) + 256;
         hipError_t e = hipMalloc(&c->scratch, scratch_bytes);
-        if (e == hipSuccess) e = hipMalloc(&c->counters, 64 * sizeof(uint32_t));
-        if (e == hipSuccess) e = hipMemset(c->counters, 0, 64 * sizeof(uint32_t));
         if (e == hipSuccess) e = hipHostMalloc(&c->host_state, sizeof(cgx::CgState));
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreate(&c->ev0);
@@ -107,8 +105,8 @@ int cgx_destroy(cgx_handle h)
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph64.reset();
+    c->graph32.reset();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
@@ -117,7 +115,6 @@ int cgx_destroy(cgx_handle h)
         if (c->ev_phase[i]) (void)hipEventDestroy(c->ev_phase[i]);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     if (c->host_state) (void)hipHostFree(c->host_state);
-    if (c->counters) (void)hipFree(c->counters);
     if (c->scratch) (void)hipFree(c->scratch);
     delete c;
     return CGX_OK;
@@ -269,7 +266,6 @@ int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, voi
         CGX_REQUIRE(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
         const size_t nb = (size_t)A->n_rows * 8;
         CGX_REQUIRE(!overlaps(b, nb, x, nb), "x overlaps b");
-        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64, "mixed precision: not built yet");
         return cgx::run_cg(ctx_of(h), A, b, x, workspace, workspace_bytes, opts, stats);
     });
 }

@@ -5,7 +5,8 @@
 // add/xmul/axpy).  Each thread moves four 16-byte pairs per trip so a wave
 // keeps several dwordx4 loads in flight; scalar code handles unaligned
 // pointers and the odd tail.  The dot product accumulates with error-free
-// transformations and finishes with the deterministic grid sum.
+// transformations; a second one-workgroup kernel adds the per-workgroup
+// partials in index order.
 #include "cgx_device.h"
 
 namespace cgx {
@@ -86,12 +87,13 @@ int launch_ew(Context *c, int64_t n, const double *x, const double *y, double *z
     return CGX_OK;
 }
 
-// Dot product: each thread accumulates (s, e) with two-product / two-sum over
-// a grid-stride walk, then the grid sum adds the s and e parts separately
-// (both in fixed order) and the last workgroup returns s + e.
-__global__ __launch_bounds__(kBlock) void dot_kernel(int64_t n, const double *__restrict__ x,
-                                                     const double *__restrict__ y, double *partials,
-                                                     uint32_t *ticket, double *result)
+// Dot product, pass 1: each thread accumulates (s, e) with two-product /
+// two-sum over a grid-stride walk; each workgroup stores its block totals of
+// s and e as plain partials.
+__global__ __launch_bounds__(kBlock) void dot_partials_kernel(int64_t n,
+                                                              const double *__restrict__ x,
+                                                              const double *__restrict__ y,
+                                                              double *partials)
 {
 #pragma clang fp contract(off)
     double s = 0.0, e = 0.0;
@@ -122,8 +124,23 @@ __global__ __launch_bounds__(kBlock) void dot_kernel(int64_t n, const double *__
         s = t;
         e += pe + te;
     }
+    __shared__ double red[2 * (kBlock / kWave)];
     double v[2] = {s, e};
-    if (grid_sum<2, kBlock>(v, partials, ticket) && threadIdx.x == 0) *result = v[0] + v[1];
+    block_sum<2, kBlock>(v, red);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = v[0];
+        partials[gridDim.x + blockIdx.x] = v[1];
+    }
+}
+
+// Dot product, pass 2 (one workgroup): the s and e partials in index order.
+__global__ __launch_bounds__(kBlock) void dot_finish_kernel(const double *partials, int count,
+                                                            double *result)
+{
+    __shared__ double red[kBlock / kWave];
+    const double s = sum_partials<kBlock>(partials, count, red);
+    const double e = sum_partials<kBlock>(partials + count, count, red);
+    if (threadIdx.x == 0) *result = s + e;
 }
 
 __global__ __launch_bounds__(kBlock) void demote_kernel(int64_t n, const double *__restrict__ src,
@@ -156,8 +173,10 @@ int launch_dot(Context *c, int64_t n, const double *x, const double *y, double *
     int grid = kReduceBlocks;
     const int64_t need = (n + kBlock - 1) / kBlock;
     if (need < grid) grid = need > 0 ? (int)need : 1;
-    hipLaunchKernelGGL(dot_kernel, dim3(grid), dim3(kBlock), 0, c->stream, n, x, y, c->scratch,
-                       c->counters, result);
+    hipLaunchKernelGGL(dot_partials_kernel, dim3(grid), dim3(kBlock), 0, c->stream, n, x, y,
+                       c->scratch);
+    hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(kBlock), 0, c->stream, c->scratch, grid,
+                       result);
     CGX_HIP_CHECK(hipGetLastError());
     return CGX_OK;
 }

@@ -1,17 +1,23 @@
 // Conjugate gradient (the paper's Section 5.3: classical CG, here with an
-// optional Jacobi preconditioner) on gfx950.
+// optional Jacobi preconditioner, and binary32-inner iterative refinement as
+// in the mixed-precision reference cited beside CG) on gfx950.
 //
 // Each iteration is three kernels whose scalars never leave the GPU:
-//   (1) q = A p fused with p.q; the last workgroup forms alpha = rho / p.q
-//   (2) x += alpha p, r -= alpha q, [z = D^-1 r], r.r [, r.z]; the last
-//       workgroup applies the stopping test and forms beta = rho' / rho
-//   (3) p = z + beta p
-// K iterations are captured once into a HIP graph and replayed; the host
-// reads one status word per replay.  After convergence the remaining kernels
-// of a replay see `done` and return at once.  Systems of at most kSmallN rows
-// run the whole solve inside one 1024-thread workgroup instead (one launch,
-// workgroup barriers between phases): at that size the cost is launches and
-// grid synchronisation, not bandwidth.
+//   (1) q = A p (CSR-stream tiles) fused with partials of p.q
+//   (2) alpha = rho / p.q, x += alpha p, r -= alpha q, [z = D^-1 r], partials
+//       of r.r [and r.z]
+//   (3) stopping test, beta = rho' / rho, p = z + beta p
+// Every workgroup of (2) and (3) adds the previous kernel's partials itself,
+// in the same order, so all of them hold bit-identical scalars without any
+// grid-wide synchronisation inside a kernel; workgroup 0 records the state.
+// The kernels are templated on the working precision: float64 for the plain
+// solve, binary32 (values, vectors and accumulation) for the inner solve of
+// the refinement.  K iterations are captured once into a HIP graph and
+// replayed; the host reads one status word per replay.  After convergence
+// the remaining kernels of a replay see `done` and return at once.  Systems
+// of at most kSmallN rows run the whole float64 solve inside one 1024-thread
+// workgroup instead (one launch, workgroup barriers between phases): at that
+// size the cost is launches and grid synchronisation, not bandwidth.
 #include <cmath>
 
 #include "cgx_device.h"
@@ -19,35 +25,46 @@
 namespace cgx {
 namespace {
 
-constexpr int kRowsPerGroup = 4;
-constexpr int kBlocksPerCu = 8;
-constexpr int kMaxPhaseBlocks = 4096;
+constexpr int kPB = kStreamBlock;    // threads per workgroup of the phase kernels
+constexpr int kPhaseBlocksPerCu = 4;
+constexpr int kMaxPhaseBlocks = 2048;
+constexpr int kRowsPerGroup = 4;     // vector-CSR rows per lane group (setup passes)
 constexpr int kSmallBlock = 1024;
 constexpr int kSmallRows = 2;
 constexpr int64_t kSmallN = 16384;
 
+// Partials of the grid-wide sums, one slot per workgroup of the phase grid.
+// Each producer writes its own region; consumers read regions written by
+// earlier kernels only.
+enum PartialRegion { kPInit = 0 /* 3 arrays */, kPPq = 3, kPRr = 4, kPRz = 5, kPAux = 6 /* 2 */,
+                     kPRegions = 8 };
+
+template <typename T>
 struct CgArgs {
     int n;
     int n_cols;
     int64_t nnz;
     const int32_t *rp;
     const int32_t *ci;
-    const double *val;
-    const double *b;
-    double *x;
-    double *r;
-    double *p;
-    double *q;
-    double *z;     // == r without preconditioner
-    double *dinv;  // nullptr without preconditioner
-    double *partials;
+    const T *val;
+    const T *b;
+    T *x;
+    T *r;
+    T *p;
+    T *q;
+    T *z;     // == r without preconditioner
+    T *dinv;  // nullptr without preconditioner
+    T *partials;  // kPRegions * kMaxPhaseBlocks values
     CgState *st;
     int tiles_per_block;  // SpMV phases: row tiles per workgroup
+    int grid_sp;          // workgroups of the SpMV phase (partials it writes)
+    int grid_ew;          // workgroups of the update phase
 };
 
-__device__ __forceinline__ int load_flag(const int32_t *p)
+template <typename T>
+__device__ __forceinline__ T *region(const CgArgs<T> &a, int r)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return a.partials + (int64_t)r * kMaxPhaseBlocks;
 }
 
 __global__ void cg_state_init_kernel(CgState *st, int maxit)
@@ -69,7 +86,7 @@ __device__ void finish_init(CgState *st, double rr, double rz, double bb, double
     st->stop2 = rtol2 * bb;
     st->iter = 0;
     int status = CGX_PENDING;
-    if (load_flag(&st->bad))
+    if (st->bad)
         status = CGX_BREAKDOWN;
     else if (!isfinite(bb) || !isfinite(rr) || !isfinite(rz))
         status = CGX_NONFINITE;
@@ -81,23 +98,256 @@ __device__ void finish_init(CgState *st, double rr, double rz, double bb, double
     st->done = status != CGX_PENDING;
 }
 
-// Status after p.q of an iteration; forms alpha.
-__device__ void finish_pq(CgState *st, double pq)
+// Lane 0 of a row group: residual, preconditioner and direction of a row.
+template <bool kJac>
+__device__ __forceinline__ void init_row(const CgArgs<double> &a, int row, double ax, double diag,
+                                         double (&part)[3])
+{
+    const double bi = a.b[row];
+    const double ri = bi - ax;
+    double zi = ri;
+    a.r[row] = ri;
+    if (kJac) {
+        double d = diag;
+        if (!(d > 0.0)) {
+            a.st->bad = 1;  // every writer stores the same value
+            d = 1.0;
+        }
+        const double di = 1.0 / d;
+        a.dinv[row] = di;
+        zi = di * ri;
+        a.z[row] = zi;
+    }
+    a.p[row] = zi;
+    part[0] += ri * ri;
+    part[1] += ri * zi;
+    part[2] += bi * bi;
+}
+
+// Row-tile range [t0, t1) of this workgroup in the SpMV-type phases; the
+// tiles of one die are contiguous.
+__device__ __forceinline__ void tile_range(int ntiles, int tiles_per_block, int &t0, int &t1)
+{
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    t0 = lb * tiles_per_block;
+    t1 = min(t0 + tiles_per_block, ntiles);
+}
+
+// ------------------------------------------------ phase kernels (large n) --
+
+// Setup: r0 = b - A x0 (vector-CSR rows, diagonal read on the way), z0, p0,
+// and the partials of r.r, r.z, b.b.
+template <int L, bool kJac>
+__global__ __launch_bounds__(kPB) void cg_init_kernel(CgArgs<double> a)
+{
+    constexpr int R = kRowsPerGroup, RPB = (kPB / L) * R;
+    const int ntiles = (a.n + RPB - 1) / RPB;
+    const int per = (ntiles + gridDim.x - 1) / gridDim.x;
+    int t0, t1;
+    tile_range(ntiles, per, t0, t1);
+    double part[3] = {0.0, 0.0, 0.0};
+    for (int t = t0; t < t1; ++t) {
+        double acc[R], dg[R];
+        int rows[R];
+        vector_rows<L, R, kPB, double, kJac>(t * RPB, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val, a.x,
+                                             acc, dg, rows);
+        if (threadIdx.x % L == 0)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (rows[r] < a.n) init_row<kJac>(a, rows[r], acc[r], dg[r], part);
+    }
+    __shared__ double red[3 * (kPB / kWave)];
+    block_sum<3, kPB>(part, red);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 3; ++j) region(a, kPInit + j)[blockIdx.x] = part[j];
+}
+
+// One workgroup: adds the setup partials and sets the initial state.
+__global__ __launch_bounds__(kPB) void cg_init_finish_kernel(CgArgs<double> a, int count,
+                                                             double rtol2, int jac)
+{
+    __shared__ double red[kPB / kWave];
+    const double rr = sum_partials<kPB>(region(a, kPInit + 0), count, red);
+    const double rz = sum_partials<kPB>(region(a, kPInit + 1), count, red);
+    const double bb = sum_partials<kPB>(region(a, kPInit + 2), count, red);
+    if (threadIdx.x == 0) finish_init(a.st, rr, rz, bb, rtol2, jac != 0);
+}
+
+// (1) q = A p by CSR-stream tiles, and the partials of p.q.
+template <int RT, typename T>
+__global__ __launch_bounds__(kPB) void cg_spmv_kernel(CgArgs<T> a)
+{
+    if (a.st->done) return;
+    __shared__ StreamSmem<kPB, kStreamE, RT, T> sm;
+    const int ntiles = (a.n + RT - 1) / RT;
+    int t0, t1;
+    tile_range(ntiles, a.tiles_per_block, t0, t1);
+    T part = T(0);
+    for (int t = t0; t < t1; ++t) {
+        int row;
+        const T acc =
+            stream_rows<kPB, kStreamE, RT, T>(t * RT, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val,
+                                              a.p, sm, row);
+        if (threadIdx.x % (kPB / RT) == 0 && row < a.n) {
+            a.q[row] = acc;
+            part += a.p[row] * acc;
+        }
+    }
+    __shared__ T red[kPB / kWave];
+    T v[1] = {part};
+    block_sum<1, kPB>(v, red);
+    if (threadIdx.x == 0) region(a, kPPq)[blockIdx.x] = v[0];
+}
+
+// (2) alpha = rho / p.q (every workgroup adds the p.q partials in the same
+// order), x += alpha p, r -= alpha q, z = D^-1 r, partials of r.r and r.z.
+// Workgroup 0 records alpha, the rho in use and the iteration count.
+template <bool kJac, typename T>
+__global__ __launch_bounds__(kPB) void cg_update_kernel(CgArgs<T> a)
+{
+    CgState *st = a.st;
+    if (st->done) return;
+    __shared__ T red[kPB / kWave];
+    const T pq = sum_partials<kPB>(region(a, kPPq), a.grid_sp, red);
+    const T rho = (T)st->rho;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!isfinite(pq) || !(pq > T(0))) {
+        if (lead) {
+            st->pq = pq;
+            st->status = isfinite(pq) ? CGX_BREAKDOWN : CGX_NONFINITE;
+            st->done = 1;
+        }
+        return;
+    }
+    const T alpha = rho / pq;
+    if (lead) {
+        st->pq = pq;
+        st->alpha = alpha;
+        st->rho_used = rho;
+        st->iter = st->iter + 1;
+    }
+    T *__restrict__ x = a.x;
+    T *__restrict__ r = a.r;
+    T *__restrict__ z = a.z;
+    const T *__restrict__ p = a.p;
+    const T *__restrict__ q = a.q;
+    const T *__restrict__ dinv = a.dinv;
+    T part[2] = {T(0), T(0)};
+    const int64_t stride = (int64_t)gridDim.x * kPB;
+#pragma unroll 4
+    for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < a.n; i += stride) {
+        const T xi = __builtin_fma(alpha, p[i], x[i]);
+        const T ri = __builtin_fma(-alpha, q[i], r[i]);
+        x[i] = xi;
+        r[i] = ri;
+        part[0] += ri * ri;
+        if (kJac) {
+            const T zi = dinv[i] * ri;
+            z[i] = zi;
+            part[1] += ri * zi;
+        }
+    }
+    __shared__ T red2[2 * (kPB / kWave)];
+    block_sum<2, kPB>(part, red2);
+    if (threadIdx.x == 0) {
+        region(a, kPRr)[blockIdx.x] = part[0];
+        region(a, kPRz)[blockIdx.x] = part[1];
+    }
+}
+
+// (3) Stopping test on r.r (every workgroup adds the partials in the same
+// order); beta = rho' / rho; p = z + beta p.  Workgroup 0 records the state.
+template <bool kJac, typename T>
+__global__ __launch_bounds__(kPB) void cg_direction_kernel(CgArgs<T> a)
+{
+    CgState *st = a.st;
+    if (st->done) return;
+    __shared__ T red[kPB / kWave];
+    const T rr = sum_partials<kPB>(region(a, kPRr), a.grid_ew, red);
+    const T rz = kJac ? sum_partials<kPB>(region(a, kPRz), a.grid_ew, red) : rr;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    int status = CGX_PENDING;
+    if (!isfinite(rr) || !isfinite(rz))
+        status = CGX_NONFINITE;
+    else if (rr <= (T)st->stop2)
+        status = CGX_OK;
+    else if (!(rz > T(0)))
+        status = CGX_BREAKDOWN;
+    else if (st->iter >= st->maxit)
+        status = CGX_NOT_CONVERGED;
+    if (status != CGX_PENDING) {
+        if (lead) {
+            st->rr = rr;
+            st->status = status;
+            st->done = 1;
+        }
+        return;
+    }
+    const T beta = rz / (T)st->rho_used;
+    if (lead) {
+        st->rr = rr;
+        st->rho = rz;
+        st->beta = beta;
+    }
+    T *__restrict__ p = a.p;
+    const T *__restrict__ z = a.z;
+    const int64_t stride = (int64_t)gridDim.x * kPB;
+#pragma unroll 4
+    for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < a.n; i += stride)
+        p[i] = __builtin_fma(beta, p[i], z[i]);
+}
+
+// ||b - A x||^2 partials (region kPAux), then one workgroup into st->rr_true.
+template <int RT>
+__global__ __launch_bounds__(kPB) void cg_true_residual_kernel(CgArgs<double> a)
+{
+    __shared__ StreamSmem<kPB, kStreamE, RT, double> sm;
+    const int ntiles = (a.n + RT - 1) / RT;
+    int t0, t1;
+    tile_range(ntiles, a.tiles_per_block, t0, t1);
+    double part = 0.0;
+    for (int t = t0; t < t1; ++t) {
+        int row;
+        const double acc = stream_rows<kPB, kStreamE, RT, double>(t * RT, a.n, a.n_cols, a.nnz,
+                                                                  a.rp, a.ci, a.val, a.x, sm, row);
+        if (threadIdx.x % (kPB / RT) == 0 && row < a.n) {
+            const double d = a.b[row] - acc;
+            part += d * d;
+        }
+    }
+    __shared__ double red[kPB / kWave];
+    double v[1] = {part};
+    block_sum<1, kPB>(v, red);
+    if (threadIdx.x == 0) region(a, kPAux)[blockIdx.x] = v[0];
+}
+
+__global__ __launch_bounds__(kPB) void cg_true_residual_finish_kernel(CgArgs<double> a, int count)
+{
+    __shared__ double red[kPB / kWave];
+    const double rr = sum_partials<kPB>(region(a, kPAux), count, red);
+    if (threadIdx.x == 0) a.st->rr_true = rr;
+}
+
+__global__ __launch_bounds__(kBlock) void zero_kernel(int64_t n, double *x)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) x[i] = 0.0;
+}
+
+// Status after p.q (single-workgroup path); forms alpha.
+__device__ void small_finish_pq(CgState *st, double pq)
 {
     st->pq = pq;
-    if (!isfinite(pq)) {
-        st->status = CGX_NONFINITE;
-        st->done = 1;
-    } else if (!(pq > 0.0)) {
-        st->status = CGX_BREAKDOWN;
+    if (!isfinite(pq) || !(pq > 0.0)) {
+        st->status = isfinite(pq) ? CGX_BREAKDOWN : CGX_NONFINITE;
         st->done = 1;
     } else {
         st->alpha = st->rho / pq;
     }
 }
 
-// Status after the update of an iteration; forms beta.
-__device__ void finish_update(CgState *st, double rr, double rz)
+// Status after the update (single-workgroup path); forms beta.
+__device__ void small_finish_update(CgState *st, double rr, double rz)
 {
     const int iter = st->iter + 1;
     st->iter = iter;
@@ -120,156 +370,10 @@ __device__ void finish_update(CgState *st, double rr, double rz)
     }
 }
 
-// Lane 0 of a row group: residual, preconditioner and direction of a row.
-template <bool kJac>
-__device__ __forceinline__ void init_row(const CgArgs &a, int row, double ax, double diag,
-                                         double (&part)[3])
-{
-    const double bi = a.b[row];
-    const double ri = bi - ax;
-    double zi = ri;
-    a.r[row] = ri;
-    if (kJac) {
-        double d = diag;
-        if (!(d > 0.0)) {
-            atomicOr(&a.st->bad, 1);
-            __threadfence();
-            d = 1.0;
-        }
-        const double di = 1.0 / d;
-        a.dinv[row] = di;
-        zi = di * ri;
-        a.z[row] = zi;
-    }
-    a.p[row] = zi;
-    part[0] += ri * ri;
-    part[1] += ri * zi;
-    part[2] += bi * bi;
-}
-
-// ------------------------------------------------ phase kernels (large n) --
-
-template <int L, bool kJac>
-__global__ __launch_bounds__(kBlock) void cg_init_kernel(CgArgs a, double rtol2)
-{
-    constexpr int R = kRowsPerGroup, RPB = (kBlock / L) * R;
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
-    const int ntiles = (a.n + RPB - 1) / RPB;
-    const int t0 = lb * a.tiles_per_block;
-    const int t1 = min(t0 + a.tiles_per_block, ntiles);
-    double part[3] = {0.0, 0.0, 0.0};
-    for (int t = t0; t < t1; ++t) {
-        double acc[R], dg[R];
-        int rows[R];
-        vector_rows<L, R, kBlock, double, kJac>(t * RPB, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val,
-                                                a.x, acc, dg, rows);
-        if (threadIdx.x % L == 0)
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (rows[r] < a.n) init_row<kJac>(a, rows[r], acc[r], dg[r], part);
-    }
-    if (grid_sum<3, kBlock>(part, a.partials, &a.st->counter[0]) && threadIdx.x == 0)
-        finish_init(a.st, part[0], part[1], part[2], rtol2, kJac);
-}
-
-template <int L>
-__global__ __launch_bounds__(kBlock) void cg_spmv_kernel(CgArgs a)
-{
-    if (a.st->done) return;
-    constexpr int R = kRowsPerGroup, RPB = (kBlock / L) * R;
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
-    const int ntiles = (a.n + RPB - 1) / RPB;
-    const int t0 = lb * a.tiles_per_block;
-    const int t1 = min(t0 + a.tiles_per_block, ntiles);
-    double part[1] = {0.0};
-    for (int t = t0; t < t1; ++t) {
-        double acc[R], dg[R];
-        int rows[R];
-        vector_rows<L, R, kBlock, double, false>(t * RPB, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val,
-                                                 a.p, acc, dg, rows);
-        if (threadIdx.x % L == 0)
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (rows[r] < a.n) {
-                    a.q[rows[r]] = acc[r];
-                    part[0] += a.p[rows[r]] * acc[r];
-                }
-    }
-    if (grid_sum<1, kBlock>(part, a.partials, &a.st->counter[1]) && threadIdx.x == 0)
-        finish_pq(a.st, part[0]);
-}
-
-template <bool kJac>
-__global__ __launch_bounds__(kBlock) void cg_update_kernel(CgArgs a)
-{
-    if (a.st->done) return;
-    const double alpha = a.st->alpha;
-    double part[2] = {0.0, 0.0};
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-#pragma unroll 4
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += stride) {
-        const double xi = __builtin_fma(alpha, a.p[i], a.x[i]);
-        const double ri = __builtin_fma(-alpha, a.q[i], a.r[i]);
-        a.x[i] = xi;
-        a.r[i] = ri;
-        part[0] += ri * ri;
-        if (kJac) {
-            const double zi = a.dinv[i] * ri;
-            a.z[i] = zi;
-            part[1] += ri * zi;
-        }
-    }
-    if (grid_sum<2, kBlock>(part, a.partials, &a.st->counter[2]) && threadIdx.x == 0)
-        finish_update(a.st, part[0], kJac ? part[1] : part[0]);
-}
-
-__global__ __launch_bounds__(kBlock) void cg_direction_kernel(CgArgs a)
-{
-    if (a.st->done) return;
-    const double beta = a.st->beta;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-#pragma unroll 4
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += stride)
-        a.p[i] = __builtin_fma(beta, a.p[i], a.z[i]);
-}
-
-// ||b - A x||^2 into st->rr_true.
-template <int L>
-__global__ __launch_bounds__(kBlock) void cg_true_residual_kernel(CgArgs a)
-{
-    constexpr int R = kRowsPerGroup, RPB = (kBlock / L) * R;
-    const int lb = xcd_block(blockIdx.x, gridDim.x);
-    const int ntiles = (a.n + RPB - 1) / RPB;
-    const int t0 = lb * a.tiles_per_block;
-    const int t1 = min(t0 + a.tiles_per_block, ntiles);
-    double part[1] = {0.0};
-    for (int t = t0; t < t1; ++t) {
-        double acc[R], dg[R];
-        int rows[R];
-        vector_rows<L, R, kBlock, double, false>(t * RPB, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val,
-                                                 a.x, acc, dg, rows);
-        if (threadIdx.x % L == 0)
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (rows[r] < a.n) {
-                    const double d = a.b[rows[r]] - acc[r];
-                    part[0] += d * d;
-                }
-    }
-    if (grid_sum<1, kBlock>(part, a.partials, &a.st->counter[3]) && threadIdx.x == 0)
-        a.st->rr_true = part[0];
-}
-
-__global__ __launch_bounds__(kBlock) void zero_kernel(int64_t n, double *x)
-{
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) x[i] = 0.0;
-}
-
 // ------------------------------------------- single-workgroup solve (small n) --
 
 template <int L, bool kJac>
-__global__ __launch_bounds__(kSmallBlock) void cg_small_kernel(CgArgs a, double rtol2)
+__global__ __launch_bounds__(kSmallBlock) void cg_small_kernel(CgArgs<double> a, double rtol2)
 {
     constexpr int BS = kSmallBlock, R = kSmallRows, RPB = (BS / L) * R;
     __shared__ double red[3 * (BS / kWave)];
@@ -314,7 +418,7 @@ __global__ __launch_bounds__(kSmallBlock) void cg_small_kernel(CgArgs a, double 
         }
         block_sum<1, BS>(p1, red);
         if (threadIdx.x == 0) {
-            finish_pq(st, p1[0]);
+            small_finish_pq(st, p1[0]);
             sh_done = st->done;
             sh_alpha = st->alpha;
         }
@@ -337,7 +441,7 @@ __global__ __launch_bounds__(kSmallBlock) void cg_small_kernel(CgArgs a, double 
         }
         block_sum<2, BS>(p2, red);
         if (threadIdx.x == 0) {
-            finish_update(st, p2[0], kJac ? p2[1] : p2[0]);
+            small_finish_update(st, p2[0], kJac ? p2[1] : p2[0]);
             sh_done = st->done;
             sh_beta = st->beta;
         }
@@ -350,21 +454,191 @@ __global__ __launch_bounds__(kSmallBlock) void cg_small_kernel(CgArgs a, double 
     }
 }
 
-// ----------------------------------------------------------------- host --
+// ------------------------------------------------ mixed-precision refinement --
+//
+// Outer state (a CgState): rr = ||b - A x||^2 of the current x, bb = ||b||^2,
+// stop2 = rtol^2 bb, alpha = the scale s = ||r|| of the current step, iter =
+// refinement steps done, maxit = their cap.
 
-struct Layout {
-    size_t state, r, p, q, z, dinv, partials, total;
+struct MxArgs {
+    int n;
+    int n_cols;
+    int64_t nnz;
+    const int32_t *rp;
+    const int32_t *ci;
+    const double *val;
+    const double *b;
+    double *x;
+    double *r;         // float64 residual b - A x
+    float *dinv32;     // Jacobi: (float)(1 / a_ii), written on the first step
+    double *partials;  // kPRegions * kMaxPhaseBlocks doubles (shared with the inner solve)
+    CgState *ost;
 };
+
+// r = b - A x in float64 and the partials of ||r||^2 (and ||b||^2 and the
+// inverse diagonal on the first step).
+template <int L, bool kFirst, bool kJac>
+__global__ __launch_bounds__(kPB) void mx_residual_kernel(MxArgs m)
+{
+    if (m.ost->done) return;
+    constexpr int R = kRowsPerGroup, RPB = (kPB / L) * R;
+    const int ntiles = (m.n + RPB - 1) / RPB;
+    const int per = (ntiles + gridDim.x - 1) / gridDim.x;
+    int t0, t1;
+    tile_range(ntiles, per, t0, t1);
+    double part[2] = {0.0, 0.0};
+    for (int t = t0; t < t1; ++t) {
+        double acc[R], dg[R];
+        int rows[R];
+        vector_rows<L, R, kPB, double, kFirst && kJac>(t * RPB, m.n, m.n_cols, m.nnz, m.rp, m.ci,
+                                                       m.val, m.x, acc, dg, rows);
+        if (threadIdx.x % L == 0)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int row = rows[r];
+                if (row >= m.n) continue;
+                const double bi = m.b[row];
+                const double ri = bi - acc[r];
+                m.r[row] = ri;
+                part[0] += ri * ri;
+                if (kFirst) {
+                    part[1] += bi * bi;
+                    if (kJac) {
+                        double d = dg[r];
+                        if (!(d > 0.0)) {
+                            m.ost->bad = 1;
+                            d = 1.0;
+                        }
+                        m.dinv32[row] = (float)(1.0 / d);
+                    }
+                }
+            }
+    }
+    __shared__ double red[2 * (kPB / kWave)];
+    block_sum<2, kPB>(part, red);
+    if (threadIdx.x == 0) {
+        m.partials[(int64_t)kPAux * kMaxPhaseBlocks + blockIdx.x] = part[0];
+        m.partials[(int64_t)(kPAux + 1) * kMaxPhaseBlocks + blockIdx.x] = part[1];
+    }
+}
+
+// One workgroup: outer stopping test on the residual partials.
+__global__ __launch_bounds__(kPB) void mx_residual_finish_kernel(MxArgs m, int count, int first,
+                                                                 double rtol2)
+{
+    CgState *o = m.ost;
+    if (o->done) return;
+    __shared__ double red[kPB / kWave];
+    const double rr = sum_partials<kPB>(m.partials + (int64_t)kPAux * kMaxPhaseBlocks, count, red);
+    const double bb =
+        sum_partials<kPB>(m.partials + (int64_t)(kPAux + 1) * kMaxPhaseBlocks, count, red);
+    if (threadIdx.x != 0) return;
+    if (first) {
+        o->bb = bb;
+        o->stop2 = rtol2 * bb;
+    }
+    o->rr = rr;
+    int status = CGX_PENDING;
+    if (o->bad)
+        status = CGX_BREAKDOWN;
+    else if (!isfinite(rr) || !isfinite(o->bb))
+        status = CGX_NONFINITE;
+    else if (o->bb == 0.0 || rr <= o->stop2)
+        status = CGX_OK;
+    else if (o->iter >= o->maxit)
+        status = CGX_NOT_CONVERGED;
+    if (status == CGX_PENDING) {
+        o->alpha = sqrt(rr);
+    } else {
+        o->status = status;
+        o->done = 1;
+    }
+}
+
+// Inner start: c = float(r / s), d = 0, r32 = c, z = D^-1 c, p = z, and the
+// partials of c.c and c.z.
+template <bool kJac>
+__global__ __launch_bounds__(kPB) void mx_inner_init_kernel(MxArgs m, CgArgs<float> in)
+{
+    if (m.ost->done) return;
+    const double inv_s = 1.0 / m.ost->alpha;
+    float part[2] = {0.0f, 0.0f};
+    const int64_t stride = (int64_t)gridDim.x * kPB;
+    for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < m.n; i += stride) {
+        const float ci = (float)(m.r[i] * inv_s);
+        const float zi = kJac ? m.dinv32[i] * ci : ci;
+        in.r[i] = ci;
+        in.x[i] = 0.0f;
+        if (kJac) in.z[i] = zi;
+        in.p[i] = zi;
+        part[0] += ci * ci;
+        part[1] += ci * zi;
+    }
+    __shared__ float red[2 * (kPB / kWave)];
+    block_sum<2, kPB>(part, red);
+    if (threadIdx.x == 0) {
+        region(in, kPInit)[blockIdx.x] = part[0];
+        region(in, kPInit + 1)[blockIdx.x] = part[1];
+    }
+}
+
+// One workgroup: inner state for a new refinement step (stop at
+// ||r32|| <= tau ||c||).
+__global__ __launch_bounds__(kPB) void mx_inner_init_finish_kernel(MxArgs m, CgArgs<float> in,
+                                                                   int count, float tau2,
+                                                                   int inner_maxit, int jac)
+{
+    if (m.ost->done) return;
+    __shared__ float red[kPB / kWave];
+    const float cc = sum_partials<kPB>(region(in, kPInit), count, red);
+    const float cz = jac ? sum_partials<kPB>(region(in, kPInit + 1), count, red) : cc;
+    if (threadIdx.x != 0) return;
+    CgState *s = in.st;
+    s->rr = cc;
+    s->rho = cz;
+    s->stop2 = (double)(tau2 * cc);
+    s->iter = 0;
+    s->maxit = inner_maxit;
+    const bool bad = !isfinite(cc) || !isfinite(cz) || !(cz > 0.0f);
+    s->status = bad ? CGX_NONFINITE : CGX_PENDING;
+    s->done = bad ? 1 : 0;
+}
+
+// x += s * double(d); one refinement step done.
+__global__ __launch_bounds__(kPB) void mx_correct_kernel(MxArgs m, const float *d)
+{
+    if (m.ost->done) return;
+    const double s = m.ost->alpha;
+    const int64_t stride = (int64_t)gridDim.x * kPB;
+    for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < m.n; i += stride)
+        m.x[i] = __builtin_fma(s, (double)d[i], m.x[i]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) m.ost->iter += 1;
+}
+
+// ----------------------------------------------------------------- host --
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Layout layout_fp64(int64_t n, bool jac)
+// Workspace layout.  float64 solve: state | r p q [z dinv] | partials.
+// Mixed: outer state | inner state | r64 | r32 p32 q32 [z32 dinv32] | d32 | partials.
+struct Layout {
+    size_t state = 0, state2 = 0, r64 = 0, r = 0, p = 0, q = 0, z = 0, dinv = 0, d = 0;
+    size_t partials = 0, total = 0;
+};
+
+Layout make_layout(int64_t n, bool jac, bool mixed)
 {
-    Layout L{};
+    Layout L;
     size_t off = 0;
-    const size_t vec = align_up((size_t)n * sizeof(double));
+    const size_t vec = align_up((size_t)n * (mixed ? sizeof(float) : sizeof(double)));
     L.state = off;
     off += align_up(sizeof(CgState));
+    if (mixed) {
+        L.state2 = off;
+        off += align_up(sizeof(CgState));
+        L.r64 = off;
+        off += align_up((size_t)n * sizeof(double));
+    }
     L.r = off;
     off += vec;
     L.p = off;
@@ -372,57 +646,116 @@ Layout layout_fp64(int64_t n, bool jac)
     L.q = off;
     off += vec;
     L.z = L.r;
-    L.dinv = 0;
     if (jac) {
         L.z = off;
         off += vec;
         L.dinv = off;
         off += vec;
     }
+    if (mixed) {
+        L.d = off;
+        off += vec;
+    }
     L.partials = off;
-    off += align_up((size_t)3 * kMaxPhaseBlocks * sizeof(double));
+    off += align_up((size_t)kPRegions * kMaxPhaseBlocks * sizeof(double));
     L.total = off;
     return L;
 }
 
-#define CGX_LANE_SWITCH(L, EXPR_T)                                                       \
-    switch (L) {                                                                         \
-        case 2: EXPR_T(2); break;                                                        \
-        case 4: EXPR_T(4); break;                                                        \
-        case 8: EXPR_T(8); break;                                                        \
-        case 16: EXPR_T(16); break;                                                      \
-        case 32: EXPR_T(32); break;                                                      \
-        default: EXPR_T(64); break;                                                      \
+#define CGX_LANE_SWITCH(L, EXPR_T)       \
+    switch (L) {                         \
+        case 2: EXPR_T(2); break;        \
+        case 4: EXPR_T(4); break;        \
+        case 8: EXPR_T(8); break;        \
+        case 16: EXPR_T(16); break;      \
+        case 32: EXPR_T(32); break;      \
+        default: EXPR_T(64); break;      \
     }
 
-void launch_init(int L, bool jac, int grid, hipStream_t s, const CgArgs &a, double rtol2)
+struct Grids {
+    int L;        // lanes per row of the vector-CSR setup passes
+    int RT;       // rows per CSR-stream tile
+    int grid_sp;  // workgroups of the SpMV phase (persistent over tiles)
+    int grid_ew;  // workgroups of the elementwise phases
+    int grid_vr;  // workgroups of the vector-CSR setup passes
+    int tiles_per_block;
+};
+
+Grids make_grids(const Context *c, int64_t n, int64_t nnz)
 {
-#define CGX_INIT(LL)                                                                        \
-    if (jac)                                                                                \
-        hipLaunchKernelGGL((cg_init_kernel<LL, true>), dim3(grid), dim3(kBlock), 0, s, a,    \
-                           rtol2);                                                          \
-    else                                                                                    \
-        hipLaunchKernelGGL((cg_init_kernel<LL, false>), dim3(grid), dim3(kBlock), 0, s, a, rtol2)
-    CGX_LANE_SWITCH(L, CGX_INIT)
-#undef CGX_INIT
+    Grids g{};
+    g.L = lanes_per_row(n, nnz);
+    g.RT = stream_tile_rows(n, nnz);
+    const int cap = std::min(c->num_cu * kPhaseBlocksPerCu, kMaxPhaseBlocks);
+    const int64_t ntiles = (n + g.RT - 1) / g.RT;
+    g.grid_sp = (int)std::max<int64_t>(1, std::min<int64_t>(cap, ntiles));
+    g.tiles_per_block = (int)((ntiles + g.grid_sp - 1) / g.grid_sp);
+    const int64_t ew_need = (n + kPB - 1) / kPB;
+    g.grid_ew = (int)std::max<int64_t>(1, std::min<int64_t>(cap, ew_need));
+    const int RPB = (kPB / g.L) * kRowsPerGroup;
+    const int64_t vr_tiles = (n + RPB - 1) / RPB;
+    g.grid_vr = (int)std::max<int64_t>(1, std::min<int64_t>(cap, vr_tiles));
+    return g;
 }
 
-void launch_spmv_phase(int L, int grid, hipStream_t s, const CgArgs &a)
+void launch_init(const Grids &g, bool jac, hipStream_t s, const CgArgs<double> &a, double rtol2)
 {
-#define CGX_SP(LL) hipLaunchKernelGGL((cg_spmv_kernel<LL>), dim3(grid), dim3(kBlock), 0, s, a)
-    CGX_LANE_SWITCH(L, CGX_SP)
+#define CGX_INIT(LL)                                                                             \
+    if (jac)                                                                                     \
+        hipLaunchKernelGGL((cg_init_kernel<LL, true>), dim3(g.grid_vr), dim3(kPB), 0, s, a);      \
+    else                                                                                         \
+        hipLaunchKernelGGL((cg_init_kernel<LL, false>), dim3(g.grid_vr), dim3(kPB), 0, s, a)
+    CGX_LANE_SWITCH(g.L, CGX_INIT)
+#undef CGX_INIT
+    hipLaunchKernelGGL(cg_init_finish_kernel, dim3(1), dim3(kPB), 0, s, a, g.grid_vr, rtol2,
+                       jac ? 1 : 0);
+}
+
+template <typename T>
+void launch_spmv_phase(const Grids &g, hipStream_t s, const CgArgs<T> &a)
+{
+#define CGX_SP(RR) \
+    hipLaunchKernelGGL((cg_spmv_kernel<RR, T>), dim3(g.grid_sp), dim3(kPB), 0, s, a)
+    CGX_RT_SWITCH(g.RT, CGX_SP)
 #undef CGX_SP
 }
 
-void launch_true_residual(int L, int grid, hipStream_t s, const CgArgs &a)
+template <typename T>
+void launch_update_phase(const Grids &g, bool jac, hipStream_t s, const CgArgs<T> &a)
 {
-#define CGX_TR(LL) \
-    hipLaunchKernelGGL((cg_true_residual_kernel<LL>), dim3(grid), dim3(kBlock), 0, s, a)
-    CGX_LANE_SWITCH(L, CGX_TR)
-#undef CGX_TR
+    if (jac)
+        hipLaunchKernelGGL((cg_update_kernel<true, T>), dim3(g.grid_ew), dim3(kPB), 0, s, a);
+    else
+        hipLaunchKernelGGL((cg_update_kernel<false, T>), dim3(g.grid_ew), dim3(kPB), 0, s, a);
 }
 
-void launch_small(int L, bool jac, hipStream_t s, const CgArgs &a, double rtol2)
+template <typename T>
+void launch_direction_phase(const Grids &g, bool jac, hipStream_t s, const CgArgs<T> &a)
+{
+    if (jac)
+        hipLaunchKernelGGL((cg_direction_kernel<true, T>), dim3(g.grid_ew), dim3(kPB), 0, s, a);
+    else
+        hipLaunchKernelGGL((cg_direction_kernel<false, T>), dim3(g.grid_ew), dim3(kPB), 0, s, a);
+}
+
+template <typename T>
+void launch_iteration(const Grids &g, bool jac, hipStream_t s, const CgArgs<T> &a)
+{
+    launch_spmv_phase<T>(g, s, a);
+    launch_update_phase<T>(g, jac, s, a);
+    launch_direction_phase<T>(g, jac, s, a);
+}
+
+void launch_true_residual(const Grids &g, hipStream_t s, const CgArgs<double> &a)
+{
+#define CGX_TR(RR) \
+    hipLaunchKernelGGL((cg_true_residual_kernel<RR>), dim3(g.grid_sp), dim3(kPB), 0, s, a)
+    CGX_RT_SWITCH(g.RT, CGX_TR)
+#undef CGX_TR
+    hipLaunchKernelGGL(cg_true_residual_finish_kernel, dim3(1), dim3(kPB), 0, s, a, g.grid_sp);
+}
+
+void launch_small(int L, bool jac, hipStream_t s, const CgArgs<double> &a, double rtol2)
 {
 #define CGX_SM(LL)                                                                            \
     if (jac)                                                                                  \
@@ -435,37 +768,112 @@ void launch_small(int L, bool jac, hipStream_t s, const CgArgs &a, double rtol2)
 #undef CGX_SM
 }
 
-void launch_iteration(int L, bool jac, int grid_sp, int grid_ew, hipStream_t s, const CgArgs &a)
+void launch_mx_residual(const Grids &g, bool first, bool jac, hipStream_t s, const MxArgs &m,
+                        double rtol2)
 {
-    launch_spmv_phase(L, grid_sp, s, a);
-    if (jac)
-        hipLaunchKernelGGL((cg_update_kernel<true>), dim3(grid_ew), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((cg_update_kernel<false>), dim3(grid_ew), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(cg_direction_kernel, dim3(grid_ew), dim3(kBlock), 0, s, a);
+#define CGX_MX(LL)                                                                             \
+    if (first && jac)                                                                          \
+        hipLaunchKernelGGL((mx_residual_kernel<LL, true, true>), dim3(g.grid_vr), dim3(kPB), 0, \
+                           s, m);                                                              \
+    else if (first)                                                                            \
+        hipLaunchKernelGGL((mx_residual_kernel<LL, true, false>), dim3(g.grid_vr), dim3(kPB), 0,\
+                           s, m);                                                              \
+    else                                                                                       \
+        hipLaunchKernelGGL((mx_residual_kernel<LL, false, false>), dim3(g.grid_vr), dim3(kPB),  \
+                           0, s, m)
+    CGX_LANE_SWITCH(g.L, CGX_MX)
+#undef CGX_MX
+    hipLaunchKernelGGL(mx_residual_finish_kernel, dim3(1), dim3(kPB), 0, s, m, g.grid_vr,
+                       first ? 1 : 0, rtol2);
 }
 
-}  // namespace
-
-size_t cg_workspace_bytes(int64_t n, int64_t /*nnz*/, const cgx_opts *o)
+// Iterations per graph replay: about 2 ms of work between host checks.
+int replay_iters(const cgx_opts *o, double bytes_per_iter)
 {
-    if (n < 0) return 0;
-    const bool jac = o && o->precond == CGX_PRECOND_JACOBI;
-    return layout_fp64(n, jac).total;
+    int K = o->check_every;
+    if (K <= 0) {
+        const double t_iter = bytes_per_iter / 4.0e12 + 8.0e-6;
+        K = (int)(2.0e-3 / t_iter);
+        K = K < 4 ? 4 : (K > 32 ? 32 : K);
+    }
+    return K;
 }
 
-int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
-           const cgx_opts *o, cgx_stats *st)
+// Capture (or reuse) a graph of K iterations and replay it until the state's
+// `done` flag is set, at most max_replays times.
+template <typename T>
+int replay_until_done(Context *c, GraphSlot &slot, const uint64_t (&key)[12], int K, const Grids &g,
+                      bool jac, hipStream_t s, const CgArgs<T> &a, int64_t max_replays)
+{
+    bool hit = slot.exec != nullptr;
+    for (int i = 0; i < 12 && hit; ++i) hit = slot.key[i] == key[i];
+    if (!hit) {
+        slot.reset();
+        CGX_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < K; ++k) launch_iteration<T>(g, jac, s, a);
+        hipGraph_t graph = nullptr;
+        CGX_HIP_CHECK(hipStreamEndCapture(s, &graph));
+        slot.graph = graph;
+        CGX_HIP_CHECK(hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0));
+        for (int i = 0; i < 12; ++i) slot.key[i] = key[i];
+    }
+    for (int64_t rep = 0; rep < max_replays; ++rep) {
+        CGX_HIP_CHECK(hipGraphLaunch(slot.exec, s));
+        CGX_HIP_CHECK(
+            hipMemcpyAsync(c->host_state, a.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        CGX_HIP_CHECK(hipStreamSynchronize(s));
+        if (c->host_state->done) break;
+    }
+    return CGX_OK;
+}
+
+// Records the end of a solve, waits for it and reads the state; returns the
+// solve's device time in ms.
+int finish_solve(Context *c, hipStream_t s, const CgState *dev_state, CgState &hs, float &ms)
+{
+    CGX_HIP_CHECK(hipEventRecord(c->ev1, s));
+    CGX_HIP_CHECK(
+        hipMemcpyAsync(c->host_state, dev_state, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    CGX_HIP_CHECK(hipStreamSynchronize(s));
+    hs = *c->host_state;
+    CGX_HIP_CHECK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    return CGX_OK;
+}
+
+// x = 0 when b = 0; then orders the caller's stream after the solve.
+int zero_if_needed(Context *c, hipStream_t s, bool zero, int64_t n, double *x)
+{
+    if (zero) {
+        hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(kBlock), 0, s, n, x);
+        CGX_HIP_CHECK(hipGetLastError());
+    }
+    CGX_HIP_CHECK(hipEventRecord(c->ev_out, s));
+    CGX_HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_out, 0));
+    CGX_HIP_CHECK(hipStreamSynchronize(s));
+    return CGX_OK;
+}
+
+int begin_solve(Context *c, hipStream_t s)
+{
+    CGX_HIP_CHECK(hipEventRecord(c->ev_in, c->stream));
+    CGX_HIP_CHECK(hipStreamWaitEvent(s, c->ev_in, 0));
+    CGX_HIP_CHECK(hipEventRecord(c->ev0, s));
+    return CGX_OK;
+}
+
+int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
+             const cgx_opts *o, cgx_stats *st)
 {
     const int64_t n = A->n_rows;
     const bool jac = o->precond == CGX_PRECOND_JACOBI;
-    const Layout lay = layout_fp64(n, jac);
+    const Layout lay = make_layout(n, jac, false);
     if (ws_bytes < lay.total) {
         set_error("workspace too small: need " + std::to_string(lay.total) + " bytes");
         return CGX_ENOMEM;
     }
     char *w = static_cast<char *>(ws);
-    CgArgs a{};
+    const Grids g = make_grids(c, n, A->nnz);
+    CgArgs<double> a{};
     a.n = (int)n;
     a.n_cols = A->n_cols;
     a.nnz = A->nnz;
@@ -481,33 +889,24 @@ int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, s
     a.dinv = jac ? reinterpret_cast<double *>(w + lay.dinv) : nullptr;
     a.partials = reinterpret_cast<double *>(w + lay.partials);
     a.st = reinterpret_cast<CgState *>(w + lay.state);
+    a.tiles_per_block = g.tiles_per_block;
+    a.grid_sp = g.grid_sp;
+    a.grid_ew = g.grid_ew;
 
     const int maxit = o->maxit > 0 ? o->maxit : (int)std::min<int64_t>(n > 0 ? n : 1, 0x7fffffff);
     const double rtol2 = o->rtol * o->rtol;
-    const int L = lanes_per_row(n, A->nnz);
-    const int RPB = (kBlock / L) * kRowsPerGroup;
-    const int64_t ntiles = (n + RPB - 1) / RPB;
-    int grid_sp = c->num_cu * kBlocksPerCu;
-    if (grid_sp > kMaxPhaseBlocks) grid_sp = kMaxPhaseBlocks;
-    if (grid_sp > ntiles) grid_sp = (int)(ntiles > 0 ? ntiles : 1);
-    a.tiles_per_block = (int)((ntiles + grid_sp - 1) / grid_sp);
-    int grid_ew = c->num_cu * kBlocksPerCu;
-    if (grid_ew > kMaxPhaseBlocks) grid_ew = kMaxPhaseBlocks;
-    const int64_t ew_need = (n + kBlock - 1) / kBlock;
-    if (grid_ew > ew_need) grid_ew = (int)(ew_need > 0 ? ew_need : 1);
 
     hipStream_t s = c->own_stream;
-    CGX_HIP_CHECK(hipEventRecord(c->ev_in, c->stream));
-    CGX_HIP_CHECK(hipStreamWaitEvent(s, c->ev_in, 0));
-    CGX_HIP_CHECK(hipEventRecord(c->ev0, s));
+    int rc = begin_solve(c, s);
+    if (rc) return rc;
     hipLaunchKernelGGL(cg_state_init_kernel, dim3(1), dim3(64), 0, s, a.st, maxit);
 
     const bool small = n <= kSmallN;
     if (small) {
-        launch_small(L, jac, s, a, rtol2);
+        launch_small(g.L, jac, s, a, rtol2);
         CGX_HIP_CHECK(hipGetLastError());
     } else {
-        launch_init(L, jac, grid_sp, s, a, rtol2);
+        launch_init(g, jac, s, a, rtol2);
         CGX_HIP_CHECK(hipGetLastError());
         if (o->profile) {
             // One iteration at a time with events around each phase kernel;
@@ -516,14 +915,11 @@ int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, s
             int counted = 0;
             for (int it = 0; it < maxit + 1; ++it) {
                 CGX_HIP_CHECK(hipEventRecord(c->ev_phase[0], s));
-                launch_spmv_phase(L, grid_sp, s, a);
+                launch_spmv_phase<double>(g, s, a);
                 CGX_HIP_CHECK(hipEventRecord(c->ev_phase[1], s));
-                if (jac)
-                    hipLaunchKernelGGL((cg_update_kernel<true>), dim3(grid_ew), dim3(kBlock), 0, s, a);
-                else
-                    hipLaunchKernelGGL((cg_update_kernel<false>), dim3(grid_ew), dim3(kBlock), 0, s, a);
+                launch_update_phase<double>(g, jac, s, a);
                 CGX_HIP_CHECK(hipEventRecord(c->ev_phase[2], s));
-                hipLaunchKernelGGL(cg_direction_kernel, dim3(grid_ew), dim3(kBlock), 0, s, a);
+                launch_direction_phase<double>(g, jac, s, a);
                 CGX_HIP_CHECK(hipEventRecord(c->ev_phase[3], s));
                 CGX_HIP_CHECK(hipMemcpyAsync(c->host_state, a.st, sizeof(CgState),
                                              hipMemcpyDeviceToHost, s));
@@ -538,68 +934,30 @@ int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, s
             }
             for (int ph = 0; ph < 3; ++ph) st->phase_ms[ph] = counted ? tot[ph] / counted : 0.0;
         } else {
-            int K = o->check_every;
-            if (K <= 0) {
-                // aim at about 2 ms of work between host checks
-                const double bytes = 12.0 * (double)A->nnz + (jac ? 104.0 : 88.0) * (double)n;
-                const double t_iter = bytes / 4.0e12 + 8.0e-6;
-                K = (int)(2.0e-3 / t_iter);
-                K = K < 4 ? 4 : (K > 32 ? 32 : K);
-            }
+            const double bytes = 12.0 * (double)A->nnz + (jac ? 104.0 : 88.0) * (double)n;
+            const int K = replay_iters(o, bytes);
             const uint64_t key[12] = {(uint64_t)(uintptr_t)a.rp, (uint64_t)(uintptr_t)a.ci,
                                       (uint64_t)(uintptr_t)a.val, (uint64_t)(uintptr_t)b,
                                       (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)ws,
                                       (uint64_t)n, (uint64_t)A->nnz, (uint64_t)A->n_cols,
                                       (uint64_t)(jac ? 1 : 0), (uint64_t)K,
-                                      ((uint64_t)grid_sp << 32) | (uint64_t)grid_ew};
-            bool hit = c->graph_exec != nullptr;
-            for (int i = 0; i < 12 && hit; ++i) hit = c->graph_key[i] == key[i];
-            if (!hit) {
-                if (c->graph_exec) {
-                    (void)hipGraphExecDestroy(c->graph_exec);
-                    c->graph_exec = nullptr;
-                }
-                if (c->graph) {
-                    (void)hipGraphDestroy(c->graph);
-                    c->graph = nullptr;
-                }
-                CGX_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                for (int k = 0; k < K; ++k) launch_iteration(L, jac, grid_sp, grid_ew, s, a);
-                hipGraph_t g = nullptr;
-                CGX_HIP_CHECK(hipStreamEndCapture(s, &g));
-                c->graph = g;
-                CGX_HIP_CHECK(hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
-                for (int i = 0; i < 12; ++i) c->graph_key[i] = key[i];
-            }
-            // Replays until `done`; maxit bounds the loop since the update kernel
-            // sets `done` when the cap is reached.
+                                      ((uint64_t)g.grid_sp << 32) | (uint64_t)g.grid_ew};
             const int64_t max_replays = (int64_t)maxit / K + 2;
-            for (int64_t rep = 0; rep < max_replays; ++rep) {
-                CGX_HIP_CHECK(hipGraphLaunch(c->graph_exec, s));
-                CGX_HIP_CHECK(hipMemcpyAsync(c->host_state, a.st, sizeof(CgState),
-                                             hipMemcpyDeviceToHost, s));
-                CGX_HIP_CHECK(hipStreamSynchronize(s));
-                if (c->host_state->done) break;
-            }
+            rc = replay_until_done<double>(c, c->graph64, key, K, g, jac, s, a, max_replays);
+            if (rc) return rc;
         }
     }
     if (o->true_residual) {
-        launch_true_residual(L, grid_sp, s, a);
+        launch_true_residual(g, s, a);
         CGX_HIP_CHECK(hipGetLastError());
     }
-    CGX_HIP_CHECK(hipEventRecord(c->ev1, s));
-    CGX_HIP_CHECK(hipMemcpyAsync(c->host_state, a.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-    CGX_HIP_CHECK(hipStreamSynchronize(s));
-    const CgState hs = *c->host_state;
-    if (hs.bb == 0.0 && hs.status == CGX_OK) {
-        hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(kBlock), 0, s, n, x);
-        CGX_HIP_CHECK(hipGetLastError());
-        CGX_HIP_CHECK(hipStreamSynchronize(s));
-    }
+    CgState hs{};
     float ms = 0.0f;
-    CGX_HIP_CHECK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    CGX_HIP_CHECK(hipEventRecord(c->ev_out, s));
-    CGX_HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_out, 0));
+    rc = finish_solve(c, s, a.st, hs, ms);
+    if (rc) return rc;
+    const bool zero_b = hs.bb == 0.0 && hs.status == CGX_OK;
+    rc = zero_if_needed(c, s, zero_b, n, x);
+    if (rc) return rc;
 
     st->status = hs.status == CGX_PENDING ? CGX_NOT_CONVERGED : hs.status;
     st->iters = hs.iter;
@@ -608,9 +966,144 @@ int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, s
     st->relres = hs.bb > 0.0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
     st->relres_true = -1.0;
     if (o->true_residual) st->relres_true = hs.bb > 0.0 ? std::sqrt(hs.rr_true / hs.bb) : 0.0;
-    if (hs.bb == 0.0 && hs.status == CGX_OK) st->relres_true = 0.0, st->relres = 0.0;
+    if (zero_b) st->relres_true = 0.0, st->relres = 0.0;
     st->device_ms = ms;
     return st->status;
+}
+
+int run_mixed(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
+              const cgx_opts *o, cgx_stats *st)
+{
+    const int64_t n = A->n_rows;
+    const bool jac = o->precond == CGX_PRECOND_JACOBI;
+    const Layout lay = make_layout(n, jac, true);
+    if (ws_bytes < lay.total) {
+        set_error("workspace too small: need " + std::to_string(lay.total) + " bytes");
+        return CGX_ENOMEM;
+    }
+    char *w = static_cast<char *>(ws);
+    const Grids g = make_grids(c, n, A->nnz);
+
+    MxArgs m{};
+    m.n = (int)n;
+    m.n_cols = A->n_cols;
+    m.nnz = A->nnz;
+    m.rp = A->row_ptr;
+    m.ci = A->col_idx;
+    m.val = A->val;
+    m.b = b;
+    m.x = x;
+    m.r = reinterpret_cast<double *>(w + lay.r64);
+    m.dinv32 = jac ? reinterpret_cast<float *>(w + lay.dinv) : nullptr;
+    m.partials = reinterpret_cast<double *>(w + lay.partials);
+    m.ost = reinterpret_cast<CgState *>(w + lay.state);
+
+    CgArgs<float> in{};
+    in.n = (int)n;
+    in.n_cols = A->n_cols;
+    in.nnz = A->nnz;
+    in.rp = A->row_ptr;
+    in.ci = A->col_idx;
+    in.val = A->val32;
+    in.b = nullptr;
+    in.x = reinterpret_cast<float *>(w + lay.d);
+    in.r = reinterpret_cast<float *>(w + lay.r);
+    in.p = reinterpret_cast<float *>(w + lay.p);
+    in.q = reinterpret_cast<float *>(w + lay.q);
+    in.z = reinterpret_cast<float *>(w + lay.z);
+    in.dinv = m.dinv32;
+    in.partials = reinterpret_cast<float *>(w + lay.partials);
+    in.st = reinterpret_cast<CgState *>(w + lay.state2);
+    in.tiles_per_block = g.tiles_per_block;
+    in.grid_sp = g.grid_sp;
+    in.grid_ew = g.grid_ew;
+
+    const int max_outer = o->max_outer > 0 ? o->max_outer : 100;
+    const int inner_maxit =
+        o->maxit > 0 ? o->maxit : (int)std::min<int64_t>(n > 0 ? n : 1, 0x7fffffff);
+    const double tau = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-3;
+    const double rtol2 = o->rtol * o->rtol;
+
+    hipStream_t s = c->own_stream;
+    int rc = begin_solve(c, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(cg_state_init_kernel, dim3(1), dim3(64), 0, s, m.ost, max_outer);
+    hipLaunchKernelGGL(cg_state_init_kernel, dim3(1), dim3(64), 0, s, in.st, inner_maxit);
+    CGX_HIP_CHECK(hipGetLastError());
+
+    const double bytes_in = 8.0 * (double)A->nnz + (jac ? 52.0 : 44.0) * (double)n;
+    const int K = replay_iters(o, bytes_in);
+    const uint64_t key[12] = {(uint64_t)(uintptr_t)in.rp, (uint64_t)(uintptr_t)in.ci,
+                              (uint64_t)(uintptr_t)in.val, (uint64_t)(uintptr_t)ws,
+                              (uint64_t)n, (uint64_t)A->nnz, (uint64_t)A->n_cols,
+                              (uint64_t)(jac ? 1 : 0), (uint64_t)K,
+                              ((uint64_t)g.grid_sp << 32) | (uint64_t)g.grid_ew, 0x4d58ull, 0};
+    int64_t inner_total = 0;
+    int status = CGX_NOT_CONVERGED;
+    for (int step = 0; step <= max_outer + 1; ++step) {
+        launch_mx_residual(g, step == 0, jac, s, m, rtol2);
+        CGX_HIP_CHECK(hipGetLastError());
+        CGX_HIP_CHECK(
+            hipMemcpyAsync(c->host_state, m.ost, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        CGX_HIP_CHECK(hipStreamSynchronize(s));
+        if (c->host_state->done) {
+            status = c->host_state->status;
+            break;
+        }
+        if (jac)
+            hipLaunchKernelGGL((mx_inner_init_kernel<true>), dim3(g.grid_ew), dim3(kPB), 0, s, m,
+                               in);
+        else
+            hipLaunchKernelGGL((mx_inner_init_kernel<false>), dim3(g.grid_ew), dim3(kPB), 0, s, m,
+                               in);
+        hipLaunchKernelGGL(mx_inner_init_finish_kernel, dim3(1), dim3(kPB), 0, s, m, in, g.grid_ew,
+                           (float)(tau * tau), inner_maxit, jac ? 1 : 0);
+        CGX_HIP_CHECK(hipGetLastError());
+        const int64_t max_replays = (int64_t)inner_maxit / K + 2;
+        rc = replay_until_done<float>(c, c->graph32, key, K, g, jac, s, in, max_replays);
+        if (rc) return rc;
+        const CgState inner = *c->host_state;
+        inner_total += inner.iter;
+        if (inner.status == CGX_NONFINITE) {
+            status = CGX_NONFINITE;
+            break;
+        }
+        hipLaunchKernelGGL(mx_correct_kernel, dim3(g.grid_ew), dim3(kPB), 0, s, m, in.x);
+        CGX_HIP_CHECK(hipGetLastError());
+    }
+    CgState hs{};
+    float ms = 0.0f;
+    rc = finish_solve(c, s, m.ost, hs, ms);
+    if (rc) return rc;
+    const bool zero_b = hs.bb == 0.0 && status == CGX_OK;
+    rc = zero_if_needed(c, s, zero_b, n, x);
+    if (rc) return rc;
+
+    st->status = status == CGX_PENDING ? CGX_NOT_CONVERGED : status;
+    st->iters = (int32_t)std::min<int64_t>(inner_total, 0x7fffffff);
+    st->outer_iters = hs.iter;
+    st->path = 2;
+    st->relres = hs.bb > 0.0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
+    st->relres_true = st->relres;
+    st->device_ms = ms;
+    return st->status;
+}
+
+}  // namespace
+
+size_t cg_workspace_bytes(int64_t n, int64_t /*nnz*/, const cgx_opts *o)
+{
+    if (n < 0) return 0;
+    const bool jac = o && o->precond == CGX_PRECOND_JACOBI;
+    const bool mixed = o && o->precision == CGX_PRECISION_MIXED;
+    return make_layout(n, jac, mixed).total;
+}
+
+int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
+           const cgx_opts *o, cgx_stats *st)
+{
+    if (o->precision == CGX_PRECISION_MIXED) return run_mixed(c, A, b, x, ws, ws_bytes, o, st);
+    return run_fp64(c, A, b, x, ws, ws_bytes, o, st);
 }
 
 }  // namespace cgx

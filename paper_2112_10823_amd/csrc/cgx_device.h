@@ -1,5 +1,12 @@
 // Device building blocks for gfx950: wave64 reductions, XCD-aware block
-// numbering, the deterministic grid-wide sum and the vector-CSR row body.
+// numbering, the vector-CSR and CSR-stream row bodies and the fixed-order sum
+// of per-workgroup partials.
+//
+// Grid-wide sums never use a per-workgroup device-scope fence (on this
+// multi-die part such a release writes back the die's L2 and halved the
+// bandwidth of the kernels that used it): each workgroup stores a plain
+// partial, and the next kernel in stream order, for which the kernel
+// boundary makes the partials visible, adds them in index order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,9 +50,9 @@ __device__ __forceinline__ T group_sum(T v)
 }
 
 // Sum NV per-thread values over the block; the result is valid in thread 0.
-// `red` is __shared__ scratch of NV * (BS / 64) doubles.
-template <int NV, int BS>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double *red)
+// `red` is __shared__ scratch of NV * (BS / 64) values of type T.
+template <int NV, int BS, typename T>
+__device__ __forceinline__ void block_sum(T (&v)[NV], T *red)
 {
     constexpr int W = BS / kWave;
     const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
@@ -58,55 +65,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red)
     if (threadIdx.x == 0)
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
-            double s = 0.0;
+            T s = T(0);
 #pragma unroll
             for (int i = 0; i < W; ++i) s += red[j * W + i];
             v[j] = s;
         }
-}
-
-// Deterministic grid-wide sum of NV values per thread.  Every workgroup
-// stores its NV block totals at partials[j * gridDim.x + blockIdx.x] and
-// takes an arrival ticket; the last workgroup to arrive adds the partials in
-// index order with a fixed tree, resets the ticket and returns true with the
-// totals in thread 0's `v`.  Other workgroups return false.  The partial
-// exchange uses device-scope atomic loads/stores so it does not depend on the
-// per-die L2s being coherent.  Must be reached by all threads of the block.
-template <int NV, int BS>
-__device__ __forceinline__ bool grid_sum(double (&v)[NV], double *partials, uint32_t *ticket)
-{
-    __shared__ double red[NV * (BS / kWave)];
-    __shared__ int is_last;
-    const int G = gridDim.x;
-    block_sum<NV, BS>(v, red);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-            __hip_atomic_store(&partials[(int64_t)j * G + blockIdx.x], v[j], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const uint32_t t = atomicAdd(ticket, 1u);
-        is_last = (t == (uint32_t)G - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double s[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        s[j] = 0.0;
-        for (int i = threadIdx.x; i < G; i += BS)
-            s[j] += __hip_atomic_load(&partials[(int64_t)j * G + i], __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();  // `red` is reused
-    block_sum<NV, BS>(s, red);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) v[j] = s[j];
-        *ticket = 0u;
-    }
-    return true;
 }
 
 // Error-free transformations (Knuth two-sum; two-product via fma).
@@ -186,6 +149,101 @@ __device__ __forceinline__ void vector_rows(int row0, int n_rows, int n_cols, in
         acc[r] = group_sum<L>(acc[r]);
         if (kDiag) dg[r] = group_sum<L>(dg[r]);
     }
+}
+
+// ------------------------------------------------------- stream CSR rows --
+
+// Shared-memory staging of one CSR-stream tile: BS * E products plus the
+// tile's RT + 1 row starts.
+template <int BS, int E, int RT, typename T>
+struct StreamSmem {
+    T prod[BS * E];
+    int rp[RT + 1];
+};
+
+// CSR-stream tile of RT consecutive rows starting at row0, BS threads, E
+// entries per thread per chunk.  Phase 1: all threads read the tile's
+// col_idx / val as one contiguous stream (thread t takes entries c0 + t +
+// BS * j, j < E: E independent coalesced loads in flight per thread), gather
+// x and stage the products in LDS.  Phase 2: TPR = BS / RT threads per row
+// add the row's staged products (thread `sub` takes entries sub, sub + TPR,
+// ...) and combine by butterfly.  Tiles with more than BS * E entries are
+// processed in several chunks.  Returns the row sum in all TPR threads of the
+// row's group; `row` receives the row index (>= n_rows for idle groups).
+// Indices are clamped as in vector_rows.  Must be reached by all threads.
+template <int BS, int E, int RT, typename T>
+__device__ __forceinline__ T stream_rows(int row0, int n_rows, int n_cols, int64_t nnz,
+                                         const int32_t *__restrict__ rp,
+                                         const int32_t *__restrict__ ci,
+                                         const T *__restrict__ val, const T *__restrict__ x,
+                                         StreamSmem<BS, E, RT, T> &sm, int &row)
+{
+    constexpr int TPR = BS / RT;
+    constexpr int C = BS * E;
+    static_assert(TPR >= 1 && TPR <= kWave && (TPR & (TPR - 1)) == 0, "threads per row");
+    const int nr = min(RT, n_rows - row0);
+    __syncthreads();  // the previous tile's readers of sm are done
+    for (int i = threadIdx.x; i <= nr; i += BS) {
+        int v = rp[row0 + i];
+        v = v < 0 ? 0 : (v > nnz ? (int)nnz : v);
+        sm.rp[i] = v;
+    }
+    __syncthreads();
+    const int k0 = sm.rp[0];
+    const int k1 = max(k0, sm.rp[nr]);
+    const int g = threadIdx.x / TPR, sub = threadIdx.x % TPR;
+    row = row0 + g;
+    int s = k0, e = k0;
+    if (g < nr) {
+        s = max(sm.rp[g], k0);
+        e = min(max(sm.rp[g + 1], s), k1);
+    }
+    T acc = T(0);
+    for (int c0 = k0; c0 < k1; c0 += C) {
+        int col[E];
+        T a[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int k = c0 + threadIdx.x + BS * j;
+            col[j] = -1;
+            a[j] = T(0);
+            if (k < k1) {
+                col[j] = ci[k];
+                a[j] = val[k];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            T v = T(0);
+            if ((unsigned)col[j] < (unsigned)n_cols) v = a[j] * x[col[j]];
+            sm.prod[threadIdx.x + BS * j] = v;
+        }
+        __syncthreads();
+        const int lo = max(s, c0), hi = min(e, c0 + C);
+        for (int k = lo + sub; k < hi; k += TPR) acc += sm.prod[k - c0];
+        __syncthreads();
+    }
+    return group_sum<TPR>(acc);
+}
+
+// Sum of `count` partials in index order (strided per thread, then a fixed
+// block tree); every thread of the block receives the same bits.  `red` is
+// __shared__ scratch of BS / 64 values.
+template <int BS, typename T>
+__device__ __forceinline__ T sum_partials(const T *partials, int count, T *red)
+{
+    T s = T(0);
+    for (int i = threadIdx.x; i < count; i += BS) s += partials[i];
+    s = wave_sum(s);
+    constexpr int W = BS / kWave;
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if (threadIdx.x % kWave == 0) red[w] = s;
+    __syncthreads();
+    T t = T(0);
+#pragma unroll
+    for (int i = 0; i < W; ++i) t += red[i];
+    return t;
 }
 
 }  // namespace cgx

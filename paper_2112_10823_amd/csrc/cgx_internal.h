@@ -36,13 +36,31 @@ void clear_error();
 
 constexpr int kBlock = 256;         // threads per workgroup for streaming kernels
 constexpr int kReduceBlocks = 1024; // fixed grid of the standalone reductions
-constexpr int kMaxPartials = 65536; // partial sums a grid reduction may hold
+constexpr int kStreamBlock = 512;   // threads per workgroup of the CSR-stream SpMV
+constexpr int kStreamE = 8;         // entries per thread per CSR-stream chunk
+
+// Rows per CSR-stream tile: the largest power of two in [8, 512] whose
+// expected entries (rows * mean row length) fill at most 90% of one chunk of
+// kStreamBlock * kStreamE entries.
+int stream_tile_rows(int64_t n_rows, int64_t nnz);
+
+#define CGX_RT_SWITCH(RT, EXPR_T)     \
+    switch (RT) {                     \
+        case 8: EXPR_T(8); break;     \
+        case 16: EXPR_T(16); break;   \
+        case 32: EXPR_T(32); break;   \
+        case 64: EXPR_T(64); break;   \
+        case 128: EXPR_T(128); break; \
+        case 256: EXPR_T(256); break; \
+        default: EXPR_T(512); break;  \
+    }
 
 // Device-side CG state, stored at the start of the solver workspace.  All
 // fields are written by the single "last" workgroup of a reduction and read
 // by the following kernels.
 struct CgState {
     double rho;    // r.z of the current iterate (r.r without preconditioner)
+    double rho_used; // rho of the iteration in flight (copied by the update kernel)
     double alpha;  // rho / p.q
     double beta;   // rho_new / rho
     double pq;     // p.Ap
@@ -56,7 +74,21 @@ struct CgState {
     int32_t done;  // nonzero once converged or failed: later kernels return at once
     int32_t bad;   // set by any thread meeting a non-positive / missing diagonal
     int32_t pad;
-    uint32_t counter[4]; // arrival tickets of the grid reductions
+    int32_t pad2[4];
+};
+
+// A captured and instantiated HIP graph plus the key it was built for.
+struct GraphSlot {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t key[12] = {0};
+    void reset()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
 };
 
 // Handle state.
@@ -65,16 +97,13 @@ struct Context {
     hipStream_t stream = nullptr;     // caller's stream: all asynchronous calls
     hipStream_t own_stream = nullptr; // solver stream (graph capture needs a non-null stream)
     int num_cu = 256;
-    double *scratch = nullptr;     // device: reduction partials
-    uint32_t *counters = nullptr;  // device: arrival tickets (zeroed at creation)
+    double *scratch = nullptr;     // device: reduction partials of the standalone calls
     CgState *host_state = nullptr; // pinned host copy of the solver state
     hipEvent_t ev0 = nullptr, ev1 = nullptr;      // timing of a solve
     hipEvent_t ev_in = nullptr, ev_out = nullptr; // ordering between the two streams
     hipEvent_t ev_phase[4] = {nullptr, nullptr, nullptr, nullptr}; // profile mode
-    // cached CG graph
-    hipGraphExec_t graph_exec = nullptr;
-    hipGraph_t graph = nullptr;
-    uint64_t graph_key[12] = {0};
+    GraphSlot graph64;  // float64 CG iterations
+    GraphSlot graph32;  // binary32 inner iterations of the refinement
 };
 
 // ----------------------------------------------------------- launchers ----

@@ -2,64 +2,45 @@
 // with CSR format", storage of Section 2.3) for gfx950, float64 and float32,
 // plus the structural validation kernel.
 //
-// Vector-CSR layout: a row is owned by a group of L lanes (L = next power of
-// two >= mean row length, 2..64), so the L lanes read one contiguous stretch
-// of col_idx / val per row; R rows per group are in flight together to keep
-// enough loads outstanding per wave.  Workgroups are renumbered per die
+// CSR-stream layout: a 512-thread workgroup owns a tile of RT consecutive
+// rows (RT from the mean row length, so a tile's entries fill one chunk of
+// 512 x 8).  The tile's col_idx / val are read as one contiguous stream with
+// eight independent coalesced loads per thread, the products are staged in
+// LDS and BS / RT threads add each row.  Workgroups are renumbered per die
 // (xcd_block) so the x gathers of neighbouring rows hit the same L2.
 #include "cgx_device.h"
 
 namespace cgx {
 namespace {
 
-constexpr int kRowsPerGroup = 4;
-
-template <int L, typename T>
-__global__ __launch_bounds__(kBlock) void spmv_vector_kernel(int n_rows, int n_cols, int64_t nnz,
-                                                             const int32_t *__restrict__ rp,
-                                                             const int32_t *__restrict__ ci,
-                                                             const T *__restrict__ val,
-                                                             const T *__restrict__ x,
-                                                             T *__restrict__ y)
+template <int RT, typename T>
+__global__ __launch_bounds__(kStreamBlock) void spmv_stream_kernel(int n_rows, int n_cols,
+                                                                    int64_t nnz,
+                                                                    const int32_t *__restrict__ rp,
+                                                                    const int32_t *__restrict__ ci,
+                                                                    const T *__restrict__ val,
+                                                                    const T *__restrict__ x,
+                                                                    T *__restrict__ y)
 {
-    constexpr int R = kRowsPerGroup;
-    constexpr int rows_per_block = (kBlock / L) * R;
+    __shared__ StreamSmem<kStreamBlock, kStreamE, RT, T> sm;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
-    T acc[R], dg[R];
-    int rows[R];
-    vector_rows<L, R, kBlock, T, false>(tile * rows_per_block, n_rows, n_cols, nnz, rp, ci, val, x,
-                                        acc, dg, rows);
-    if (threadIdx.x % L == 0) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (rows[r] < n_rows) y[rows[r]] = acc[r];
-    }
+    int row;
+    const T acc = stream_rows<kStreamBlock, kStreamE, RT, T>(tile * RT, n_rows, n_cols, nnz, rp, ci,
+                                                             val, x, sm, row);
+    if (threadIdx.x % (kStreamBlock / RT) == 0 && row < n_rows) y[row] = acc;
 }
 
 template <typename T>
 int launch_spmv_t(Context *c, const cgx_csr *A, const T *val, const T *x, T *y)
 {
     if (A->n_rows == 0) return CGX_OK;
-    const int L = lanes_per_row(A->n_rows, A->nnz);
-    const int64_t rows_per_block = (int64_t)(kBlock / L) * kRowsPerGroup;
-    const int64_t grid = (A->n_rows + rows_per_block - 1) / rows_per_block;
-#define CGX_SPMV_CASE(LL)                                                                     \
-    case LL:                                                                                  \
-        hipLaunchKernelGGL((spmv_vector_kernel<LL, T>), dim3((unsigned)grid), dim3(kBlock), 0, \
-                           c->stream, A->n_rows, A->n_cols, A->nnz, A->row_ptr, A->col_idx,   \
-                           val, x, y);                                                        \
-        break;
-    switch (L) {
-        CGX_SPMV_CASE(2)
-        CGX_SPMV_CASE(4)
-        CGX_SPMV_CASE(8)
-        CGX_SPMV_CASE(16)
-        CGX_SPMV_CASE(32)
-        CGX_SPMV_CASE(64)
-        default:
-            set_error("internal: bad lanes per row");
-            return CGX_EINVAL;
-    }
+    const int RT = stream_tile_rows(A->n_rows, A->nnz);
+    const int64_t grid = (A->n_rows + RT - 1) / RT;
+#define CGX_SPMV_CASE(RR)                                                                    \
+    hipLaunchKernelGGL((spmv_stream_kernel<RR, T>), dim3((unsigned)grid), dim3(kStreamBlock), \
+                       0, c->stream, A->n_rows, A->n_cols, A->nnz, A->row_ptr, A->col_idx, val,  \
+                       x, y)
+    CGX_RT_SWITCH(RT, CGX_SPMV_CASE)
 #undef CGX_SPMV_CASE
     CGX_HIP_CHECK(hipGetLastError());
     return CGX_OK;
@@ -96,6 +77,15 @@ __global__ __launch_bounds__(kBlock) void csr_validate_kernel(int n_rows, int n_
 }
 
 }  // namespace
+
+int stream_tile_rows(int64_t n_rows, int64_t nnz)
+{
+    const double mean = n_rows > 0 ? (double)nnz / (double)n_rows : 1.0;
+    const double budget = 0.9 * kStreamBlock * kStreamE;
+    int rt = 512;
+    while (rt > 8 && rt * (mean > 1.0 ? mean : 1.0) > budget) rt /= 2;
+    return rt;
+}
 
 int lanes_per_row(int64_t n_rows, int64_t nnz)
 {
