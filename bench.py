@@ -241,7 +241,7 @@ def main():
         "relres_true": chk.relres_true,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "cg_spmv_kernel<32> (q = A p, p.q)",
+                     "traffic": traffic, "kernel": "cg_spmv_kernel<64, double> (q = A p fused with p.q partials)",
                      "algorithmic_bytes": sp_bytes, "mean_launch_ms": round(spmv_ms, 5),
                      "kernel_source_hash": khash},
         "cpu_baseline": cpu,

@@ -165,6 +165,43 @@ size_t cgx_cg_workspace_bytes(int64_t n_rows, int64_t nnz, const cgx_opts *opts)
 int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, void *workspace,
                  size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats);
 
+/* ------------------------------------------------------------ batched -- */
+
+/* One system of a batch: matrix, right-hand sides and solutions.  B and X
+ * are device arrays of nrhs x n_rows float64, right-hand-side major (vector j
+ * at B + j * n_rows); X holds the initial guesses on entry.  1 <= nrhs <= 16. */
+typedef struct cgx_system {
+    cgx_csr A;
+    int32_t nrhs;
+    int32_t pad;
+    const double *B;
+    double *X;
+} cgx_system;
+
+/* Workspace bytes of cgx_cg_solve_batched for this batch (0 on bad input). */
+size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems);
+
+/* (sync) Solve every system of the batch by conjugate gradient (Section 5.3;
+ * Jacobi preconditioning optional), all systems and right-hand sides
+ * advanced together: each phase of an iteration is one kernel launch over a
+ * work table of (system, row tile) entries, the matrix of a system is read
+ * once per iteration for all its right-hand sides, and each right-hand side
+ * has its own scalars and stopping test (||r|| <= rtol ||b||).  The rows of
+ * a system are served by K * M lanes, M chosen per shape class by a timing
+ * autotuner kept in the handle.  A system's results do not depend on the
+ * other systems in the batch.  stats: array of sum(nrhs) entries in
+ * (system, right-hand side) order.  Returns CGX_OK if all converged, else
+ * the first non-OK status; argument errors as usual.  opts->precision must
+ * be FP64; opts->maxit <= 0 means the largest n. */
+int cgx_cg_solve_batched(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
+                         size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats);
+
+/* (sync) The slice count M the autotuner picks for each system (running the
+ * tuning for shape classes not seen yet by this handle).  workspace as for
+ * cgx_cg_solve_batched; M_out: host int32[nsys]. */
+int cgx_batch_schedule(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
+                       size_t workspace_bytes, int32_t *M_out);
+
 #ifdef __cplusplus
 }
 #endif

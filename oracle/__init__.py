@@ -77,7 +77,7 @@ def _load():
                                   ctypes.POINTER(_Stats), ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_cg.restype = ctypes.c_int
         lib.oracle_mixed_ir.argtypes = [i64, i32p, i32p, f64p, f32p, f64p, f64p, dbl, dbl, i32,
-                                        i32, ctypes.POINTER(_Stats)]
+                                        i32, i32, ctypes.POINTER(_Stats)]
         lib.oracle_mixed_ir.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -184,14 +184,16 @@ def cg(A, b, x0=None, rtol=1e-8, maxit=0, jacobi=False, history=False) -> SolveR
     return res
 
 
-def mixed_ir(A, val32, b, x0=None, rtol=1e-10, tau=1e-3, inner_maxit=0, max_outer=50):
-    """FP64 iterative refinement around a binary32 inner CG; see oracle.c."""
+def mixed_ir(A, val32, b, x0=None, rtol=1e-10, tau=1e-3, inner_maxit=0, max_outer=50,
+             jacobi=False):
+    """FP64 iterative refinement around a binary32 inner CG (optionally
+    Jacobi-preconditioned); see oracle.c."""
     b = _f64(b)
     x = np.zeros(A.n_rows) if x0 is None else _f64(x0).copy()
     st = _Stats()
     _load().oracle_mixed_ir(A.n_rows, _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val), _f32(val32),
                             b, x, float(rtol), float(tau), int(inner_maxit), int(max_outer),
-                            ctypes.byref(st))
+                            int(bool(jacobi)), ctypes.byref(st))
     return SolveResult(x, st.status, st.iters, st.outer_iters, st.relres, st.relres_true)
 
 

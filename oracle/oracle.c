@@ -259,49 +259,62 @@ done:
 
 /* ------------------------------------------ mixed-precision refinement -- */
 
-/* Unpreconditioned CG in binary32 for A32 d = c, d0 = 0, stopping when
- * ||r_k|| <= tau ||c||: every product, sum and dot is a float operation.
- * Returns the iteration count; stops early (keeping the current d) when the
- * recurrences break down in binary32. */
+/* CG in binary32 for A32 d = c, d0 = 0, stopping when ||r_k|| <= tau ||c||;
+ * with dinv32 (nullable) the residual is preconditioned by z = dinv32 .* r.
+ * Every product, sum and dot is a float operation.  Returns the iteration
+ * count; stops early (keeping the current d) when the recurrences break down
+ * in binary32. */
 static int32_t cg_f32(int64_t n, const int32_t *rp, const int32_t *ci, const float *val,
-                      const float *c, float *d, float tau, int32_t maxit)
+                      const float *dinv32, const float *c, float *d, float tau, int32_t maxit)
 {
     float *r = (float *)malloc((size_t)n * sizeof(float));
     float *p = (float *)malloc((size_t)n * sizeof(float));
     float *q = (float *)malloc((size_t)n * sizeof(float));
-    for (int64_t i = 0; i < n; ++i) { d[i] = 0.0f; r[i] = c[i]; p[i] = c[i]; }
-    float rho = oracle_dot_f32(n, r, r);
-    float stop = tau * sqrtf(rho);
+    float *z = dinv32 ? (float *)malloc((size_t)n * sizeof(float)) : r;
+    for (int64_t i = 0; i < n; ++i) {
+        d[i] = 0.0f;
+        r[i] = c[i];
+        if (dinv32) z[i] = dinv32[i] * c[i];
+        p[i] = z[i];
+    }
+    float rr = oracle_dot_f32(n, r, r);
+    float rho = dinv32 ? oracle_dot_f32(n, r, z) : rr;
+    const float stop = tau * sqrtf(rr);
     int32_t k = 0;
-    while (k < maxit && sqrtf(rho) > stop) {
+    while (k < maxit && sqrtf(rr) > stop) {
         oracle_spmv_f32(n, rp, ci, val, p, q);
         float pq = oracle_dot_f32(n, p, q);
         if (!(pq > 0.0f) || !isfinite(pq)) break;
         float alpha = rho / pq;
         for (int64_t i = 0; i < n; ++i) d[i] = fmaf(alpha, p[i], d[i]);
         for (int64_t i = 0; i < n; ++i) r[i] = fmaf(-alpha, q[i], r[i]);
-        float rho_new = oracle_dot_f32(n, r, r);
+        if (dinv32)
+            for (int64_t i = 0; i < n; ++i) z[i] = dinv32[i] * r[i];
+        float rho_new = dinv32 ? oracle_dot_f32(n, r, z) : oracle_dot_f32(n, r, r);
+        rr = dinv32 ? oracle_dot_f32(n, r, r) : rho_new;
         ++k;
         if (!(rho_new > 0.0f) || !isfinite(rho_new)) break;
         float beta = rho_new / rho;
         rho = rho_new;
-        for (int64_t i = 0; i < n; ++i) p[i] = fmaf(beta, p[i], r[i]);
+        for (int64_t i = 0; i < n; ++i) p[i] = fmaf(beta, p[i], z[i]);
     }
     free(r);
     free(p);
     free(q);
+    if (dinv32) free(z);
     return k;
 }
 
 /* Iterative refinement with a binary32 inner CG:
  *   repeat: r = b - A64 x (float64); stop when ||r|| <= rtol ||b||;
  *           s = ||r||;  c = float(r / s);
- *           d = CG32(A32, c) to relative tolerance tau (x0 = 0);
+ *           d = CG32(A32, c) to relative tolerance tau (d0 = 0);
  *           x += s * double(d).
- * val32 holds the values of A rounded to binary32 (same pattern as val). */
+ * val32 holds the values of A rounded to binary32 (same pattern as val).
+ * jacobi: the inner CG is preconditioned by float(1 / a_ii). */
 int oracle_mixed_ir(int64_t n, const int32_t *rp, const int32_t *ci, const double *val,
                     const float *val32, const double *b, double *x, double rtol, double tau,
-                    int32_t inner_maxit, int32_t max_outer, oracle_stats *st)
+                    int32_t inner_maxit, int32_t max_outer, int32_t jacobi, oracle_stats *st)
 {
     memset(st, 0, sizeof(*st));
     if (inner_maxit <= 0) inner_maxit = (int32_t)(n > 0x7fffffff ? 0x7fffffff : n);
@@ -310,6 +323,18 @@ int oracle_mixed_ir(int64_t n, const int32_t *rp, const int32_t *ci, const doubl
     if (bnorm == 0.0) {
         for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
         return ORC_OK;
+    }
+    float *dinv32 = NULL;
+    if (jacobi) {
+        double *dinv = (double *)malloc((size_t)n * sizeof(double));
+        if (oracle_inv_diag(n, rp, ci, val, dinv) != 0) {
+            free(dinv);
+            st->status = ORC_BREAKDOWN;
+            return st->status;
+        }
+        dinv32 = (float *)malloc((size_t)n * sizeof(float));
+        for (int64_t i = 0; i < n; ++i) dinv32[i] = (float)dinv[i];
+        free(dinv);
     }
     double *r = (double *)malloc((size_t)n * sizeof(double));
     float *c = (float *)malloc((size_t)n * sizeof(float));
@@ -326,7 +351,7 @@ int oracle_mixed_ir(int64_t n, const int32_t *rp, const int32_t *ci, const doubl
         if (relres <= rtol) { status = ORC_OK; break; }
         if (outer >= max_outer) break;
         for (int64_t i = 0; i < n; ++i) c[i] = (float)(r[i] / s);
-        inner_total += cg_f32(n, rp, ci, val32, c, d, (float)tau, inner_maxit);
+        inner_total += cg_f32(n, rp, ci, val32, dinv32, c, d, (float)tau, inner_maxit);
         for (int64_t i = 0; i < n; ++i) x[i] = fma(s, (double)d[i], x[i]);
         ++outer;
     }
@@ -338,5 +363,6 @@ int oracle_mixed_ir(int64_t n, const int32_t *rp, const int32_t *ci, const doubl
     free(r);
     free(c);
     free(d);
+    free(dinv32);
     return status;
 }

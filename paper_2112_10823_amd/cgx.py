@@ -57,10 +57,16 @@ class Stats(ctypes.Structure):
         return d
 
 
+class _System(ctypes.Structure):
+    _fields_ = [("A", _Csr), ("nrhs", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("B", ctypes.c_void_p), ("X", ctypes.c_void_p)]
+
+
 EXPORTS = [
     "cgx_create", "cgx_destroy", "cgx_set_stream", "cgx_last_error", "cgx_version",
     "cgx_csr_validate", "cgx_csr_spmv", "cgx_csr_spmv_f32", "cgx_add", "cgx_axpy", "cgx_xmul",
     "cgx_dot", "cgx_demote", "cgx_cg_workspace_bytes", "cgx_cg_solve",
+    "cgx_batch_workspace_bytes", "cgx_cg_solve_batched", "cgx_batch_schedule",
 ]
 
 _lib = None
@@ -93,6 +99,10 @@ def load_library(path: str = LIB_PATH):
         "cgx_cg_workspace_bytes": ([i64, i64, P(Opts)], ctypes.c_size_t),
         "cgx_cg_solve": ([vp, P(_Csr), vp, vp, vp, ctypes.c_size_t, P(Opts), P(Stats)],
                          ctypes.c_int),
+        "cgx_batch_workspace_bytes": ([i32, P(_System)], ctypes.c_size_t),
+        "cgx_cg_solve_batched": ([vp, i32, P(_System), vp, ctypes.c_size_t, P(Opts), P(Stats)],
+                                 ctypes.c_int),
+        "cgx_batch_schedule": ([vp, i32, P(_System), vp, ctypes.c_size_t, P(i32)], ctypes.c_int),
     }
     for name, (argt, rest) in sig.items():
         fn = getattr(lib, name)
@@ -328,3 +338,61 @@ def cg_solve(A: DeviceCSR, b, x, opts: Opts | None = None, workspace=None, handl
     if rc in (EINVAL, ENOMEM, EHIP) or (raise_on_fail and rc != OK):
         _check(rc)
     return st
+
+
+# ---------------------------------------------------------------- batched --
+
+def _systems(items):
+    """items: list of (DeviceCSR, B, X) with B, X float64 GPU tensors of shape
+    (nrhs, n) (right-hand-side major, contiguous)."""
+    arr = (_System * len(items))()
+    for i, (A, B, X) in enumerate(items):
+        _dev_tensor(B, torch.float64, "B")
+        _dev_tensor(X, torch.float64, "X")
+        if B.dim() != 2 or B.shape != X.shape or B.shape[1] != A.n_rows:
+            raise ValueError("B and X must be (nrhs, n_rows)")
+        arr[i].A = A.desc()
+        arr[i].nrhs = B.shape[0]
+        arr[i].B = B.data_ptr()
+        arr[i].X = X.data_ptr()
+    return arr
+
+
+def batch_workspace_bytes(items) -> int:
+    arr = _systems(items)
+    return int(load_library().cgx_batch_workspace_bytes(len(items), arr))
+
+
+def batch_workspace(items, device="cuda") -> torch.Tensor:
+    return torch.empty(max(batch_workspace_bytes(items), 1), dtype=torch.uint8, device=device)
+
+
+def cg_solve_batched(items, opts: Opts | None = None, workspace=None, handle=None):
+    """Solve every (system, right-hand side) of the batch in place on X.
+    Returns a list with one Stats per system, each a list over its right-hand sides."""
+    opts = opts or make_opts()
+    arr = _systems(items)
+    if workspace is None:
+        workspace = batch_workspace(items)
+    nstat = sum(int(B.shape[0]) for _, B, _ in items)
+    st = (Stats * nstat)()
+    rc = load_library().cgx_cg_solve_batched(_h(handle), len(items), arr, _ptr(workspace),
+                                             workspace.numel(), ctypes.byref(opts), st)
+    if rc in (EINVAL, ENOMEM, EHIP):
+        _check(rc)
+    out, k = [], 0
+    for _, B, _ in items:
+        out.append([st[k + j] for j in range(B.shape[0])])
+        k += B.shape[0]
+    return out
+
+
+def batch_schedule(items, workspace=None, handle=None):
+    """Slice counts M picked by the autotuner for each system."""
+    arr = _systems(items)
+    if workspace is None:
+        workspace = batch_workspace(items)
+    m = (ctypes.c_int32 * len(items))()
+    _check(load_library().cgx_batch_schedule(_h(handle), len(items), arr, _ptr(workspace),
+                                             workspace.numel(), m))
+    return list(m)

@@ -107,6 +107,7 @@ int cgx_destroy(cgx_handle h)
     if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
     c->graph64.reset();
     c->graph32.reset();
+    c->graph_batch.reset();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
@@ -267,6 +268,74 @@ int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, voi
         const size_t nb = (size_t)A->n_rows * 8;
         CGX_REQUIRE(!overlaps(b, nb, x, nb), "x overlaps b");
         return cgx::run_cg(ctx_of(h), A, b, x, workspace, workspace_bytes, opts, stats);
+    });
+}
+
+static int check_batch(cgx_handle h, int32_t nsys, const cgx_system *systems)
+{
+    CGX_REQUIRE(h != nullptr, "handle is NULL");
+    CGX_REQUIRE(nsys >= 1 && systems != nullptr, "empty batch");
+    for (int32_t s = 0; s < nsys; ++s) {
+        const cgx_system &q = systems[s];
+        int rc = check_csr(&q.A, true, false);
+        if (rc) return rc;
+        CGX_REQUIRE(q.A.n_rows == q.A.n_cols, "batched matrices must be square");
+        CGX_REQUIRE(q.A.n_rows >= 1, "empty system in batch");
+        CGX_REQUIRE(q.nrhs >= 1 && q.nrhs <= 16, "nrhs must be in [1, 16]");
+        CGX_REQUIRE(q.B != nullptr && q.X != nullptr, "NULL B or X");
+        const size_t nb = (size_t)q.A.n_rows * q.nrhs * 8;
+        CGX_REQUIRE(!overlaps(q.B, nb, q.X, nb), "X overlaps B");
+    }
+    return CGX_OK;
+}
+
+size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems)
+{
+    if (nsys < 1 || systems == nullptr) return 0;
+    try {
+        return cgx::batch_workspace_bytes(nsys, systems);
+    } catch (...) {
+        return 0;
+    }
+}
+
+int cgx_cg_solve_batched(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
+                         size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats)
+{
+    return guarded([&]() -> int {
+        int rc = check_batch(h, nsys, systems);
+        if (rc) return rc;
+        CGX_REQUIRE(opts != nullptr && stats != nullptr, "opts or stats is NULL");
+        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64, "batched solve is float64");
+        CGX_REQUIRE(opts->precond == CGX_PRECOND_NONE || opts->precond == CGX_PRECOND_JACOBI,
+                    "unknown preconditioner");
+        CGX_REQUIRE(opts->rtol >= 0.0, "rtol must be >= 0");
+        CGX_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
+                    "workspace must be 256-byte aligned");
+        return cgx::run_batched(ctx_of(h), nsys, systems, workspace, workspace_bytes, opts, stats);
+    });
+}
+
+int cgx_batch_schedule(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
+                       size_t workspace_bytes, int32_t *M_out)
+{
+    return guarded([&]() -> int {
+        int rc = check_batch(h, nsys, systems);
+        if (rc) return rc;
+        CGX_REQUIRE(M_out != nullptr, "M_out is NULL");
+        CGX_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
+                    "workspace must be 256-byte aligned");
+        CGX_REQUIRE(workspace_bytes >= cgx::batch_workspace_bytes(nsys, systems),
+                    "workspace too small");
+        std::vector<int> Ms;
+        Context *c = ctx_of(h);
+        CGX_HIP_CHECK(hipEventRecord(c->ev_in, c->stream));
+        CGX_HIP_CHECK(hipStreamWaitEvent(c->own_stream, c->ev_in, 0));
+        rc = cgx::batch_autotune(c, nsys, systems, workspace, workspace_bytes, Ms);
+        if (rc) return rc;
+        for (int32_t s = 0; s < nsys; ++s) M_out[s] = Ms[s];
+        CGX_HIP_CHECK(hipStreamSynchronize(c->own_stream));
+        return CGX_OK;
     });
 }
 

@@ -25,7 +25,9 @@
 namespace cgx {
 namespace {
 
-constexpr int kPB = kStreamBlock;    // threads per workgroup of the phase kernels
+constexpr int kSB = kStreamBlock;    // threads per workgroup of the SpMV phase
+constexpr int kPB = 512;             // threads per workgroup of the other phase kernels
+constexpr int kSpmvBlocksPerCu = 8;
 constexpr int kPhaseBlocksPerCu = 4;
 constexpr int kMaxPhaseBlocks = 2048;
 constexpr int kRowsPerGroup = 4;     // vector-CSR rows per lane group (setup passes)
@@ -175,10 +177,10 @@ __global__ __launch_bounds__(kPB) void cg_init_finish_kernel(CgArgs<double> a, i
 
 // (1) q = A p by CSR-stream tiles, and the partials of p.q.
 template <int RT, typename T>
-__global__ __launch_bounds__(kPB) void cg_spmv_kernel(CgArgs<T> a)
+__global__ __launch_bounds__(kSB) void cg_spmv_kernel(CgArgs<T> a)
 {
     if (a.st->done) return;
-    __shared__ StreamSmem<kPB, kStreamE, RT, T> sm;
+    __shared__ StreamSmem<kSB, kStreamE, RT, T> sm;
     const int ntiles = (a.n + RT - 1) / RT;
     int t0, t1;
     tile_range(ntiles, a.tiles_per_block, t0, t1);
@@ -186,16 +188,16 @@ __global__ __launch_bounds__(kPB) void cg_spmv_kernel(CgArgs<T> a)
     for (int t = t0; t < t1; ++t) {
         int row;
         const T acc =
-            stream_rows<kPB, kStreamE, RT, T>(t * RT, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val,
+            stream_rows<kSB, kStreamE, RT, T>(t * RT, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val,
                                               a.p, sm, row);
-        if (threadIdx.x % (kPB / RT) == 0 && row < a.n) {
+        if (threadIdx.x % (kSB / RT) == 0 && row < a.n) {
             a.q[row] = acc;
             part += a.p[row] * acc;
         }
     }
-    __shared__ T red[kPB / kWave];
+    __shared__ T red[kSB / kWave];
     T v[1] = {part};
-    block_sum<1, kPB>(v, red);
+    block_sum<1, kSB>(v, red);
     if (threadIdx.x == 0) region(a, kPPq)[blockIdx.x] = v[0];
 }
 
@@ -299,25 +301,25 @@ __global__ __launch_bounds__(kPB) void cg_direction_kernel(CgArgs<T> a)
 
 // ||b - A x||^2 partials (region kPAux), then one workgroup into st->rr_true.
 template <int RT>
-__global__ __launch_bounds__(kPB) void cg_true_residual_kernel(CgArgs<double> a)
+__global__ __launch_bounds__(kSB) void cg_true_residual_kernel(CgArgs<double> a)
 {
-    __shared__ StreamSmem<kPB, kStreamE, RT, double> sm;
+    __shared__ StreamSmem<kSB, kStreamE, RT, double> sm;
     const int ntiles = (a.n + RT - 1) / RT;
     int t0, t1;
     tile_range(ntiles, a.tiles_per_block, t0, t1);
     double part = 0.0;
     for (int t = t0; t < t1; ++t) {
         int row;
-        const double acc = stream_rows<kPB, kStreamE, RT, double>(t * RT, a.n, a.n_cols, a.nnz,
+        const double acc = stream_rows<kSB, kStreamE, RT, double>(t * RT, a.n, a.n_cols, a.nnz,
                                                                   a.rp, a.ci, a.val, a.x, sm, row);
-        if (threadIdx.x % (kPB / RT) == 0 && row < a.n) {
+        if (threadIdx.x % (kSB / RT) == 0 && row < a.n) {
             const double d = a.b[row] - acc;
             part += d * d;
         }
     }
-    __shared__ double red[kPB / kWave];
+    __shared__ double red[kSB / kWave];
     double v[1] = {part};
-    block_sum<1, kPB>(v, red);
+    block_sum<1, kSB>(v, red);
     if (threadIdx.x == 0) region(a, kPAux)[blockIdx.x] = v[0];
 }
 
@@ -687,8 +689,9 @@ Grids make_grids(const Context *c, int64_t n, int64_t nnz)
     g.L = lanes_per_row(n, nnz);
     g.RT = stream_tile_rows(n, nnz);
     const int cap = std::min(c->num_cu * kPhaseBlocksPerCu, kMaxPhaseBlocks);
+    const int cap_sp = std::min(c->num_cu * kSpmvBlocksPerCu, kMaxPhaseBlocks);
     const int64_t ntiles = (n + g.RT - 1) / g.RT;
-    g.grid_sp = (int)std::max<int64_t>(1, std::min<int64_t>(cap, ntiles));
+    g.grid_sp = (int)std::max<int64_t>(1, std::min<int64_t>(cap_sp, ntiles));
     g.tiles_per_block = (int)((ntiles + g.grid_sp - 1) / g.grid_sp);
     const int64_t ew_need = (n + kPB - 1) / kPB;
     g.grid_ew = (int)std::max<int64_t>(1, std::min<int64_t>(cap, ew_need));
@@ -715,7 +718,7 @@ template <typename T>
 void launch_spmv_phase(const Grids &g, hipStream_t s, const CgArgs<T> &a)
 {
 #define CGX_SP(RR) \
-    hipLaunchKernelGGL((cg_spmv_kernel<RR, T>), dim3(g.grid_sp), dim3(kPB), 0, s, a)
+    hipLaunchKernelGGL((cg_spmv_kernel<RR, T>), dim3(g.grid_sp), dim3(kSB), 0, s, a)
     CGX_RT_SWITCH(g.RT, CGX_SP)
 #undef CGX_SP
 }
@@ -749,7 +752,7 @@ void launch_iteration(const Grids &g, bool jac, hipStream_t s, const CgArgs<T> &
 void launch_true_residual(const Grids &g, hipStream_t s, const CgArgs<double> &a)
 {
 #define CGX_TR(RR) \
-    hipLaunchKernelGGL((cg_true_residual_kernel<RR>), dim3(g.grid_sp), dim3(kPB), 0, s, a)
+    hipLaunchKernelGGL((cg_true_residual_kernel<RR>), dim3(g.grid_sp), dim3(kSB), 0, s, a)
     CGX_RT_SWITCH(g.RT, CGX_TR)
 #undef CGX_TR
     hipLaunchKernelGGL(cg_true_residual_finish_kernel, dim3(1), dim3(kPB), 0, s, a, g.grid_sp);

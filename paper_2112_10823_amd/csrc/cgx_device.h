@@ -164,8 +164,9 @@ struct StreamSmem {
 // CSR-stream tile of RT consecutive rows starting at row0, BS threads, E
 // entries per thread per chunk.  Phase 1: all threads read the tile's
 // col_idx / val as one contiguous stream (thread t takes entries c0 + t +
-// BS * j, j < E: E independent coalesced loads in flight per thread), gather
-// x and stage the products in LDS.  Phase 2: TPR = BS / RT threads per row
+// BS * j, j < E: E independent coalesced loads in flight per thread, with the
+// non-temporal hint since each entry is used once), gather x and stage the
+// products in LDS.  Phase 2: TPR = BS / RT threads per row
 // add the row's staged products (thread `sub` takes entries sub, sub + TPR,
 // ...) and combine by butterfly.  Tiles with more than BS * E entries are
 // processed in several chunks.  Returns the row sum in all TPR threads of the
@@ -207,9 +208,9 @@ __device__ __forceinline__ T stream_rows(int row0, int n_rows, int n_cols, int64
             const int k = c0 + threadIdx.x + BS * j;
             col[j] = -1;
             a[j] = T(0);
-            if (k < k1) {
-                col[j] = ci[k];
-                a[j] = val[k];
+            if (k < k1) {  // streamed once: non-temporal, keeps x resident in L2
+                col[j] = __builtin_nontemporal_load(&ci[k]);
+                a[j] = __builtin_nontemporal_load(&val[k]);
             }
         }
 #pragma unroll

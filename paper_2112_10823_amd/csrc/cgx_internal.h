@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "../../include/cgx.h"
 
@@ -36,10 +39,10 @@ void clear_error();
 
 constexpr int kBlock = 256;         // threads per workgroup for streaming kernels
 constexpr int kReduceBlocks = 1024; // fixed grid of the standalone reductions
-constexpr int kStreamBlock = 512;   // threads per workgroup of the CSR-stream SpMV
+constexpr int kStreamBlock = 256;   // threads per workgroup of the CSR-stream SpMV
 constexpr int kStreamE = 8;         // entries per thread per CSR-stream chunk
 
-// Rows per CSR-stream tile: the largest power of two in [8, 512] whose
+// Rows per CSR-stream tile: the largest power of two in [8, kStreamBlock] whose
 // expected entries (rows * mean row length) fill at most 90% of one chunk of
 // kStreamBlock * kStreamE entries.
 int stream_tile_rows(int64_t n_rows, int64_t nnz);
@@ -51,8 +54,7 @@ int stream_tile_rows(int64_t n_rows, int64_t nnz);
         case 32: EXPR_T(32); break;   \
         case 64: EXPR_T(64); break;   \
         case 128: EXPR_T(128); break; \
-        case 256: EXPR_T(256); break; \
-        default: EXPR_T(512); break;  \
+        default: EXPR_T(256); break;  \
     }
 
 // Device-side CG state, stored at the start of the solver workspace.  All
@@ -104,6 +106,9 @@ struct Context {
     hipEvent_t ev_phase[4] = {nullptr, nullptr, nullptr, nullptr}; // profile mode
     GraphSlot graph64;  // float64 CG iterations
     GraphSlot graph32;  // binary32 inner iterations of the refinement
+    GraphSlot graph_batch;  // batched CG iterations
+    // batched-SpMM autotuner: (K, mean row length, log2 rows) -> slice count M
+    std::map<std::tuple<int, int, int>, int> batch_tune;
 };
 
 // ----------------------------------------------------------- launchers ----
@@ -119,6 +124,11 @@ int run_csr_validate(Context *c, const cgx_csr *A, int64_t *bad_row);
 int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
            const cgx_opts *o, cgx_stats *st);
 size_t cg_workspace_bytes(int64_t n, int64_t nnz, const cgx_opts *o);
+size_t batch_workspace_bytes(int32_t nsys, const cgx_system *in);
+int run_batched(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t ws_bytes,
+                const cgx_opts *o, cgx_stats *stats);
+int batch_autotune(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t ws_bytes,
+                   std::vector<int> &Ms);
 
 // Lanes per row for the vector CSR kernel, from the mean row length.
 int lanes_per_row(int64_t n_rows, int64_t nnz);

@@ -39,6 +39,8 @@ def _load():
         lib.synth_fd7_nnz.argtypes = [ctypes.c_int]
         lib.synth_fd7_nnz.restype = ctypes.c_int64
         lib.synth_fd7.argtypes = [ctypes.c_int, i32p, i32p, f64p]
+        lib.synth_fd7_var.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, i32p, i32p,
+                                      f64p]
         lib.synth_q1_coeffs.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64, f64p]
         lib.synth_q1cube_nnz.argtypes = [ctypes.c_int]
         lib.synth_q1cube_nnz.restype = ctypes.c_int64
@@ -103,6 +105,34 @@ def fd7(N: int) -> CSR:
     v = np.empty(nnz, np.float64)
     lib.synth_fd7(N, rp, ci, v)
     return CSR(n, n, rp, ci, v, name=f"fd7_{N}")
+
+
+def fd7_var(N: int, sigma: float, seed: int) -> CSR:
+    """7-point -div(k grad u), node coefficients exp(sigma Z), harmonic-mean faces."""
+    lib = _load()
+    n = N ** 3
+    nnz = lib.synth_fd7_nnz(N)
+    rp = np.empty(n + 1, np.int32)
+    ci = np.empty(nnz, np.int32)
+    v = np.empty(nnz, np.float64)
+    lib.synth_fd7_var(N, sigma, seed, rp, ci, v)
+    return CSR(n, n, rp, ci, v, name=f"fd7var_{N}_s{sigma:g}")
+
+
+def batch_systems(count: int = 64, n_lo: int = 24, n_hi: int = 96, sigma: float = 1.0,
+                  seed0: int = 1000):
+    """The batched workload: `count` systems, grid size N ~ U{n_lo..n_hi} drawn
+    per system from its own stream (seed0 + s), 7-point FD for even s and Q1
+    FEM for odd s, lognormal(0, sigma) coefficients."""
+    out = []
+    for s in range(count):
+        u = splitmix64(seed0 + s, 2)
+        N = n_lo + int(u[0] % np.uint64(n_hi - n_lo + 1))
+        if s % 2 == 0:
+            out.append(fd7_var(N, sigma, int(u[1])))
+        else:
+            out.append(q1cube(N, sigma, int(u[1])))
+    return out
 
 
 def q1_coeffs(N: int, sigma: float, seed: int) -> np.ndarray:

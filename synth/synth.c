@@ -103,6 +103,64 @@ void synth_fd7(int N, int32_t *row_ptr, int32_t *col_idx, double *val)
             }
 }
 
+/* Variable-coefficient 7-point operator of -div(k grad u) on the N^3 grid
+ * (cell-centred finite volumes, unit spacing): node coefficients k_i =
+ * exp(sigma * Z_i) in lexicographic order; the coupling across a face is the
+ * harmonic mean 2 k_i k_j / (k_i + k_j); a face on the Dirichlet boundary
+ * couples to the boundary value with k_i.  Off-diagonal = -face, diagonal =
+ * sum of the six faces (so the matrix is SPD).  sigma = 0 gives fd7. */
+void synth_fd7_var(int N, double sigma, uint64_t seed, int32_t *row_ptr, int32_t *col_idx,
+                   double *val)
+{
+    const int64_t n = (int64_t)N * N * N;
+    double *k = (double *)malloc((size_t)n * sizeof(double));
+    uint64_t s = seed;
+    for (int64_t i = 0; i < n; ++i) k[i] = exp(sigma * sm64_normal(&s));
+    int64_t e = 0, row = 0;
+    row_ptr[0] = 0;
+    const int64_t strides[3] = {1, N, (int64_t)N * N};
+    for (int z = 0; z < N; ++z)
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x, ++row) {
+                const int c[3] = {x, y, z};
+                double diag = 0.0;
+                double off[6];
+                int64_t oc[6];
+                int no = 0;
+                /* faces in ascending column order: -z, -y, -x, +x, +y, +z */
+                const int dims[6] = {2, 1, 0, 0, 1, 2};
+                const int sgn[6] = {-1, -1, -1, 1, 1, 1};
+                for (int f = 0; f < 6; ++f) {
+                    const int d = dims[f];
+                    const int cc = c[d] + sgn[f];
+                    if (cc < 0 || cc >= N) {
+                        diag += k[row];
+                        continue;
+                    }
+                    const int64_t nb = row + sgn[f] * strides[d];
+                    const double w = 2.0 * k[row] * k[nb] / (k[row] + k[nb]);
+                    diag += w;
+                    off[no] = -w;
+                    oc[no++] = nb;
+                }
+                /* emit: the three lower neighbours, the diagonal, the upper ones */
+                int o = 0;
+                while (o < no && oc[o] < row) {
+                    col_idx[e] = (int32_t)oc[o];
+                    val[e++] = off[o];
+                    ++o;
+                }
+                col_idx[e] = (int32_t)row;
+                val[e++] = diag;
+                for (; o < no; ++o) {
+                    col_idx[e] = (int32_t)oc[o];
+                    val[e++] = off[o];
+                }
+                row_ptr[row + 1] = (int32_t)e;
+            }
+    free(k);
+}
+
 /* ----------------------------------------------------------------- Q1 -- */
 
 /* Per-element coefficients of q1cube: (N+1)^3 values exp(sigma * Z), element

@@ -1,0 +1,119 @@
+"""GPU parity of the batched solve (many systems, up to 16 right-hand sides
+each, one launch per phase for the whole batch) against the CPU oracle run
+on every (system, right-hand side) separately, plus the property that a
+system's result is bit-identical alone and inside a batch."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2112_10823_amd import cgx
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def make_items(mats, nrhs, seed=300):
+    items, hostB = [], []
+    for s, (A, k) in enumerate(zip(mats, nrhs)):
+        B = np.stack([synth.uniform(seed + 17 * s + j, A.n_rows) for j in range(k)])
+        hostB.append(B)
+        items.append((cgx.DeviceCSR.from_host(A), dev(B), torch.zeros(k, A.n_rows,
+                                                                     dtype=torch.float64,
+                                                                     device="cuda")))
+    return items, hostB
+
+
+def true_relres(A, b, x):
+    return float(np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b))
+
+
+MATS = [lambda: synth.fd7_var(6, 1.0, 1), lambda: synth.q1cube(9, 1.0, 2),
+        lambda: synth.fd7_var(13, 1.0, 3), lambda: synth.q1cube(17, 1.0, 4),
+        lambda: synth.fd7_var(30, 1.0, 5), lambda: synth.q1cube(11, 1.0, 6)]
+NRHS = [1, 3, 16, 4, 2, 8]
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_batched_vs_oracle(jacobi):
+    mats = [f() for f in MATS]
+    items, hostB = make_items(mats, NRHS)
+    st = cgx.cg_solve_batched(items, cgx.make_opts(rtol=1e-9, precond=int(jacobi)))
+    for s, (A, (dA, dB, dX)) in enumerate(zip(mats, items)):
+        X = dX.cpu().numpy()
+        for j in range(NRHS[s]):
+            ref = oracle.cg(A, hostB[s][j], rtol=1e-9, jacobi=jacobi)
+            assert st[s][j].status == cgx.OK, (s, j, st[s][j].as_dict())
+            assert abs(st[s][j].iters - ref.iters) <= 2, (s, j, st[s][j].iters, ref.iters)
+            assert true_relres(A, hostB[s][j], X[j]) <= 1.5e-9
+            assert np.linalg.norm(X[j] - ref.x) / np.linalg.norm(ref.x) <= 1e-6
+
+
+def test_batched_alone_equals_in_mix():
+    mats = [f() for f in MATS]
+    items, hostB = make_items(mats, NRHS, seed=900)
+    opts = cgx.make_opts(rtol=1e-10, precond=1)
+    st_mix = cgx.cg_solve_batched(items, opts)
+    mix = [it[2].cpu().numpy().copy() for it in items]
+    for s in (1, 2, 4):
+        A, B, X = items[s]
+        X.zero_()
+        st_alone = cgx.cg_solve_batched([(A, B, X)], opts)
+        alone = X.cpu().numpy()
+        assert np.array_equal(alone, mix[s]), s
+        assert [v.iters for v in st_alone[0]] == [v.iters for v in st_mix[s]]
+
+
+def test_batched_status_isolation():
+    good = synth.q1cube(10, 1.0, 7)
+    bad = synth.fd7(8)
+    bad = synth.CSR(bad.n_rows, bad.n_cols, bad.row_ptr, bad.col_idx, -bad.val)  # negative definite
+    items, hostB = make_items([good, bad, good], [2, 1, 3])
+    hostB[2][1][:] = 0.0
+    items[2][1][1].zero_()            # a zero right-hand side
+    items[2][2][1].fill_(5.0)         # with a nonzero initial guess
+    st = cgx.cg_solve_batched(items, cgx.make_opts(rtol=1e-10))
+    assert [v.status for v in st[0]] == [cgx.OK, cgx.OK]
+    assert st[1][0].status == cgx.BREAKDOWN
+    assert st[2][0].status == cgx.OK and st[2][1].status == cgx.OK and st[2][2].status == cgx.OK
+    assert not items[2][2][1].any().item()  # b = 0 gives x = 0
+    st = cgx.cg_solve_batched(items[:1], cgx.make_opts(rtol=1e-15, maxit=5))
+    assert all(v.status == cgx.NOT_CONVERGED and v.iters == 5 for v in st[0])
+
+
+def test_batched_schedule_reported():
+    mats = [f() for f in MATS[:3]]
+    items, _ = make_items(mats, NRHS[:3])
+    ms = cgx.batch_schedule(items)
+    for M, k in zip(ms, NRHS[:3]):
+        K = 1
+        while K < k:
+            K *= 2
+        assert M >= 1 and K * M <= 64 and K * M >= 8
+
+
+def test_batched_64_systems_16_rhs_full_size():
+    """The batched configuration: 64 systems, N ~ U{24..96}, 7-point FD (even
+    index) and Q1 FEM (odd), lognormal(0,1), 16 right-hand sides U[-1,1] each.
+    Gate on a sample of (system, right-hand side) pairs: the oracle's SpMV of
+    the GPU solution."""
+    mats = synth.batch_systems(64)
+    items = []
+    for s, A in enumerate(mats):
+        B = torch.empty(16, A.n_rows, dtype=torch.float64)
+        for j in range(16):
+            B[j] = torch.from_numpy(synth.uniform(1000 + s * 16 + j, A.n_rows))
+        items.append((cgx.DeviceCSR.from_host(A), B.cuda(),
+                      torch.zeros(16, A.n_rows, dtype=torch.float64, device="cuda")))
+    st = cgx.cg_solve_batched(items, cgx.make_opts(rtol=1e-8, precond=1))
+    assert all(v.status == cgx.OK for row in st for v in row)
+    rng = np.random.default_rng(0)
+    for s in rng.choice(64, 8, replace=False):
+        for j in rng.choice(16, 2, replace=False):
+            b = items[s][1][j].cpu().numpy()
+            x = items[s][2][j].cpu().numpy()
+            assert true_relres(mats[s], b, x) <= 1.5e-8

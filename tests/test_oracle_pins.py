@@ -336,13 +336,14 @@ def test_cg_status_codes():
 
 # ------------------------------------------------------- mixed precision --
 
-def test_mixed_ir_reaches_fp64_accuracy():
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_mixed_ir_reaches_fp64_accuracy(jacobi):
     N = 14
     A = synth.q1cube(N, sigma=1.5, seed=synth.SEED_C3_COEFF)
     b = synth.uniform(synth.SEED_C3_RHS, N ** 3)
     v32 = A.val.astype(np.float32)
     tau = 1e-3
-    r = oracle.mixed_ir(A, v32, b, rtol=1e-10, tau=tau)
+    r = oracle.mixed_ir(A, v32, b, rtol=1e-10, tau=tau, jacobi=jacobi)
     assert r.status == oracle.OK and r.relres <= 1e-10
     # each refinement step contracts by about tau (plus the binary32 floor)
     assert r.outer_iters <= 2 * math.ceil(math.log(1e-10) / math.log(tau)) + 1
