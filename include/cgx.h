@@ -141,12 +141,15 @@ typedef struct cgx_stats {
     int32_t status;      /* CGX_OK, CGX_NOT_CONVERGED, CGX_BREAKDOWN, CGX_NONFINITE */
     int32_t iters;       /* CG iterations (binary32 inner iterations for MIXED) */
     int32_t outer_iters; /* MIXED: refinement steps */
-    int32_t path;        /* kernel path taken: 0 phase kernels, 1 single-workgroup */
+    int32_t path;        /* kernel path: 0 phase kernels, 1 single workgroup, 2 mixed
+                          * refinement, 3 batched, 4 served */
     double relres;       /* recursive ||r|| / ||b|| at exit (outer residual for MIXED) */
     double relres_true;  /* ||b - A x|| / ||b|| if requested, else -1 */
     double device_ms;    /* GPU time of the solve, from stream events */
     double phase_ms[3];  /* profile: mean duration of one launch of phase kernel
                           * (1) q = A p + p.q, (2) x/r/z update + dots, (3) p update */
+    double queue_ms;     /* served requests: submission to admission, wall clock */
+    double latency_ms;   /* served requests: submission to completion, wall clock */
 } cgx_stats;
 
 /* Bytes of device workspace cg_solve needs for an n-row system and `opts`
@@ -201,6 +204,40 @@ int cgx_cg_solve_batched(cgx_handle h, int32_t nsys, const cgx_system *systems, 
  * cgx_cg_solve_batched; M_out: host int32[nsys]. */
 int cgx_batch_schedule(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
                        size_t workspace_bytes, int32_t *M_out);
+
+/* ------------------------------------------------------------- serving -- */
+
+/* (sync) Start a continuous-batching solve server on the handle.  pool:
+ * caller device memory (256-byte aligned) the server carves its tables and
+ * every admitted request's Krylov vectors from; max_slots: requests on the
+ * GPU at once.  A progress thread admits queued requests while a slot and
+ * pool memory are free (FIFO with backfill; a head request blocked for
+ * 0.25 s stops the backfill), advances all admitted requests together a few
+ * CG iterations at a time with the batched kernels, and retires finished
+ * ones.  The handle must not run other solves while the server runs. */
+int cgx_serve_start(cgx_handle h, void *pool, size_t pool_bytes, int32_t max_slots);
+
+/* (sync) Finish every queued and running request, then stop the server. */
+int cgx_serve_stop(cgx_handle h);
+
+/* Pool bytes one request of n_rows needs while admitted. */
+size_t cgx_serve_request_bytes(int64_t n_rows);
+
+/* Queue a solve of A x = b (A resident and square, b / x device float64[n],
+ * x holds x0 and receives the solution; all must stay valid until the
+ * request completes).  opts: rtol, maxit, precond are used.  Non-blocking;
+ * *ticket identifies the request.  CGX_ENOMEM at once if the request can
+ * never fit the pool. */
+int cgx_submit(cgx_handle h, const cgx_csr *A, const double *b, double *x, const cgx_opts *opts,
+               uint64_t *ticket);
+
+/* CGX_PENDING while queued or running; otherwise the request's final status
+ * with *stats filled (stats->latency_ms, queue_ms set), after which the
+ * ticket is forgotten. */
+int cgx_poll(cgx_handle h, uint64_t ticket, cgx_stats *stats);
+
+/* (sync) Like cgx_poll but waits for completion. */
+int cgx_wait(cgx_handle h, uint64_t ticket, cgx_stats *stats);
 
 #ifdef __cplusplus
 }

@@ -49,7 +49,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("outer_iters", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
-                ("device_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 3)]
+                ("device_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 3),
+                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -67,6 +68,8 @@ EXPORTS = [
     "cgx_csr_validate", "cgx_csr_spmv", "cgx_csr_spmv_f32", "cgx_add", "cgx_axpy", "cgx_xmul",
     "cgx_dot", "cgx_demote", "cgx_cg_workspace_bytes", "cgx_cg_solve",
     "cgx_batch_workspace_bytes", "cgx_cg_solve_batched", "cgx_batch_schedule",
+    "cgx_serve_start", "cgx_serve_stop", "cgx_serve_request_bytes", "cgx_submit", "cgx_poll",
+    "cgx_wait",
 ]
 
 _lib = None
@@ -103,6 +106,12 @@ def load_library(path: str = LIB_PATH):
         "cgx_cg_solve_batched": ([vp, i32, P(_System), vp, ctypes.c_size_t, P(Opts), P(Stats)],
                                  ctypes.c_int),
         "cgx_batch_schedule": ([vp, i32, P(_System), vp, ctypes.c_size_t, P(i32)], ctypes.c_int),
+        "cgx_serve_start": ([vp, vp, ctypes.c_size_t, i32], ctypes.c_int),
+        "cgx_serve_stop": ([vp], ctypes.c_int),
+        "cgx_serve_request_bytes": ([i64], ctypes.c_size_t),
+        "cgx_submit": ([vp, P(_Csr), vp, vp, P(Opts), P(ctypes.c_uint64)], ctypes.c_int),
+        "cgx_poll": ([vp, ctypes.c_uint64, P(Stats)], ctypes.c_int),
+        "cgx_wait": ([vp, ctypes.c_uint64, P(Stats)], ctypes.c_int),
     }
     for name, (argt, rest) in sig.items():
         fn = getattr(lib, name)
@@ -396,3 +405,68 @@ def batch_schedule(items, workspace=None, handle=None):
     _check(load_library().cgx_batch_schedule(_h(handle), len(items), arr, _ptr(workspace),
                                              workspace.numel(), m))
     return list(m)
+
+
+# ---------------------------------------------------------------- serving --
+
+class Server:
+    """Continuous-batching solve server on a handle (see cgx_serve_start).
+
+    pool: uint8 GPU tensor the server carves its tables and request vectors
+    from.  Matrices, right-hand sides and solution vectors stay owned by the
+    caller and must outlive their requests."""
+
+    def __init__(self, pool: torch.Tensor, max_slots: int = 64, handle: Handle | None = None):
+        self.handle = handle or Handle()
+        self.pool = pool
+        self._keep = {}
+        _check(load_library().cgx_serve_start(self.handle.ptr, _ptr(pool), pool.numel(),
+                                              int(max_slots)))
+        self.running = True
+
+    @staticmethod
+    def request_bytes(n_rows: int) -> int:
+        return int(load_library().cgx_serve_request_bytes(int(n_rows)))
+
+    def submit(self, A: DeviceCSR, b: torch.Tensor, x: torch.Tensor, opts: Opts | None = None) -> int:
+        _dev_tensor(b, torch.float64, "b")
+        _dev_tensor(x, torch.float64, "x")
+        if b.numel() != A.n_rows or x.numel() != A.n_rows:
+            raise ValueError("b / x length does not match A")
+        opts = opts or make_opts()
+        d = A.desc()
+        t = ctypes.c_uint64()
+        _check(load_library().cgx_submit(self.handle.ptr, ctypes.byref(d), _ptr(b), _ptr(x),
+                                         ctypes.byref(opts), ctypes.byref(t)))
+        self._keep[t.value] = (A, b, x)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else the final Stats."""
+        st = Stats()
+        rc = load_library().cgx_poll(self.handle.ptr, ticket, ctypes.byref(st))
+        if rc == PENDING:
+            return None
+        if rc in (EINVAL, ENOMEM, EHIP):
+            _check(rc)
+        self._keep.pop(ticket, None)
+        return st
+
+    def wait(self, ticket: int) -> Stats:
+        st = Stats()
+        rc = load_library().cgx_wait(self.handle.ptr, ticket, ctypes.byref(st))
+        if rc in (EINVAL, ENOMEM, EHIP):
+            _check(rc)
+        self._keep.pop(ticket, None)
+        return st
+
+    def stop(self):
+        if self.running:
+            self.running = False
+            _check(load_library().cgx_serve_stop(self.handle.ptr))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()

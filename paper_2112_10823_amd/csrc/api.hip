@@ -102,6 +102,7 @@ int cgx_destroy(cgx_handle h)
 {
     Context *c = ctx_of(h);
     if (!c) return CGX_OK;
+    if (c->engine) (void)cgx::serve_stop(c);
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
@@ -336,6 +337,71 @@ int cgx_batch_schedule(cgx_handle h, int32_t nsys, const cgx_system *systems, vo
         for (int32_t s = 0; s < nsys; ++s) M_out[s] = Ms[s];
         CGX_HIP_CHECK(hipStreamSynchronize(c->own_stream));
         return CGX_OK;
+    });
+}
+
+int cgx_serve_start(cgx_handle h, void *pool, size_t pool_bytes, int32_t max_slots)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(pool != nullptr && ((uintptr_t)pool & 255) == 0,
+                    "pool must be 256-byte aligned device memory");
+        CGX_REQUIRE(max_slots >= 1 && max_slots <= 4096, "max_slots must be in [1, 4096]");
+        return cgx::serve_start(ctx_of(h), pool, pool_bytes, max_slots);
+    });
+}
+
+int cgx_serve_stop(cgx_handle h)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        return cgx::serve_stop(ctx_of(h));
+    });
+}
+
+size_t cgx_serve_request_bytes(int64_t n_rows)
+{
+    if (n_rows < 1 || n_rows > 0x7fffffff) return 0;
+    try {
+        return cgx::serve_request_bytes(n_rows);
+    } catch (...) {
+        return 0;
+    }
+}
+
+int cgx_submit(cgx_handle h, const cgx_csr *A, const double *b, double *x, const cgx_opts *opts,
+               uint64_t *ticket)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(opts != nullptr && ticket != nullptr, "opts or ticket is NULL");
+        int rc = check_csr(A, true, false);
+        if (rc) return rc;
+        CGX_REQUIRE(A->n_rows == A->n_cols && A->n_rows >= 1, "matrix must be square, n >= 1");
+        CGX_REQUIRE(b != nullptr && x != nullptr, "NULL b or x");
+        const size_t nb = (size_t)A->n_rows * 8;
+        CGX_REQUIRE(!overlaps(b, nb, x, nb), "x overlaps b");
+        CGX_REQUIRE(opts->precond == CGX_PRECOND_NONE || opts->precond == CGX_PRECOND_JACOBI,
+                    "unknown preconditioner");
+        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64, "served solves are float64");
+        CGX_REQUIRE(opts->rtol >= 0.0, "rtol must be >= 0");
+        return cgx::serve_submit(ctx_of(h), A, b, x, opts, ticket);
+    });
+}
+
+int cgx_poll(cgx_handle h, uint64_t ticket, cgx_stats *stats)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        return cgx::serve_poll(ctx_of(h), ticket, stats, false);
+    });
+}
+
+int cgx_wait(cgx_handle h, uint64_t ticket, cgx_stats *stats)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        return cgx::serve_poll(ctx_of(h), ticket, stats, true);
     });
 }
 

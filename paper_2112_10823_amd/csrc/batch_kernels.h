@@ -1,0 +1,428 @@
+// Device side of the batched solver (shared by the batch call and the
+// solve server): system descriptors, work-table entries and the phase kernels.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "cgx_device.h"
+
+namespace cgx {
+
+struct BSys {
+    const int32_t *rp;
+    const int32_t *ci;
+    const double *val;
+    const double *B;  // caller right-hand sides, [nrhs][n]
+    double *X;        // caller solutions, [nrhs][n]
+    double *x, *r, *p, *q, *z;  // interleaved [n][K]
+    double *dinv;     // [n]
+    int64_t nnz;
+    int n, K, nrhs, M;
+    int tile0, ntiles, trows, scal0;
+    int n_cols, jac;     // jac: Jacobi preconditioning for this system
+    int maxit, pad;
+    double rtol2;        // squared relative tolerance of this system
+};
+
+struct BTile {
+    int sys, row0, rows, tile;  // tile = index within the whole table
+};
+
+struct BScal {
+    double rho, rho_used, alpha, beta, rr, bb, stop2, pq;
+    int32_t iter, status, active, pad;
+};
+
+struct BArgs {
+    const BSys *sys;
+    const BTile *tiles;     // tiles this launch covers (one workgroup each)
+    const int32_t *list;    // systems the per-system kernels cover (one workgroup each)
+    BScal *scal;
+    int32_t *sys_done;      // per system: all right-hand sides finished
+    double *part;           // 3 regions of part_stride doubles
+    int64_t part_stride;    // (tiles of the whole table) * 16
+    int ntiles;
+    int nlist;
+};
+
+namespace bk {
+namespace {  // internal linkage: each translation unit keeps its own copy
+
+constexpr int kBB = 256;  // threads per workgroup of the batched kernels
+constexpr int kMaxK = 16;
+
+__device__ __forceinline__ int clampk(int v, int64_t nnz)
+{
+    return v < 0 ? 0 : (v > nnz ? (int)nnz : v);
+}
+
+// Per-RHS block sum: thread t holds a value for right-hand side t % K; the
+// K totals (fixed order) are written to out[0..K) by threads 0..K-1.
+__device__ __forceinline__ void block_sum_by_rhs(double v, int K, double *red, double *out)
+{
+    __syncthreads();
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < kBB; i += K) s += red[i];
+        out[threadIdx.x] = s;
+    }
+}
+
+// Row sum of one row for right-hand side j over nonzero slice m of M, using
+// interleaved vector v ([n][K]); combined over the M slices by butterfly.
+// Also returns the diagonal entry (summed the same way; one slice holds it).
+__device__ __forceinline__ double row_spmm(const BSys &S, int row, int j, int m, double &diag,
+                                           const double *v)
+{
+    int s = S.rp[row], e = S.rp[row + 1];
+    s = clampk(s, S.nnz);
+    e = clampk(e, S.nnz);
+    if (e < s) e = s;
+    double acc = 0.0, dg = 0.0;
+    for (int k = s + m; k < e; k += S.M) {
+        const int c = S.ci[k];
+        const double a = S.val[k];
+        if ((unsigned)c < (unsigned)S.n_cols) acc += a * v[(int64_t)c * S.K + j];
+        if (c == row) dg = a;
+    }
+    const int G = S.K * S.M;
+    for (int off = S.K; off < G; off <<= 1) {
+        acc += __shfl_xor(acc, off);
+        dg += __shfl_xor(dg, off);
+    }
+    diag = dg;
+    return acc;
+}
+
+// Caller layout -> interleaved x.
+__global__ __launch_bounds__(kBB) void batch_in_kernel(BArgs a)
+{
+    const BTile t = a.tiles[blockIdx.x];
+    const BSys S = a.sys[t.sys];
+    const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) {
+        const int row = (int)(e / S.K), j = (int)(e % S.K);
+        S.x[e] = j < S.nrhs ? S.X[(int64_t)j * S.n + row] : 0.0;
+    }
+}
+
+// r0 = b - A x0, D^-1, z0, p0 and the partials of r.r, r.z, b.b.
+__global__ __launch_bounds__(kBB) void batch_init_kernel(BArgs a)
+{
+    __shared__ double red[kBB];
+    const int w = xcd_block(blockIdx.x, gridDim.x);
+    const BTile t = a.tiles[w];
+    const BSys S = a.sys[t.sys];
+    const int G = S.K * S.M, gpw = kWave / G;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
+    double prr = 0.0, prz = 0.0, pbb = 0.0;
+    for (int row = t.row0 + wave * gpw + grp; row < t.row0 + t.rows; row += (kBB / kWave) * gpw) {
+        double dg;
+        const double ax = row_spmm(S, row, j, m, dg, S.x);
+        if (m == 0) {
+            const int64_t e = (int64_t)row * S.K + j;
+            const double bi = j < S.nrhs ? S.B[(int64_t)j * S.n + row] : 0.0;
+            const double ri = bi - ax;
+            double zi = ri;
+            S.r[e] = ri;
+            if (S.jac) {
+                const double d = dg > 0.0 ? dg : 1.0;
+                if (!(dg > 0.0)) a.scal[S.scal0 + j].pad = 1;  // same value from every writer
+                const double di = 1.0 / d;
+                if (j == 0) S.dinv[row] = di;
+                zi = di * ri;
+                S.z[e] = zi;
+            }
+            S.p[e] = zi;
+            prr += ri * ri;
+            prz += ri * zi;
+            pbb += bi * bi;
+        }
+    }
+    // lanes with m > 0 hold zeros; the lane of (grp, j, m = 0) is lane % K == j
+    double *base = a.part + (int64_t)t.tile * kMaxK;
+    block_sum_by_rhs(prr, S.K, red, base);
+    block_sum_by_rhs(prz, S.K, red, base + a.part_stride);
+    block_sum_by_rhs(pbb, S.K, red, base + 2 * a.part_stride);
+}
+
+// Sum of region `reg` partials of system s for right-hand side j (fixed
+// order: tile-strided per thread slice, then slices in order).
+__device__ __forceinline__ double sys_sum(const BArgs &a, const BSys &S, int reg, double *red)
+{
+    const int K = S.K;
+    const int slice = threadIdx.x / K, j = threadIdx.x % K, nsl = kBB / K;
+    double s = 0.0;
+    const double *base = a.part + reg * a.part_stride;
+    for (int t = S.tile0 + slice; t < S.tile0 + S.ntiles; t += nsl) s += base[(int64_t)t * kMaxK + j];
+    __syncthreads();
+    red[threadIdx.x] = s;
+    __syncthreads();
+    double tot = 0.0;
+    if (threadIdx.x < K)
+        for (int i = 0; i < nsl; ++i) tot += red[i * K + threadIdx.x];
+    return tot;  // valid in threads 0..K-1
+}
+
+__global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgs a)
+{
+    __shared__ double red[kBB];
+    const int sid = a.list[blockIdx.x];
+    const BSys S = a.sys[sid];
+    const double rr = sys_sum(a, S, 0, red);
+    const double rz = sys_sum(a, S, 1, red);
+    const double bb = sys_sum(a, S, 2, red);
+    __shared__ int any_active;
+    if (threadIdx.x == 0) any_active = 0;
+    __syncthreads();
+    if (threadIdx.x < S.K) {
+        const int j = threadIdx.x;
+        BScal &c = a.scal[S.scal0 + j];
+        const bool badd = c.pad != 0;
+        c.rr = rr;
+        c.bb = bb;
+        c.rho = S.jac ? rz : rr;
+        c.stop2 = S.rtol2 * bb;
+        c.iter = 0;
+        int status = CGX_PENDING;
+        if (j >= S.nrhs)
+            status = CGX_OK;
+        else if (badd)
+            status = CGX_BREAKDOWN;
+        else if (!isfinite(bb) || !isfinite(rr) || !isfinite(rz))
+            status = CGX_NONFINITE;
+        else if (bb == 0.0 || rr <= S.rtol2 * bb)
+            status = CGX_OK;
+        else if (S.jac && !(rz > 0.0))
+            status = CGX_BREAKDOWN;
+        c.status = status;
+        c.active = status == CGX_PENDING;
+        if (c.active) atomicOr(&any_active, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.sys_done[sid] = any_active ? 0 : 1;
+}
+
+// (1) q = A p for every active system, p.q partials per right-hand side.
+__global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgs a)
+{
+    __shared__ double red[kBB];
+    const int w = xcd_block(blockIdx.x, gridDim.x);
+    const BTile t = a.tiles[w];
+    if (a.sys_done[t.sys]) return;
+    const BSys S = a.sys[t.sys];
+    const int G = S.K * S.M, gpw = kWave / G;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
+    double ppq = 0.0;
+    for (int row = t.row0 + wave * gpw + grp; row < t.row0 + t.rows; row += (kBB / kWave) * gpw) {
+        double dg;
+        const double qv = row_spmm(S, row, j, m, dg, S.p);
+        if (m == 0) {
+            const int64_t e = (int64_t)row * S.K + j;
+            S.q[e] = qv;
+            ppq += S.p[e] * qv;
+        }
+    }
+    block_sum_by_rhs(ppq, S.K, red, a.part + (int64_t)t.tile * kMaxK);
+}
+
+// (R1) alpha per right-hand side; breakdown / non-finite p.q ends it.
+__global__ __launch_bounds__(kBB) void batch_r1_kernel(BArgs a)
+{
+    __shared__ double red[kBB];
+    const int sid = a.list[blockIdx.x];
+    if (a.sys_done[sid]) return;
+    const BSys S = a.sys[sid];
+    const double pq = sys_sum(a, S, 0, red);
+    if (threadIdx.x < S.K) {
+        BScal &c = a.scal[S.scal0 + threadIdx.x];
+        if (c.active) {
+            c.pq = pq;
+            if (!isfinite(pq) || !(pq > 0.0)) {
+                c.status = isfinite(pq) ? CGX_BREAKDOWN : CGX_NONFINITE;
+                c.active = 0;
+            } else {
+                c.alpha = c.rho / pq;
+                c.rho_used = c.rho;
+                c.iter += 1;
+            }
+        }
+    }
+}
+
+// (2) x += alpha p, r -= alpha q, z = D^-1 r for active right-hand sides;
+// r.r and r.z partials.
+__global__ __launch_bounds__(kBB) void batch_update_kernel(BArgs a)
+{
+    __shared__ double red[kBB];
+    const int w = xcd_block(blockIdx.x, gridDim.x);
+    const BTile t = a.tiles[w];
+    if (a.sys_done[t.sys]) return;
+    const BSys S = a.sys[t.sys];
+    const int j = threadIdx.x % S.K;  // fixed per thread: K divides kBB
+    const BScal c = a.scal[S.scal0 + j];
+    double prr = 0.0, prz = 0.0;
+    if (c.active) {
+        const double alpha = c.alpha;
+        const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) {
+            const double xi = __builtin_fma(alpha, S.p[e], S.x[e]);
+            const double ri = __builtin_fma(-alpha, S.q[e], S.r[e]);
+            S.x[e] = xi;
+            S.r[e] = ri;
+            prr += ri * ri;
+            if (S.jac) {
+                const double zi = S.dinv[e / S.K] * ri;
+                S.z[e] = zi;
+                prz += ri * zi;
+            }
+        }
+    }
+    double *base = a.part + (int64_t)t.tile * kMaxK;
+    block_sum_by_rhs(prr, S.K, red, base + a.part_stride);
+    block_sum_by_rhs(prz, S.K, red, base + 2 * a.part_stride);
+}
+
+// (R2) stopping test and beta per right-hand side; system-done flag.
+__global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgs a)
+{
+    __shared__ double red[kBB];
+    __shared__ int any_active;
+    const int sid = a.list[blockIdx.x];
+    if (a.sys_done[sid]) return;
+    const BSys S = a.sys[sid];
+    const double rr = sys_sum(a, S, 1, red);
+    const double rz0 = sys_sum(a, S, 2, red);
+    if (threadIdx.x == 0) any_active = 0;
+    __syncthreads();
+    if (threadIdx.x < S.K) {
+        BScal &c = a.scal[S.scal0 + threadIdx.x];
+        if (c.active) {
+            const double rz = S.jac ? rz0 : rr;
+            c.rr = rr;
+            int status = CGX_PENDING;
+            if (!isfinite(rr) || !isfinite(rz))
+                status = CGX_NONFINITE;
+            else if (rr <= c.stop2)
+                status = CGX_OK;
+            else if (!(rz > 0.0))
+                status = CGX_BREAKDOWN;
+            else if (c.iter >= S.maxit)
+                status = CGX_NOT_CONVERGED;
+            if (status == CGX_PENDING) {
+                c.beta = rz / c.rho_used;
+                c.rho = rz;
+                atomicOr(&any_active, 1);
+            } else {
+                c.status = status;
+                c.active = 0;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && !any_active) a.sys_done[sid] = 1;
+}
+
+// (3) p = z + beta p for active right-hand sides.
+__global__ __launch_bounds__(kBB) void batch_direction_kernel(BArgs a)
+{
+    const int w = xcd_block(blockIdx.x, gridDim.x);
+    const BTile t = a.tiles[w];
+    if (a.sys_done[t.sys]) return;
+    const BSys S = a.sys[t.sys];
+    const int j = threadIdx.x % S.K;
+    const BScal c = a.scal[S.scal0 + j];
+    if (!c.active) return;
+    const double beta = c.beta;
+    const double *z = S.jac ? S.z : S.r;
+    const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) S.p[e] = __builtin_fma(beta, S.p[e], z[e]);
+}
+
+// Interleaved x -> caller layout (x = 0 where b = 0).
+__global__ __launch_bounds__(kBB) void batch_out_kernel(BArgs a)
+{
+    const BTile t = a.tiles[blockIdx.x];
+    const BSys S = a.sys[t.sys];
+    const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) {
+        const int row = (int)(e / S.K), j = (int)(e % S.K);
+        if (j < S.nrhs) {
+            const BScal &c = a.scal[S.scal0 + j];
+            S.X[(int64_t)j * S.n + row] = (c.bb == 0.0 && c.status == CGX_OK) ? 0.0 : S.x[e];
+        }
+    }
+}
+
+__global__ void batch_scal_init_kernel(BScal *scal, int64_t n, int32_t *done, int nsys)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) scal[i] = BScal{};
+    if (i < nsys) done[i] = 0;
+}
+
+// x[0..n) = 0 (solutions of zero right-hand sides).
+__global__ void batch_zero_kernel(double *x, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = 0.0;
+}
+
+void launch_batch_iteration(const BArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_spmm_kernel, dim3(a.ntiles), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(batch_r1_kernel, dim3(a.nlist), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(batch_update_kernel, dim3(a.ntiles), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(batch_r2_kernel, dim3(a.nlist), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(batch_direction_kernel, dim3(a.ntiles), dim3(kBB), 0, s, a);
+}
+
+int pad_k(int nrhs)
+{
+    int K = 1;
+    while (K < nrhs) K *= 2;
+    return K;
+}
+
+int tile_rows_for(int K) { return K >= 16 ? 128 : 2048 / K; }
+
+// Candidate slice counts M for K right-hand sides: groups of K * M lanes in
+// {8, 16, 32, 64} (at least one lane per right-hand side).
+std::vector<int> m_candidates(int K)
+{
+    std::vector<int> out;
+    for (int G = 8; G <= 64; G *= 2)
+        if (G >= K) out.push_back(G / K);
+    if (out.empty()) out.push_back(1);
+    return out;
+}
+
+// Deterministic default before tuning: about one lane per nonzero of a row
+// (half for many right-hand sides), within the candidates.
+int default_m(int K, double mean_row)
+{
+    int best = m_candidates(K).front();
+    for (int M : m_candidates(K))
+        if (K * M <= std::max(8.0, mean_row * (K >= 8 ? 0.5 : 1.0))) best = M;
+    return best;
+}
+
+std::tuple<int, int, int> shape_key(int K, int64_t n, int64_t nnz)
+{
+    const int mean = n ? (int)std::lround((double)nnz / (double)n) : 0;
+    int lg = 0;
+    while (((int64_t)1 << (lg + 1)) <= n) ++lg;
+    return std::make_tuple(K, mean, lg);
+}
+
+}  // namespace
+}  // namespace bk
+}  // namespace cgx

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -108,7 +109,9 @@ struct Context {
     GraphSlot graph32;  // binary32 inner iterations of the refinement
     GraphSlot graph_batch;  // batched CG iterations
     // batched-SpMM autotuner: (K, mean row length, log2 rows) -> slice count M
+    std::mutex tune_mu;
     std::map<std::tuple<int, int, int>, int> batch_tune;
+    struct Engine *engine = nullptr;  // solve server, while running
 };
 
 // ----------------------------------------------------------- launchers ----
@@ -129,6 +132,14 @@ int run_batched(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t
                 const cgx_opts *o, cgx_stats *stats);
 int batch_autotune(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t ws_bytes,
                    std::vector<int> &Ms);
+int tune_one(Context *c, const cgx_system &sys, void *ws, size_t ws_bytes, hipStream_t s,
+             int &M_out);
+int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots);
+int serve_stop(Context *c);
+size_t serve_request_bytes(int64_t n_rows);
+int serve_submit(Context *c, const cgx_csr *A, const double *b, double *x, const cgx_opts *o,
+                 uint64_t *ticket);
+int serve_poll(Context *c, uint64_t ticket, cgx_stats *st, bool wait);
 
 // Lanes per row for the vector CSR kernel, from the mean row length.
 int lanes_per_row(int64_t n_rows, int64_t nnz);

@@ -1,0 +1,151 @@
+"""GPU tests of the continuous-batching solve server: served results against
+the CPU oracle, the same bits alone and in a mix (and the same as the
+batched path), memory admission, and requests admitted while others run."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2112_10823_amd import cgx
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def pool(nbytes):
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def true_relres(A, b, x):
+    return float(np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def resident():
+    mats = [synth.q1cube(N, 1.0, 2000 + i) for i, N in enumerate((12, 22, 31, 40))]
+    return mats, [cgx.DeviceCSR.from_host(A) for A in mats]
+
+
+def test_served_results_match_oracle(resident):
+    mats, dmats = resident
+    opts = cgx.make_opts(rtol=1e-8)
+    with cgx.Server(pool(1 << 28), max_slots=8) as srv:
+        reqs = []
+        for i in range(10):
+            k = i % 4
+            b = synth.uniform(50 + i, mats[k].n_rows)
+            x = torch.zeros(mats[k].n_rows, dtype=torch.float64, device="cuda")
+            reqs.append((k, b, x, srv.submit(dmats[k], dev(b), x, opts)))
+        for k, b, x, t in reqs:
+            st = srv.wait(t)
+            ref = oracle.cg(mats[k], b, rtol=1e-8)
+            assert st.status == cgx.OK and st.path == 4
+            assert abs(st.iters - ref.iters) <= 2
+            assert true_relres(mats[k], b, x.cpu().numpy()) <= 1.5e-8
+            assert st.latency_ms >= st.queue_ms >= 0.0
+
+
+def test_alone_equals_mix_equals_batched(resident):
+    mats, dmats = resident
+    opts = cgx.make_opts(rtol=1e-10, precond=cgx.PRECOND_JACOBI)
+    b = dev(synth.uniform(77, mats[2].n_rows))
+    h = cgx.Handle()
+    # alone
+    x_alone = torch.zeros_like(b)
+    with cgx.Server(pool(1 << 28), max_slots=8, handle=h) as srv:
+        st_alone = srv.wait(srv.submit(dmats[2], b, x_alone, opts))
+    # in a mix, arriving while others run
+    x_mix = torch.zeros_like(b)
+    others = []
+    with cgx.Server(pool(1 << 28), max_slots=8, handle=h) as srv:
+        for i in range(6):
+            k = i % 4
+            bo = dev(synth.uniform(300 + i, mats[k].n_rows))
+            xo = torch.zeros_like(bo)
+            others.append((bo, xo, srv.submit(dmats[k], bo, xo, opts)))
+        time.sleep(0.002)
+        t = srv.submit(dmats[2], b, x_mix, opts)
+        for i in range(4):
+            k = (i + 1) % 4
+            bo = dev(synth.uniform(400 + i, mats[k].n_rows))
+            xo = torch.zeros_like(bo)
+            others.append((bo, xo, srv.submit(dmats[k], bo, xo, opts)))
+        st_mix = srv.wait(t)
+        for _, _, to in others:
+            assert srv.wait(to).status == cgx.OK
+    assert st_alone.status == st_mix.status == cgx.OK
+    assert st_alone.iters == st_mix.iters
+    assert torch.equal(x_alone, x_mix)
+    # the batched path with one right-hand side runs the same arithmetic
+    X = torch.zeros(1, b.numel(), dtype=torch.float64, device="cuda")
+    st_b = cgx.cg_solve_batched([(dmats[2], b.view(1, -1), X)], opts, handle=h)
+    assert st_b[0][0].iters == st_alone.iters
+    assert torch.equal(X[0], x_alone)
+
+
+def test_admission_by_memory(resident):
+    mats, dmats = resident
+    need = cgx.Server.request_bytes(mats[3].n_rows)
+    # room for the tables plus about two of the largest requests
+    with cgx.Server(pool(need * 2 + (8 << 20)), max_slots=16) as srv:
+        big = synth.fd7(100)  # 1e6 rows: more than the whole pool
+        dbig = cgx.DeviceCSR.from_host(big)
+        with pytest.raises(cgx.CgxError) as ei:
+            srv.submit(dbig, dev(np.ones(big.n_rows)), torch.zeros(big.n_rows, dtype=torch.float64,
+                                                                    device="cuda"))
+        assert ei.value.code == cgx.ENOMEM
+        ts = []
+        for i in range(8):
+            b = dev(synth.uniform(500 + i, mats[3].n_rows))
+            x = torch.zeros_like(b)
+            ts.append((b, x, srv.submit(dmats[3], b, x, cgx.make_opts(rtol=1e-8))))
+        for b, x, t in ts:
+            st = srv.wait(t)
+            assert st.status == cgx.OK
+            assert true_relres(mats[3], b.cpu().numpy(), x.cpu().numpy()) <= 1.5e-8
+
+
+def test_small_requests_overtake_a_large_one(resident):
+    """Continuous batching: small requests submitted after a large one start
+    while it runs and finish first."""
+    mats, dmats = resident
+    big = synth.q1cube(80, 1.0, 3)
+    dbig = cgx.DeviceCSR.from_host(big)
+    opts = cgx.make_opts(rtol=1e-10)
+    with cgx.Server(pool(1 << 30), max_slots=8) as srv:
+        bb = dev(synth.uniform(9, big.n_rows))
+        xb = torch.zeros_like(bb)
+        tb = srv.submit(dbig, bb, xb, opts)
+        time.sleep(0.02)
+        small = []
+        for i in range(4):
+            b = dev(synth.uniform(600 + i, mats[0].n_rows))
+            x = torch.zeros_like(b)
+            small.append((b, x, srv.submit(dmats[0], b, x, opts)))
+        st_small = [srv.wait(t) for _, _, t in small]
+        assert srv.poll(tb) is None  # the large request is still running
+        st_big = srv.wait(tb)
+    assert st_big.status == cgx.OK and all(s.status == cgx.OK for s in st_small)
+    assert max(s.latency_ms for s in st_small) < st_big.latency_ms
+    assert all(s.queue_ms < 50.0 for s in st_small)
+
+
+def test_poll_unknown_ticket_and_restart():
+    h = cgx.Handle()
+    srv = cgx.Server(pool(1 << 24), max_slots=2, handle=h)
+    with pytest.raises(cgx.CgxError):
+        srv.poll(12345)
+    srv.stop()
+    srv2 = cgx.Server(pool(1 << 24), max_slots=2, handle=h)
+    A = synth.fd7(10)
+    dA = cgx.DeviceCSR.from_host(A)
+    b = dev(synth.uniform(1, A.n_rows))
+    x = torch.zeros_like(b)
+    assert srv2.wait(srv2.submit(dA, b, x)).status == cgx.OK
+    srv2.stop()
