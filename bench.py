@@ -23,6 +23,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -109,6 +111,309 @@ def cpu_baseline(A, b, n, nnz, iters=20):
                       f"Q1 {N_GRID}^3 system, {dt:.1f} s"}
 
 
+# ------------------------------------------------------------------ extras --
+# One JSON line per workload of the benchmark suite, outside the default run.
+
+def _timeit(fn, reps=20, warm=3):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3  # s
+
+
+def extra_small_cg(cgx, synth, oracle_mod, meter):
+    """Plain CG on the 7-point 16^3 grid, b = A x*, x* ~ U[-1,1] seed 0, to
+    1e-10; BLAS-1 on 4096-element vectors.  Latency-bound (0.5 MB of data)."""
+    import torch
+    A = synth.fd7(16)
+    xs = synth.uniform(synth.SEED_C1_XSTAR, A.n_rows)
+    dA = cgx.DeviceCSR.from_host(A)
+    dxs = torch.from_numpy(xs).cuda()
+    db = cgx.csr_spmv(dA, dxs)
+    dx = torch.zeros_like(db)
+    opts = cgx.make_opts(rtol=1e-10)
+    ws = cgx.cg_workspace(dA, opts)
+    st = None
+
+    def solve():
+        nonlocal st
+        dx.zero_()
+        st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
+
+    for _ in range(5):
+        solve()
+    e0 = meter.read()
+    t0 = time.perf_counter()
+    reps = 200
+    for _ in range(reps):
+        solve()
+    wall = (time.perf_counter() - t0) / reps
+    e1 = meter.read()
+    err = float(torch.linalg.norm(dx - dxs) / torch.linalg.norm(dxs))
+    x4 = torch.from_numpy(synth.uniform(synth.SEED_VEC_X, 4096)).cuda()
+    y4 = torch.from_numpy(synth.uniform(synth.SEED_VEC_Y, 4096)).cuda()
+    z4 = torch.empty_like(x4)
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    t_add = _timeit(lambda: cgx.add(x4, y4, z4), reps=200)
+    t_mul = _timeit(lambda: cgx.xmul(x4, y4, z4), reps=200)
+    t_dot = _timeit(lambda: cgx.dot(x4, y4, out), reps=200)
+    return {"workload": "plain CG, 7-point 16^3 (4096 rows, 27136 nnz), rtol 1e-10",
+            "iters": st.iters, "status": st.status, "solve_us": round(wall * 1e6, 1),
+            "device_us": round(st.device_ms * 1e3, 1),
+            "us_per_iter": round(st.device_ms * 1e3 / max(st.iters, 1), 2),
+            "solves_per_s": round(1.0 / wall, 1), "path": "single workgroup",
+            "rel_err_vs_xstar": err,
+            "j_per_solve": round((e1 - e0) / reps, 5) if e0 is not None and e1 > e0 else None,
+            "blas1_n4096_us": {"add": round(t_add * 1e6, 2), "xmul": round(t_mul * 1e6, 2),
+                               "dot": round(t_dot * 1e6, 2)},
+            "bound": "latency (whole problem on chip)"}
+
+
+def extra_blas1_sweep(cgx, synth):
+    """BLAS-1 GB/s for n = 2^20 .. 2^26.  Same buffers every call: sizes up to
+    2^23 (<= 200 MB working set) sit in the 256 MB MALL, so those rates are
+    cache-resident, not HBM."""
+    import torch
+    rows = []
+    for lg in range(20, 27):
+        n = 1 << lg
+        x = torch.from_numpy(synth.uniform(synth.SEED_VEC_X, n)).cuda()
+        y = torch.from_numpy(synth.uniform(synth.SEED_VEC_Y, n)).cuda()
+        z = torch.empty_like(x)
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+        reps = max(10, min(200, (1 << 28) // n))
+        t_add = _timeit(lambda: cgx.add(x, y, z), reps=reps)
+        t_mul = _timeit(lambda: cgx.xmul(x, y, z), reps=reps)
+        t_axpy = _timeit(lambda: cgx.axpy(0.5, x, z), reps=reps)
+        t_dot = _timeit(lambda: cgx.dot(x, y, out), reps=reps)
+        rows.append({"n": n, "add_GBs": round(24 * n / t_add / 1e9, 1),
+                     "xmul_GBs": round(24 * n / t_mul / 1e9, 1),
+                     "axpy_GBs": round(24 * n / t_axpy / 1e9, 1),
+                     "dot_GBs": round(16 * n / t_dot / 1e9, 1),
+                     "mall_resident": 24 * n < 256e6})
+        del x, y, z
+    return {"workload": "BLAS-1 add / xmul / axpy / dot, float64 U[-1,1]", "rows": rows}
+
+
+def extra_spmv_and_cg(cgx, synth, meter):
+    """Standalone SpMV and plain / Jacobi CG on the Q1 128^3 system."""
+    import torch
+    A = synth.q1cube(N_GRID, SIGMA, seed=synth.SEED_C2_COEFF)
+    b = synth.blob_rhs(N_GRID, synth.SEED_C2_BLOBS)
+    n, nnz = A.n_rows, A.nnz
+    dA = cgx.DeviceCSR.from_host(A)
+    xv = torch.from_numpy(synth.uniform(4, n)).cuda()
+    yv = torch.empty_like(xv)
+    t_sp = _timeit(lambda: cgx.csr_spmv(dA, xv, yv), reps=50)
+    db = torch.from_numpy(b).cuda()
+    res = {"workload": "Q1 128^3 lognormal(0,1), blob RHS, rtol 1e-8",
+           "spmv_us": round(t_sp * 1e6, 1),
+           "spmv_GBs": round(spmv_bytes(n, nnz) / t_sp / 1e9, 1)}
+    for name, pc in (("plain", 0), ("jacobi", 1)):
+        dx = torch.zeros_like(db)
+        opts = cgx.make_opts(rtol=RTOL, precond=pc)
+        ws = cgx.cg_workspace(dA, opts)
+        st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
+        e0 = meter.read()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            dx.zero_()
+            st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
+        wall = (time.perf_counter() - t0) / reps
+        e1 = meter.read()
+        per_it = spmv_bytes(n, nnz) + (72 * n if pc == 0 else 88 * n)
+        res[name] = {"iters": st.iters, "solve_ms": round(wall * 1e3, 2),
+                     "GBs": round(per_it * st.iters / wall / 1e9, 1),
+                     "j_per_solve": round((e1 - e0) / reps, 3) if e0 is not None and e1 > e0 else None}
+    return res
+
+
+def extra_mixed(cgx, synth, meter):
+    """Q1 192^3 lognormal(0,1.5): binary32-inner refinement to 1e-10 against
+    float64 CG to 1e-10, both Jacobi-preconditioned, uniform[-1,1] RHS."""
+    import torch
+    import oracle
+    A = synth.q1cube(192, 1.5, seed=synth.SEED_C3_COEFF)
+    b = synth.uniform(synth.SEED_C3_RHS, A.n_rows)
+    dA = cgx.DeviceCSR.from_host(A, with_f32=True)
+    db = torch.from_numpy(b).cuda()
+    out = {"workload": "Q1 192^3 (7,077,888 rows, 189,119,224 nnz) lognormal(0,1.5), "
+                       "uniform RHS, rtol 1e-10, Jacobi"}
+    sols = {}
+    for name, prec in (("fp64", cgx.PRECISION_FP64), ("mixed", cgx.PRECISION_MIXED)):
+        opts = cgx.make_opts(rtol=1e-10, precond=1, precision=prec, inner_rtol=1e-2,
+                             true_residual=True)
+        ws = cgx.cg_workspace(dA, opts)
+        dx = torch.zeros_like(db)
+        st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
+        e0 = meter.read()
+        t0 = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            dx.zero_()
+            st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
+        wall = (time.perf_counter() - t0) / reps
+        e1 = meter.read()
+        x = dx.cpu().numpy()
+        sols[name] = x
+        tr = float(np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b))
+        out[name] = {"status": st.status, "iters": st.iters, "outer": st.outer_iters,
+                     "solve_ms": round(wall * 1e3, 1), "solves_per_s": round(1 / wall, 3),
+                     "j_per_solve": round((e1 - e0) / reps, 2) if e0 is not None and e1 > e0 else None,
+                     "true_relres_by_oracle_spmv": tr}
+        del ws
+    out["rel_diff_mixed_vs_fp64"] = float(np.linalg.norm(sols["mixed"] - sols["fp64"]) /
+                                          np.linalg.norm(sols["fp64"]))
+    return out
+
+
+def extra_batched(cgx, synth, meter):
+    """64 systems (7-point / Q1 alternating, N ~ U{24..96}, lognormal(0,1)),
+    16 RHS each, Jacobi CG to 1e-8: batched against one solve at a time."""
+    import torch
+    mats = synth.batch_systems(64)
+    items = []
+    for s, A in enumerate(mats):
+        B = torch.empty(16, A.n_rows, dtype=torch.float64)
+        for j in range(16):
+            B[j] = torch.from_numpy(synth.uniform(1000 + s * 16 + j, A.n_rows))
+        items.append((cgx.DeviceCSR.from_host(A), B.cuda(),
+                      torch.zeros(16, A.n_rows, dtype=torch.float64, device="cuda")))
+    opts = cgx.make_opts(rtol=1e-8, precond=1)
+    ws = cgx.batch_workspace(items)
+    st = cgx.cg_solve_batched(items, opts, workspace=ws)  # tunes + warms
+    for _, _, X in items:
+        X.zero_()
+    torch.cuda.synchronize()
+    e0 = meter.read()
+    t0 = time.perf_counter()
+    st = cgx.cg_solve_batched(items, opts, workspace=ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    e1 = meter.read()
+    ok = sum(v.status == cgx.OK for row in st for v in row)
+    byts = 0.0
+    for (dA, B, X), row in zip(items, st):
+        it = max(v.iters for v in row)
+        byts += it * (12 * dA.nnz + 4 * (dA.n_rows + 1) + 88 * 16 * dA.n_rows)
+    sched = cgx.batch_schedule(items, workspace=ws)
+    # one right-hand side at a time with the single-system solver (a sample, scaled)
+    sample = list(range(0, 64, 8))
+    t_single = 0.0
+    for s in sample:
+        dA, B, _ = items[s]
+        x1 = torch.zeros(dA.n_rows, dtype=torch.float64, device="cuda")
+        o1 = cgx.make_opts(rtol=1e-8, precond=1)
+        w1 = cgx.cg_workspace(dA, o1)
+        cgx.cg_solve(dA, B[0].contiguous(), x1, o1, workspace=w1)
+        t1 = time.perf_counter()
+        for j in range(4):
+            x1.zero_()
+            cgx.cg_solve(dA, B[j].contiguous(), x1, o1, workspace=w1)
+        t_single += (time.perf_counter() - t1) / 4 * 16
+    t_single *= 64 / len(sample)
+    return {"workload": "64 systems N~U{24..96} 7-point/Q1 lognormal(0,1), 16 RHS each, "
+                        "Jacobi CG rtol 1e-8",
+            "solves": 1024, "converged": ok, "batch_s": round(wall, 3),
+            "solves_per_s": round(1024 / wall, 1),
+            "model_GBs": round(byts / wall / 1e9, 1),
+            "j_per_solve": round((e1 - e0) / 1024, 4) if e0 is not None and e1 > e0 else None,
+            "one_at_a_time_est_s": round(t_single, 3),
+            "one_at_a_time_solves_per_s": round(1024 / t_single, 1),
+            "schedule_M": {"fd7": sched[0], "q1": sched[1]}}
+
+
+def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
+    """Poisson arrivals of solve requests on resident Q1 systems whose row
+    counts follow ln(rows) ~ N(mu, sigma) truncated to [1e4, 4e6] (pool of
+    `pool_systems` resident systems, bounded from the 256 of the full
+    workload), lognormal(0,1), uniform RHS, rtol 1e-8."""
+    import torch
+    rng = np.random.default_rng(seed)
+    mu = 0.5 * (math.log(1e4) + math.log(4e6))
+    sg = (math.log(4e6) - math.log(1e4)) / 4
+    mats = []
+    for i in range(pool_systems):
+        while True:
+            r = math.exp(rng.normal(mu, sg))
+            if 1e4 <= r <= 4e6:
+                break
+        N = max(2, round(r ** (1 / 3)))
+        A = synth.q1cube(N, 1.0, 2000 + i)
+        mats.append((A, cgx.DeviceCSR.from_host(A)))
+    opts = cgx.make_opts(rtol=1e-8)
+    picks = rng.integers(0, pool_systems, n_req)
+    max_n = max(A.n_rows for A, _ in mats)
+    pool_bytes = 48 * cgx.Server.request_bytes(max_n) + (64 << 20)
+    pool_t = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+    bs = [torch.from_numpy(synth.uniform(7000 + i, A.n_rows)).cuda() for i, (A, _) in enumerate(mats)]
+
+    def run(qps):
+        h = cgx.Handle()
+        gaps = rng.exponential(1.0 / qps, n_req) if qps else np.zeros(n_req)
+        lat, ok = [], 0
+        out = [torch.zeros_like(bs[k]) for k in picks]
+        e0 = meter.read()
+        with cgx.Server(pool_t, max_slots=48, handle=h) as srv:
+            t0 = time.perf_counter()
+            tickets = []
+            nxt = t0
+            for i, k in enumerate(picks):
+                nxt += gaps[i]
+                while time.perf_counter() < nxt:
+                    pass
+                tickets.append(srv.submit(mats[k][1], bs[k], out[i], opts))
+            for t in tickets:
+                st = srv.wait(t)
+                ok += st.status == cgx.OK
+                lat.append(st.latency_ms)
+            wall = time.perf_counter() - t0
+        e1 = meter.read()
+        lat.sort()
+        return {"qps": round(qps, 2) if qps else "burst", "solves_per_s": round(n_req / wall, 2),
+                "p50_ms": round(lat[len(lat) // 2], 2),
+                "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 2),
+                "ok": ok, "wall_s": round(wall, 2),
+                "j_per_solve": round((e1 - e0) / n_req, 3) if e0 is not None and e1 > e0 else None}
+
+    sat = run(0)  # all requests at once: saturation throughput
+    rows = [sat]
+    for f in (0.5, 0.8, 0.95):
+        rows.append(run(f * sat["solves_per_s"]))
+    return {"workload": f"{n_req} Poisson-arrival requests on {pool_systems} resident Q1 systems "
+                        f"(rows lognormal in [1e4, 4e6]), lognormal(0,1), rtol 1e-8",
+            "rows": rows, "pool_rows": sorted(A.n_rows for A, _ in mats)}
+
+
+def run_extras(which):
+    import numpy as _np  # noqa: F401
+    import torch
+    import oracle as oracle_mod
+    import synth
+    from paper_2112_10823_amd import cgx
+    torch.cuda.set_device(0)
+    meter = EnergyMeter()
+    table = {"small": lambda: extra_small_cg(cgx, synth, oracle_mod, meter),
+             "blas1": lambda: extra_blas1_sweep(cgx, synth),
+             "q1": lambda: extra_spmv_and_cg(cgx, synth, meter),
+             "mixed": lambda: extra_mixed(cgx, synth, meter),
+             "batched": lambda: extra_batched(cgx, synth, meter),
+             "serving": lambda: extra_serving(cgx, synth, meter)}
+    for name in which:
+        print(f"# extra {name}", file=sys.stderr, flush=True)
+        res = table[name]()
+        print(json.dumps({"extra": name, **res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +423,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--profile-only", action="store_true",
                     help="warm-up plus a few solves, for profiler runs")
+    ap.add_argument("--extras", default="",
+                    help="comma list of extra workloads (small,blas1,q1,mixed,batched,serving); "
+                         "prints one JSON line each instead of the benchmark line")
     ap.add_argument("--calib", action="store_true",
                     help="with --profile-only: first run cgx_add on 2^26 float64 elements "
                          "(reads 1 GiB, writes 0.5 GiB) to calibrate byte counters")
@@ -127,6 +435,9 @@ def main():
               "(independent systems per GPU, row-slab halo exchange for one big system) "
               "and is not run. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.extras:
+        run_extras([w for w in args.extras.split(",") if w])
+        return
 
     import numpy as np
     import torch
