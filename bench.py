@@ -129,6 +129,25 @@ def _timeit(fn, reps=20, warm=3):
     return e0.elapsed_time(e1) / reps * 1e-3  # s
 
 
+def _energy_window(fn, meter, min_s=2.0, min_reps=1):
+    """Run fn repeatedly for at least min_s seconds (the GPU energy counter
+    updates too coarsely for shorter windows); returns (s per call, J per call
+    or None)."""
+    import torch
+    torch.cuda.synchronize()
+    e0 = meter.read()
+    t0 = time.perf_counter()
+    reps = 0
+    while reps < min_reps or time.perf_counter() - t0 < min_s:
+        fn()
+        reps += 1
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    e1 = meter.read()
+    j = (e1 - e0) / reps if (e0 is not None and e1 is not None and e1 > e0) else None
+    return wall, j
+
+
 def extra_small_cg(cgx, synth, oracle_mod, meter):
     """Plain CG on the 7-point 16^3 grid, b = A x*, x* ~ U[-1,1] seed 0, to
     1e-10; BLAS-1 on 4096-element vectors.  Latency-bound (0.5 MB of data)."""
@@ -150,13 +169,7 @@ def extra_small_cg(cgx, synth, oracle_mod, meter):
 
     for _ in range(5):
         solve()
-    e0 = meter.read()
-    t0 = time.perf_counter()
-    reps = 200
-    for _ in range(reps):
-        solve()
-    wall = (time.perf_counter() - t0) / reps
-    e1 = meter.read()
+    wall, jsolve = _energy_window(solve, meter, min_s=2.0)
     err = float(torch.linalg.norm(dx - dxs) / torch.linalg.norm(dxs))
     x4 = torch.from_numpy(synth.uniform(synth.SEED_VEC_X, 4096)).cuda()
     y4 = torch.from_numpy(synth.uniform(synth.SEED_VEC_Y, 4096)).cuda()
@@ -171,7 +184,7 @@ def extra_small_cg(cgx, synth, oracle_mod, meter):
             "us_per_iter": round(st.device_ms * 1e3 / max(st.iters, 1), 2),
             "solves_per_s": round(1.0 / wall, 1), "path": "single workgroup",
             "rel_err_vs_xstar": err,
-            "j_per_solve": round((e1 - e0) / reps, 5) if e0 is not None and e1 > e0 else None,
+            "j_per_solve": round(jsolve, 5) if jsolve is not None else None,
             "blas1_n4096_us": {"add": round(t_add * 1e6, 2), "xmul": round(t_mul * 1e6, 2),
                                "dot": round(t_dot * 1e6, 2)},
             "bound": "latency (whole problem on chip)"}
@@ -222,24 +235,22 @@ def extra_spmv_and_cg(cgx, synth, meter):
         opts = cgx.make_opts(rtol=RTOL, precond=pc)
         ws = cgx.cg_workspace(dA, opts)
         st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
-        e0 = meter.read()
-        t0 = time.perf_counter()
-        reps = 3
-        for _ in range(reps):
+
+        def solve():
             dx.zero_()
-            st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
-        wall = (time.perf_counter() - t0) / reps
-        e1 = meter.read()
+            cgx.cg_solve(dA, db, dx, opts, workspace=ws)
+
+        wall, j = _energy_window(solve, meter, min_s=2.0)
         per_it = spmv_bytes(n, nnz) + (72 * n if pc == 0 else 88 * n)
         res[name] = {"iters": st.iters, "solve_ms": round(wall * 1e3, 2),
                      "GBs": round(per_it * st.iters / wall / 1e9, 1),
-                     "j_per_solve": round((e1 - e0) / reps, 3) if e0 is not None and e1 > e0 else None}
+                     "j_per_solve": round(j, 3) if j is not None else None}
     return res
 
 
 def extra_mixed(cgx, synth, meter):
-    """Q1 192^3 lognormal(0,1.5): binary32-inner refinement to 1e-10 against
-    float64 CG to 1e-10, both Jacobi-preconditioned, uniform[-1,1] RHS."""
+    """Q1 192^3 lognormal(0,1.5), uniform RHS, to 1e-10: float64 CG against
+    binary32-inner refinement, each plain and Jacobi-preconditioned."""
     import torch
     import oracle
     A = synth.q1cube(192, 1.5, seed=synth.SEED_C3_COEFF)
@@ -247,32 +258,37 @@ def extra_mixed(cgx, synth, meter):
     dA = cgx.DeviceCSR.from_host(A, with_f32=True)
     db = torch.from_numpy(b).cuda()
     out = {"workload": "Q1 192^3 (7,077,888 rows, 189,119,224 nnz) lognormal(0,1.5), "
-                       "uniform RHS, rtol 1e-10, Jacobi"}
-    sols = {}
-    for name, prec in (("fp64", cgx.PRECISION_FP64), ("mixed", cgx.PRECISION_MIXED)):
-        opts = cgx.make_opts(rtol=1e-10, precond=1, precision=prec, inner_rtol=1e-2,
-                             true_residual=True)
+                       "uniform RHS, rtol 1e-10"}
+    runs = [("fp64_plain", cgx.PRECISION_FP64, 0, 0.0), ("fp64_jacobi", cgx.PRECISION_FP64, 1, 0.0),
+            ("mixed_plain_tau1e-3", cgx.PRECISION_MIXED, 0, 1e-3),
+            ("mixed_jacobi_tau1e-2", cgx.PRECISION_MIXED, 1, 1e-2),
+            ("mixed_jacobi_tau1e-3", cgx.PRECISION_MIXED, 1, 1e-3),
+            ("mixed_jacobi_tau1e-4", cgx.PRECISION_MIXED, 1, 1e-4)]
+    ref = None
+    for name, prec, pc, tau in runs:
+        opts = cgx.make_opts(rtol=1e-10, precond=pc, precision=prec, inner_rtol=tau,
+                             maxit=20000)
         ws = cgx.cg_workspace(dA, opts)
         dx = torch.zeros_like(db)
-        st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
-        e0 = meter.read()
-        t0 = time.perf_counter()
-        reps = 2
-        for _ in range(reps):
+        st = None
+
+        def solve():
+            nonlocal st
             dx.zero_()
             st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
-        wall = (time.perf_counter() - t0) / reps
-        e1 = meter.read()
+
+        solve()
+        wall, j = _energy_window(solve, meter, min_s=2.0)
         x = dx.cpu().numpy()
-        sols[name] = x
+        if ref is None:
+            ref = x
         tr = float(np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b))
         out[name] = {"status": st.status, "iters": st.iters, "outer": st.outer_iters,
                      "solve_ms": round(wall * 1e3, 1), "solves_per_s": round(1 / wall, 3),
-                     "j_per_solve": round((e1 - e0) / reps, 2) if e0 is not None and e1 > e0 else None,
-                     "true_relres_by_oracle_spmv": tr}
+                     "j_per_solve": round(j, 2) if j is not None else None,
+                     "true_relres_by_oracle_spmv": tr,
+                     "rel_diff_vs_fp64_plain": float(np.linalg.norm(x - ref) / np.linalg.norm(ref))}
         del ws
-    out["rel_diff_mixed_vs_fp64"] = float(np.linalg.norm(sols["mixed"] - sols["fp64"]) /
-                                          np.linalg.norm(sols["fp64"]))
     return out
 
 
@@ -291,15 +307,14 @@ def extra_batched(cgx, synth, meter):
     opts = cgx.make_opts(rtol=1e-8, precond=1)
     ws = cgx.batch_workspace(items)
     st = cgx.cg_solve_batched(items, opts, workspace=ws)  # tunes + warms
-    for _, _, X in items:
-        X.zero_()
-    torch.cuda.synchronize()
-    e0 = meter.read()
-    t0 = time.perf_counter()
-    st = cgx.cg_solve_batched(items, opts, workspace=ws)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    e1 = meter.read()
+
+    def solve():
+        nonlocal st
+        for _, _, X in items:
+            X.zero_()
+        st = cgx.cg_solve_batched(items, opts, workspace=ws)
+
+    wall, jb = _energy_window(solve, meter, min_s=2.0)
     ok = sum(v.status == cgx.OK for row in st for v in row)
     byts = 0.0
     for (dA, B, X), row in zip(items, st):
@@ -326,7 +341,7 @@ def extra_batched(cgx, synth, meter):
             "solves": 1024, "converged": ok, "batch_s": round(wall, 3),
             "solves_per_s": round(1024 / wall, 1),
             "model_GBs": round(byts / wall / 1e9, 1),
-            "j_per_solve": round((e1 - e0) / 1024, 4) if e0 is not None and e1 > e0 else None,
+            "j_per_solve": round(jb / 1024, 4) if jb is not None else None,
             "one_at_a_time_est_s": round(t_single, 3),
             "one_at_a_time_solves_per_s": round(1024 / t_single, 1),
             "schedule_M": {"fd7": sched[0], "q1": sched[1]}}

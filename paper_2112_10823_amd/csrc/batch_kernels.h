@@ -77,6 +77,9 @@ __device__ __forceinline__ void block_sum_by_rhs(double v, int K, double *red, d
 // Row sum of one row for right-hand side j over nonzero slice m of M, using
 // interleaved vector v ([n][K]); combined over the M slices by butterfly.
 // Also returns the diagonal entry (summed the same way; one slice holds it).
+// The nonzero loop is unrolled four ways (four col/val loads, then four
+// gathers in flight per lane); the accumulation order is k, k + M, ... in
+// both the unrolled and the remainder part.
 __device__ __forceinline__ double row_spmm(const BSys &S, int row, int j, int m, double &diag,
                                            const double *v)
 {
@@ -84,15 +87,34 @@ __device__ __forceinline__ double row_spmm(const BSys &S, int row, int j, int m,
     s = clampk(s, S.nnz);
     e = clampk(e, S.nnz);
     if (e < s) e = s;
+    const int M = S.M, K = S.K;
     double acc = 0.0, dg = 0.0;
-    for (int k = s + m; k < e; k += S.M) {
+    int k = s + m;
+    for (; k + 3 * M < e; k += 4 * M) {
+        int c[4];
+        double a[4], pv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = S.ci[k + u * M];
+            a[u] = S.val[k + u * M];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            pv[u] = (unsigned)c[u] < (unsigned)S.n_cols ? v[(int64_t)c[u] * K + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if ((unsigned)c[u] < (unsigned)S.n_cols) acc += a[u] * pv[u];
+            if (c[u] == row) dg = a[u];
+        }
+    }
+    for (; k < e; k += M) {
         const int c = S.ci[k];
         const double a = S.val[k];
-        if ((unsigned)c < (unsigned)S.n_cols) acc += a * v[(int64_t)c * S.K + j];
+        if ((unsigned)c < (unsigned)S.n_cols) acc += a * v[(int64_t)c * K + j];
         if (c == row) dg = a;
     }
-    const int G = S.K * S.M;
-    for (int off = S.K; off < G; off <<= 1) {
+    const int G = K * M;
+    for (int off = K; off < G; off <<= 1) {
         acc += __shfl_xor(acc, off);
         dg += __shfl_xor(dg, off);
     }

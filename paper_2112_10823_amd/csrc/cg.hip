@@ -180,7 +180,7 @@ template <int RT, typename T>
 __global__ __launch_bounds__(kSB) void cg_spmv_kernel(CgArgs<T> a)
 {
     if (a.st->done) return;
-    __shared__ StreamSmem<kSB, kStreamE, RT, T> sm;
+    __shared__ StreamSmem<kSB, stream_e<T>(), RT, T> sm;
     const int ntiles = (a.n + RT - 1) / RT;
     int t0, t1;
     tile_range(ntiles, a.tiles_per_block, t0, t1);
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kSB) void cg_spmv_kernel(CgArgs<T> a)
     for (int t = t0; t < t1; ++t) {
         int row;
         const T acc =
-            stream_rows<kSB, kStreamE, RT, T>(t * RT, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val,
+            stream_rows<kSB, stream_e<T>(), RT, T>(t * RT, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val,
                                               a.p, sm, row);
         if (threadIdx.x % (kSB / RT) == 0 && row < a.n) {
             a.q[row] = acc;
@@ -683,11 +683,11 @@ struct Grids {
     int tiles_per_block;
 };
 
-Grids make_grids(const Context *c, int64_t n, int64_t nnz)
+Grids make_grids(const Context *c, int64_t n, int64_t nnz, int entries = kStreamE)
 {
     Grids g{};
     g.L = lanes_per_row(n, nnz);
-    g.RT = stream_tile_rows(n, nnz);
+    g.RT = stream_tile_rows(n, nnz, entries);
     const int cap = std::min(c->num_cu * kPhaseBlocksPerCu, kMaxPhaseBlocks);
     const int cap_sp = std::min(c->num_cu * kSpmvBlocksPerCu, kMaxPhaseBlocks);
     const int64_t ntiles = (n + g.RT - 1) / g.RT;
@@ -985,7 +985,7 @@ int run_mixed(Context *c, const cgx_csr *A, const double *b, double *x, void *ws
         return CGX_ENOMEM;
     }
     char *w = static_cast<char *>(ws);
-    const Grids g = make_grids(c, n, A->nnz);
+    const Grids g = make_grids(c, n, A->nnz, stream_e<float>());
 
     MxArgs m{};
     m.n = (int)n;

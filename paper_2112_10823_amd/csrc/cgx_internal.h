@@ -41,12 +41,17 @@ void clear_error();
 constexpr int kBlock = 256;         // threads per workgroup for streaming kernels
 constexpr int kReduceBlocks = 1024; // fixed grid of the standalone reductions
 constexpr int kStreamBlock = 256;   // threads per workgroup of the CSR-stream SpMV
-constexpr int kStreamE = 8;         // entries per thread per CSR-stream chunk
+constexpr int kStreamE = 8;         // float64 entries per thread per CSR-stream chunk
+
+// Entries per thread per chunk for value type T: 64 bytes of values in flight
+// per thread (8 float64 or 16 binary32), the same LDS footprint either way.
+template <typename T>
+constexpr int stream_e() { return 64 / (int)sizeof(T); }
 
 // Rows per CSR-stream tile: the largest power of two in [8, kStreamBlock] whose
 // expected entries (rows * mean row length) fill at most 90% of one chunk of
 // kStreamBlock * kStreamE entries.
-int stream_tile_rows(int64_t n_rows, int64_t nnz);
+int stream_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_thread = kStreamE);
 
 #define CGX_RT_SWITCH(RT, EXPR_T)     \
     switch (RT) {                     \

@@ -24,10 +24,10 @@ __global__ __launch_bounds__(kStreamBlock) void spmv_stream_kernel(int n_rows, i
                                                                     const T *__restrict__ x,
                                                                     T *__restrict__ y)
 {
-    __shared__ StreamSmem<kStreamBlock, kStreamE, RT, T> sm;
+    __shared__ StreamSmem<kStreamBlock, stream_e<T>(), RT, T> sm;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     int row;
-    const T acc = stream_rows<kStreamBlock, kStreamE, RT, T>(tile * RT, n_rows, n_cols, nnz, rp, ci,
+    const T acc = stream_rows<kStreamBlock, stream_e<T>(), RT, T>(tile * RT, n_rows, n_cols, nnz, rp, ci,
                                                              val, x, sm, row);
     if (threadIdx.x % (kStreamBlock / RT) == 0 && row < n_rows) y[row] = acc;
 }
@@ -36,7 +36,7 @@ template <typename T>
 int launch_spmv_t(Context *c, const cgx_csr *A, const T *val, const T *x, T *y)
 {
     if (A->n_rows == 0) return CGX_OK;
-    const int RT = stream_tile_rows(A->n_rows, A->nnz);
+    const int RT = stream_tile_rows(A->n_rows, A->nnz, stream_e<T>());
     const int64_t grid = (A->n_rows + RT - 1) / RT;
 #define CGX_SPMV_CASE(RR)                                                                    \
     hipLaunchKernelGGL((spmv_stream_kernel<RR, T>), dim3((unsigned)grid), dim3(kStreamBlock), \
@@ -80,10 +80,10 @@ __global__ __launch_bounds__(kBlock) void csr_validate_kernel(int n_rows, int n_
 
 }  // namespace
 
-int stream_tile_rows(int64_t n_rows, int64_t nnz)
+int stream_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_thread)
 {
     const double mean = n_rows > 0 ? (double)nnz / (double)n_rows : 1.0;
-    const double budget = 0.9 * kStreamBlock * kStreamE;
+    const double budget = 0.9 * kStreamBlock * entries_per_thread;
     int rt = kStreamBlock;
     while (rt > 8 && rt * (mean > 1.0 ? mean : 1.0) > budget) rt /= 2;
     return rt;
