@@ -146,14 +146,17 @@ typedef struct cgx_stats {
     double relres;       /* recursive ||r|| / ||b|| at exit (outer residual for MIXED) */
     double relres_true;  /* ||b - A x|| / ||b|| if requested, else -1 */
     double device_ms;    /* GPU time of the solve, from stream events */
-    double phase_ms[3];  /* profile: mean duration of one launch of phase kernel
-                          * (1) q = A p + p.q, (2) x/r/z update + dots, (3) p update */
+    double phase_ms[3];  /* profile: mean duration per iteration of (1) the SpMV
+                          * kernel q = A p with its p.q tile partials, (2) the
+                          * reduction of those partials (for more than 2048 tiles)
+                          * plus the x/r/z update and its dots, (3) the p update */
     double queue_ms;     /* served requests: submission to admission, wall clock */
     double latency_ms;   /* served requests: submission to completion, wall clock */
 } cgx_stats;
 
-/* Bytes of device workspace cg_solve needs for an n-row system and `opts`
- * (0 on invalid arguments).  The caller allocates it (256-byte aligned) and
+/* Bytes of device workspace cg_solve needs for a system of n_rows rows and
+ * nnz stored entries (the SpMV tile count depends on the mean row length)
+ * and `opts` (0 on invalid arguments).  The caller allocates it (256-byte aligned) and
  * keeps it alive for the duration of the call. */
 size_t cgx_cg_workspace_bytes(int64_t n_rows, int64_t nnz, const cgx_opts *opts);
 

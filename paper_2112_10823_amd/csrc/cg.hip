@@ -2,12 +2,14 @@
 // optional Jacobi preconditioner, and binary32-inner iterative refinement as
 // in the mixed-precision reference cited beside CG) on gfx950.
 //
-// Each iteration is three kernels whose scalars never leave the GPU:
-//   (1) q = A p (CSR-stream tiles) fused with partials of p.q
+// Each iteration is three phases whose scalars never leave the GPU:
+//   (1) q = A p (one wave tile per 64-thread workgroup) fused with one p.q
+//       partial per tile; for more tiles than partial slots, a small kernel
+//       adds the tile partials in fixed slices
 //   (2) alpha = rho / p.q, x += alpha p, r -= alpha q, [z = D^-1 r], partials
 //       of r.r [and r.z]
 //   (3) stopping test, beta = rho' / rho, p = z + beta p
-// Every workgroup of (2) and (3) adds the previous kernel's partials itself,
+// Every workgroup of (2) and (3) adds the previous phase's partials itself,
 // in the same order, so all of them hold bit-identical scalars without any
 // grid-wide synchronisation inside a kernel; workgroup 0 records the state.
 // The kernels are templated on the working precision: float64 for the plain
@@ -25,7 +27,9 @@
 namespace cgx {
 namespace {
 
-constexpr int kSB = kStreamBlock;    // threads per workgroup of the SpMV phase
+constexpr int kSB = kStreamBlock;    // threads per workgroup of the CSR-stream pass (true residual)
+constexpr int kRB = 256;             // threads per workgroup of the p.q tile-partial reduction
+constexpr int kMinTilesPerRed = 512; // tile partials per reduction workgroup, at least
 constexpr int kPB = 512;             // threads per workgroup of the other phase kernels
 constexpr int kSpmvBlocksPerCu = 8;
 constexpr int kPhaseBlocksPerCu = 4;
@@ -57,14 +61,18 @@ struct CgArgs {
     T *z;     // == r without preconditioner
     T *dinv;  // nullptr without preconditioner
     T *partials;  // kPRegions * kMaxPhaseBlocks values
+    T *tpart;     // p.q partial of each SpMV wave tile (region kPPq itself when it fits)
     CgState *st;
-    int tiles_per_block;  // SpMV phases: row tiles per workgroup
-    int grid_sp;          // workgroups of the SpMV phase (partials it writes)
+    int ntiles;           // wave tiles of the SpMV phase (= its workgroups)
+    int tiles_per_red;    // tile partials added by one reduction workgroup
+    int n_pq;             // p.q partials in region kPPq
+    int tiles_per_block;  // CSR-stream pass: row tiles per workgroup
+    int grid_sp;          // workgroups of the CSR-stream pass (partials it writes)
     int grid_ew;          // workgroups of the update phase
 };
 
 template <typename T>
-__device__ __forceinline__ T *region(const CgArgs<T> &a, int r)
+__host__ __device__ __forceinline__ T *region(const CgArgs<T> &a, int r)
 {
     return a.partials + (int64_t)r * kMaxPhaseBlocks;
 }
@@ -175,30 +183,36 @@ __global__ __launch_bounds__(kPB) void cg_init_finish_kernel(CgArgs<double> a, i
     if (threadIdx.x == 0) finish_init(a.st, rr, rz, bb, rtol2, jac != 0);
 }
 
-// (1) q = A p by CSR-stream tiles, and the partials of p.q.
+// (1) q = A p, one wave tile per workgroup, and the tile's partial of p.q.
 template <int RT, typename T>
-__global__ __launch_bounds__(kSB) void cg_spmv_kernel(CgArgs<T> a)
+__global__ __launch_bounds__(kWave) void cg_spmv_kernel(CgArgs<T> a)
 {
     if (a.st->done) return;
-    __shared__ StreamSmem<kSB, stream_e<T>(), RT, T> sm;
-    const int ntiles = (a.n + RT - 1) / RT;
-    int t0, t1;
-    tile_range(ntiles, a.tiles_per_block, t0, t1);
+    __shared__ WaveSmem<wave_e<T>(), RT, T> sm;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    int row;
+    const T acc = wave_rows<wave_e<T>(), RT, 4, T>(tile * RT, a.n, a.n_cols, a.nnz, a.rp, a.ci,
+                                                   a.val, a.p, sm, row);
     T part = T(0);
-    for (int t = t0; t < t1; ++t) {
-        int row;
-        const T acc =
-            stream_rows<kSB, stream_e<T>(), RT, T>(t * RT, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val,
-                                              a.p, sm, row);
-        if (threadIdx.x % (kSB / RT) == 0 && row < a.n) {
-            a.q[row] = acc;
-            part += a.p[row] * acc;
-        }
+    if (threadIdx.x % (kWave / RT) == 0 && row < a.n) {
+        a.q[row] = acc;
+        part = a.p[row] * acc;
     }
-    __shared__ T red[kSB / kWave];
-    T v[1] = {part};
-    block_sum<1, kSB>(v, red);
-    if (threadIdx.x == 0) region(a, kPPq)[blockIdx.x] = v[0];
+    part = wave_sum(part);
+    if (threadIdx.x == 0) a.tpart[tile] = part;
+}
+
+// (1b) Workgroup b adds tile partials [b * tiles_per_red, ...) in index order
+// into slot b of region kPPq.
+template <typename T>
+__global__ __launch_bounds__(kRB) void cg_pq_reduce_kernel(CgArgs<T> a)
+{
+    if (a.st->done) return;
+    const int t0 = blockIdx.x * a.tiles_per_red;
+    const int count = max(0, min(a.tiles_per_red, a.ntiles - t0));
+    __shared__ T red[kRB / kWave];
+    const T s = sum_partials<kRB>(a.tpart + t0, count, red);
+    if (threadIdx.x == 0) region(a, kPPq)[blockIdx.x] = s;
 }
 
 // (2) alpha = rho / p.q (every workgroup adds the p.q partials in the same
@@ -210,7 +224,7 @@ __global__ __launch_bounds__(kPB) void cg_update_kernel(CgArgs<T> a)
     CgState *st = a.st;
     if (st->done) return;
     __shared__ T red[kPB / kWave];
-    const T pq = sum_partials<kPB>(region(a, kPPq), a.grid_sp, red);
+    const T pq = sum_partials<kPB>(region(a, kPPq), a.n_pq, red);
     const T rho = (T)st->rho;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (!isfinite(pq) || !(pq > T(0))) {
@@ -625,10 +639,17 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 // Mixed: outer state | inner state | r64 | r32 p32 q32 [z32 dinv32] | d32 | partials.
 struct Layout {
     size_t state = 0, state2 = 0, r64 = 0, r = 0, p = 0, q = 0, z = 0, dinv = 0, d = 0;
-    size_t partials = 0, total = 0;
+    size_t partials = 0, tpart = 0, total = 0;
 };
 
-Layout make_layout(int64_t n, bool jac, bool mixed)
+// Wave tiles of the SpMV phase for a system of n rows and nnz entries.
+int64_t spmv_tiles(int64_t n, int64_t nnz, bool mixed)
+{
+    const int rt = wave_tile_rows(n, nnz, mixed ? wave_e<float>() : wave_e<double>());
+    return (n + rt - 1) / rt;
+}
+
+Layout make_layout(int64_t n, int64_t nnz, bool jac, bool mixed)
 {
     Layout L;
     size_t off = 0;
@@ -660,6 +681,8 @@ Layout make_layout(int64_t n, bool jac, bool mixed)
     }
     L.partials = off;
     off += align_up((size_t)kPRegions * kMaxPhaseBlocks * sizeof(double));
+    L.tpart = off;
+    off += align_up((size_t)std::max<int64_t>(spmv_tiles(n, nnz, mixed), 1) * sizeof(double));
     L.total = off;
     return L;
 }
@@ -675,30 +698,60 @@ Layout make_layout(int64_t n, bool jac, bool mixed)
     }
 
 struct Grids {
-    int L;        // lanes per row of the vector-CSR setup passes
-    int RT;       // rows per CSR-stream tile
-    int grid_sp;  // workgroups of the SpMV phase (persistent over tiles)
-    int grid_ew;  // workgroups of the elementwise phases
-    int grid_vr;  // workgroups of the vector-CSR setup passes
+    int L;              // lanes per row of the vector-CSR setup passes
+    int RT;             // rows per wave tile of the SpMV phase
+    int ntiles;         // wave tiles (= workgroups) of the SpMV phase
+    int grid_red;       // workgroups of the p.q reduction, 0 when the tiles write region kPPq
+    int tiles_per_red;  // tile partials per reduction workgroup
+    int n_pq;           // p.q partials the update phase adds
+    int RTs;            // rows per CSR-stream tile (true-residual pass)
+    int grid_sp;        // workgroups of the CSR-stream pass (persistent over tiles)
     int tiles_per_block;
+    int grid_ew;        // workgroups of the elementwise phases
+    int grid_vr;        // workgroups of the vector-CSR setup passes
 };
 
-Grids make_grids(const Context *c, int64_t n, int64_t nnz, int entries = kStreamE)
+Grids make_grids(const Context *c, int64_t n, int64_t nnz, bool mixed)
 {
     Grids g{};
     g.L = lanes_per_row(n, nnz);
-    g.RT = stream_tile_rows(n, nnz, entries);
+    g.RT = wave_tile_rows(n, nnz, mixed ? wave_e<float>() : wave_e<double>());
+    g.ntiles = (int)std::max<int64_t>(1, (n + g.RT - 1) / g.RT);
+    if (g.ntiles <= kMaxPhaseBlocks) {
+        g.grid_red = 0;
+        g.tiles_per_red = 0;
+        g.n_pq = g.ntiles;
+    } else {
+        const int64_t per = (g.ntiles + kMaxPhaseBlocks - 1) / kMaxPhaseBlocks;
+        g.tiles_per_red = (int)std::max<int64_t>(kMinTilesPerRed, per);
+        g.grid_red = (int)((g.ntiles + g.tiles_per_red - 1) / g.tiles_per_red);
+        g.n_pq = g.grid_red;
+    }
+    g.RTs = stream_tile_rows(n, nnz, kStreamE);
     const int cap = std::min(c->num_cu * kPhaseBlocksPerCu, kMaxPhaseBlocks);
     const int cap_sp = std::min(c->num_cu * kSpmvBlocksPerCu, kMaxPhaseBlocks);
-    const int64_t ntiles = (n + g.RT - 1) / g.RT;
-    g.grid_sp = (int)std::max<int64_t>(1, std::min<int64_t>(cap_sp, ntiles));
-    g.tiles_per_block = (int)((ntiles + g.grid_sp - 1) / g.grid_sp);
+    const int64_t stiles = (n + g.RTs - 1) / g.RTs;
+    g.grid_sp = (int)std::max<int64_t>(1, std::min<int64_t>(cap_sp, stiles));
+    g.tiles_per_block = (int)((stiles + g.grid_sp - 1) / g.grid_sp);
     const int64_t ew_need = (n + kPB - 1) / kPB;
     g.grid_ew = (int)std::max<int64_t>(1, std::min<int64_t>(cap, ew_need));
     const int RPB = (kPB / g.L) * kRowsPerGroup;
     const int64_t vr_tiles = (n + RPB - 1) / RPB;
     g.grid_vr = (int)std::max<int64_t>(1, std::min<int64_t>(cap, vr_tiles));
     return g;
+}
+
+// Fills the launch-shape fields of a and points tpart at the tile partials.
+template <typename T>
+void bind_grids(const Grids &g, CgArgs<T> &a, void *tpart_ws)
+{
+    a.ntiles = g.ntiles;
+    a.tiles_per_red = g.tiles_per_red;
+    a.n_pq = g.n_pq;
+    a.tiles_per_block = g.tiles_per_block;
+    a.grid_sp = g.grid_sp;
+    a.grid_ew = g.grid_ew;
+    a.tpart = g.grid_red > 0 ? static_cast<T *>(tpart_ws) : region(a, kPPq);
 }
 
 void launch_init(const Grids &g, bool jac, hipStream_t s, const CgArgs<double> &a, double rtol2)
@@ -715,12 +768,19 @@ void launch_init(const Grids &g, bool jac, hipStream_t s, const CgArgs<double> &
 }
 
 template <typename T>
-void launch_spmv_phase(const Grids &g, hipStream_t s, const CgArgs<T> &a)
+void launch_spmv_kernel(const Grids &g, hipStream_t s, const CgArgs<T> &a)
 {
 #define CGX_SP(RR) \
-    hipLaunchKernelGGL((cg_spmv_kernel<RR, T>), dim3(g.grid_sp), dim3(kSB), 0, s, a)
-    CGX_RT_SWITCH(g.RT, CGX_SP)
+    hipLaunchKernelGGL((cg_spmv_kernel<RR, T>), dim3(g.ntiles), dim3(kWave), 0, s, a)
+    CGX_WRT_SWITCH(g.RT, CGX_SP)
 #undef CGX_SP
+}
+
+template <typename T>
+void launch_pq_reduce(const Grids &g, hipStream_t s, const CgArgs<T> &a)
+{
+    if (g.grid_red > 0)
+        hipLaunchKernelGGL((cg_pq_reduce_kernel<T>), dim3(g.grid_red), dim3(kRB), 0, s, a);
 }
 
 template <typename T>
@@ -744,7 +804,8 @@ void launch_direction_phase(const Grids &g, bool jac, hipStream_t s, const CgArg
 template <typename T>
 void launch_iteration(const Grids &g, bool jac, hipStream_t s, const CgArgs<T> &a)
 {
-    launch_spmv_phase<T>(g, s, a);
+    launch_spmv_kernel<T>(g, s, a);
+    launch_pq_reduce<T>(g, s, a);
     launch_update_phase<T>(g, jac, s, a);
     launch_direction_phase<T>(g, jac, s, a);
 }
@@ -753,7 +814,7 @@ void launch_true_residual(const Grids &g, hipStream_t s, const CgArgs<double> &a
 {
 #define CGX_TR(RR) \
     hipLaunchKernelGGL((cg_true_residual_kernel<RR>), dim3(g.grid_sp), dim3(kSB), 0, s, a)
-    CGX_RT_SWITCH(g.RT, CGX_TR)
+    CGX_RT_SWITCH(g.RTs, CGX_TR)
 #undef CGX_TR
     hipLaunchKernelGGL(cg_true_residual_finish_kernel, dim3(1), dim3(kPB), 0, s, a, g.grid_sp);
 }
@@ -869,13 +930,13 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
 {
     const int64_t n = A->n_rows;
     const bool jac = o->precond == CGX_PRECOND_JACOBI;
-    const Layout lay = make_layout(n, jac, false);
+    const Layout lay = make_layout(n, A->nnz, jac, false);
     if (ws_bytes < lay.total) {
         set_error("workspace too small: need " + std::to_string(lay.total) + " bytes");
         return CGX_ENOMEM;
     }
     char *w = static_cast<char *>(ws);
-    const Grids g = make_grids(c, n, A->nnz);
+    const Grids g = make_grids(c, n, A->nnz, false);
     CgArgs<double> a{};
     a.n = (int)n;
     a.n_cols = A->n_cols;
@@ -892,9 +953,7 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
     a.dinv = jac ? reinterpret_cast<double *>(w + lay.dinv) : nullptr;
     a.partials = reinterpret_cast<double *>(w + lay.partials);
     a.st = reinterpret_cast<CgState *>(w + lay.state);
-    a.tiles_per_block = g.tiles_per_block;
-    a.grid_sp = g.grid_sp;
-    a.grid_ew = g.grid_ew;
+    bind_grids(g, a, w + lay.tpart);
 
     const int maxit = o->maxit > 0 ? o->maxit : (int)std::min<int64_t>(n > 0 ? n : 1, 0x7fffffff);
     const double rtol2 = o->rtol * o->rtol;
@@ -912,14 +971,17 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
         launch_init(g, jac, s, a, rtol2);
         CGX_HIP_CHECK(hipGetLastError());
         if (o->profile) {
-            // One iteration at a time with events around each phase kernel;
-            // only iterations that ran all three phases are averaged.
+            // One iteration at a time with events around each phase; the
+            // first interval is the SpMV kernel alone, the second the p.q
+            // reduction (if any) and the update.  Only iterations that ran
+            // all phases are averaged.
             double tot[3] = {0.0, 0.0, 0.0};
             int counted = 0;
             for (int it = 0; it < maxit + 1; ++it) {
                 CGX_HIP_CHECK(hipEventRecord(c->ev_phase[0], s));
-                launch_spmv_phase<double>(g, s, a);
+                launch_spmv_kernel<double>(g, s, a);
                 CGX_HIP_CHECK(hipEventRecord(c->ev_phase[1], s));
+                launch_pq_reduce<double>(g, s, a);
                 launch_update_phase<double>(g, jac, s, a);
                 CGX_HIP_CHECK(hipEventRecord(c->ev_phase[2], s));
                 launch_direction_phase<double>(g, jac, s, a);
@@ -944,7 +1006,7 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
                                       (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)ws,
                                       (uint64_t)n, (uint64_t)A->nnz, (uint64_t)A->n_cols,
                                       (uint64_t)(jac ? 1 : 0), (uint64_t)K,
-                                      ((uint64_t)g.grid_sp << 32) | (uint64_t)g.grid_ew};
+                                      ((uint64_t)g.n_pq << 32) | (uint64_t)g.grid_ew};
             const int64_t max_replays = (int64_t)maxit / K + 2;
             rc = replay_until_done<double>(c, c->graph64, key, K, g, jac, s, a, max_replays);
             if (rc) return rc;
@@ -979,13 +1041,13 @@ int run_mixed(Context *c, const cgx_csr *A, const double *b, double *x, void *ws
 {
     const int64_t n = A->n_rows;
     const bool jac = o->precond == CGX_PRECOND_JACOBI;
-    const Layout lay = make_layout(n, jac, true);
+    const Layout lay = make_layout(n, A->nnz, jac, true);
     if (ws_bytes < lay.total) {
         set_error("workspace too small: need " + std::to_string(lay.total) + " bytes");
         return CGX_ENOMEM;
     }
     char *w = static_cast<char *>(ws);
-    const Grids g = make_grids(c, n, A->nnz, stream_e<float>());
+    const Grids g = make_grids(c, n, A->nnz, true);
 
     MxArgs m{};
     m.n = (int)n;
@@ -1017,9 +1079,7 @@ int run_mixed(Context *c, const cgx_csr *A, const double *b, double *x, void *ws
     in.dinv = m.dinv32;
     in.partials = reinterpret_cast<float *>(w + lay.partials);
     in.st = reinterpret_cast<CgState *>(w + lay.state2);
-    in.tiles_per_block = g.tiles_per_block;
-    in.grid_sp = g.grid_sp;
-    in.grid_ew = g.grid_ew;
+    bind_grids(g, in, w + lay.tpart);
 
     const int max_outer = o->max_outer > 0 ? o->max_outer : 100;
     const int inner_maxit =
@@ -1040,7 +1100,7 @@ int run_mixed(Context *c, const cgx_csr *A, const double *b, double *x, void *ws
                               (uint64_t)(uintptr_t)in.val, (uint64_t)(uintptr_t)ws,
                               (uint64_t)n, (uint64_t)A->nnz, (uint64_t)A->n_cols,
                               (uint64_t)(jac ? 1 : 0), (uint64_t)K,
-                              ((uint64_t)g.grid_sp << 32) | (uint64_t)g.grid_ew, 0x4d58ull, 0};
+                              ((uint64_t)g.n_pq << 32) | (uint64_t)g.grid_ew, 0x4d58ull, 0};
     int64_t inner_total = 0;
     int status = CGX_NOT_CONVERGED;
     for (int step = 0; step <= max_outer + 1; ++step) {
@@ -1094,12 +1154,12 @@ int run_mixed(Context *c, const cgx_csr *A, const double *b, double *x, void *ws
 
 }  // namespace
 
-size_t cg_workspace_bytes(int64_t n, int64_t /*nnz*/, const cgx_opts *o)
+size_t cg_workspace_bytes(int64_t n, int64_t nnz, const cgx_opts *o)
 {
     if (n < 0) return 0;
     const bool jac = o && o->precond == CGX_PRECOND_JACOBI;
     const bool mixed = o && o->precision == CGX_PRECISION_MIXED;
-    return make_layout(n, jac, mixed).total;
+    return make_layout(n, nnz, jac, mixed).total;
 }
 
 int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,

@@ -1,6 +1,6 @@
 // Device building blocks for gfx950: wave64 reductions, XCD-aware block
-// numbering, the vector-CSR and CSR-stream row bodies and the fixed-order sum
-// of per-workgroup partials.
+// numbering, the vector-CSR, CSR-stream and wave-tile row bodies and the
+// fixed-order sum of per-workgroup partials.
 //
 // Grid-wide sums never use a per-workgroup device-scope fence (on this
 // multi-die part such a release writes back the die's L2 and halved the
@@ -223,6 +223,110 @@ __device__ __forceinline__ T stream_rows(int row0, int n_rows, int n_cols, int64
         const int lo = max(s, c0), hi = min(e, c0 + C);
         for (int k = lo + sub; k < hi; k += TPR) acc += sm.prod[k - c0];
         __syncthreads();
+    }
+    return group_sum<TPR>(acc);
+}
+
+// ---------------------------------------------------------- wave CSR rows --
+
+// Wave-local barrier for LDS data exchanged between the lanes of one wave:
+// orders the wave's LDS accesses around it (no workgroup barrier needed).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS staging of one wave tile: a chunk of 64 * E column indices and values
+// and the tile's RT + 1 row starts.
+template <int E, int RT, typename T>
+struct WaveSmem {
+    T val[kWave * E];
+    int col[kWave * E];
+    int rp[RT + 1];
+};
+
+// Wave tile: one wavefront computes RT consecutive rows starting at row0.
+// Phase 1 reads the tile's col_idx / val as one contiguous stream (lane l
+// takes entries c0 + l + 64 j, j < E, non-temporal: each entry is used once)
+// and stages them in LDS.  Phase 2 gives each row TPR = 64 / RT lanes; lane
+// `sub` walks entries sub, sub + TPR, ... of its row, U at a time, gathering
+// x[col].  At each step the lanes of a wave hold the same entry position of
+// 64 / TPR neighbouring rows, so for banded / stencil matrices their gathers
+// fall on a few cache lines instead of one line per row.  The TPR lanes then
+// combine by butterfly.  A tile with more than 64 * E entries is processed in
+// several chunks.  Returns the row sum in all TPR lanes of the row's group;
+// `row` receives the row index (>= n_rows for idle groups).  Indices are
+// clamped as in vector_rows.  Must be reached by all 64 lanes of the wave.
+template <int E, int RT, int U, typename T>
+__device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t nnz,
+                                       const int32_t *__restrict__ rp,
+                                       const int32_t *__restrict__ ci,
+                                       const T *__restrict__ val, const T *__restrict__ x,
+                                       WaveSmem<E, RT, T> &sm, int &row)
+{
+    constexpr int TPR = kWave / RT;
+    constexpr int C = kWave * E;
+    static_assert(RT >= 1 && RT <= kWave && (RT & (RT - 1)) == 0, "rows per wave tile");
+    const int lane = threadIdx.x % kWave;
+    const int nr = min(RT, n_rows - row0);
+    wave_lds_sync();  // earlier readers of sm are done
+    for (int i = lane; i <= nr; i += kWave) {
+        int v = rp[row0 + i];
+        v = v < 0 ? 0 : (v > nnz ? (int)nnz : v);
+        sm.rp[i] = v;
+    }
+    wave_lds_sync();
+    const int k0 = sm.rp[0];
+    const int k1 = max(k0, sm.rp[nr]);
+    const int g = lane / TPR, sub = lane % TPR;
+    row = row0 + g;
+    int s = k0, e = k0;
+    if (g < nr) {
+        s = max(sm.rp[g], k0);
+        e = min(max(sm.rp[g + 1], s), k1);
+    }
+    T acc = T(0);
+    for (int c0 = k0; c0 < k1; c0 += C) {
+        int col[E];
+        T a[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int k = c0 + lane + kWave * j;
+            col[j] = -1;
+            a[j] = T(0);
+            if (k < k1) {  // streamed once: non-temporal, keeps x resident in L2
+                col[j] = __builtin_nontemporal_load(&ci[k]);
+                a[j] = __builtin_nontemporal_load(&val[k]);
+            }
+        }
+        wave_lds_sync();  // the previous chunk's readers are done
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            sm.col[lane + kWave * j] = col[j];
+            sm.val[lane + kWave * j] = a[j];
+        }
+        wave_lds_sync();
+        const int lo = max(s, c0) - c0, hi = min(e, c0 + C) - c0;
+        for (int k = lo + sub; k < hi; k += U * TPR) {
+            int cc[U];
+            T vv[U], xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int kk = k + u * TPR;
+                cc[u] = -1;
+                vv[u] = T(0);
+                if (kk < hi) {
+                    cc[u] = sm.col[kk];
+                    vv[u] = sm.val[kk];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = (unsigned)cc[u] < (unsigned)n_cols ? x[cc[u]] : T(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += vv[u] * xv[u];
+        }
     }
     return group_sum<TPR>(acc);
 }

@@ -43,15 +43,30 @@ constexpr int kReduceBlocks = 1024; // fixed grid of the standalone reductions
 constexpr int kStreamBlock = 256;   // threads per workgroup of the CSR-stream SpMV
 constexpr int kStreamE = 8;         // float64 entries per thread per CSR-stream chunk
 
-// Entries per thread per chunk for value type T: 64 bytes of values in flight
-// per thread (8 float64 or 16 binary32), the same LDS footprint either way.
-template <typename T>
-constexpr int stream_e() { return 64 / (int)sizeof(T); }
-
 // Rows per CSR-stream tile: the largest power of two in [8, kStreamBlock] whose
 // expected entries (rows * mean row length) fill at most 90% of one chunk of
 // kStreamBlock * kStreamE entries.
 int stream_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_thread = kStreamE);
+
+// Wave tiles (one wavefront per tile, 64 * E entries per chunk): E = 8
+// float64 or 16 binary32 entries per lane, as for the CSR-stream tiles.
+template <typename T>
+constexpr int wave_e() { return 64 / (int)sizeof(T); }
+
+// Rows per wave tile: the largest power of two in [1, 64] whose expected
+// entries fill at most 90% of one chunk of 64 * entries_per_lane entries.
+int wave_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_lane);
+
+#define CGX_WRT_SWITCH(RT, EXPR_T)    \
+    switch (RT) {                     \
+        case 1: EXPR_T(1); break;     \
+        case 2: EXPR_T(2); break;     \
+        case 4: EXPR_T(4); break;     \
+        case 8: EXPR_T(8); break;     \
+        case 16: EXPR_T(16); break;   \
+        case 32: EXPR_T(32); break;   \
+        default: EXPR_T(64); break;   \
+    }
 
 #define CGX_RT_SWITCH(RT, EXPR_T)     \
     switch (RT) {                     \

@@ -2,47 +2,50 @@
 // with CSR format", storage of Section 2.3) for gfx950, float64 and float32,
 // plus the structural validation kernel.
 //
-// CSR-stream layout: a 256-thread workgroup owns a tile of RT consecutive
-// rows (RT from the mean row length, so a tile's entries fill one chunk of
-// 256 x 8).  The tile's col_idx / val are read as one contiguous stream with
-// eight independent coalesced non-temporal loads per thread, the products are
-// staged in LDS and 256 / RT threads add each row.  Small workgroups keep
-// eight tiles per CU in different phases (load / reduce), which measured
-// faster than 512-thread tiles with the same bytes per thread.  Workgroups are renumbered per die
-// (xcd_block) so the x gathers of neighbouring rows hit the same L2.
+// Wave-tile layout: each 64-thread workgroup (one wavefront) owns a tile of
+// RT consecutive rows, RT from the mean row length so that a tile's entries
+// fill one chunk of 64 x 8 float64 (64 x 16 binary32) entries.  The tile's
+// col_idx / val are read as one contiguous stream with eight (sixteen)
+// independent coalesced non-temporal loads per lane and staged in LDS; then
+// 64 / RT lanes per row walk the row's entries in step, so that the x gathers
+// of neighbouring rows coalesce.  One tile per workgroup and many small
+// workgroups (the hardware keeps the waves of a die in dispatch order, a
+// compact moving front over x) measured faster than persistent workgroups
+// looping over tiles and than 256-thread tiles gathering in entry order.
+// Workgroups are renumbered per die (xcd_block) so the x gathers of
+// neighbouring rows hit the same L2.
 #include "cgx_device.h"
 
 namespace cgx {
 namespace {
 
 template <int RT, typename T>
-__global__ __launch_bounds__(kStreamBlock) void spmv_stream_kernel(int n_rows, int n_cols,
-                                                                    int64_t nnz,
-                                                                    const int32_t *__restrict__ rp,
-                                                                    const int32_t *__restrict__ ci,
-                                                                    const T *__restrict__ val,
-                                                                    const T *__restrict__ x,
-                                                                    T *__restrict__ y)
+__global__ __launch_bounds__(kWave) void spmv_wave_kernel(int n_rows, int n_cols, int64_t nnz,
+                                                          const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ ci,
+                                                          const T *__restrict__ val,
+                                                          const T *__restrict__ x,
+                                                          T *__restrict__ y)
 {
-    __shared__ StreamSmem<kStreamBlock, stream_e<T>(), RT, T> sm;
+    __shared__ WaveSmem<wave_e<T>(), RT, T> sm;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     int row;
-    const T acc = stream_rows<kStreamBlock, stream_e<T>(), RT, T>(tile * RT, n_rows, n_cols, nnz, rp, ci,
-                                                             val, x, sm, row);
-    if (threadIdx.x % (kStreamBlock / RT) == 0 && row < n_rows) y[row] = acc;
+    const T acc = wave_rows<wave_e<T>(), RT, 4, T>(tile * RT, n_rows, n_cols, nnz, rp, ci, val, x,
+                                                   sm, row);
+    if (threadIdx.x % (kWave / RT) == 0 && row < n_rows) y[row] = acc;
 }
 
 template <typename T>
 int launch_spmv_t(Context *c, const cgx_csr *A, const T *val, const T *x, T *y)
 {
     if (A->n_rows == 0) return CGX_OK;
-    const int RT = stream_tile_rows(A->n_rows, A->nnz, stream_e<T>());
+    const int RT = wave_tile_rows(A->n_rows, A->nnz, wave_e<T>());
     const int64_t grid = (A->n_rows + RT - 1) / RT;
 #define CGX_SPMV_CASE(RR)                                                                    \
-    hipLaunchKernelGGL((spmv_stream_kernel<RR, T>), dim3((unsigned)grid), dim3(kStreamBlock), \
-                       0, c->stream, A->n_rows, A->n_cols, A->nnz, A->row_ptr, A->col_idx, val,  \
-                       x, y)
-    CGX_RT_SWITCH(RT, CGX_SPMV_CASE)
+    hipLaunchKernelGGL((spmv_wave_kernel<RR, T>), dim3((unsigned)grid), dim3(kWave), 0,       \
+                       c->stream, A->n_rows, A->n_cols, A->nnz, A->row_ptr, A->col_idx, val, x, \
+                       y)
+    CGX_WRT_SWITCH(RT, CGX_SPMV_CASE)
 #undef CGX_SPMV_CASE
     CGX_HIP_CHECK(hipGetLastError());
     return CGX_OK;
@@ -86,6 +89,15 @@ int stream_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_thread)
     const double budget = 0.9 * kStreamBlock * entries_per_thread;
     int rt = kStreamBlock;
     while (rt > 8 && rt * (mean > 1.0 ? mean : 1.0) > budget) rt /= 2;
+    return rt;
+}
+
+int wave_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_lane)
+{
+    const double mean = n_rows > 0 ? (double)nnz / (double)n_rows : 1.0;
+    const double budget = 0.9 * kWave * entries_per_lane;
+    int rt = kWave;
+    while (rt > 1 && rt * (mean > 1.0 ? mean : 1.0) > budget) rt /= 2;
     return rt;
 }
 

@@ -110,6 +110,40 @@ def test_q1_tight_tolerance_matches_oracle_solution():
     assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
 
 
+def banded_spd(n, half_band):
+    """SPD by strict diagonal dominance: a_ij = -1 / (1 + |i - j|) inside the
+    band, a_ii = 1 + sum of the row's off-diagonal magnitudes."""
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        lo, hi = max(0, i - half_band), min(n, i + half_band + 1)
+        js = np.arange(lo, hi)
+        off = -1.0 / (1.0 + np.abs(js - i))
+        off[js == i] = 0.0
+        v = off.copy()
+        v[js == i] = 1.0 + np.abs(off).sum()
+        rows.append(np.full(js.size, i))
+        cols.append(js)
+        vals.append(v)
+    ci = np.concatenate(cols).astype(np.int32)
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum([c.size for c in cols])
+    return CSR(n, n, rp, ci, np.concatenate(vals))
+
+
+@pytest.mark.parametrize("n,half_band", [(20000, 2), (20000, 300)])
+def test_banded_long_rows_vs_oracle(n, half_band):
+    """Rows of 5 entries (64 rows per wave tile) and of up to 601 entries
+    (one row per wave tile, staged in two chunks)."""
+    A = banded_spd(n, half_band)
+    b = synth.uniform(31, n)
+    ref = oracle.cg(A, b, rtol=1e-10, jacobi=True)
+    st, x = solve(A, b, rtol=1e-10, precond=1, true_residual=True)
+    assert st.status == cgx.OK and st.path == 0
+    assert abs(st.iters - ref.iters) <= 2
+    assert true_relres(A, b, x) <= 1.5e-10
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+
+
 def test_nonzero_initial_guess():
     A = synth.q1cube(28, 1.0, seed=5)
     b = synth.uniform(6, A.n_rows)

@@ -68,7 +68,7 @@ def random_csr(seed, n_rows, n_cols, max_len, integer=False):
 
 @pytest.mark.parametrize("seed,n_rows,n_cols,max_len", [
     (0, 1, 1, 1), (1, 37, 50, 9), (2, 1000, 700, 30), (3, 5003, 5003, 70),
-    (4, 20000, 3000, 130), (5, 333, 100000, 3)])
+    (4, 20000, 3000, 130), (5, 333, 100000, 3), (6, 300, 9000, 5000)])
 def test_random_unsorted_rows_normwise(seed, n_rows, n_cols, max_len):
     A = random_csr(seed, n_rows, n_cols, max_len)
     assert oracle.csr_check(A.n_rows, A.n_cols, A.row_ptr, A.col_idx) == 0
@@ -77,6 +77,21 @@ def test_random_unsorted_rows_normwise(seed, n_rows, n_cols, max_len):
     assert normwise(y, oracle.spmv(A, x), A, x) <= 1e-13
     empty = np.diff(A.row_ptr) == 0
     assert np.all(y[empty] == 0) and not np.any(np.signbit(y[empty]))
+
+
+def test_skewed_rows_multi_chunk():
+    """A few rows far longer than one staged chunk among short rows."""
+    rng = np.random.default_rng(21)
+    n = 8000
+    lens = rng.integers(0, 12, n)
+    lens[[5, 6, 1700, n - 1]] = [2500, 0, 7000, 1300]
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum(lens)
+    ci = np.concatenate([rng.choice(n, l, replace=False) for l in lens]).astype(np.int32)
+    A = CSR(n, n, rp, ci, rng.uniform(-1, 1, ci.size))
+    x = synth.uniform(22, n)
+    y = run(A, x)
+    assert normwise(y, oracle.spmv(A, x), A, x) <= 1e-13
 
 
 def test_random_integer_exact():
