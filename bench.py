@@ -445,7 +445,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=300,
+                    help="Jacobi-CG iterations of the CPU oracle sample (about 10-15 s)")
     ap.add_argument("--profile-only", action="store_true",
                     help="warm-up plus a few solves, for profiler runs")
     ap.add_argument("--extras", default="",

@@ -86,7 +86,8 @@ int cgx_create(cgx_handle *out, int device, void *stream)
         if (e == hipSuccess) e = hipEventCreate(&c->ev1);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
-        for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev_phase[i]);
+        for (int i = 0; i < 4 * cgx::kProfWindow && e == hipSuccess; ++i)
+            e = hipEventCreate(&c->ev_phase[i]);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
             cgx::set_error(std::string("cgx_create: ") + hipGetErrorString(e));
@@ -113,7 +114,7 @@ int cgx_destroy(cgx_handle h)
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4 * cgx::kProfWindow; ++i)
         if (c->ev_phase[i]) (void)hipEventDestroy(c->ev_phase[i]);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     if (c->host_state) (void)hipHostFree(c->host_state);

@@ -187,12 +187,12 @@ __global__ __launch_bounds__(kPB) void cg_init_finish_kernel(CgArgs<double> a, i
 template <int RT, typename T>
 __global__ __launch_bounds__(kWave) void cg_spmv_kernel(CgArgs<T> a)
 {
-    if (a.st->done) return;
     __shared__ WaveSmem<wave_e<T>(), RT, T> sm;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     int row;
     const T acc = wave_rows<wave_e<T>(), RT, 4, T>(tile * RT, a.n, a.n_cols, a.nnz, a.rp, a.ci,
-                                                   a.val, a.p, sm, row);
+                                                   a.val, a.p, sm, row, &a.st->done);
+    if (row < 0) return;  // the solve has stopped
     T part = T(0);
     if (threadIdx.x % (kWave / RT) == 0 && row < a.n) {
         a.q[row] = acc;
@@ -207,11 +207,11 @@ __global__ __launch_bounds__(kWave) void cg_spmv_kernel(CgArgs<T> a)
 template <typename T>
 __global__ __launch_bounds__(kRB) void cg_pq_reduce_kernel(CgArgs<T> a)
 {
-    if (a.st->done) return;
     const int t0 = blockIdx.x * a.tiles_per_red;
     const int count = max(0, min(a.tiles_per_red, a.ntiles - t0));
     __shared__ T red[kRB / kWave];
-    const T s = sum_partials<kRB>(a.tpart + t0, count, red);
+    const T s = sum_partials<kRB>(a.tpart + t0, count, red);  // loads in flight with st->done's
+    if (a.st->done) return;
     if (threadIdx.x == 0) region(a, kPPq)[blockIdx.x] = s;
 }
 
@@ -222,9 +222,10 @@ template <bool kJac, typename T>
 __global__ __launch_bounds__(kPB) void cg_update_kernel(CgArgs<T> a)
 {
     CgState *st = a.st;
-    if (st->done) return;
     __shared__ T red[kPB / kWave];
+    // the partials' loads are in flight with those of the state fields
     const T pq = sum_partials<kPB>(region(a, kPPq), a.n_pq, red);
+    if (st->done) return;
     const T rho = (T)st->rho;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (!isfinite(pq) || !(pq > T(0))) {
@@ -277,10 +278,10 @@ template <bool kJac, typename T>
 __global__ __launch_bounds__(kPB) void cg_direction_kernel(CgArgs<T> a)
 {
     CgState *st = a.st;
-    if (st->done) return;
     __shared__ T red[kPB / kWave];
     const T rr = sum_partials<kPB>(region(a, kPRr), a.grid_ew, red);
     const T rz = kJac ? sum_partials<kPB>(region(a, kPRz), a.grid_ew, red) : rr;
+    if (st->done) return;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     int status = CGX_PENDING;
     if (!isfinite(rr) || !isfinite(rz))
@@ -971,31 +972,44 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
         launch_init(g, jac, s, a, rtol2);
         CGX_HIP_CHECK(hipGetLastError());
         if (o->profile) {
-            // One iteration at a time with events around each phase; the
-            // first interval is the SpMV kernel alone, the second the p.q
-            // reduction (if any) and the update.  Only iterations that ran
-            // all phases are averaged.
+            // Phase kernels launched one by one (no graph), back to back in
+            // windows of kProfWindow iterations, with events around each
+            // phase: the first interval is the SpMV kernel alone, the second
+            // the p.q reduction (if any) and the update, the third the p
+            // update.  Only iterations that ran all phases are averaged.
             double tot[3] = {0.0, 0.0, 0.0};
             int counted = 0;
-            for (int it = 0; it < maxit + 1; ++it) {
-                CGX_HIP_CHECK(hipEventRecord(c->ev_phase[0], s));
-                launch_spmv_kernel<double>(g, s, a);
-                CGX_HIP_CHECK(hipEventRecord(c->ev_phase[1], s));
-                launch_pq_reduce<double>(g, s, a);
-                launch_update_phase<double>(g, jac, s, a);
-                CGX_HIP_CHECK(hipEventRecord(c->ev_phase[2], s));
-                launch_direction_phase<double>(g, jac, s, a);
-                CGX_HIP_CHECK(hipEventRecord(c->ev_phase[3], s));
+            int iters_before = 0;
+            for (int64_t base = 0; base < (int64_t)maxit + 1; base += kProfWindow) {
+                const int cnt = (int)std::min<int64_t>(kProfWindow, (int64_t)maxit + 1 - base);
+                for (int i = 0; i < cnt; ++i) {
+                    hipEvent_t *e = c->ev_phase + 4 * i;
+                    CGX_HIP_CHECK(hipEventRecord(e[0], s));
+                    launch_spmv_kernel<double>(g, s, a);
+                    CGX_HIP_CHECK(hipEventRecord(e[1], s));
+                    launch_pq_reduce<double>(g, s, a);
+                    launch_update_phase<double>(g, jac, s, a);
+                    CGX_HIP_CHECK(hipEventRecord(e[2], s));
+                    launch_direction_phase<double>(g, jac, s, a);
+                    CGX_HIP_CHECK(hipEventRecord(e[3], s));
+                }
                 CGX_HIP_CHECK(hipMemcpyAsync(c->host_state, a.st, sizeof(CgState),
                                              hipMemcpyDeviceToHost, s));
                 CGX_HIP_CHECK(hipStreamSynchronize(s));
-                if (c->host_state->done) break;
-                for (int ph = 0; ph < 3; ++ph) {
-                    float ms = 0.0f;
-                    CGX_HIP_CHECK(hipEventElapsedTime(&ms, c->ev_phase[ph], c->ev_phase[ph + 1]));
-                    tot[ph] += ms;
-                }
-                ++counted;
+                const bool done = c->host_state->done != 0;
+                const int ran = c->host_state->iter - iters_before;
+                iters_before = c->host_state->iter;
+                // the iteration that set `done` skipped part of its work
+                const int full = done ? std::max(0, std::min(cnt, ran - 1)) : cnt;
+                for (int i = 0; i < full; ++i)
+                    for (int ph = 0; ph < 3; ++ph) {
+                        float ms = 0.0f;
+                        CGX_HIP_CHECK(hipEventElapsedTime(&ms, c->ev_phase[4 * i + ph],
+                                                          c->ev_phase[4 * i + ph + 1]));
+                        tot[ph] += ms;
+                    }
+                counted += full;
+                if (done) break;
             }
             for (int ph = 0; ph < 3; ++ph) st->phase_ms[ph] = counted ? tot[ph] / counted : 0.0;
         } else {

@@ -259,16 +259,21 @@ struct WaveSmem {
 // several chunks.  Returns the row sum in all TPR lanes of the row's group;
 // `row` receives the row index (>= n_rows for idle groups).  Indices are
 // clamped as in vector_rows.  Must be reached by all 64 lanes of the wave.
+// With a non-null `stop`, *stop is read together with the row starts (its
+// latency hidden behind theirs); if nonzero the tile is skipped: returns 0
+// with row = -1 in every lane.
 template <int E, int RT, int U, typename T>
 __device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t nnz,
                                        const int32_t *__restrict__ rp,
                                        const int32_t *__restrict__ ci,
                                        const T *__restrict__ val, const T *__restrict__ x,
-                                       WaveSmem<E, RT, T> &sm, int &row)
+                                       WaveSmem<E, RT, T> &sm, int &row,
+                                       const int *stop = nullptr)
 {
     constexpr int TPR = kWave / RT;
     constexpr int C = kWave * E;
     static_assert(RT >= 1 && RT <= kWave && (RT & (RT - 1)) == 0, "rows per wave tile");
+    const int halt = stop != nullptr ? *stop : 0;
     const int lane = threadIdx.x % kWave;
     const int nr = min(RT, n_rows - row0);
     wave_lds_sync();  // earlier readers of sm are done
@@ -276,6 +281,10 @@ __device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t
         int v = rp[row0 + i];
         v = v < 0 ? 0 : (v > nnz ? (int)nnz : v);
         sm.rp[i] = v;
+    }
+    if (halt) {
+        row = -1;
+        return T(0);
     }
     wave_lds_sync();
     const int k0 = sm.rp[0];

@@ -42,6 +42,7 @@ constexpr int kBlock = 256;         // threads per workgroup for streaming kerne
 constexpr int kReduceBlocks = 1024; // fixed grid of the standalone reductions
 constexpr int kStreamBlock = 256;   // threads per workgroup of the CSR-stream SpMV
 constexpr int kStreamE = 8;         // float64 entries per thread per CSR-stream chunk
+constexpr int kProfWindow = 32;     // profile mode: iterations launched between host checks
 
 // Rows per CSR-stream tile: the largest power of two in [8, kStreamBlock] whose
 // expected entries (rows * mean row length) fill at most 90% of one chunk of
@@ -124,7 +125,7 @@ struct Context {
     CgState *host_state = nullptr; // pinned host copy of the solver state
     hipEvent_t ev0 = nullptr, ev1 = nullptr;      // timing of a solve
     hipEvent_t ev_in = nullptr, ev_out = nullptr; // ordering between the two streams
-    hipEvent_t ev_phase[4] = {nullptr, nullptr, nullptr, nullptr}; // profile mode
+    hipEvent_t ev_phase[4 * kProfWindow] = {};  // profile mode: 4 per iteration of a window
     GraphSlot graph64;  // float64 CG iterations
     GraphSlot graph32;  // binary32 inner iterations of the refinement
     GraphSlot graph_batch;  // batched CG iterations
