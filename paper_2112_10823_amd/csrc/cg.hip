@@ -17,9 +17,10 @@
 // the refinement.  K iterations are captured once into a HIP graph and
 // replayed; the host reads one status word per replay.  After convergence
 // the remaining kernels of a replay see `done` and return at once.  Systems
-// of at most kSmallN rows run the whole float64 solve inside one 1024-thread
-// workgroup instead (one launch, workgroup barriers between phases): at that
-// size the cost is launches and grid synchronisation, not bandwidth.
+// of at most 4096 rows whose rows fit the register slots run the whole
+// float64 solve inside one 1024-thread workgroup with the matrix on chip
+// (one launch, workgroup barriers between phases): at that size the cost is
+// launches and grid synchronisation, not bandwidth.
 #include <cmath>
 
 #include "cgx_device.h"
@@ -36,8 +37,6 @@ constexpr int kPhaseBlocksPerCu = 4;
 constexpr int kMaxPhaseBlocks = 2048;
 constexpr int kRowsPerGroup = 4;     // vector-CSR rows per lane group (setup passes)
 constexpr int kSmallBlock = 1024;
-constexpr int kSmallRows = 2;
-constexpr int64_t kSmallN = 16384;
 
 // Partials of the grid-wide sums, one slot per workgroup of the phase grid.
 // Each producer writes its own region; consumers read regions written by
@@ -387,88 +386,181 @@ __device__ void small_finish_update(CgState *st, double rr, double rz)
     }
 }
 
-// ------------------------------------------- single-workgroup solve (small n) --
+// ------------------------------------ matrix-resident solve (n <= 4096) --
+//
+// One 1024-thread workgroup holds the whole system on chip for the solve:
+// thread t owns rows t + 1024 j (j < R) with their values in registers (row
+// j's entries in slots j * MAXE ...) and their column indices, as uint16, in
+// LDS; p lives in LDS too, and x, r, z, D^-1, q of the owned rows in
+// registers, and the solver state (rho, alpha, iteration count, status) in
+// LDS.  An iteration then touches no global memory: SpMV from registers and
+// LDS, three workgroup reductions, the p update in LDS.  A
+// system with a row longer than MAXE does not fit: the kernel stores
+// kStatusRetry before touching x and the host runs the phase kernels.
+// (R, MAXE) = (1, 16), (2, 8), (4, 7): at most 28 value slots per thread,
+// what the 128 registers of a 1024-thread workgroup hold beside the rest.
 
-template <int L, bool kJac>
-__global__ __launch_bounds__(kSmallBlock) void cg_small_kernel(CgArgs<double> a, double rtol2)
+constexpr int kStatusRetry = 2;
+constexpr int kResN = 4 * kSmallBlock;
+
+template <int R, int MAXE, bool kJac>
+__global__ __launch_bounds__(kSmallBlock) void cg_res_kernel(CgArgs<double> a, double rtol2)
 {
-    constexpr int BS = kSmallBlock, R = kSmallRows, RPB = (BS / L) * R;
+    constexpr int BS = kSmallBlock;
+    __shared__ double sp[R * BS];           // x0 during the setup, then p
+    __shared__ double sx[R * BS];           // x
+    __shared__ uint16_t cs[R * MAXE * BS];  // column of slot (j, e) of thread t
     __shared__ double red[3 * (BS / kWave)];
     __shared__ double sh_alpha, sh_beta;
     __shared__ int sh_done;
-    CgState *st = a.st;
-    const int n = a.n;
-
-    double p3[3] = {0.0, 0.0, 0.0};
-    for (int row0 = 0; row0 < n; row0 += RPB) {
-        double acc[R], dg[R];
-        int rows[R];
-        vector_rows<L, R, BS, double, kJac>(row0, n, a.n_cols, a.nnz, a.rp, a.ci, a.val, a.x, acc,
-                                            dg, rows);
-        if (threadIdx.x % L == 0)
+    __shared__ CgState sst;  // the solve's state, written back to a.st at exit
+    CgState *st = &sst;
+    const int n = a.n, t = threadIdx.x;
+    if (t == 0) sst = *a.st;
+    bool too_long = false;
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (rows[r] < n) init_row<kJac>(a, rows[r], acc[r], dg[r], p3);
+    for (int j = 0; j < R; ++j) {
+        const int i = t + BS * j;
+        if (i < n) too_long |= a.rp[i + 1] - a.rp[i] > MAXE;
     }
+    if (__syncthreads_or(too_long)) {
+        if (t == 0) {
+            a.st->status = kStatusRetry;
+            a.st->done = 1;
+        }
+        return;
+    }
+    // values to registers, columns to LDS; padding and out-of-range columns
+    // become (value 0, column 0), which adds 0 * p[0]
+    double v[R][MAXE], r[R], dv[R], q[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = t + BS * j;
+        int s0 = 0, s1 = 0;
+        if (i < n) {
+            s0 = a.rp[i];
+            s1 = a.rp[i + 1];
+            s0 = s0 < 0 ? 0 : (s0 > a.nnz ? (int)a.nnz : s0);
+            s1 = s1 < s0 ? s0 : (s1 > a.nnz ? (int)a.nnz : s1);
+        }
+        double d = 0.0;
+#pragma unroll
+        for (int e = 0; e < MAXE; ++e) {
+            const int k = s0 + e;
+            double vv = 0.0;
+            int c = 0;
+            if (k < s1) {
+                const int cc = a.ci[k];
+                if ((unsigned)cc < (unsigned)n) {
+                    vv = a.val[k];
+                    c = cc;
+                    if (cc == i) d = vv;
+                }
+            }
+            v[j][e] = vv;
+            cs[(j * MAXE + e) * BS + t] = (uint16_t)c;
+        }
+        dv[j] = d;
+        const double xi = i < n ? a.x[i] : 0.0;
+        sx[i] = xi;
+        sp[i] = xi;
+    }
+    __syncthreads();
+    auto spmv = [&](double (&acc)[R]) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int e = 0; e < MAXE; ++e) {
+                s += v[j][e] * sp[cs[(j * MAXE + e) * BS + t]];
+            }
+            acc[j] = s;
+        }
+    };
+    // r0 = b - A x0, z0 = D^-1 r0, p0 = z0 and the sums r.r, r.z, b.b
+    spmv(q);
+    double p3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = t + BS * j;
+        r[j] = 0.0;
+        if (i < n) {
+            const double bi = a.b[i];
+            r[j] = bi - q[j];
+            double zj = r[j];
+            if (kJac) {
+                double d = dv[j];
+                if (!(d > 0.0)) {
+                    st->bad = 1;
+                    d = 1.0;
+                }
+                dv[j] = 1.0 / d;
+                zj = dv[j] * r[j];
+            }
+            p3[0] += r[j] * r[j];
+            p3[1] += r[j] * zj;
+            p3[2] += bi * bi;
+        }
+    }
+    __syncthreads();  // every thread is done reading x0 from sp
+#pragma unroll
+    for (int j = 0; j < R; ++j) sp[t + BS * j] = kJac ? dv[j] * r[j] : r[j];
     block_sum<3, BS>(p3, red);
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         finish_init(st, p3[0], p3[1], p3[2], rtol2, kJac);
         sh_done = st->done;
     }
     __syncthreads();
 
     while (!sh_done) {
-        // (1) q = A p, p.q
+        // q = A p, p.q
+        spmv(q);
         double p1[1] = {0.0};
-        for (int row0 = 0; row0 < n; row0 += RPB) {
-            double acc[R], dg[R];
-            int rows[R];
-            vector_rows<L, R, BS, double, false>(row0, n, a.n_cols, a.nnz, a.rp, a.ci, a.val, a.p,
-                                                 acc, dg, rows);
-            if (threadIdx.x % L == 0)
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if (rows[r] < n) {
-                        a.q[rows[r]] = acc[r];
-                        p1[0] += a.p[rows[r]] * acc[r];
-                    }
-        }
+        for (int j = 0; j < R; ++j)
+            if (t + BS * j < n) p1[0] += sp[t + BS * j] * q[j];
         block_sum<1, BS>(p1, red);
-        if (threadIdx.x == 0) {
+        if (t == 0) {
             small_finish_pq(st, p1[0]);
             sh_done = st->done;
             sh_alpha = st->alpha;
         }
         __syncthreads();
         if (sh_done) break;
-        // (2) x, r, z updates and r.r, r.z
+        // x += alpha p, r -= alpha q, z = D^-1 r, r.r and r.z
         const double alpha = sh_alpha;
         double p2[2] = {0.0, 0.0};
-        for (int i = threadIdx.x; i < n; i += BS) {
-            const double xi = __builtin_fma(alpha, a.p[i], a.x[i]);
-            const double ri = __builtin_fma(-alpha, a.q[i], a.r[i]);
-            a.x[i] = xi;
-            a.r[i] = ri;
-            p2[0] += ri * ri;
-            if (kJac) {
-                const double zi = a.dinv[i] * ri;
-                a.z[i] = zi;
-                p2[1] += ri * zi;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = t + BS * j;
+            if (i < n) {
+                sx[i] = __builtin_fma(alpha, sp[i], sx[i]);
+                r[j] = __builtin_fma(-alpha, q[j], r[j]);
+                p2[0] += r[j] * r[j];
+                if (kJac) p2[1] += r[j] * (dv[j] * r[j]);
             }
         }
         block_sum<2, BS>(p2, red);
-        if (threadIdx.x == 0) {
+        if (t == 0) {
             small_finish_update(st, p2[0], kJac ? p2[1] : p2[0]);
             sh_done = st->done;
             sh_beta = st->beta;
         }
         __syncthreads();
         if (sh_done) break;
-        // (3) p = z + beta p
+        // p = z + beta p (each thread rewrites only its own rows)
         const double beta = sh_beta;
-        for (int i = threadIdx.x; i < n; i += BS) a.p[i] = __builtin_fma(beta, a.p[i], a.z[i]);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = t + BS * j;
+            if (i < n) sp[i] = __builtin_fma(beta, sp[i], kJac ? dv[j] * r[j] : r[j]);
+        }
         __syncthreads();
     }
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        if (t + BS * j < n) a.x[t + BS * j] = sx[t + BS * j];
+    if (t == 0) *a.st = sst;
 }
 
 // ------------------------------------------------ mixed-precision refinement --
@@ -820,17 +912,23 @@ void launch_true_residual(const Grids &g, hipStream_t s, const CgArgs<double> &a
     hipLaunchKernelGGL(cg_true_residual_finish_kernel, dim3(1), dim3(kPB), 0, s, a, g.grid_sp);
 }
 
-void launch_small(int L, bool jac, hipStream_t s, const CgArgs<double> &a, double rtol2)
+void launch_resident(bool jac, hipStream_t s, const CgArgs<double> &a, double rtol2)
 {
-#define CGX_SM(LL)                                                                            \
+#define CGX_RES(RR, EE)                                                                       \
     if (jac)                                                                                  \
-        hipLaunchKernelGGL((cg_small_kernel<LL, true>), dim3(1), dim3(kSmallBlock), 0, s, a,   \
+        hipLaunchKernelGGL((cg_res_kernel<RR, EE, true>), dim3(1), dim3(kSmallBlock), 0, s, a, \
                            rtol2);                                                            \
     else                                                                                      \
-        hipLaunchKernelGGL((cg_small_kernel<LL, false>), dim3(1), dim3(kSmallBlock), 0, s, a, \
-                           rtol2)
-    CGX_LANE_SWITCH(L, CGX_SM)
-#undef CGX_SM
+        hipLaunchKernelGGL((cg_res_kernel<RR, EE, false>), dim3(1), dim3(kSmallBlock), 0, s,   \
+                           a, rtol2)
+    if (a.n <= kSmallBlock) {
+        CGX_RES(1, 16);
+    } else if (a.n <= 2 * kSmallBlock) {
+        CGX_RES(2, 8);
+    } else {
+        CGX_RES(4, 7);
+    }
+#undef CGX_RES
 }
 
 void launch_mx_residual(const Grids &g, bool first, bool jac, hipStream_t s, const MxArgs &m,
@@ -914,7 +1012,7 @@ int zero_if_needed(Context *c, hipStream_t s, bool zero, int64_t n, double *x)
     }
     CGX_HIP_CHECK(hipEventRecord(c->ev_out, s));
     CGX_HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_out, 0));
-    CGX_HIP_CHECK(hipStreamSynchronize(s));
+    if (zero) CGX_HIP_CHECK(hipStreamSynchronize(s));  // else finish_solve has waited
     return CGX_OK;
 }
 
@@ -964,11 +1062,27 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
     if (rc) return rc;
     hipLaunchKernelGGL(cg_state_init_kernel, dim3(1), dim3(64), 0, s, a.st, maxit);
 
-    const bool small = n <= kSmallN;
+    bool small = n <= kResN;
+    CgState hs{};
+    float ms = 0.0f;
     if (small) {
-        launch_small(g.L, jac, s, a, rtol2);
+        launch_resident(jac, s, a, rtol2);
         CGX_HIP_CHECK(hipGetLastError());
-    } else {
+        if (!o->true_residual) {
+            rc = finish_solve(c, s, a.st, hs, ms);
+            if (rc) return rc;
+        } else {
+            CGX_HIP_CHECK(
+                hipMemcpyAsync(c->host_state, a.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            CGX_HIP_CHECK(hipStreamSynchronize(s));
+            hs = *c->host_state;
+        }
+        if (hs.status == kStatusRetry) {  // a row does not fit: phase kernels
+            small = false;
+            hipLaunchKernelGGL(cg_state_init_kernel, dim3(1), dim3(64), 0, s, a.st, maxit);
+        }
+    }
+    if (!small) {
         launch_init(g, jac, s, a, rtol2);
         CGX_HIP_CHECK(hipGetLastError());
         if (o->profile) {
@@ -1030,10 +1144,10 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
         launch_true_residual(g, s, a);
         CGX_HIP_CHECK(hipGetLastError());
     }
-    CgState hs{};
-    float ms = 0.0f;
-    rc = finish_solve(c, s, a.st, hs, ms);
-    if (rc) return rc;
+    if (!small || o->true_residual) {
+        rc = finish_solve(c, s, a.st, hs, ms);
+        if (rc) return rc;
+    }
     const bool zero_b = hs.bb == 0.0 && hs.status == CGX_OK;
     rc = zero_if_needed(c, s, zero_b, n, x);
     if (rc) return rc;

@@ -92,7 +92,7 @@ def test_q1_lognormal_vs_oracle(N, jacobi):
     ref = oracle.cg(A, b, rtol=1e-8, jacobi=jacobi)
     st, x = solve(A, b, rtol=1e-8, precond=int(jacobi), true_residual=True)
     assert st.status == cgx.OK
-    assert st.path == (1 if A.n_rows <= 16384 else 0)
+    assert st.path == 0  # above 4096 rows: phase kernels
     assert abs(st.iters - ref.iters) <= 2
     assert true_relres(A, b, x) <= 1.5e-8
     # error between the two solutions is bounded by the residual gap times kappa;
@@ -107,6 +107,28 @@ def test_q1_tight_tolerance_matches_oracle_solution():
     ref = oracle.cg(A, b, rtol=1e-13, jacobi=True)
     st, x = solve(A, b, rtol=1e-13, precond=1, maxit=5000)
     assert st.status == cgx.OK and st.path == 0
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+
+
+@pytest.mark.parametrize("kind,N,jacobi,x0", [
+    ("fd7", 8, True, False), ("fd7", 12, False, True), ("q1", 12, True, False),
+    ("q1", 16, True, True), ("q1", 16, False, False), ("fd7", 22, True, False)])
+def test_single_workgroup_paths_vs_oracle(kind, N, jacobi, x0):
+    """Systems of up to 4096 rows whose rows fit the register slots (1, 2 or 4
+    rows per thread, up to 16, 8 or 7 entries per row) run the whole solve in
+    one workgroup; the others (Q1 rows of 27 entries at 4096 rows, and all
+    systems above 4096 rows) fall back to the phase kernels."""
+    A = synth.fd7(N) if kind == "fd7" else synth.q1cube(N, 1.0, seed=synth.SEED_C2_COEFF)
+    b = synth.uniform(40 + N, A.n_rows)
+    x0v = synth.uniform(60 + N, A.n_rows) if x0 else None
+    ref = oracle.cg(A, b, x0=x0v, rtol=1e-12, jacobi=jacobi)
+    st, x = solve(A, b, x0=x0v, rtol=1e-12, precond=int(jacobi), true_residual=True)
+    max_row = int(np.diff(A.row_ptr).max())
+    fits = A.n_rows <= 4096 and max_row <= {1: 16, 2: 8}.get(-(-A.n_rows // 1024), 7)
+    assert st.status == cgx.OK and st.path == (1 if fits else 0)
+    assert abs(st.iters - ref.iters) <= 2
+    assert true_relres(A, b, x) <= 1.5e-12
+    # kappa < 1e3 here, so both solutions are within 2 kappa 1e-12 of x*
     assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
 
 
