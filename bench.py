@@ -410,13 +410,33 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
                 "ok": ok, "wall_s": round(wall, 2),
                 "j_per_solve": round((e1 - e0) / n_req, 3) if e0 is not None and e1 > e0 else None}
 
+    def sequential():
+        """The same requests solved one after another with the single-system
+        float64 solver (plain CG, the paper's method), no batching."""
+        h = cgx.Handle()
+        out = [torch.zeros_like(bs[k]) for k in picks]
+        wss = {k: cgx.cg_workspace(mats[k][1], opts) for k in set(picks.tolist())}
+        torch.cuda.synchronize()
+        e0 = meter.read()
+        t0 = time.perf_counter()
+        ok = 0
+        for i, k in enumerate(picks):
+            st = cgx.cg_solve(mats[k][1], bs[k], out[i], opts, workspace=wss[k], handle=h)
+            ok += st.status == cgx.OK
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e1 = meter.read()
+        return {"solves_per_s": round(n_req / wall, 2), "wall_s": round(wall, 2), "ok": ok,
+                "j_per_solve": round((e1 - e0) / n_req, 3) if e0 is not None and e1 > e0 else None}
+
     sat = run(0)  # all requests at once: saturation throughput
     rows = [sat]
     for f in (0.5, 0.8, 0.95):
         rows.append(run(f * sat["solves_per_s"]))
     return {"workload": f"{n_req} Poisson-arrival requests on {pool_systems} resident Q1 systems "
                         f"(rows lognormal in [1e4, 4e6]), lognormal(0,1), rtol 1e-8",
-            "rows": rows, "pool_rows": sorted(A.n_rows for A, _ in mats)}
+            "rows": rows, "one_at_a_time_fp64_cg": sequential(),
+            "pool_rows": sorted(A.n_rows for A, _ in mats)}
 
 
 def run_extras(which):

@@ -175,11 +175,15 @@ int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, voi
 
 /* One system of a batch: matrix, right-hand sides and solutions.  B and X
  * are device arrays of nrhs x n_rows float64, right-hand-side major (vector j
- * at B + j * n_rows); X holds the initial guesses on entry.  1 <= nrhs <= 16. */
+ * at B + j * n_rows); X holds the initial guesses on entry.  1 <= nrhs <= 16.
+ * schedule: 0 lets the autotuner pick the SpMM schedule; otherwise it is
+ * used as given: M > 0 gives K * M lanes per row (K = nrhs rounded up to a
+ * power of two; K * M must be 8, 16, 32 or 64), M < 0 gives wave tiles of
+ * -M rows per wavefront (nrhs = 1 only; -M a power of two <= 64). */
 typedef struct cgx_system {
     cgx_csr A;
     int32_t nrhs;
-    int32_t pad;
+    int32_t schedule;
     const double *B;
     double *X;
 } cgx_system;
@@ -193,8 +197,9 @@ size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems);
  * work table of (system, row tile) entries, the matrix of a system is read
  * once per iteration for all its right-hand sides, and each right-hand side
  * has its own scalars and stopping test (||r|| <= rtol ||b||).  The rows of
- * a system are served by K * M lanes, M chosen per shape class by a timing
- * autotuner kept in the handle.  A system's results do not depend on the
+ * a system are served by K * M lanes, or for one right-hand side possibly by
+ * wave tiles, the schedule chosen per shape class by a timing autotuner kept
+ * in the handle (unless the system fixes it).  A system's results do not depend on the
  * other systems in the batch.  stats: array of sum(nrhs) entries in
  * (system, right-hand side) order.  Returns CGX_OK if all converged, else
  * the first non-OK status; argument errors as usual.  opts->precision must
@@ -202,8 +207,10 @@ size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems);
 int cgx_cg_solve_batched(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
                          size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats);
 
-/* (sync) The slice count M the autotuner picks for each system (running the
- * tuning for shape classes not seen yet by this handle).  workspace as for
+/* (sync) The schedule each system of the batch runs with (its own
+ * `schedule` if nonzero, else the autotuner's pick, tuning shape classes not
+ * seen yet by this handle): M > 0 slices per right-hand side, M < 0 wave
+ * tiles of -M rows.  workspace as for
  * cgx_cg_solve_batched; M_out: host int32[nsys]. */
 int cgx_batch_schedule(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
                        size_t workspace_bytes, int32_t *M_out);

@@ -59,7 +59,7 @@ class Stats(ctypes.Structure):
 
 
 class _System(ctypes.Structure):
-    _fields_ = [("A", _Csr), ("nrhs", ctypes.c_int32), ("pad", ctypes.c_int32),
+    _fields_ = [("A", _Csr), ("nrhs", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("B", ctypes.c_void_p), ("X", ctypes.c_void_p)]
 
 
@@ -355,7 +355,9 @@ def _systems(items):
     """items: list of (DeviceCSR, B, X) with B, X float64 GPU tensors of shape
     (nrhs, n) (right-hand-side major, contiguous)."""
     arr = (_System * len(items))()
-    for i, (A, B, X) in enumerate(items):
+    for i, item in enumerate(items):
+        A, B, X = item[:3]
+        arr[i].schedule = int(item[3]) if len(item) > 3 else 0
         _dev_tensor(B, torch.float64, "B")
         _dev_tensor(X, torch.float64, "X")
         if B.dim() != 2 or B.shape != X.shape or B.shape[1] != A.n_rows:
@@ -378,26 +380,29 @@ def batch_workspace(items, device="cuda") -> torch.Tensor:
 
 def cg_solve_batched(items, opts: Opts | None = None, workspace=None, handle=None):
     """Solve every (system, right-hand side) of the batch in place on X.
+    items: (A, B, X) or (A, B, X, schedule) tuples, B and X (nrhs, n_rows).
     Returns a list with one Stats per system, each a list over its right-hand sides."""
     opts = opts or make_opts()
     arr = _systems(items)
     if workspace is None:
         workspace = batch_workspace(items)
-    nstat = sum(int(B.shape[0]) for _, B, _ in items)
+    nstat = sum(int(item[1].shape[0]) for item in items)
     st = (Stats * nstat)()
     rc = load_library().cgx_cg_solve_batched(_h(handle), len(items), arr, _ptr(workspace),
                                              workspace.numel(), ctypes.byref(opts), st)
     if rc in (EINVAL, ENOMEM, EHIP):
         _check(rc)
     out, k = [], 0
-    for _, B, _ in items:
-        out.append([st[k + j] for j in range(B.shape[0])])
-        k += B.shape[0]
+    for item in items:
+        nr = int(item[1].shape[0])
+        out.append([st[k + j] for j in range(nr)])
+        k += nr
     return out
 
 
 def batch_schedule(items, workspace=None, handle=None):
-    """Slice counts M picked by the autotuner for each system."""
+    """Schedule of each system: its own if fixed, else the autotuner's pick
+    (M > 0 slices per right-hand side, M < 0 wave tiles of -M rows)."""
     arr = _systems(items)
     if workspace is None:
         workspace = batch_workspace(items)

@@ -287,6 +287,18 @@ static int check_batch(cgx_handle h, int32_t nsys, const cgx_system *systems)
         CGX_REQUIRE(q.B != nullptr && q.X != nullptr, "NULL B or X");
         const size_t nb = (size_t)q.A.n_rows * q.nrhs * 8;
         CGX_REQUIRE(!overlaps(q.B, nb, q.X, nb), "X overlaps B");
+        if (q.schedule > 0) {
+            int K = 1;
+            while (K < q.nrhs) K *= 2;
+            const int64_t G = (int64_t)K * q.schedule;
+            CGX_REQUIRE(G == 8 || G == 16 || G == 32 || G == 64,
+                        "schedule M: K * M must be 8, 16, 32 or 64");
+        } else if (q.schedule < 0) {
+            const int rt = -q.schedule;
+            CGX_REQUIRE(q.nrhs == 1, "wave-tile schedule needs nrhs = 1");
+            CGX_REQUIRE(rt <= 64 && (rt & (rt - 1)) == 0,
+                        "wave-tile schedule: -M must be a power of two <= 64");
+        }
     }
     return CGX_OK;
 }

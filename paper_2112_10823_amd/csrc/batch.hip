@@ -135,6 +135,9 @@ BArgs make_args(const Plan &P, char *ws)
     a.ntiles = (int)P.tiles.size();
     a.part_stride = (int64_t)std::max<size_t>(P.tiles.size(), 1) * kMaxK;
     a.nlist = (int)P.sys.size();
+    a.wave_lds = 0;
+    for (const BSys &S : P.sys)
+        if (S.M < 0) a.wave_lds = kWaveStageBytes;
     return a;
 }
 
@@ -173,7 +176,7 @@ int tune_one(Context *c, const cgx_system &sys, void *ws, size_t ws_bytes, hipSt
     hipEvent_t e0 = nullptr, e1 = nullptr;
     CGX_HIP_CHECK(hipEventCreate(&e0));
     CGX_HIP_CHECK(hipEventCreate(&e1));
-    for (int M : m_candidates(K)) {
+    for (int M : m_candidates(K, sys.A.n_rows, sys.A.nnz)) {
         int Mv[1] = {M};
         Plan P;
         if (build_plan(1, &sys, Mv, nullptr, P) != CGX_OK || P.total > ws_bytes) continue;
@@ -186,10 +189,10 @@ int tune_one(Context *c, const cgx_system &sys, void *ws, size_t ws_bytes, hipSt
                            dim3(256), 0, s, a.scal, P.nscal, a.sys_done, 1);
         // p holds whatever the workspace held: only the time is used
         for (int rep = 0; rep < 2; ++rep)
-            hipLaunchKernelGGL(batch_spmm_kernel, dim3(a.ntiles), dim3(kBB), 0, s, a);
+            hipLaunchKernelGGL(batch_spmm_kernel, dim3(a.ntiles), dim3(kBB), a.wave_lds, s, a);
         CGX_HIP_CHECK(hipEventRecord(e0, s));
         for (int rep = 0; rep < 5; ++rep)
-            hipLaunchKernelGGL(batch_spmm_kernel, dim3(a.ntiles), dim3(kBB), 0, s, a);
+            hipLaunchKernelGGL(batch_spmm_kernel, dim3(a.ntiles), dim3(kBB), a.wave_lds, s, a);
         CGX_HIP_CHECK(hipEventRecord(e1, s));
         CGX_HIP_CHECK(hipEventSynchronize(e1));
         float ms = 0.0f;
@@ -212,6 +215,10 @@ int batch_autotune(Context *c, int32_t nsys, const cgx_system *in, void *ws, siz
 {
     Ms.assign(nsys, 0);
     for (int s = 0; s < nsys; ++s) {
+        if (in[s].schedule != 0) {  // fixed by the caller
+            Ms[s] = in[s].schedule;
+            continue;
+        }
         int rc = tune_one(c, in[s], ws, ws_bytes, c->own_stream, Ms[s]);
         if (rc) return rc;
     }

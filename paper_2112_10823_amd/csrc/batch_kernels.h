@@ -47,6 +47,7 @@ struct BArgs {
     int64_t part_stride;    // (tiles of the whole table) * 16
     int ntiles;
     int nlist;
+    int wave_lds;           // dynamic LDS bytes of the SpMM launch (wave-tile staging or 0)
 };
 
 namespace bk {
@@ -74,20 +75,24 @@ __device__ __forceinline__ void block_sum_by_rhs(double v, int K, double *red, d
     }
 }
 
+// Slices per row of the setup pass: the tuned M, or 8 lanes per row for
+// systems whose SpMM runs on wave tiles (M < 0).
+__device__ __forceinline__ int setup_m(const BSys &S) { return S.M > 0 ? S.M : 8; }
+
 // Row sum of one row for right-hand side j over nonzero slice m of M, using
 // interleaved vector v ([n][K]); combined over the M slices by butterfly.
 // Also returns the diagonal entry (summed the same way; one slice holds it).
 // The nonzero loop is unrolled four ways (four col/val loads, then four
 // gathers in flight per lane); the accumulation order is k, k + M, ... in
 // both the unrolled and the remainder part.
-__device__ __forceinline__ double row_spmm(const BSys &S, int row, int j, int m, double &diag,
-                                           const double *v)
+__device__ __forceinline__ double row_spmm(const BSys &S, int row, int j, int m, int M,
+                                           double &diag, const double *v)
 {
     int s = S.rp[row], e = S.rp[row + 1];
     s = clampk(s, S.nnz);
     e = clampk(e, S.nnz);
     if (e < s) e = s;
-    const int M = S.M, K = S.K;
+    const int K = S.K;
     double acc = 0.0, dg = 0.0;
     int k = s + m;
     for (; k + 3 * M < e; k += 4 * M) {
@@ -141,13 +146,14 @@ __global__ __launch_bounds__(kBB) void batch_init_kernel(BArgs a)
     const int w = xcd_block(blockIdx.x, gridDim.x);
     const BTile t = a.tiles[w];
     const BSys S = a.sys[t.sys];
-    const int G = S.K * S.M, gpw = kWave / G;
+    const int M = setup_m(S);
+    const int G = S.K * M, gpw = kWave / G;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
     double prr = 0.0, prz = 0.0, pbb = 0.0;
     for (int row = t.row0 + wave * gpw + grp; row < t.row0 + t.rows; row += (kBB / kWave) * gpw) {
         double dg;
-        const double ax = row_spmm(S, row, j, m, dg, S.x);
+        const double ax = row_spmm(S, row, j, m, M, dg, S.x);
         if (m == 0) {
             const int64_t e = (int64_t)row * S.K + j;
             const double bi = j < S.nrhs ? S.B[(int64_t)j * S.n + row] : 0.0;
@@ -232,25 +238,70 @@ __global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgs a)
     if (threadIdx.x == 0) a.sys_done[sid] = any_active ? 0 : 1;
 }
 
+// Single right-hand side on wave tiles: the four waves of the workgroup take
+// RT-row wave tiles of the work tile in turn (wave w: tiles w, w + 4, ...);
+// returns this lane's share of p.q.  The staging is dynamic LDS, requested
+// only by launches that contain such a system, so that the vector-CSR
+// schedules keep their occupancy.
+constexpr int kWaveStageBytes = (kBB / kWave) * (kWave * 8 * 12 + 65 * 4 + 8);
+
+template <int RT>
+__device__ __forceinline__ double spmm_wave_tiles(const BSys &S, const BTile &t, double *lds)
+{
+    using Sm = WaveSmem<8, RT, double>;
+    static_assert((kBB / kWave) * sizeof(Sm) <= kWaveStageBytes, "wave staging");
+    Sm *sm = reinterpret_cast<Sm *>(lds) + threadIdx.x / kWave;
+    constexpr int TPR = kWave / RT;
+    const int end = t.row0 + t.rows;
+    double ppq = 0.0;
+    for (int r0 = t.row0 + (threadIdx.x / kWave) * RT; r0 < end; r0 += (kBB / kWave) * RT) {
+        int row;
+        const double acc =
+            wave_rows<8, RT, 4, double>(r0, end, S.n_cols, S.nnz, S.rp, S.ci, S.val, S.p, *sm, row);
+        if (threadIdx.x % TPR == 0 && row < end) {
+            S.q[row] = acc;
+            ppq += S.p[row] * acc;
+        }
+    }
+    return ppq;
+}
+
 // (1) q = A p for every active system, p.q partials per right-hand side.
+// Systems with M > 0 use K * M lanes per row (vector CSR over the
+// interleaved vectors); single-right-hand-side systems with M < 0 use wave
+// tiles of -M rows.
 __global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgs a)
 {
     __shared__ double red[kBB];
+    extern __shared__ double stage[];  // kWaveStageBytes when a system runs on wave tiles
     const int w = xcd_block(blockIdx.x, gridDim.x);
     const BTile t = a.tiles[w];
     if (a.sys_done[t.sys]) return;
     const BSys S = a.sys[t.sys];
-    const int G = S.K * S.M, gpw = kWave / G;
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
     double ppq = 0.0;
-    for (int row = t.row0 + wave * gpw + grp; row < t.row0 + t.rows; row += (kBB / kWave) * gpw) {
-        double dg;
-        const double qv = row_spmm(S, row, j, m, dg, S.p);
-        if (m == 0) {
-            const int64_t e = (int64_t)row * S.K + j;
-            S.q[e] = qv;
-            ppq += S.p[e] * qv;
+    if (S.M < 0) {
+        switch (-S.M) {
+            case 1: ppq = spmm_wave_tiles<1>(S, t, stage); break;
+            case 2: ppq = spmm_wave_tiles<2>(S, t, stage); break;
+            case 4: ppq = spmm_wave_tiles<4>(S, t, stage); break;
+            case 8: ppq = spmm_wave_tiles<8>(S, t, stage); break;
+            case 16: ppq = spmm_wave_tiles<16>(S, t, stage); break;
+            case 32: ppq = spmm_wave_tiles<32>(S, t, stage); break;
+            default: ppq = spmm_wave_tiles<64>(S, t, stage); break;
+        }
+    } else {
+        const int G = S.K * S.M, gpw = kWave / G;
+        const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+        const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
+        for (int row = t.row0 + wave * gpw + grp; row < t.row0 + t.rows;
+             row += (kBB / kWave) * gpw) {
+            double dg;
+            const double qv = row_spmm(S, row, j, m, S.M, dg, S.p);
+            if (m == 0) {
+                const int64_t e = (int64_t)row * S.K + j;
+                S.q[e] = qv;
+                ppq += S.p[e] * qv;
+            }
         }
     }
     block_sum_by_rhs(ppq, S.K, red, a.part + (int64_t)t.tile * kMaxK);
@@ -400,7 +451,7 @@ __global__ void batch_zero_kernel(double *x, int64_t n)
 
 void launch_batch_iteration(const BArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(batch_spmm_kernel, dim3(a.ntiles), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL(batch_spmm_kernel, dim3(a.ntiles), dim3(kBB), a.wave_lds, s, a);
     hipLaunchKernelGGL(batch_r1_kernel, dim3(a.nlist), dim3(kBB), 0, s, a);
     hipLaunchKernelGGL(batch_update_kernel, dim3(a.ntiles), dim3(kBB), 0, s, a);
     hipLaunchKernelGGL(batch_r2_kernel, dim3(a.nlist), dim3(kBB), 0, s, a);
@@ -416,14 +467,21 @@ int pad_k(int nrhs)
 
 int tile_rows_for(int K) { return K >= 16 ? 128 : 2048 / K; }
 
-// Candidate slice counts M for K right-hand sides: groups of K * M lanes in
-// {8, 16, 32, 64} (at least one lane per right-hand side).
-std::vector<int> m_candidates(int K)
+// Candidate schedules for K right-hand sides: slice counts M > 0, groups of
+// K * M lanes in {8, 16, 32, 64} (at least one lane per right-hand side);
+// for one right-hand side also wave tiles (M = -rows per wave tile, the
+// rows whose expected entries fill one 64 x 8 chunk, and half of that).
+std::vector<int> m_candidates(int K, int64_t n = 0, int64_t nnz = 0)
 {
     std::vector<int> out;
     for (int G = 8; G <= 64; G *= 2)
         if (G >= K) out.push_back(G / K);
     if (out.empty()) out.push_back(1);
+    if (K == 1 && n > 0) {
+        const int rt = wave_tile_rows(n, nnz, 8);
+        out.push_back(-rt);
+        if (rt > 1) out.push_back(-rt / 2);
+    }
     return out;
 }
 

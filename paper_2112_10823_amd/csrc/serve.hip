@@ -184,6 +184,9 @@ BArgs engine_args(const Engine &E, bool fresh, int ntiles, int nlist)
     a.part_stride = E.max_tiles * kMaxK;
     a.ntiles = ntiles;
     a.nlist = nlist;
+    a.wave_lds = 0;
+    for (const Slot &sl : E.slots)
+        if (sl.used && sl.M < 0) a.wave_lds = kWaveStageBytes;
     return a;
 }
 

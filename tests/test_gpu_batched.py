@@ -93,7 +93,38 @@ def test_batched_schedule_reported():
         K = 1
         while K < k:
             K *= 2
-        assert M >= 1 and K * M <= 64 and K * M >= 8
+        if M < 0:  # wave tiles: one right-hand side, a power of two of rows
+            assert k == 1 and -M <= 64 and (-M & (-M - 1)) == 0
+        else:
+            assert M >= 1 and K * M <= 64 and K * M >= 8
+    fixed = [items[0] + (-4,), items[1] + (8 // 4,), items[2]]
+    ms = cgx.batch_schedule(fixed)
+    assert ms[0] == -4 and ms[1] == 2
+
+
+@pytest.mark.parametrize("schedule", [-16, -64, -1, 8])
+def test_single_rhs_schedules_vs_oracle(schedule):
+    """One right-hand side per system with each SpMM schedule forced: wave
+    tiles of 16, 64 or 1 rows per wavefront and 8 lanes per row."""
+    mats = [synth.q1cube(14, 1.0, 21), synth.fd7_var(19, 1.0, 22), synth.q1cube(5, 1.0, 23)]
+    items, hostB = make_items(mats, [1, 1, 1], seed=700)
+    items = [it + (schedule,) for it in items]
+    st = cgx.cg_solve_batched(items, cgx.make_opts(rtol=1e-10, precond=1))
+    for s, A in enumerate(mats):
+        X = items[s][2].cpu().numpy()
+        ref = oracle.cg(A, hostB[s][0], rtol=1e-10, jacobi=True)
+        assert st[s][0].status == cgx.OK
+        assert abs(st[s][0].iters - ref.iters) <= 2
+        assert true_relres(A, hostB[s][0], X[0]) <= 1.5e-10
+        assert np.linalg.norm(X[0] - ref.x) / np.linalg.norm(ref.x) <= 1e-7
+
+
+def test_schedule_argument_errors():
+    mats = [synth.q1cube(6, 1.0, 1)]
+    items, _ = make_items(mats, [2])
+    for bad in (-8, 3, 64):  # wave tiles need nrhs 1; K * M must be 8..64
+        with pytest.raises(cgx.CgxError):
+            cgx.cg_solve_batched([items[0] + (bad,)], cgx.make_opts())
 
 
 def test_batched_64_systems_16_rhs_full_size():
