@@ -382,13 +382,13 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
     pool_t = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
     bs = [torch.from_numpy(synth.uniform(7000 + i, A.n_rows)).cuda() for i, (A, _) in enumerate(mats)]
 
-    def run(qps):
+    def run(qps, max_group=16):
         h = cgx.Handle()
         gaps = rng.exponential(1.0 / qps, n_req) if qps else np.zeros(n_req)
         lat, ok = [], 0
         out = [torch.zeros_like(bs[k]) for k in picks]
         e0 = meter.read()
-        with cgx.Server(pool_t, max_slots=48, handle=h) as srv:
+        with cgx.Server(pool_t, max_slots=48, handle=h, max_group=max_group) as srv:
             t0 = time.perf_counter()
             tickets = []
             nxt = t0
@@ -404,7 +404,8 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
             wall = time.perf_counter() - t0
         e1 = meter.read()
         lat.sort()
-        return {"qps": round(qps, 2) if qps else "burst", "solves_per_s": round(n_req / wall, 2),
+        return {"qps": round(qps, 2) if qps else "burst", "max_group": max_group,
+                "solves_per_s": round(n_req / wall, 2),
                 "p50_ms": round(lat[len(lat) // 2], 2),
                 "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 2),
                 "ok": ok, "wall_s": round(wall, 2),
@@ -430,7 +431,7 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
                 "j_per_solve": round((e1 - e0) / n_req, 3) if e0 is not None and e1 > e0 else None}
 
     sat = run(0)  # all requests at once: saturation throughput
-    rows = [sat]
+    rows = [sat, run(0, max_group=1)]
     for f in (0.5, 0.8, 0.95):
         rows.append(run(f * sat["solves_per_s"]))
     return {"workload": f"{n_req} Poisson-arrival requests on {pool_systems} resident Q1 systems "

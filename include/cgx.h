@@ -140,7 +140,8 @@ typedef struct cgx_opts {
 typedef struct cgx_stats {
     int32_t status;      /* CGX_OK, CGX_NOT_CONVERGED, CGX_BREAKDOWN, CGX_NONFINITE */
     int32_t iters;       /* CG iterations (binary32 inner iterations for MIXED) */
-    int32_t outer_iters; /* MIXED: refinement steps */
+    int32_t outer_iters; /* MIXED: refinement steps; served requests: requests in its
+                          * slot's group (1 when it ran alone) */
     int32_t path;        /* kernel path: 0 phase kernels, 1 single workgroup, 2 mixed
                           * refinement, 3 batched, 4 served */
     double relres;       /* recursive ||r|| / ||b|| at exit (outer residual for MIXED) */
@@ -219,18 +220,27 @@ int cgx_batch_schedule(cgx_handle h, int32_t nsys, const cgx_system *systems, vo
 
 /* (sync) Start a continuous-batching solve server on the handle.  pool:
  * caller device memory (256-byte aligned) the server carves its tables and
- * every admitted request's Krylov vectors from; max_slots: requests on the
- * GPU at once.  A progress thread admits queued requests while a slot and
- * pool memory are free (FIFO with backfill; a head request blocked for
- * 0.25 s stops the backfill), advances all admitted requests together a few
- * CG iterations at a time with the batched kernels, and retires finished
- * ones.  The handle must not run other solves while the server runs. */
-int cgx_serve_start(cgx_handle h, void *pool, size_t pool_bytes, int32_t max_slots);
+ * every admitted slot's Krylov vectors from; max_slots: slots on the GPU at
+ * once; max_group (1..16): requests on the same matrix (same arrays and
+ * options) one slot may hold as the right-hand sides of one multi-RHS
+ * solve, streaming the matrix once per iteration for all of them (1: every
+ * request alone in its slot).  A progress thread admits queued requests
+ * while a slot and pool memory are free (FIFO with backfill; a head request
+ * blocked for 0.25 s stops the backfill; an admitted request takes queued
+ * requests on its matrix along), advances all admitted requests together a
+ * few CG iterations at a time with the batched kernels, and retires each
+ * request as soon as it finishes.  With max_group = 1 a request's result is
+ * bit-identical alone and in any mix; with grouping it is the same within
+ * the solve tolerance.  The handle must not run other solves while the
+ * server runs. */
+int cgx_serve_start(cgx_handle h, void *pool, size_t pool_bytes, int32_t max_slots,
+                    int32_t max_group);
 
 /* (sync) Finish every queued and running request, then stop the server. */
 int cgx_serve_stop(cgx_handle h);
 
-/* Pool bytes one request of n_rows needs while admitted. */
+/* Pool bytes one request of n_rows needs while admitted alone (a group of
+ * g requests on one matrix needs less than g times this). */
 size_t cgx_serve_request_bytes(int64_t n_rows);
 
 /* Queue a solve of A x = b (A resident and square, b / x device float64[n],

@@ -106,7 +106,7 @@ def load_library(path: str = LIB_PATH):
         "cgx_cg_solve_batched": ([vp, i32, P(_System), vp, ctypes.c_size_t, P(Opts), P(Stats)],
                                  ctypes.c_int),
         "cgx_batch_schedule": ([vp, i32, P(_System), vp, ctypes.c_size_t, P(i32)], ctypes.c_int),
-        "cgx_serve_start": ([vp, vp, ctypes.c_size_t, i32], ctypes.c_int),
+        "cgx_serve_start": ([vp, vp, ctypes.c_size_t, i32, i32], ctypes.c_int),
         "cgx_serve_stop": ([vp], ctypes.c_int),
         "cgx_serve_request_bytes": ([i64], ctypes.c_size_t),
         "cgx_submit": ([vp, P(_Csr), vp, vp, P(Opts), P(ctypes.c_uint64)], ctypes.c_int),
@@ -418,15 +418,18 @@ class Server:
     """Continuous-batching solve server on a handle (see cgx_serve_start).
 
     pool: uint8 GPU tensor the server carves its tables and request vectors
-    from.  Matrices, right-hand sides and solution vectors stay owned by the
-    caller and must outlive their requests."""
+    from; max_group: requests on one matrix that may share a slot as the
+    right-hand sides of one solve (1: no grouping).  Matrices, right-hand
+    sides and solution vectors stay owned by the caller and must outlive
+    their requests."""
 
-    def __init__(self, pool: torch.Tensor, max_slots: int = 64, handle: Handle | None = None):
+    def __init__(self, pool: torch.Tensor, max_slots: int = 64, handle: Handle | None = None,
+                 max_group: int = 16):
         self.handle = handle or Handle()
         self.pool = pool
         self._keep = {}
         _check(load_library().cgx_serve_start(self.handle.ptr, _ptr(pool), pool.numel(),
-                                              int(max_slots)))
+                                              int(max_slots), int(max_group)))
         self.running = True
 
     @staticmethod

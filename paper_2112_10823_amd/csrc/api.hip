@@ -353,14 +353,16 @@ int cgx_batch_schedule(cgx_handle h, int32_t nsys, const cgx_system *systems, vo
     });
 }
 
-int cgx_serve_start(cgx_handle h, void *pool, size_t pool_bytes, int32_t max_slots)
+int cgx_serve_start(cgx_handle h, void *pool, size_t pool_bytes, int32_t max_slots,
+                    int32_t max_group)
 {
     return guarded([&]() -> int {
         CGX_REQUIRE(h != nullptr, "handle is NULL");
         CGX_REQUIRE(pool != nullptr && ((uintptr_t)pool & 255) == 0,
                     "pool must be 256-byte aligned device memory");
         CGX_REQUIRE(max_slots >= 1 && max_slots <= 4096, "max_slots must be in [1, 4096]");
-        return cgx::serve_start(ctx_of(h), pool, pool_bytes, max_slots);
+        CGX_REQUIRE(max_group >= 1 && max_group <= 16, "max_group must be in [1, 16]");
+        return cgx::serve_start(ctx_of(h), pool, pool_bytes, max_slots, max_group);
     });
 }
 

@@ -12,12 +12,19 @@
 
 namespace cgx {
 
+// Caller vectors of one right-hand side of a served group.
+struct LanePtr {
+    const double *b;
+    double *x;
+};
+
 struct BSys {
     const int32_t *rp;
     const int32_t *ci;
     const double *val;
-    const double *B;  // caller right-hand sides, [nrhs][n]
-    double *X;        // caller solutions, [nrhs][n]
+    const double *B;  // caller right-hand sides, [nrhs][n] (batch call)
+    double *X;        // caller solutions, [nrhs][n] (batch call)
+    const LanePtr *lanes;  // served groups: per right-hand side b / x (else null)
     double *x, *r, *p, *q, *z;  // interleaved [n][K]
     double *dinv;     // [n]
     int64_t nnz;
@@ -135,7 +142,9 @@ __global__ __launch_bounds__(kBB) void batch_in_kernel(BArgs a)
     const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) {
         const int row = (int)(e / S.K), j = (int)(e % S.K);
-        S.x[e] = j < S.nrhs ? S.X[(int64_t)j * S.n + row] : 0.0;
+        double v = 0.0;
+        if (j < S.nrhs) v = S.lanes ? S.lanes[j].x[row] : S.X[(int64_t)j * S.n + row];
+        S.x[e] = v;
     }
 }
 
@@ -156,7 +165,8 @@ __global__ __launch_bounds__(kBB) void batch_init_kernel(BArgs a)
         const double ax = row_spmm(S, row, j, m, M, dg, S.x);
         if (m == 0) {
             const int64_t e = (int64_t)row * S.K + j;
-            const double bi = j < S.nrhs ? S.B[(int64_t)j * S.n + row] : 0.0;
+            double bi = 0.0;
+            if (j < S.nrhs) bi = S.lanes ? S.lanes[j].b[row] : S.B[(int64_t)j * S.n + row];
             const double ri = bi - ax;
             double zi = ri;
             S.r[e] = ri;
@@ -433,6 +443,20 @@ __global__ __launch_bounds__(kBB) void batch_out_kernel(BArgs a)
             S.X[(int64_t)j * S.n + row] = (c.bb == 0.0 && c.status == CGX_OK) ? 0.0 : S.x[e];
         }
     }
+}
+
+// Served group: right-hand side j of system `si` (finished) -> its caller x
+// (x = 0 where b = 0).
+__global__ __launch_bounds__(kBB) void lane_out_kernel(const BSys *sys, int si, int j,
+                                                       const BScal *scal)
+{
+    const BSys &S = sys[si];
+    const BScal &c = scal[S.scal0 + j];
+    const bool zero = c.bb == 0.0 && c.status == CGX_OK;
+    double *x = S.lanes[j].x;
+    const int64_t stride = (int64_t)gridDim.x * kBB;
+    for (int64_t i = (int64_t)blockIdx.x * kBB + threadIdx.x; i < S.n; i += stride)
+        x[i] = zero ? 0.0 : S.x[i * S.K + j];
 }
 
 __global__ void batch_scal_init_kernel(BScal *scal, int64_t n, int32_t *done, int nsys)

@@ -155,7 +155,7 @@ int batch_autotune(Context *c, int32_t nsys, const cgx_system *in, void *ws, siz
                    std::vector<int> &Ms);
 int tune_one(Context *c, const cgx_system &sys, void *ws, size_t ws_bytes, hipStream_t s,
              int &M_out);
-int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots);
+int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots, int32_t max_group);
 int serve_stop(Context *c);
 size_t serve_request_bytes(int64_t n_rows);
 int serve_submit(Context *c, const cgx_csr *A, const double *b, double *x, const cgx_opts *o,

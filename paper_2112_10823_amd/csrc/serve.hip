@@ -2,16 +2,24 @@
 // right-hand side and a solution vector, all device memory owned by the
 // caller) are admitted while a slot and pool memory are free, and every
 // admitted request advances inside one batched CG iteration sequence with
-// all others (the batched kernels of batch_kernels.h, one right-hand side per
-// request).  A progress thread alternates: admit queued requests, run a few
-// iterations of all active requests, retire the finished ones.  Requests that
-// arrive while others are on the GPU join at the next cycle.
+// all others (the batched kernels of batch_kernels.h).  A progress thread
+// alternates: admit queued requests, run a few iterations of all active
+// requests, retire the finished ones.  Requests that arrive while others are
+// on the GPU join at the next cycle.
+//
+// Grouping: when a request is admitted, up to max_group - 1 queued requests
+// on the same matrix (same arrays and options) join its slot as further
+// right-hand sides, so the matrix is streamed once per iteration for all of
+// them (the batched solver's multi-right-hand-side SpMM).  Each request keeps
+// its own scalars and stopping test and is retired as soon as it finishes.
 //
 // Device memory comes only from the caller's pool: a fixed arena (system
-// table, work table, scalars, reduction partials) at its start and a
-// first-fit heap for per-request Krylov vectors.  A request's arithmetic
-// depends only on its own rows, tiles and schedule, so its result does not
-// depend on what else is being served.
+// table, lane table, work table, scalars, reduction partials) at its start
+// and a first-fit heap for per-slot Krylov vectors.  A request's arithmetic
+// depends only on its slot's rows, tiles, right-hand-side count and
+// schedule: alone and in any mix it gets the same bits when it is served
+// ungrouped (max_group = 1) and the same solution within the solve
+// tolerance when grouping changes its slot's right-hand-side count.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -51,11 +59,14 @@ struct Request {
 struct Slot {
     bool used = false;
     bool fresh = false;
-    Request req;
-    size_t off = 0;
+    std::vector<Request> reqs;     // the group: right-hand side j is reqs[j]
+    std::vector<uint8_t> reported;  // per right-hand side: result published
+    size_t off = 0, bytes = 0;     // heap block of the group's vectors
     int M = 1;
+    int K = 1;
     int ntiles = 0;
     double t_admit = 0.0;
+    const Request &head() const { return reqs.front(); }
 };
 
 struct Result {
@@ -70,9 +81,10 @@ struct Engine {
     char *pool = nullptr;
     size_t pool_bytes = 0;
     int max_slots = 0;
+    int max_group = 1;
     int64_t max_tiles = 0;
-    size_t off_sys = 0, off_list = 0, off_list2 = 0, off_scal = 0, off_done = 0, off_tiles = 0,
-           off_tiles2 = 0, off_part = 0, heap0 = 0;
+    size_t off_sys = 0, off_lanes = 0, off_list = 0, off_list2 = 0, off_scal = 0, off_done = 0,
+           off_tiles = 0, off_tiles2 = 0, off_part = 0, heap0 = 0;
     std::map<size_t, size_t> free_list;  // heap offset -> size
     std::vector<Slot> slots;
     std::deque<Request> queue;
@@ -127,45 +139,60 @@ struct Engine {
 
 namespace {
 
-int tiles_of(int64_t n) { return (int)((n + tile_rows_for(1) - 1) / tile_rows_for(1)); }
+int tiles_of(int64_t n, int nrhs)
+{
+    const int tr = tile_rows_for(pad_k(nrhs));
+    return (int)((n + tr - 1) / tr);
+}
 
-size_t request_bytes(int64_t n)
+// Heap bytes of a group of nrhs requests on an n-row matrix: its Krylov
+// vectors, and room for the one-system plan the autotuner times in place.
+size_t group_bytes(int64_t n, int nrhs)
 {
     cgx_system sys{};
     sys.A.n_rows = (int32_t)n;
     sys.A.n_cols = (int32_t)n;
-    sys.nrhs = 1;
+    sys.nrhs = nrhs;
     return batch_workspace_bytes(1, &sys);
 }
 
-// Device descriptor of a slot (K = 1: the caller's x is the interleaved x).
-BSys slot_sys(const Engine &E, const Slot &s, int tile0)
+size_t request_bytes(int64_t n) { return group_bytes(n, 1); }
+
+// Requests that may share a slot: same matrix arrays and solver options.
+bool same_group(const Request &a, const Request &b)
 {
-    const Request &q = s.req;
+    return a.A.row_ptr == b.A.row_ptr && a.A.col_idx == b.A.col_idx && a.A.val == b.A.val &&
+           a.A.n_rows == b.A.n_rows && a.A.nnz == b.A.nnz && a.jac == b.jac &&
+           a.maxit == b.maxit && a.rtol == b.rtol;
+}
+
+// Device descriptor of slot `si`: interleaved x r p q z of the group's K
+// right-hand sides and dinv at the start of its heap block; b / x of each
+// request through the slot's lane table.
+BSys slot_sys(const Engine &E, int si, int tile0)
+{
+    const Slot &s = E.slots[si];
+    const Request &q = s.head();
     BSys S{};
     S.rp = q.A.row_ptr;
     S.ci = q.A.col_idx;
     S.val = q.A.val;
-    S.B = q.b;
-    S.X = q.x;
-    S.x = q.x;
-    const size_t vb = a256((size_t)q.A.n_rows * sizeof(double));
+    S.lanes = reinterpret_cast<const LanePtr *>(E.pool + E.off_lanes) + (size_t)si * kMaxK;
+    const size_t vb = a256((size_t)q.A.n_rows * s.K * sizeof(double));
     char *base = E.pool + s.off;
-    S.r = reinterpret_cast<double *>(base);
-    S.p = reinterpret_cast<double *>(base + vb);
-    S.q = reinterpret_cast<double *>(base + 2 * vb);
-    S.z = reinterpret_cast<double *>(base + 3 * vb);
-    S.dinv = reinterpret_cast<double *>(base + 4 * vb);
+    double **vecs[5] = {&S.x, &S.r, &S.p, &S.q, &S.z};
+    for (int v = 0; v < 5; ++v) *vecs[v] = reinterpret_cast<double *>(base + v * vb);
+    S.dinv = reinterpret_cast<double *>(base + 5 * vb);
     S.nnz = q.A.nnz;
     S.n = q.A.n_rows;
     S.n_cols = q.A.n_cols;
-    S.K = 1;
-    S.nrhs = 1;
+    S.K = s.K;
+    S.nrhs = (int)s.reqs.size();
     S.M = s.M;
-    S.trows = tile_rows_for(1);
+    S.trows = tile_rows_for(s.K);
     S.tile0 = tile0;
     S.ntiles = s.ntiles;
-    S.scal0 = (int)(&s - &E.slots[0]);
+    S.scal0 = si * kMaxK;
     S.jac = q.jac;
     S.maxit = q.maxit;
     S.rtol2 = q.rtol * q.rtol;
@@ -201,7 +228,8 @@ BArgs engine_args(const Engine &E, bool fresh, int ntiles, int nlist)
     } while (0)
 
 // One cycle's device work: rebuild tables if membership changed, initialise
-// fresh slots, run `iters` iterations, read back the slot states.
+// fresh slots, run `iters` iterations, copy finished right-hand sides out,
+// read back the slot states.
 bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
 {
     hipStream_t s = E.stream;
@@ -213,7 +241,7 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
             const Slot &sl = E.slots[i];
             if (!sl.used) continue;
             const int tile0 = (int)tiles.size();
-            sys[i] = slot_sys(E, sl, tile0);
+            sys[i] = slot_sys(E, i, tile0);
             for (int t = 0; t < sl.ntiles; ++t) {
                 BTile bt{};
                 bt.sys = i;
@@ -239,15 +267,22 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
                                      sizeof(BTile) * tiles2.size(), hipMemcpyHostToDevice, s));
             ENG_CHECK(hipMemcpyAsync(E.pool + E.off_list2, list2.data(),
                                      sizeof(int32_t) * list2.size(), hipMemcpyHostToDevice, s));
-            const BScal zero{};
+            const std::vector<BScal> zero(kMaxK);
             const int32_t zd = 0;
             for (int i : list2) {
-                ENG_CHECK(hipMemcpyAsync(E.pool + E.off_scal + sizeof(BScal) * i, &zero,
-                                         sizeof(BScal), hipMemcpyHostToDevice, s));
+                LanePtr lanes[kMaxK] = {};
+                const Slot &sl = E.slots[i];
+                for (size_t j = 0; j < sl.reqs.size(); ++j) lanes[j] = {sl.reqs[j].b, sl.reqs[j].x};
+                ENG_CHECK(hipMemcpyAsync(E.pool + E.off_lanes + sizeof(LanePtr) * kMaxK * i, lanes,
+                                         sizeof(lanes), hipMemcpyHostToDevice, s));
+                ENG_CHECK(hipMemcpyAsync(E.pool + E.off_scal + sizeof(BScal) * kMaxK * i,
+                                         zero.data(), sizeof(BScal) * kMaxK,
+                                         hipMemcpyHostToDevice, s));
                 ENG_CHECK(hipMemcpyAsync(E.pool + E.off_done + sizeof(int32_t) * i, &zd,
                                          sizeof(int32_t), hipMemcpyHostToDevice, s));
             }
             const BArgs f = engine_args(E, true, (int)tiles2.size(), (int)list2.size());
+            hipLaunchKernelGGL(batch_in_kernel, dim3(f.ntiles), dim3(kBB), 0, s, f);
             hipLaunchKernelGGL(batch_init_kernel, dim3(f.ntiles), dim3(kBB), 0, s, f);
             hipLaunchKernelGGL(batch_r0_kernel, dim3(f.nlist), dim3(kBB), 0, s, f);
             ENG_CHECK(hipGetLastError());
@@ -264,10 +299,76 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
     }
     ENG_CHECK(hipMemcpyAsync(E.h_done, E.pool + E.off_done, sizeof(int32_t) * E.max_slots,
                              hipMemcpyDeviceToHost, s));
-    ENG_CHECK(hipMemcpyAsync(E.h_scal, E.pool + E.off_scal, sizeof(BScal) * E.max_slots,
+    ENG_CHECK(hipMemcpyAsync(E.h_scal, E.pool + E.off_scal, sizeof(BScal) * kMaxK * E.max_slots,
                              hipMemcpyDeviceToHost, s));
     ENG_CHECK(hipStreamSynchronize(s));
     return true;
+}
+
+// Admission, FIFO with backfill: a head blocked longer than the limit stops
+// backfilling so large requests are not starved.  An admitted request takes
+// queued requests on the same matrix along, up to max_group, as long as the
+// group's vectors fit the heap (else the group shrinks).  Caller holds E.mu.
+bool admit(Engine &E, int &ntiles_active)
+{
+    bool changed = false;
+    const double t = now_s();
+    bool blocked_head = false;
+    std::vector<Request> pending(E.queue.begin(), E.queue.end());
+    std::vector<uint8_t> taken(pending.size(), 0);
+    for (size_t h = 0; h < pending.size(); ++h) {
+        if (taken[h]) continue;
+        int free_slot = -1;
+        for (int i = 0; i < E.max_slots; ++i)
+            if (!E.slots[i].used) {
+                free_slot = i;
+                break;
+            }
+        if (free_slot < 0) break;
+        std::vector<size_t> members{h};
+        for (size_t k = h + 1; k < pending.size() && (int)members.size() < E.max_group; ++k)
+            if (!taken[k] && same_group(pending[h], pending[k])) members.push_back(k);
+        bool fits = false;
+        size_t off = 0, bytes = 0;
+        int nt = 0;
+        while (!members.empty()) {
+            const int g = (int)members.size();
+            bytes = group_bytes(pending[h].A.n_rows, g);
+            nt = tiles_of(pending[h].A.n_rows, g);
+            if (ntiles_active + nt <= E.max_tiles && E.alloc(bytes, off)) {
+                fits = true;
+                break;
+            }
+            members.resize(g > 1 ? g / 2 : 0);
+        }
+        if (!fits) {
+            if (h == 0 && t - pending[h].t_submit > E.head_wait_limit) blocked_head = true;
+            if (blocked_head) break;
+            continue;
+        }
+        Slot &sl = E.slots[free_slot];
+        sl.used = true;
+        sl.fresh = true;
+        sl.reqs.clear();
+        for (size_t m : members) {
+            sl.reqs.push_back(pending[m]);
+            taken[m] = 1;
+        }
+        sl.reported.assign(sl.reqs.size(), 0);
+        sl.K = pad_k((int)sl.reqs.size());
+        sl.off = off;
+        sl.bytes = bytes;
+        sl.ntiles = nt;
+        sl.t_admit = t;
+        ntiles_active += nt;
+        changed = true;
+    }
+    if (changed) {
+        E.queue.clear();
+        for (size_t k = 0; k < pending.size(); ++k)
+            if (!taken[k]) E.queue.push_back(pending[k]);
+    }
+    return changed;
 }
 
 void engine_loop(Engine *Ep)
@@ -280,39 +381,7 @@ void engine_loop(Engine *Ep)
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(E.mu);
-            // admission: FIFO with backfill; a head blocked longer than the
-            // limit stops backfilling so large requests are not starved
-            const double t = now_s();
-            bool blocked_head = false;
-            for (auto it = E.queue.begin(); it != E.queue.end();) {
-                int free_slot = -1;
-                for (int i = 0; i < E.max_slots; ++i)
-                    if (!E.slots[i].used) {
-                        free_slot = i;
-                        break;
-                    }
-                if (free_slot < 0) break;
-                const int nt = tiles_of(it->A.n_rows);
-                size_t off = 0;
-                const bool fits = ntiles_active + nt <= E.max_tiles && E.alloc(it->bytes, off);
-                if (!fits) {
-                    if (it == E.queue.begin() && t - it->t_submit > E.head_wait_limit)
-                        blocked_head = true;
-                    if (blocked_head) break;
-                    ++it;
-                    continue;
-                }
-                Slot &sl = E.slots[free_slot];
-                sl.used = true;
-                sl.fresh = true;
-                sl.req = *it;
-                sl.off = off;
-                sl.ntiles = nt;
-                sl.t_admit = t;
-                ntiles_active += nt;
-                changed = true;
-                it = E.queue.erase(it);
-            }
+            changed = admit(E, ntiles_active) || changed;
             bool any = false;
             for (const Slot &sl : E.slots) any = any || sl.used;
             if (!any) {
@@ -325,12 +394,10 @@ void engine_loop(Engine *Ep)
         for (Slot &sl : E.slots) {
             if (!sl.used || !sl.fresh) continue;
             cgx_system sys{};
-            sys.A = sl.req.A;
-            sys.nrhs = 1;
-            sys.B = sl.req.b;
-            sys.X = sl.req.x;
+            sys.A = sl.head().A;
+            sys.nrhs = (int)sl.reqs.size();
             int M = 1;
-            if (tune_one(E.c, sys, E.pool + sl.off, sl.req.bytes, E.stream, M) != CGX_OK) {
+            if (tune_one(E.c, sys, E.pool + sl.off, sl.bytes, E.stream, M) != CGX_OK) {
                 std::lock_guard<std::mutex> lk(E.mu);
                 E.fail = CGX_EHIP;
                 E.fail_msg = "autotuning failed";
@@ -341,7 +408,8 @@ void engine_loop(Engine *Ep)
         // iterations this cycle: about 1 ms of device work
         double bytes = 0.0;
         for (const Slot &sl : E.slots)
-            if (sl.used) bytes += 12.0 * sl.req.A.nnz + 88.0 * sl.req.A.n_rows;
+            if (sl.used)
+                bytes += 12.0 * sl.head().A.nnz + 88.0 * sl.K * sl.head().A.n_rows;
         int iters = (int)(1.0e-3 / (bytes / 4.0e12 + 25.0e-6));
         iters = iters < 1 ? 1 : (iters > 16 ? 16 : iters);
         if (!device_cycle(E, changed, iters, active)) {
@@ -350,28 +418,36 @@ void engine_loop(Engine *Ep)
             return;
         }
         changed = false;
-        // retire finished slots
+        // retire finished right-hand sides (copied out at once), and slots
+        // whose right-hand sides are all finished
         const double t = now_s();
         std::vector<std::pair<uint64_t, cgx_stats>> finished;
+        const BSys *dsys = reinterpret_cast<const BSys *>(E.pool + E.off_sys);
+        const BScal *dscal = reinterpret_cast<const BScal *>(E.pool + E.off_scal);
         for (int i : active) {
             Slot &sl = E.slots[i];
-            if (!sl.used || !E.h_done[i]) continue;
-            const BScal &v = E.h_scal[i];
-            cgx_stats st{};
-            st.status = v.status == CGX_PENDING ? CGX_NOT_CONVERGED : v.status;
-            st.iters = v.iter;
-            st.path = 4;
-            st.relres = v.bb > 0.0 ? std::sqrt(v.rr / v.bb) : 0.0;
-            st.relres_true = -1.0;
-            st.queue_ms = 1e3 * (sl.t_admit - sl.req.t_submit);
-            st.latency_ms = 1e3 * (t - sl.req.t_submit);
-            if (v.bb == 0.0 && v.status == CGX_OK) {
-                hipLaunchKernelGGL(batch_zero_kernel, dim3(64), dim3(256), 0, E.stream, sl.req.x,
-                                   (int64_t)sl.req.A.n_rows);
-                st.relres = 0.0;
+            if (!sl.used) continue;
+            for (size_t j = 0; j < sl.reqs.size(); ++j) {
+                const BScal &v = E.h_scal[(size_t)i * kMaxK + j];
+                if (sl.reported[j] || (v.active && !E.h_done[i])) continue;
+                const Request &q = sl.reqs[j];
+                cgx_stats st{};
+                st.status = v.status == CGX_PENDING ? CGX_NOT_CONVERGED : v.status;
+                st.iters = v.iter;
+                st.outer_iters = (int)sl.reqs.size();
+                st.path = 4;
+                st.relres = v.bb > 0.0 ? std::sqrt(v.rr / v.bb) : 0.0;
+                if (v.bb == 0.0 && v.status == CGX_OK) st.relres = 0.0;
+                st.relres_true = -1.0;
+                st.queue_ms = 1e3 * (sl.t_admit - q.t_submit);
+                st.latency_ms = 1e3 * (t - q.t_submit);
+                hipLaunchKernelGGL(lane_out_kernel, dim3(256), dim3(kBB), 0, E.stream, dsys, i,
+                                   (int)j, dscal);
+                finished.emplace_back(q.ticket, st);
+                sl.reported[j] = 1;
             }
-            finished.emplace_back(sl.req.ticket, st);
-            E.release(sl.off, sl.req.bytes);
+            if (!E.h_done[i]) continue;
+            E.release(sl.off, sl.bytes);
             ntiles_active -= sl.ntiles;
             sl.used = false;
             changed = true;
@@ -400,7 +476,7 @@ void engine_loop(Engine *Ep)
 
 }  // namespace
 
-int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots)
+int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots, int32_t max_group)
 {
     if (c->engine) {
         set_error("server already running on this handle");
@@ -412,17 +488,20 @@ int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots)
     E->pool = static_cast<char *>(pool);
     E->pool_bytes = pool_bytes;
     E->max_slots = max_slots;
+    E->max_group = max_group;
     // arena: tables sized for the most tiles the heap can hold
     E->max_tiles = (int64_t)(pool_bytes / (40.0 * tile_rows_for(1))) + max_slots + 1;
     size_t off = 0;
     E->off_sys = off;
     off += a256(sizeof(BSys) * max_slots);
+    E->off_lanes = off;
+    off += a256(sizeof(LanePtr) * kMaxK * max_slots);
     E->off_list = off;
     off += a256(sizeof(int32_t) * max_slots);
     E->off_list2 = off;
     off += a256(sizeof(int32_t) * max_slots);
     E->off_scal = off;
-    off += a256(sizeof(BScal) * max_slots);
+    off += a256(sizeof(BScal) * kMaxK * max_slots);
     E->off_done = off;
     off += a256(sizeof(int32_t) * max_slots);
     E->off_tiles = off;
@@ -439,7 +518,7 @@ int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots)
     }
     E->free_list[off] = (pool_bytes - off) & ~(size_t)255;
     E->slots.resize(max_slots);
-    hipError_t e = hipHostMalloc(&E->h_scal, sizeof(BScal) * max_slots);
+    hipError_t e = hipHostMalloc(&E->h_scal, sizeof(BScal) * kMaxK * max_slots);
     if (e == hipSuccess) e = hipHostMalloc(&E->h_done, sizeof(int32_t) * max_slots);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -510,7 +589,7 @@ int serve_submit(Context *c, const cgx_csr *A, const double *b, double *x, const
         return CGX_EINVAL;
     }
     if (a256(q.bytes) > E->heap_capacity() ||
-        tiles_of(A->n_rows) > E->max_tiles || E->max_slots < 1) {
+        tiles_of(A->n_rows, 1) > E->max_tiles || E->max_slots < 1) {
         set_error("request larger than the server pool");
         return CGX_ENOMEM;
     }

@@ -1,6 +1,8 @@
 """GPU tests of the continuous-batching solve server: served results against
-the CPU oracle, the same bits alone and in a mix (and the same as the
-batched path), memory admission, and requests admitted while others run."""
+the CPU oracle, the same bits alone and in a mix without grouping (and the
+same as the batched path), grouped requests on one matrix against the
+oracle and against their ungrouped results, memory admission, and requests
+admitted while others run."""
 import time
 
 import numpy as np
@@ -58,12 +60,12 @@ def test_alone_equals_mix_equals_batched(resident):
     h = cgx.Handle()
     # alone
     x_alone = torch.zeros_like(b)
-    with cgx.Server(pool(1 << 28), max_slots=8, handle=h) as srv:
+    with cgx.Server(pool(1 << 28), max_slots=8, handle=h, max_group=1) as srv:
         st_alone = srv.wait(srv.submit(dmats[2], b, x_alone, opts))
     # in a mix, arriving while others run
     x_mix = torch.zeros_like(b)
     others = []
-    with cgx.Server(pool(1 << 28), max_slots=8, handle=h) as srv:
+    with cgx.Server(pool(1 << 28), max_slots=8, handle=h, max_group=1) as srv:
         for i in range(6):
             k = i % 4
             bo = dev(synth.uniform(300 + i, mats[k].n_rows))
@@ -87,6 +89,39 @@ def test_alone_equals_mix_equals_batched(resident):
     st_b = cgx.cg_solve_batched([(dmats[2], b.view(1, -1), X)], opts, handle=h)
     assert st_b[0][0].iters == st_alone.iters
     assert torch.equal(X[0], x_alone)
+
+
+def test_grouped_requests_match_oracle_and_alone(resident):
+    """Requests on one matrix queued behind a running one are admitted as one
+    slot (right-hand sides of one multi-RHS solve); each result matches the
+    oracle and its ungrouped solve within the tolerance."""
+    mats, dmats = resident
+    big = synth.q1cube(60, 1.0, 8)
+    dbig = cgx.DeviceCSR.from_host(big)
+    opts = cgx.make_opts(rtol=1e-12)
+    A, dA = mats[1], dmats[1]
+    bs = [synth.uniform(800 + i, A.n_rows) for i in range(5)]
+    xs = [torch.zeros(A.n_rows, dtype=torch.float64, device="cuda") for _ in bs]
+    with cgx.Server(pool(1 << 30), max_slots=1, max_group=16) as srv:
+        bb = dev(synth.uniform(9, big.n_rows))
+        tb = srv.submit(dbig, bb, torch.zeros_like(bb), opts)  # holds the only slot
+        ts = [srv.submit(dA, dev(b), x, opts) for b, x in zip(bs, xs)]
+        assert srv.wait(tb).status == cgx.OK
+        sts = [srv.wait(t) for t in ts]
+    assert all(st.outer_iters == 5 for st in sts)  # one group of five
+    for b, x, st in zip(bs, xs, sts):
+        ref = oracle.cg(A, b, rtol=1e-12)
+        xg = x.cpu().numpy()
+        assert st.status == cgx.OK and abs(st.iters - ref.iters) <= 2
+        assert true_relres(A, b, xg) <= 1.5e-12
+        assert np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+    # ungrouped, one at a time
+    with cgx.Server(pool(1 << 28), max_slots=1, max_group=1) as srv:
+        for b, x in zip(bs, xs):
+            xa = torch.zeros_like(x)
+            st = srv.wait(srv.submit(dA, dev(b), xa, opts))
+            assert st.outer_iters == 1
+            assert (torch.linalg.norm(xa - x) / torch.linalg.norm(xa)).item() <= 1e-8
 
 
 def test_admission_by_memory(resident):
