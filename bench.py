@@ -382,7 +382,7 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
     pool_t = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
     bs = [torch.from_numpy(synth.uniform(7000 + i, A.n_rows)).cuda() for i, (A, _) in enumerate(mats)]
 
-    def run(qps, max_group=16):
+    def run(qps, max_group=16, opts=opts):
         h = cgx.Handle()
         gaps = rng.exponential(1.0 / qps, n_req) if qps else np.zeros(n_req)
         lat, ok = [], 0
@@ -405,15 +405,17 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
         e1 = meter.read()
         lat.sort()
         return {"qps": round(qps, 2) if qps else "burst", "max_group": max_group,
+                "precond": "jacobi" if opts.precond else "none",
                 "solves_per_s": round(n_req / wall, 2),
                 "p50_ms": round(lat[len(lat) // 2], 2),
                 "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 2),
                 "ok": ok, "wall_s": round(wall, 2),
                 "j_per_solve": round((e1 - e0) / n_req, 3) if e0 is not None and e1 > e0 else None}
 
-    def sequential():
+    def sequential(opts=opts):
         """The same requests solved one after another with the single-system
-        float64 solver (plain CG, the paper's method), no batching."""
+        float64 solver (plain CG, the paper's method, unless Jacobi is asked
+        for), no batching."""
         h = cgx.Handle()
         out = [torch.zeros_like(bs[k]) for k in picks]
         wss = {k: cgx.cg_workspace(mats[k][1], opts) for k in set(picks.tolist())}
@@ -430,13 +432,16 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
         return {"solves_per_s": round(n_req / wall, 2), "wall_s": round(wall, 2), "ok": ok,
                 "j_per_solve": round((e1 - e0) / n_req, 3) if e0 is not None and e1 > e0 else None}
 
+    jac = cgx.make_opts(rtol=1e-8, precond=cgx.PRECOND_JACOBI)
     sat = run(0)  # all requests at once: saturation throughput
     rows = [sat, run(0, max_group=1)]
     for f in (0.5, 0.8, 0.95):
         rows.append(run(f * sat["solves_per_s"]))
+    rows.append(run(0, opts=jac))
     return {"workload": f"{n_req} Poisson-arrival requests on {pool_systems} resident Q1 systems "
                         f"(rows lognormal in [1e4, 4e6]), lognormal(0,1), rtol 1e-8",
             "rows": rows, "one_at_a_time_fp64_cg": sequential(),
+            "one_at_a_time_fp64_jacobi_cg": sequential(jac),
             "pool_rows": sorted(A.n_rows for A, _ in mats)}
 
 

@@ -294,10 +294,11 @@ static int check_batch(cgx_handle h, int32_t nsys, const cgx_system *systems)
             CGX_REQUIRE(G == 8 || G == 16 || G == 32 || G == 64,
                         "schedule M: K * M must be 8, 16, 32 or 64");
         } else if (q.schedule < 0) {
-            const int rt = -q.schedule;
-            CGX_REQUIRE(q.nrhs == 1, "wave-tile schedule needs nrhs = 1");
-            CGX_REQUIRE(rt <= 64 && (rt & (rt - 1)) == 0,
-                        "wave-tile schedule: -M must be a power of two <= 64");
+            int K = 1;
+            while (K < q.nrhs) K *= 2;
+            CGX_REQUIRE(q.schedule >= -64 && cgx::batch_wave_schedule_ok(-q.schedule, K),
+                        "wave-tile schedule: -M must be a power of two <= 64 with -M * K "
+                        "<= 64, and -M * K >= 16 for several right-hand sides");
         }
     }
     return CGX_OK;

@@ -154,6 +154,8 @@ int upload_plan(const Plan &P, char *w, hipStream_t s)
 
 }  // namespace
 
+bool batch_wave_schedule_ok(int rt, int K) { return wave_schedule_ok(rt, K); }
+
 // Autotuner: per shape class (K, mean row length, log2 rows) time the SpMM
 // phase of the first system of that class alone for every candidate slice
 // count M and keep the fastest.  Results stay in the handle, so a class is

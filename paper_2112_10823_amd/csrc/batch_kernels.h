@@ -82,9 +82,10 @@ __device__ __forceinline__ void block_sum_by_rhs(double v, int K, double *red, d
     }
 }
 
-// Slices per row of the setup pass: the tuned M, or 8 lanes per row for
-// systems whose SpMM runs on wave tiles (M < 0).
-__device__ __forceinline__ int setup_m(const BSys &S) { return S.M > 0 ? S.M : 8; }
+// Slices per row of the setup pass: the tuned M, or for systems whose SpMM
+// runs on wave tiles (M < 0) M = max(1, 8 / K): groups of K * M <= 64 lanes
+// (K <= 16), so every wave holds at least one row group.
+__device__ __forceinline__ int setup_m(const BSys &S) { return S.M > 0 ? S.M : max(1, 8 / S.K); }
 
 // Row sum of one row for right-hand side j over nonzero slice m of M, using
 // interleaved vector v ([n][K]); combined over the M slices by butterfly.
@@ -157,6 +158,7 @@ __global__ __launch_bounds__(kBB) void batch_init_kernel(BArgs a)
     const BSys S = a.sys[t.sys];
     const int M = setup_m(S);
     const int G = S.K * M, gpw = kWave / G;
+    if (gpw < 1) return;  // not reached: K * M <= 64 is validated on the host
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
     double prr = 0.0, prz = 0.0, pbb = 0.0;
@@ -248,38 +250,115 @@ __global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgs a)
     if (threadIdx.x == 0) a.sys_done[sid] = any_active ? 0 : 1;
 }
 
-// Single right-hand side on wave tiles: the four waves of the workgroup take
-// RT-row wave tiles of the work tile in turn (wave w: tiles w, w + 4, ...);
-// returns this lane's share of p.q.  The staging is dynamic LDS, requested
-// only by launches that contain such a system, so that the vector-CSR
-// schedules keep their occupancy.
+// Wave tiles for K right-hand sides: a wavefront owns RT consecutive rows and
+// gives each row K * T lanes (T = 64 / (RT K)), lane = g K T + t K + j for row
+// g, right-hand side j and entry slice t.  The tile's col_idx / val are
+// streamed once into LDS (coalesced, non-temporal) and every lane walks its
+// row's entries t, t + T, ... four at a time, gathering p[col][j] from the
+// interleaved vector; the T slices are then combined by butterfly.  For
+// K = 1 this is the single-system wave tile.  The four waves of the
+// workgroup take the work tile's wave tiles in turn.  The staging is dynamic
+// LDS, requested only by launches that contain such a system, so that the
+// vector-CSR schedules keep their occupancy.
 constexpr int kWaveStageBytes = (kBB / kWave) * (kWave * 8 * 12 + 65 * 4 + 8);
 
-template <int RT>
+template <int RT, int K>
 __device__ __forceinline__ double spmm_wave_tiles(const BSys &S, const BTile &t, double *lds)
 {
     using Sm = WaveSmem<8, RT, double>;
     static_assert((kBB / kWave) * sizeof(Sm) <= kWaveStageBytes, "wave staging");
-    Sm *sm = reinterpret_cast<Sm *>(lds) + threadIdx.x / kWave;
-    constexpr int TPR = kWave / RT;
+    constexpr int T = kWave / (RT * K);
+    static_assert(T >= 1 && RT * K * T == kWave, "lanes per row");
+    constexpr int C = kWave * 8, U = 4;
+    Sm &sm = reinterpret_cast<Sm *>(lds)[threadIdx.x / kWave];
+    const int lane = threadIdx.x % kWave;
+    const int g = lane / (K * T), sl = (lane / K) % T, j = lane % K;
     const int end = t.row0 + t.rows;
+    const double *__restrict__ p = S.p;
     double ppq = 0.0;
     for (int r0 = t.row0 + (threadIdx.x / kWave) * RT; r0 < end; r0 += (kBB / kWave) * RT) {
-        int row;
-        const double acc =
-            wave_rows<8, RT, 4, double>(r0, end, S.n_cols, S.nnz, S.rp, S.ci, S.val, S.p, *sm, row);
-        if (threadIdx.x % TPR == 0 && row < end) {
-            S.q[row] = acc;
-            ppq += S.p[row] * acc;
+        const int nr = min(RT, end - r0);
+        wave_lds_sync();  // the previous tile's readers of sm are done
+        for (int i = lane; i <= nr; i += kWave) sm.rp[i] = clampk(S.rp[r0 + i], S.nnz);
+        wave_lds_sync();
+        const int k0 = sm.rp[0], k1 = max(k0, sm.rp[nr]);
+        int s = k0, e = k0;
+        if (g < nr) {
+            s = max(sm.rp[g], k0);
+            e = min(max(sm.rp[g + 1], s), k1);
+        }
+        double acc = 0.0;
+        for (int c0 = k0; c0 < k1; c0 += C) {
+            int col[8];
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = c0 + lane + kWave * u;
+                col[u] = -1;
+                a[u] = 0.0;
+                if (k < k1) {
+                    col[u] = __builtin_nontemporal_load(&S.ci[k]);
+                    a[u] = __builtin_nontemporal_load(&S.val[k]);
+                }
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                sm.col[lane + kWave * u] = col[u];
+                sm.val[lane + kWave * u] = a[u];
+            }
+            wave_lds_sync();
+            const int lo = max(s, c0) - c0, hi = min(e, c0 + C) - c0;
+            for (int k = lo + sl; k < hi; k += U * T) {
+                int cc[U];
+                double vv[U], xv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int kk = k + u * T;
+                    cc[u] = -1;
+                    vv[u] = 0.0;
+                    if (kk < hi) {
+                        cc[u] = sm.col[kk];
+                        vv[u] = sm.val[kk];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    xv[u] = (unsigned)cc[u] < (unsigned)S.n_cols ? p[(int64_t)cc[u] * K + j] : 0.0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) acc += vv[u] * xv[u];
+            }
+        }
+#pragma unroll
+        for (int off = T / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off * K);
+        const int row = r0 + g;
+        if (sl == 0 && g < nr) {
+            const int64_t ei = (int64_t)row * K + j;
+            S.q[ei] = acc;
+            ppq += p[ei] * acc;
         }
     }
     return ppq;
 }
 
+// Wave-tile schedule (M < 0: RT = -M rows per wave tile) for K = S.K.
+__device__ __forceinline__ double spmm_wave_dispatch(const BSys &S, const BTile &t, double *lds)
+{
+    const int rt = -S.M;
+#define CGX_WT(R, KK) \
+    if (rt == R && S.K == KK) return spmm_wave_tiles<R, KK>(S, t, lds);
+    CGX_WT(1, 1) CGX_WT(2, 1) CGX_WT(4, 1) CGX_WT(8, 1) CGX_WT(16, 1) CGX_WT(32, 1) CGX_WT(64, 1)
+    CGX_WT(8, 2) CGX_WT(16, 2) CGX_WT(32, 2)
+    CGX_WT(4, 4) CGX_WT(8, 4) CGX_WT(16, 4)
+    CGX_WT(2, 8) CGX_WT(4, 8) CGX_WT(8, 8)
+    CGX_WT(1, 16) CGX_WT(2, 16) CGX_WT(4, 16)
+#undef CGX_WT
+    return 0.0;  // not reached: schedules are validated on the host
+}
+
 // (1) q = A p for every active system, p.q partials per right-hand side.
 // Systems with M > 0 use K * M lanes per row (vector CSR over the
-// interleaved vectors); single-right-hand-side systems with M < 0 use wave
-// tiles of -M rows.
+// interleaved vectors), systems with M < 0 wave tiles of -M rows.
 __global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgs a)
 {
     __shared__ double red[kBB];
@@ -290,20 +369,12 @@ __global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgs a)
     const BSys S = a.sys[t.sys];
     double ppq = 0.0;
     if (S.M < 0) {
-        switch (-S.M) {
-            case 1: ppq = spmm_wave_tiles<1>(S, t, stage); break;
-            case 2: ppq = spmm_wave_tiles<2>(S, t, stage); break;
-            case 4: ppq = spmm_wave_tiles<4>(S, t, stage); break;
-            case 8: ppq = spmm_wave_tiles<8>(S, t, stage); break;
-            case 16: ppq = spmm_wave_tiles<16>(S, t, stage); break;
-            case 32: ppq = spmm_wave_tiles<32>(S, t, stage); break;
-            default: ppq = spmm_wave_tiles<64>(S, t, stage); break;
-        }
+        ppq = spmm_wave_dispatch(S, t, stage);
     } else {
         const int G = S.K * S.M, gpw = kWave / G;
         const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
         const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
-        for (int row = t.row0 + wave * gpw + grp; row < t.row0 + t.rows;
+        for (int row = t.row0 + wave * gpw + grp; gpw >= 1 && row < t.row0 + t.rows;
              row += (kBB / kWave) * gpw) {
             double dg;
             const double qv = row_spmm(S, row, j, m, S.M, dg, S.p);
@@ -491,20 +562,35 @@ int pad_k(int nrhs)
 
 int tile_rows_for(int K) { return K >= 16 ? 128 : 2048 / K; }
 
+// Wave-tile schedules the kernels instantiate: RT rows per wave with
+// RT * K <= 64 (K = 1: any power of two; K > 1: 1, 2 or 4 lanes per
+// right-hand side and row).
+bool wave_schedule_ok(int rt, int K)
+{
+    if (rt < 1 || rt > 64 || (rt & (rt - 1)) || rt * K > 64) return false;
+    return K == 1 || rt * K >= 16;
+}
+
 // Candidate schedules for K right-hand sides: slice counts M > 0, groups of
-// K * M lanes in {8, 16, 32, 64} (at least one lane per right-hand side);
-// for one right-hand side also wave tiles (M = -rows per wave tile, the
-// rows whose expected entries fill one 64 x 8 chunk, and half of that).
+// K * M lanes in {8, 16, 32, 64} (at least one lane per right-hand side), and
+// wave tiles (M = -rows per wave tile): for one right-hand side the rows
+// whose expected entries fill one 64 x 8 chunk and half of that, for K > 1
+// one or two lanes per right-hand side and row.
 std::vector<int> m_candidates(int K, int64_t n = 0, int64_t nnz = 0)
 {
     std::vector<int> out;
     for (int G = 8; G <= 64; G *= 2)
         if (G >= K) out.push_back(G / K);
     if (out.empty()) out.push_back(1);
-    if (K == 1 && n > 0) {
-        const int rt = wave_tile_rows(n, nnz, 8);
-        out.push_back(-rt);
-        if (rt > 1) out.push_back(-rt / 2);
+    if (n > 0) {
+        if (K == 1) {
+            const int rt = wave_tile_rows(n, nnz, 8);
+            out.push_back(-rt);
+            if (rt > 1) out.push_back(-rt / 2);
+        } else {
+            out.push_back(-(64 / K));
+            out.push_back(-(32 / K));
+        }
     }
     return out;
 }

@@ -149,6 +149,9 @@ int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, s
            const cgx_opts *o, cgx_stats *st);
 size_t cg_workspace_bytes(int64_t n, int64_t nnz, const cgx_opts *o);
 size_t batch_workspace_bytes(int32_t nsys, const cgx_system *in);
+// Whether wave tiles of rt rows are an instantiated schedule for K = the
+// right-hand-side count rounded up to a power of two.
+bool batch_wave_schedule_ok(int rt, int K);
 int run_batched(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t ws_bytes,
                 const cgx_opts *o, cgx_stats *stats);
 int batch_autotune(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t ws_bytes,

@@ -93,8 +93,8 @@ def test_batched_schedule_reported():
         K = 1
         while K < k:
             K *= 2
-        if M < 0:  # wave tiles: one right-hand side, a power of two of rows
-            assert k == 1 and -M <= 64 and (-M & (-M - 1)) == 0
+        if M < 0:  # wave tiles: a power of two of rows, at most 64 lanes per row group
+            assert -M * K <= 64 and (-M & (-M - 1)) == 0
         else:
             assert M >= 1 and K * M <= 64 and K * M >= 8
     fixed = [items[0] + (-4,), items[1] + (8 // 4,), items[2]]
@@ -122,9 +122,29 @@ def test_single_rhs_schedules_vs_oracle(schedule):
 def test_schedule_argument_errors():
     mats = [synth.q1cube(6, 1.0, 1)]
     items, _ = make_items(mats, [2])
-    for bad in (-8, 3, 64):  # wave tiles need nrhs 1; K * M must be 8..64
+    for bad in (-64, -3, -2, 3, 64):  # wave rows * K in [16, 64]; K * M in 8..64
         with pytest.raises(cgx.CgxError):
             cgx.cg_solve_batched([items[0] + (bad,)], cgx.make_opts())
+
+
+@pytest.mark.parametrize("nrhs,schedule", [(16, -4), (16, -1), (8, -8), (4, -16), (2, -32),
+                                           (3, -8), (16, 1)])
+def test_multi_rhs_schedules_vs_oracle(nrhs, schedule):
+    """Several right-hand sides with each SpMM schedule forced: wave tiles of
+    64 / K rows (one lane per right-hand side and row) or fewer rows (slices
+    combined by butterfly), and the vector-CSR schedule."""
+    mats = [synth.q1cube(11, 1.0, 31), synth.fd7_var(15, 1.0, 32)]
+    items, hostB = make_items(mats, [nrhs, nrhs], seed=710)
+    items = [it + (schedule,) for it in items]
+    st = cgx.cg_solve_batched(items, cgx.make_opts(rtol=1e-10, precond=1))
+    for s, A in enumerate(mats):
+        X = items[s][2].cpu().numpy()
+        for j in range(nrhs):
+            ref = oracle.cg(A, hostB[s][j], rtol=1e-10, jacobi=True)
+            assert st[s][j].status == cgx.OK
+            assert abs(st[s][j].iters - ref.iters) <= 2
+            assert true_relres(A, hostB[s][j], X[j]) <= 1.5e-10
+            assert np.linalg.norm(X[j] - ref.x) / np.linalg.norm(ref.x) <= 1e-7
 
 
 def test_batched_64_systems_16_rhs_full_size():
