@@ -445,6 +445,54 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
             "pool_rows": sorted(A.n_rows for A, _ in mats)}
 
 
+# The paper's seven gravity matrices, rebuilt by shape (Q1 on an a x a x c
+# node grid of the 200 x 200 x 10 km box, Dirichlet nodes as identity rows):
+# (a, c) and the SpMV / plain-CG times and energies the paper prints for
+# its own GPU, as context.
+PAPER_SHAPES = [(46, 48), (66, 68), (86, 88), (94, 96), (106, 108), (106, 118), (116, 118)]
+PAPER_SPMV_MS = [0.943, 2.699, 5.963, 7.877, 11.222, 12.405, 14.661]
+PAPER_SPMV_J = [0.136, 0.401, 0.891, 1.176, 1.676, 1.807, 2.165]
+PAPER_CG_ITERS = [203, 299, 394, 435, 491, 538, None]
+PAPER_CG_S = [0.313, 1.155, 2.460, 4.336, 6.872, 8.180, None]
+PAPER_CG_J = [31.363, 142.284, 329.078, 597.618, 970.115, 1159.492, None]
+
+
+def extra_paper_shapes(cgx, synth, meter):
+    """SpMV and plain CG (rtol 1e-6, RHS U[-1,1] seed 7: the paper states
+    neither) on the paper-shape matrices, beside the paper's own figures."""
+    import torch
+    rows = []
+    for i, (a, c) in enumerate(PAPER_SHAPES):
+        A = synth.q1box(a, c)
+        n, nnz = A.n_rows, A.nnz
+        dA = cgx.DeviceCSR.from_host(A)
+        b = torch.from_numpy(synth.uniform(7, n)).cuda()
+        y = torch.empty_like(b)
+        sp_s, sp_j = _energy_window(lambda: cgx.csr_spmv(dA, b, y), meter, min_s=2.0, min_reps=50)
+        opts = cgx.make_opts(rtol=1e-6)
+        ws = cgx.cg_workspace(dA, opts)
+        x = torch.zeros_like(b)
+        st = cgx.cg_solve(dA, b, x, opts, workspace=ws)
+
+        def solve():
+            x.zero_()
+            cgx.cg_solve(dA, b, x, opts, workspace=ws)
+
+        cg_s, cg_j = _energy_window(solve, meter, min_s=2.0)
+        rows.append({"a": a, "c": c, "n": n, "nnz": nnz,
+                     "spmv_us": round(sp_s * 1e6, 2),
+                     "spmv_GBs": round(spmv_bytes(n, nnz) / sp_s / 1e9, 1),
+                     "spmv_j": round(sp_j, 5) if sp_j is not None else None,
+                     "paper_spmv_ms": PAPER_SPMV_MS[i], "paper_spmv_j": PAPER_SPMV_J[i],
+                     "cg_iters": st.iters, "cg_ms": round(cg_s * 1e3, 3),
+                     "cg_j": round(cg_j, 4) if cg_j is not None else None,
+                     "paper_cg_iters": PAPER_CG_ITERS[i], "paper_cg_s": PAPER_CG_S[i],
+                     "paper_cg_j": PAPER_CG_J[i]})
+        del dA, ws
+    return {"workload": "the paper's 7 gravity-matrix shapes (Q1, a x a x c nodes, identity "
+                        "Dirichlet rows); SpMV, plain CG to 1e-6", "rows": rows}
+
+
 def run_extras(which):
     import numpy as _np  # noqa: F401
     import torch
@@ -458,7 +506,8 @@ def run_extras(which):
              "q1": lambda: extra_spmv_and_cg(cgx, synth, meter),
              "mixed": lambda: extra_mixed(cgx, synth, meter),
              "batched": lambda: extra_batched(cgx, synth, meter),
-             "serving": lambda: extra_serving(cgx, synth, meter)}
+             "serving": lambda: extra_serving(cgx, synth, meter),
+             "paper": lambda: extra_paper_shapes(cgx, synth, meter)}
     for name in which:
         print(f"# extra {name}", file=sys.stderr, flush=True)
         res = table[name]()
@@ -468,7 +517,7 @@ def run_extras(which):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=300,
@@ -476,7 +525,7 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="warm-up plus a few solves, for profiler runs")
     ap.add_argument("--extras", default="",
-                    help="comma list of extra workloads (small,blas1,q1,mixed,batched,serving); "
+                    help="comma list of extra workloads (small,blas1,q1,mixed,batched,serving,paper); "
                          "prints one JSON line each instead of the benchmark line")
     ap.add_argument("--calib", action="store_true",
                     help="with --profile-only: first run cgx_add on 2^26 float64 elements "
