@@ -201,6 +201,8 @@ __device__ __forceinline__ double sys_sum(const BArgs &a, const BSys &S, int reg
     const int slice = threadIdx.x / K, j = threadIdx.x % K, nsl = kBB / K;
     double s = 0.0;
     const double *base = a.part + reg * a.part_stride;
+    // unrolled: eight loads in flight, still added one by one in tile order
+#pragma unroll 8
     for (int t = S.tile0 + slice; t < S.tile0 + S.ntiles; t += nsl) s += base[(int64_t)t * kMaxK + j];
     __syncthreads();
     red[threadIdx.x] = s;
