@@ -141,7 +141,7 @@ typedef struct cgx_stats {
     int32_t status;      /* CGX_OK, CGX_NOT_CONVERGED, CGX_BREAKDOWN, CGX_NONFINITE */
     int32_t iters;       /* CG iterations (binary32 inner iterations for MIXED) */
     int32_t outer_iters; /* MIXED: refinement steps; served requests: requests in its
-                          * slot's group (1 when it ran alone) */
+                          * slot when it started, itself included (1: alone) */
     int32_t path;        /* kernel path: 0 phase kernels, 1 single workgroup, 2 mixed
                           * refinement, 3 batched, 4 served */
     double relres;       /* recursive ||r|| / ||b|| at exit (outer residual for MIXED) */
@@ -227,9 +227,11 @@ int cgx_batch_schedule(cgx_handle h, int32_t nsys, const cgx_system *systems, vo
  * request alone in its slot).  A progress thread admits queued requests
  * while a slot and pool memory are free (FIFO with backfill; a head request
  * blocked for 0.25 s stops the backfill; an admitted request takes queued
- * requests on its matrix along), advances all admitted requests together a
- * few CG iterations at a time with the batched kernels, and retires each
- * request as soon as it finishes.  With max_group = 1 a request's result is
+ * requests on its matrix along, and a request arriving while a slot on its
+ * matrix runs takes a free lane of that slot), advances all admitted
+ * requests together a few CG iterations at a time with the batched kernels,
+ * and retires each request as soon as it finishes.  Slots of matrices with
+ * at least 65536 rows keep one spare lane for such late arrivals.  With max_group = 1 a request's result is
  * bit-identical alone and in any mix; with grouping it is the same within
  * the solve tolerance.  The handle must not run other solves while the
  * server runs. */

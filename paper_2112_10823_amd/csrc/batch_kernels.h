@@ -144,7 +144,12 @@ __global__ __launch_bounds__(kBB) void batch_in_kernel(BArgs a)
     for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) {
         const int row = (int)(e / S.K), j = (int)(e % S.K);
         double v = 0.0;
-        if (j < S.nrhs) v = S.lanes ? S.lanes[j].x[row] : S.X[(int64_t)j * S.n + row];
+        if (j < S.nrhs) {
+            if (!S.lanes)
+                v = S.X[(int64_t)j * S.n + row];
+            else if (S.lanes[j].x)  // a free lane of a served slot holds zeros
+                v = S.lanes[j].x[row];
+        }
         S.x[e] = v;
     }
 }
@@ -168,7 +173,12 @@ __global__ __launch_bounds__(kBB) void batch_init_kernel(BArgs a)
         if (m == 0) {
             const int64_t e = (int64_t)row * S.K + j;
             double bi = 0.0;
-            if (j < S.nrhs) bi = S.lanes ? S.lanes[j].b[row] : S.B[(int64_t)j * S.n + row];
+            if (j < S.nrhs) {
+                if (!S.lanes)
+                    bi = S.B[(int64_t)j * S.n + row];
+                else if (S.lanes[j].b)
+                    bi = S.lanes[j].b[row];
+            }
             const double ri = bi - ax;
             double zi = ri;
             S.r[e] = ri;
@@ -191,6 +201,21 @@ __global__ __launch_bounds__(kBB) void batch_init_kernel(BArgs a)
     block_sum_by_rhs(prr, S.K, red, base);
     block_sum_by_rhs(prz, S.K, red, base + a.part_stride);
     block_sum_by_rhs(pbb, S.K, red, base + 2 * a.part_stride);
+}
+
+// Block sum of one value per thread in a fixed order (wave butterflies, then
+// the waves in order); the result is valid in thread 0.  `red` holds
+// kBB / 64 values.
+__device__ __forceinline__ double sum_partials_in_block(double v, double *red)
+{
+    v = wave_sum(v);
+    __syncthreads();
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBB / kWave; ++w) t += red[w];
+    return t;
 }
 
 // Sum of region `reg` partials of system s for right-hand side j (fixed
@@ -518,7 +543,92 @@ __global__ __launch_bounds__(kBB) void batch_out_kernel(BArgs a)
     }
 }
 
-// Served group: right-hand side j of system `si` (finished) -> its caller x
+// Served slot: a request joins free lane j of running system `si`.  Setup of
+// that lane alone, one workgroup per tile of the system (a.tiles + tile0):
+// x[:, j] = caller x0, r = b - A x0 (SpMV over the caller's x0 directly), z =
+// D^-1 r (dinv from the slot's setup; the lane checks its diagonal itself),
+// p = z, and the tile partials of r.r, r.z, b.b for lane j.
+__global__ __launch_bounds__(kBB) void lane_init_kernel(BArgs a, int si, int j)
+{
+    __shared__ double red[3 * (kBB / kWave)];
+    const BSys S = a.sys[si];
+    const BTile t = a.tiles[S.tile0 + blockIdx.x];
+    const double *x0 = S.lanes[j].x;
+    const double *b = S.lanes[j].b;
+    const int K = S.K;
+    double part[3] = {0.0, 0.0, 0.0};
+    bool bad = false;
+    for (int row = t.row0 + threadIdx.x; row < t.row0 + t.rows; row += kBB) {
+        const int s0 = clampk(S.rp[row], S.nnz);
+        const int s1 = max(s0, clampk(S.rp[row + 1], S.nnz));
+        double ax = 0.0, dg = 0.0;
+        for (int k = s0; k < s1; ++k) {
+            const int c = S.ci[k];
+            if ((unsigned)c < (unsigned)S.n_cols) ax += S.val[k] * x0[c];
+            if (c == row) dg = S.val[k];
+        }
+        const int64_t e = (int64_t)row * K + j;
+        const double bi = b[row];
+        const double ri = bi - ax;
+        double zi = ri;
+        S.x[e] = x0[row];
+        S.r[e] = ri;
+        if (S.jac) {
+            bad = bad || !(dg > 0.0);
+            zi = S.dinv[row] * ri;
+            S.z[e] = zi;
+        }
+        S.p[e] = zi;
+        part[0] += ri * ri;
+        part[1] += ri * zi;
+        part[2] += bi * bi;
+    }
+    if (bad) a.scal[S.scal0 + j].pad = 1;  // same value from every writer
+    block_sum<3, kBB>(part, red);
+    if (threadIdx.x == 0)
+        for (int r = 0; r < 3; ++r)
+            a.part[r * a.part_stride + (int64_t)t.tile * kMaxK + j] = part[r];
+}
+
+// One workgroup: lane j's initial state from its tile partials (tile order),
+// as batch_r0_kernel does for a whole system; an active lane clears the
+// system's done flag.
+__global__ __launch_bounds__(kBB) void lane_r0_kernel(BArgs a, int si, int j)
+{
+    __shared__ double red[kBB / kWave];
+    const BSys S = a.sys[si];
+    double v[3];
+    for (int r = 0; r < 3; ++r) {
+        const double *base = a.part + r * a.part_stride;
+        double s = 0.0;
+        for (int q = threadIdx.x; q < S.ntiles; q += kBB) s += base[(int64_t)(S.tile0 + q) * kMaxK + j];
+        v[r] = sum_partials_in_block(s, red);
+    }
+    if (threadIdx.x == 0) {
+        BScal &c = a.scal[S.scal0 + j];
+        const bool badd = c.pad != 0;
+        const double rr = v[0], rz = v[1], bb = v[2];
+        c.rr = rr;
+        c.bb = bb;
+        c.rho = S.jac ? rz : rr;
+        c.stop2 = S.rtol2 * bb;
+        c.iter = 0;
+        int status = CGX_PENDING;
+        if (badd)
+            status = CGX_BREAKDOWN;
+        else if (!isfinite(bb) || !isfinite(rr) || !isfinite(rz))
+            status = CGX_NONFINITE;
+        else if (bb == 0.0 || rr <= S.rtol2 * bb)
+            status = CGX_OK;
+        else if (S.jac && !(rz > 0.0))
+            status = CGX_BREAKDOWN;
+        c.status = status;
+        c.active = status == CGX_PENDING;
+        if (c.active) a.sys_done[si] = 0;
+    }
+}
+
+// Served slot: right-hand side j of system `si` (finished) -> its caller x
 // (x = 0 where b = 0).
 __global__ __launch_bounds__(kBB) void lane_out_kernel(const BSys *sys, int si, int j,
                                                        const BScal *scal)

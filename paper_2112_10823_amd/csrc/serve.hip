@@ -56,17 +56,32 @@ struct Request {
     size_t bytes = 0;  // heap bytes: Krylov vectors plus a one-system tuning plan
 };
 
+enum LaneState : uint8_t { kLaneFree = 0, kLaneRunning = 1, kLaneJoining = 2 };
+
 struct Slot {
     bool used = false;
     bool fresh = false;
-    std::vector<Request> reqs;     // the group: right-hand side j is reqs[j]
-    std::vector<uint8_t> reported;  // per right-hand side: result published
-    size_t off = 0, bytes = 0;     // heap block of the group's vectors
+    std::vector<Request> lane;      // K lanes; lane j serves lane[j] while not free
+    std::vector<uint8_t> state;     // LaneState per lane
+    std::vector<double> t_start;    // admission / join time per lane
+    std::vector<int> sharing;       // per lane: requests in the slot when it started
+    size_t off = 0, bytes = 0;      // heap block of the slot's vectors
     int M = 1;
     int K = 1;
     int ntiles = 0;
-    double t_admit = 0.0;
-    const Request &head() const { return reqs.front(); }
+    Request key;                    // matrix and options every lane shares
+    int running() const
+    {
+        int c = 0;
+        for (uint8_t v : state) c += v != kLaneFree;
+        return c;
+    }
+    int free_lane() const
+    {
+        for (size_t j = 0; j < state.size(); ++j)
+            if (state[j] == kLaneFree) return (int)j;
+        return -1;
+    }
 };
 
 struct Result {
@@ -166,13 +181,13 @@ bool same_group(const Request &a, const Request &b)
            a.maxit == b.maxit && a.rtol == b.rtol;
 }
 
-// Device descriptor of slot `si`: interleaved x r p q z of the group's K
-// right-hand sides and dinv at the start of its heap block; b / x of each
-// request through the slot's lane table.
+// Device descriptor of slot `si`: interleaved x r p q z of its K lanes and
+// dinv at the start of its heap block; b / x of each request through the
+// slot's lane table (null for a free lane).
 BSys slot_sys(const Engine &E, int si, int tile0)
 {
     const Slot &s = E.slots[si];
-    const Request &q = s.head();
+    const Request &q = s.key;
     BSys S{};
     S.rp = q.A.row_ptr;
     S.ci = q.A.col_idx;
@@ -187,7 +202,7 @@ BSys slot_sys(const Engine &E, int si, int tile0)
     S.n = q.A.n_rows;
     S.n_cols = q.A.n_cols;
     S.K = s.K;
-    S.nrhs = (int)s.reqs.size();
+    S.nrhs = s.K;
     S.M = s.M;
     S.trows = tile_rows_for(s.K);
     S.tile0 = tile0;
@@ -228,8 +243,8 @@ BArgs engine_args(const Engine &E, bool fresh, int ntiles, int nlist)
     } while (0)
 
 // One cycle's device work: rebuild tables if membership changed, initialise
-// fresh slots, run `iters` iterations, copy finished right-hand sides out,
-// read back the slot states.
+// fresh slots and the lanes requests joined, run `iters` iterations, read
+// back the slot states.
 bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
 {
     hipStream_t s = E.stream;
@@ -271,8 +286,9 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
             const int32_t zd = 0;
             for (int i : list2) {
                 LanePtr lanes[kMaxK] = {};
-                const Slot &sl = E.slots[i];
-                for (size_t j = 0; j < sl.reqs.size(); ++j) lanes[j] = {sl.reqs[j].b, sl.reqs[j].x};
+                Slot &sl = E.slots[i];
+                for (int j = 0; j < sl.K; ++j)
+                    if (sl.state[j] != kLaneFree) lanes[j] = {sl.lane[j].b, sl.lane[j].x};
                 ENG_CHECK(hipMemcpyAsync(E.pool + E.off_lanes + sizeof(LanePtr) * kMaxK * i, lanes,
                                          sizeof(lanes), hipMemcpyHostToDevice, s));
                 ENG_CHECK(hipMemcpyAsync(E.pool + E.off_scal + sizeof(BScal) * kMaxK * i,
@@ -280,6 +296,8 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
                                          hipMemcpyHostToDevice, s));
                 ENG_CHECK(hipMemcpyAsync(E.pool + E.off_done + sizeof(int32_t) * i, &zd,
                                          sizeof(int32_t), hipMemcpyHostToDevice, s));
+                for (int j = 0; j < sl.K; ++j)
+                    if (sl.state[j] == kLaneJoining) sl.state[j] = kLaneRunning;
             }
             const BArgs f = engine_args(E, true, (int)tiles2.size(), (int)list2.size());
             hipLaunchKernelGGL(batch_in_kernel, dim3(f.ntiles), dim3(kBB), 0, s, f);
@@ -290,6 +308,24 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
         }
         active.assign(list.begin(), list.end());
         E.active_tiles = (int)tiles.size();
+    }
+    // requests that joined a free lane of a running slot: set that lane up
+    const BArgs m = engine_args(E, false, E.active_tiles, (int)active.size());
+    for (int i : active) {
+        Slot &sl = E.slots[i];
+        for (int j = 0; j < sl.K; ++j) {
+            if (sl.state[j] != kLaneJoining) continue;
+            const LanePtr lp = {sl.lane[j].b, sl.lane[j].x};
+            const BScal zero{};
+            ENG_CHECK(hipMemcpyAsync(E.pool + E.off_lanes + sizeof(LanePtr) * (kMaxK * i + j), &lp,
+                                     sizeof(lp), hipMemcpyHostToDevice, s));
+            ENG_CHECK(hipMemcpyAsync(E.pool + E.off_scal + sizeof(BScal) * (kMaxK * i + j), &zero,
+                                     sizeof(zero), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(lane_init_kernel, dim3(sl.ntiles), dim3(kBB), 0, s, m, i, j);
+            hipLaunchKernelGGL(lane_r0_kernel, dim3(1), dim3(kBB), 0, s, m, i, j);
+            ENG_CHECK(hipGetLastError());
+            sl.state[j] = kLaneRunning;
+        }
     }
     const int ntiles = E.active_tiles;
     if (!active.empty() && ntiles > 0) {
@@ -305,17 +341,39 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
     return true;
 }
 
-// Admission, FIFO with backfill: a head blocked longer than the limit stops
-// backfilling so large requests are not starved.  An admitted request takes
-// queued requests on the same matrix along, up to max_group, as long as the
-// group's vectors fit the heap (else the group shrinks).  Caller holds E.mu.
+// Rows from which a slot keeps one spare lane for later requests on its
+// matrix: there the matrix stream dominates an iteration and a joined
+// request costs little more than its own vectors.
+constexpr int64_t kSpareLaneRows = 1 << 16;
+
+// Admission.  A queued request first joins a free lane of a running slot on
+// the same matrix and options (at most max_group requests per slot); the
+// rest go FIFO with backfill into free slots (a head blocked longer than the
+// limit stops backfilling so large requests are not starved), each taking
+// queued requests on its matrix along, up to max_group, as long as the
+// slot's vectors fit the heap (else the group shrinks).  Caller holds E.mu.
 bool admit(Engine &E, int &ntiles_active)
 {
     bool changed = false;
     const double t = now_s();
-    bool blocked_head = false;
     std::vector<Request> pending(E.queue.begin(), E.queue.end());
     std::vector<uint8_t> taken(pending.size(), 0);
+    bool joined = false;
+    for (size_t h = 0; h < pending.size(); ++h)
+        for (int i = 0; i < E.max_slots; ++i) {
+            Slot &sl = E.slots[i];
+            if (!sl.used || sl.fresh || E.h_done[i] || !same_group(sl.key, pending[h])) continue;
+            const int j = sl.free_lane();
+            if (j < 0 || sl.running() >= E.max_group) continue;
+            sl.lane[j] = pending[h];
+            sl.state[j] = kLaneJoining;
+            sl.t_start[j] = t;
+            sl.sharing[j] = sl.running();
+            taken[h] = 1;
+            joined = true;
+            break;
+        }
+    bool blocked_head = false;
     for (size_t h = 0; h < pending.size(); ++h) {
         if (taken[h]) continue;
         int free_slot = -1;
@@ -330,11 +388,14 @@ bool admit(Engine &E, int &ntiles_active)
             if (!taken[k] && same_group(pending[h], pending[k])) members.push_back(k);
         bool fits = false;
         size_t off = 0, bytes = 0;
-        int nt = 0;
+        int nt = 0, K = 1;
         while (!members.empty()) {
             const int g = (int)members.size();
-            bytes = group_bytes(pending[h].A.n_rows, g);
-            nt = tiles_of(pending[h].A.n_rows, g);
+            const bool spare = g < E.max_group && pending[h].A.n_rows >= kSpareLaneRows;
+            K = pad_k(g);
+            if (K == g && spare) K = pad_k(g + 1);
+            bytes = group_bytes(pending[h].A.n_rows, K);
+            nt = tiles_of(pending[h].A.n_rows, K);
             if (ntiles_active + nt <= E.max_tiles && E.alloc(bytes, off)) {
                 fits = true;
                 break;
@@ -349,21 +410,24 @@ bool admit(Engine &E, int &ntiles_active)
         Slot &sl = E.slots[free_slot];
         sl.used = true;
         sl.fresh = true;
-        sl.reqs.clear();
-        for (size_t m : members) {
-            sl.reqs.push_back(pending[m]);
-            taken[m] = 1;
+        sl.K = K;
+        sl.key = pending[h];
+        sl.lane.assign(K, Request{});
+        sl.state.assign(K, kLaneFree);
+        sl.t_start.assign(K, t);
+        sl.sharing.assign(K, (int)members.size());
+        for (size_t q = 0; q < members.size(); ++q) {
+            sl.lane[q] = pending[members[q]];
+            sl.state[q] = kLaneJoining;
+            taken[members[q]] = 1;
         }
-        sl.reported.assign(sl.reqs.size(), 0);
-        sl.K = pad_k((int)sl.reqs.size());
         sl.off = off;
         sl.bytes = bytes;
         sl.ntiles = nt;
-        sl.t_admit = t;
         ntiles_active += nt;
         changed = true;
     }
-    if (changed) {
+    if (changed || joined) {
         E.queue.clear();
         for (size_t k = 0; k < pending.size(); ++k)
             if (!taken[k]) E.queue.push_back(pending[k]);
@@ -394,8 +458,8 @@ void engine_loop(Engine *Ep)
         for (Slot &sl : E.slots) {
             if (!sl.used || !sl.fresh) continue;
             cgx_system sys{};
-            sys.A = sl.head().A;
-            sys.nrhs = (int)sl.reqs.size();
+            sys.A = sl.key.A;
+            sys.nrhs = sl.K;
             int M = 1;
             if (tune_one(E.c, sys, E.pool + sl.off, sl.bytes, E.stream, M) != CGX_OK) {
                 std::lock_guard<std::mutex> lk(E.mu);
@@ -408,8 +472,7 @@ void engine_loop(Engine *Ep)
         // iterations this cycle: about 1 ms of device work
         double bytes = 0.0;
         for (const Slot &sl : E.slots)
-            if (sl.used)
-                bytes += 12.0 * sl.head().A.nnz + 88.0 * sl.K * sl.head().A.n_rows;
+            if (sl.used) bytes += 12.0 * sl.key.A.nnz + 88.0 * sl.K * sl.key.A.n_rows;
         int iters = (int)(1.0e-3 / (bytes / 4.0e12 + 25.0e-6));
         iters = iters < 1 ? 1 : (iters > 16 ? 16 : iters);
         if (!device_cycle(E, changed, iters, active)) {
@@ -418,8 +481,8 @@ void engine_loop(Engine *Ep)
             return;
         }
         changed = false;
-        // retire finished right-hand sides (copied out at once), and slots
-        // whose right-hand sides are all finished
+        // retire each finished request (its x copied out at once), and slots
+        // whose lanes have all finished
         const double t = now_s();
         std::vector<std::pair<uint64_t, cgx_stats>> finished;
         const BSys *dsys = reinterpret_cast<const BSys *>(E.pool + E.off_sys);
@@ -427,24 +490,24 @@ void engine_loop(Engine *Ep)
         for (int i : active) {
             Slot &sl = E.slots[i];
             if (!sl.used) continue;
-            for (size_t j = 0; j < sl.reqs.size(); ++j) {
+            for (int j = 0; j < sl.K; ++j) {
                 const BScal &v = E.h_scal[(size_t)i * kMaxK + j];
-                if (sl.reported[j] || (v.active && !E.h_done[i])) continue;
-                const Request &q = sl.reqs[j];
+                if (sl.state[j] != kLaneRunning || (v.active && !E.h_done[i])) continue;
+                const Request &q = sl.lane[j];
                 cgx_stats st{};
                 st.status = v.status == CGX_PENDING ? CGX_NOT_CONVERGED : v.status;
                 st.iters = v.iter;
-                st.outer_iters = (int)sl.reqs.size();
+                st.outer_iters = sl.sharing[j];
                 st.path = 4;
                 st.relres = v.bb > 0.0 ? std::sqrt(v.rr / v.bb) : 0.0;
                 if (v.bb == 0.0 && v.status == CGX_OK) st.relres = 0.0;
                 st.relres_true = -1.0;
-                st.queue_ms = 1e3 * (sl.t_admit - q.t_submit);
+                st.queue_ms = 1e3 * (sl.t_start[j] - q.t_submit);
                 st.latency_ms = 1e3 * (t - q.t_submit);
-                hipLaunchKernelGGL(lane_out_kernel, dim3(256), dim3(kBB), 0, E.stream, dsys, i,
-                                   (int)j, dscal);
+                hipLaunchKernelGGL(lane_out_kernel, dim3(256), dim3(kBB), 0, E.stream, dsys, i, j,
+                                   dscal);
                 finished.emplace_back(q.ticket, st);
-                sl.reported[j] = 1;
+                sl.state[j] = kLaneFree;
             }
             if (!E.h_done[i]) continue;
             E.release(sl.off, sl.bytes);

@@ -124,6 +124,34 @@ def test_grouped_requests_match_oracle_and_alone(resident):
             assert (torch.linalg.norm(xa - x) / torch.linalg.norm(xa)).item() <= 1e-8
 
 
+def test_late_requests_join_a_running_slot():
+    """A request arriving while a slot on its matrix runs takes a free lane of
+    that slot (started mid-solve of the others) and still matches the oracle."""
+    A = synth.q1cube(44, 1.0, 12)  # 85184 rows: its slot keeps a spare lane
+    dA = cgx.DeviceCSR.from_host(A)
+    opts = cgx.make_opts(rtol=1e-11)
+    bs = [synth.uniform(900 + i, A.n_rows) for i in range(4)]
+    xs = [torch.zeros(A.n_rows, dtype=torch.float64, device="cuda") for _ in bs]
+    with cgx.Server(pool(1 << 30), max_slots=1, max_group=16) as srv:
+        t0 = srv.submit(dA, dev(bs[0]), xs[0], opts)
+        time.sleep(0.002)  # the first request now holds the only slot (one spare lane)
+        ts = [t0] + [srv.submit(dA, dev(b), x, opts) for b, x in zip(bs[1:], xs[1:])]
+        sts = [srv.wait(t) for t in ts]
+    assert sts[0].outer_iters == 1
+    # the second request took the spare lane while the first was running; the
+    # other two waited for the slot and then ran as one group
+    assert sts[1].outer_iters == 2 and sts[1].queue_ms < sts[0].latency_ms
+    assert sts[2].outer_iters == sts[3].outer_iters == 2
+    for b, x, st in zip(bs, xs, sts):
+        ref = oracle.cg(A, b, rtol=1e-11)
+        xg = x.cpu().numpy()
+        # about 380 iterations with the multi-RHS SpMM's summation order: the
+        # crossing of the threshold may move by a few iterations
+        assert st.status == cgx.OK and abs(st.iters - ref.iters) <= 4, (st.as_dict(), ref.iters)
+        assert true_relres(A, b, xg) <= 1.5e-11
+        assert np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x) <= 1e-7
+
+
 def test_admission_by_memory(resident):
     mats, dmats = resident
     need = cgx.Server.request_bytes(mats[3].n_rows)
