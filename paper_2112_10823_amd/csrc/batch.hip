@@ -13,12 +13,14 @@
 // systems: (1) SpMM q = A p with per-tile p.q partials, (R1) one workgroup
 // per system adds them in tile order and forms alpha per right-hand side,
 // (2) x/r/z updates with r.r / r.z partials, (R2) the stopping test and beta,
-// (3) p = z + beta p.  A row is served by K * M lanes (lane = m * K + j:
-// right-hand side j, nonzero slice m); M is picked per system by the
-// autotuner.  Every reduction a system depends on runs over that system's
-// own tiles in a fixed order, so a system's iterates are the same bits alone
-// or in any batch (given the same schedule).  Converged right-hand sides are
-// masked; a system whose right-hand sides are all done is skipped.
+// (3) p = z + beta p.  The SpMM schedule of a system is either K * M lanes
+// per row (lane = m * K + j: right-hand side j, nonzero slice m) or wave
+// tiles (M < 0: -M rows per wavefront, col_idx / val staged in LDS), picked
+// per shape class by the autotuner unless the system fixes it.  Every
+// reduction a system depends on runs over that system's own tiles in a fixed
+// order, so a system's iterates are the same bits alone or in any batch
+// (given the same schedule).  Converged right-hand sides are masked; a
+// system whose right-hand sides are all done is skipped.
 #include <algorithm>
 #include <cmath>
 #include <mutex>

@@ -28,11 +28,9 @@
 namespace cgx {
 namespace {
 
-constexpr int kSB = kStreamBlock;    // threads per workgroup of the CSR-stream pass (true residual)
 constexpr int kRB = 256;             // threads per workgroup of the p.q tile-partial reduction
 constexpr int kMinTilesPerRed = 512; // tile partials per reduction workgroup, at least
 constexpr int kPB = 512;             // threads per workgroup of the other phase kernels
-constexpr int kSpmvBlocksPerCu = 8;
 constexpr int kPhaseBlocksPerCu = 4;
 constexpr int kMaxPhaseBlocks = 2048;
 constexpr int kRowsPerGroup = 4;     // vector-CSR rows per lane group (setup passes)
@@ -65,8 +63,6 @@ struct CgArgs {
     int ntiles;           // wave tiles of the SpMV phase (= its workgroups)
     int tiles_per_red;    // tile partials added by one reduction workgroup
     int n_pq;             // p.q partials in region kPPq
-    int tiles_per_block;  // CSR-stream pass: row tiles per workgroup
-    int grid_sp;          // workgroups of the CSR-stream pass (partials it writes)
     int grid_ew;          // workgroups of the update phase
 };
 
@@ -203,14 +199,16 @@ __global__ __launch_bounds__(kWave) void cg_spmv_kernel(CgArgs<T> a)
 
 // (1b) Workgroup b adds tile partials [b * tiles_per_red, ...) in index order
 // into slot b of region kPPq.
-template <typename T>
+// kStop: return once the solve has stopped (inside the iteration; the true
+// residual pass after the solve reduces regardless).
+template <typename T, bool kStop>
 __global__ __launch_bounds__(kRB) void cg_pq_reduce_kernel(CgArgs<T> a)
 {
     const int t0 = blockIdx.x * a.tiles_per_red;
     const int count = max(0, min(a.tiles_per_red, a.ntiles - t0));
     __shared__ T red[kRB / kWave];
     const T s = sum_partials<kRB>(a.tpart + t0, count, red);  // loads in flight with st->done's
-    if (a.st->done) return;
+    if (kStop && a.st->done) return;
     if (threadIdx.x == 0) region(a, kPPq)[blockIdx.x] = s;
 }
 
@@ -313,34 +311,30 @@ __global__ __launch_bounds__(kPB) void cg_direction_kernel(CgArgs<T> a)
         p[i] = __builtin_fma(beta, p[i], z[i]);
 }
 
-// ||b - A x||^2 partials (region kPAux), then one workgroup into st->rr_true.
+// ||b - A x||^2 after the solve: one partial per wave tile, written to the
+// p.q tile partials (free once the iteration has stopped), reduced like p.q
+// into region kPPq, then one workgroup into st->rr_true.
 template <int RT>
-__global__ __launch_bounds__(kSB) void cg_true_residual_kernel(CgArgs<double> a)
+__global__ __launch_bounds__(kWave) void cg_true_residual_kernel(CgArgs<double> a)
 {
-    __shared__ StreamSmem<kSB, kStreamE, RT, double> sm;
-    const int ntiles = (a.n + RT - 1) / RT;
-    int t0, t1;
-    tile_range(ntiles, a.tiles_per_block, t0, t1);
-    double part = 0.0;
-    for (int t = t0; t < t1; ++t) {
-        int row;
-        const double acc = stream_rows<kSB, kStreamE, RT, double>(t * RT, a.n, a.n_cols, a.nnz,
+    __shared__ WaveSmem<wave_e<double>(), RT, double> sm;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    int row;
+    const double acc = wave_rows<wave_e<double>(), RT, 4, double>(tile * RT, a.n, a.n_cols, a.nnz,
                                                                   a.rp, a.ci, a.val, a.x, sm, row);
-        if (threadIdx.x % (kSB / RT) == 0 && row < a.n) {
-            const double d = a.b[row] - acc;
-            part += d * d;
-        }
+    double part = 0.0;
+    if (threadIdx.x % (kWave / RT) == 0 && row < a.n) {
+        const double d = a.b[row] - acc;
+        part = d * d;
     }
-    __shared__ double red[kSB / kWave];
-    double v[1] = {part};
-    block_sum<1, kSB>(v, red);
-    if (threadIdx.x == 0) region(a, kPAux)[blockIdx.x] = v[0];
+    part = wave_sum(part);
+    if (threadIdx.x == 0) a.tpart[tile] = part;
 }
 
-__global__ __launch_bounds__(kPB) void cg_true_residual_finish_kernel(CgArgs<double> a, int count)
+__global__ __launch_bounds__(kPB) void cg_true_residual_finish_kernel(CgArgs<double> a)
 {
     __shared__ double red[kPB / kWave];
-    const double rr = sum_partials<kPB>(region(a, kPAux), count, red);
+    const double rr = sum_partials<kPB>(region(a, kPPq), a.n_pq, red);
     if (threadIdx.x == 0) a.st->rr_true = rr;
 }
 
@@ -797,9 +791,6 @@ struct Grids {
     int grid_red;       // workgroups of the p.q reduction, 0 when the tiles write region kPPq
     int tiles_per_red;  // tile partials per reduction workgroup
     int n_pq;           // p.q partials the update phase adds
-    int RTs;            // rows per CSR-stream tile (true-residual pass)
-    int grid_sp;        // workgroups of the CSR-stream pass (persistent over tiles)
-    int tiles_per_block;
     int grid_ew;        // workgroups of the elementwise phases
     int grid_vr;        // workgroups of the vector-CSR setup passes
 };
@@ -820,12 +811,7 @@ Grids make_grids(const Context *c, int64_t n, int64_t nnz, bool mixed)
         g.grid_red = (int)((g.ntiles + g.tiles_per_red - 1) / g.tiles_per_red);
         g.n_pq = g.grid_red;
     }
-    g.RTs = stream_tile_rows(n, nnz, kStreamE);
     const int cap = std::min(c->num_cu * kPhaseBlocksPerCu, kMaxPhaseBlocks);
-    const int cap_sp = std::min(c->num_cu * kSpmvBlocksPerCu, kMaxPhaseBlocks);
-    const int64_t stiles = (n + g.RTs - 1) / g.RTs;
-    g.grid_sp = (int)std::max<int64_t>(1, std::min<int64_t>(cap_sp, stiles));
-    g.tiles_per_block = (int)((stiles + g.grid_sp - 1) / g.grid_sp);
     const int64_t ew_need = (n + kPB - 1) / kPB;
     g.grid_ew = (int)std::max<int64_t>(1, std::min<int64_t>(cap, ew_need));
     const int RPB = (kPB / g.L) * kRowsPerGroup;
@@ -841,8 +827,6 @@ void bind_grids(const Grids &g, CgArgs<T> &a, void *tpart_ws)
     a.ntiles = g.ntiles;
     a.tiles_per_red = g.tiles_per_red;
     a.n_pq = g.n_pq;
-    a.tiles_per_block = g.tiles_per_block;
-    a.grid_sp = g.grid_sp;
     a.grid_ew = g.grid_ew;
     a.tpart = g.grid_red > 0 ? static_cast<T *>(tpart_ws) : region(a, kPPq);
 }
@@ -873,7 +857,7 @@ template <typename T>
 void launch_pq_reduce(const Grids &g, hipStream_t s, const CgArgs<T> &a)
 {
     if (g.grid_red > 0)
-        hipLaunchKernelGGL((cg_pq_reduce_kernel<T>), dim3(g.grid_red), dim3(kRB), 0, s, a);
+        hipLaunchKernelGGL((cg_pq_reduce_kernel<T, true>), dim3(g.grid_red), dim3(kRB), 0, s, a);
 }
 
 template <typename T>
@@ -906,10 +890,13 @@ void launch_iteration(const Grids &g, bool jac, hipStream_t s, const CgArgs<T> &
 void launch_true_residual(const Grids &g, hipStream_t s, const CgArgs<double> &a)
 {
 #define CGX_TR(RR) \
-    hipLaunchKernelGGL((cg_true_residual_kernel<RR>), dim3(g.grid_sp), dim3(kSB), 0, s, a)
-    CGX_RT_SWITCH(g.RTs, CGX_TR)
+    hipLaunchKernelGGL((cg_true_residual_kernel<RR>), dim3(g.ntiles), dim3(kWave), 0, s, a)
+    CGX_WRT_SWITCH(g.RT, CGX_TR)
 #undef CGX_TR
-    hipLaunchKernelGGL(cg_true_residual_finish_kernel, dim3(1), dim3(kPB), 0, s, a, g.grid_sp);
+    if (g.grid_red > 0)
+        hipLaunchKernelGGL((cg_pq_reduce_kernel<double, false>), dim3(g.grid_red), dim3(kRB), 0, s,
+                           a);
+    hipLaunchKernelGGL(cg_true_residual_finish_kernel, dim3(1), dim3(kPB), 0, s, a);
 }
 
 void launch_resident(bool jac, hipStream_t s, const CgArgs<double> &a, double rtol2)

@@ -1,6 +1,6 @@
 // Device building blocks for gfx950: wave64 reductions, XCD-aware block
-// numbering, the vector-CSR, CSR-stream and wave-tile row bodies and the
-// fixed-order sum of per-workgroup partials.
+// numbering, the vector-CSR and wave-tile row bodies and the fixed-order sum
+// of per-workgroup partials.
 //
 // Grid-wide sums never use a per-workgroup device-scope fence (on this
 // multi-die part such a release writes back the die's L2 and halved the
@@ -149,82 +149,6 @@ __device__ __forceinline__ void vector_rows(int row0, int n_rows, int n_cols, in
         acc[r] = group_sum<L>(acc[r]);
         if (kDiag) dg[r] = group_sum<L>(dg[r]);
     }
-}
-
-// ------------------------------------------------------- stream CSR rows --
-
-// Shared-memory staging of one CSR-stream tile: BS * E products plus the
-// tile's RT + 1 row starts.
-template <int BS, int E, int RT, typename T>
-struct StreamSmem {
-    T prod[BS * E];
-    int rp[RT + 1];
-};
-
-// CSR-stream tile of RT consecutive rows starting at row0, BS threads, E
-// entries per thread per chunk.  Phase 1: all threads read the tile's
-// col_idx / val as one contiguous stream (thread t takes entries c0 + t +
-// BS * j, j < E: E independent coalesced loads in flight per thread, with the
-// non-temporal hint since each entry is used once), gather x and stage the
-// products in LDS.  Phase 2: TPR = BS / RT threads per row
-// add the row's staged products (thread `sub` takes entries sub, sub + TPR,
-// ...) and combine by butterfly.  Tiles with more than BS * E entries are
-// processed in several chunks.  Returns the row sum in all TPR threads of the
-// row's group; `row` receives the row index (>= n_rows for idle groups).
-// Indices are clamped as in vector_rows.  Must be reached by all threads.
-template <int BS, int E, int RT, typename T>
-__device__ __forceinline__ T stream_rows(int row0, int n_rows, int n_cols, int64_t nnz,
-                                         const int32_t *__restrict__ rp,
-                                         const int32_t *__restrict__ ci,
-                                         const T *__restrict__ val, const T *__restrict__ x,
-                                         StreamSmem<BS, E, RT, T> &sm, int &row)
-{
-    constexpr int TPR = BS / RT;
-    constexpr int C = BS * E;
-    static_assert(TPR >= 1 && TPR <= kWave && (TPR & (TPR - 1)) == 0, "threads per row");
-    const int nr = min(RT, n_rows - row0);
-    __syncthreads();  // the previous tile's readers of sm are done
-    for (int i = threadIdx.x; i <= nr; i += BS) {
-        int v = rp[row0 + i];
-        v = v < 0 ? 0 : (v > nnz ? (int)nnz : v);
-        sm.rp[i] = v;
-    }
-    __syncthreads();
-    const int k0 = sm.rp[0];
-    const int k1 = max(k0, sm.rp[nr]);
-    const int g = threadIdx.x / TPR, sub = threadIdx.x % TPR;
-    row = row0 + g;
-    int s = k0, e = k0;
-    if (g < nr) {
-        s = max(sm.rp[g], k0);
-        e = min(max(sm.rp[g + 1], s), k1);
-    }
-    T acc = T(0);
-    for (int c0 = k0; c0 < k1; c0 += C) {
-        int col[E];
-        T a[E];
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-            const int k = c0 + threadIdx.x + BS * j;
-            col[j] = -1;
-            a[j] = T(0);
-            if (k < k1) {  // streamed once: non-temporal, keeps x resident in L2
-                col[j] = __builtin_nontemporal_load(&ci[k]);
-                a[j] = __builtin_nontemporal_load(&val[k]);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-            T v = T(0);
-            if ((unsigned)col[j] < (unsigned)n_cols) v = a[j] * x[col[j]];
-            sm.prod[threadIdx.x + BS * j] = v;
-        }
-        __syncthreads();
-        const int lo = max(s, c0), hi = min(e, c0 + C);
-        for (int k = lo + sub; k < hi; k += TPR) acc += sm.prod[k - c0];
-        __syncthreads();
-    }
-    return group_sum<TPR>(acc);
 }
 
 // ---------------------------------------------------------- wave CSR rows --

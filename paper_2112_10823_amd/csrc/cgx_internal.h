@@ -40,17 +40,11 @@ void clear_error();
 
 constexpr int kBlock = 256;         // threads per workgroup for streaming kernels
 constexpr int kReduceBlocks = 1024; // fixed grid of the standalone reductions
-constexpr int kStreamBlock = 256;   // threads per workgroup of the CSR-stream SpMV
-constexpr int kStreamE = 8;         // float64 entries per thread per CSR-stream chunk
 constexpr int kProfWindow = 32;     // profile mode: iterations launched between host checks
 
-// Rows per CSR-stream tile: the largest power of two in [8, kStreamBlock] whose
-// expected entries (rows * mean row length) fill at most 90% of one chunk of
-// kStreamBlock * kStreamE entries.
-int stream_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_thread = kStreamE);
-
 // Wave tiles (one wavefront per tile, 64 * E entries per chunk): E = 8
-// float64 or 16 binary32 entries per lane, as for the CSR-stream tiles.
+// float64 or 16 binary32 entries per lane (64 bytes of values in flight per
+// lane either way).
 template <typename T>
 constexpr int wave_e() { return 64 / (int)sizeof(T); }
 
@@ -69,19 +63,10 @@ int wave_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_lane);
         default: EXPR_T(64); break;   \
     }
 
-#define CGX_RT_SWITCH(RT, EXPR_T)     \
-    switch (RT) {                     \
-        case 8: EXPR_T(8); break;     \
-        case 16: EXPR_T(16); break;   \
-        case 32: EXPR_T(32); break;   \
-        case 64: EXPR_T(64); break;   \
-        case 128: EXPR_T(128); break; \
-        default: EXPR_T(256); break;  \
-    }
-
-// Device-side CG state, stored at the start of the solver workspace.  All
-// fields are written by the single "last" workgroup of a reduction and read
-// by the following kernels.
+// Device-side CG state, stored at the start of the solver workspace.  Its
+// fields are written by thread 0 of workgroup 0 of the kernel that forms
+// them (every workgroup computes the same values) and read by the following
+// kernels.
 struct CgState {
     double rho;    // r.z of the current iterate (r.r without preconditioner)
     double rho_used; // rho of the iteration in flight (copied by the update kernel)

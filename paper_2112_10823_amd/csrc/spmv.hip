@@ -83,15 +83,6 @@ __global__ __launch_bounds__(kBlock) void csr_validate_kernel(int n_rows, int n_
 
 }  // namespace
 
-int stream_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_thread)
-{
-    const double mean = n_rows > 0 ? (double)nnz / (double)n_rows : 1.0;
-    const double budget = 0.9 * kStreamBlock * entries_per_thread;
-    int rt = kStreamBlock;
-    while (rt > 8 && rt * (mean > 1.0 ? mean : 1.0) > budget) rt /= 2;
-    return rt;
-}
-
 int wave_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_lane)
 {
     const double mean = n_rows > 0 ? (double)nnz / (double)n_rows : 1.0;
