@@ -236,19 +236,29 @@ def extra_spmv_and_cg(cgx, synth, meter):
     xv = torch.from_numpy(synth.uniform(4, n)).cuda()
     yv = torch.empty_like(xv)
     t_sp = _timeit(lambda: cgx.csr_spmv(dA, xv, yv), reps=50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = cgx.SellMatrix(dA)  # sliced-ELL copy (sync build)
+    t_build = time.perf_counter() - t0
+    t_sell = _timeit(lambda: cgx.sell_spmv(S, xv, yv), reps=50)
+    sell_bytes = 12 * S.stored + 8 * (S.n_slices + 1) + 16 * n
     db = torch.from_numpy(b).cuda()
     res = {"workload": "Q1 128^3 lognormal(0,1), blob RHS, rtol 1e-8",
            "spmv_us": round(t_sp * 1e6, 1),
-           "spmv_GBs": round(spmv_bytes(n, nnz) / t_sp / 1e9, 1)}
-    for name, pc in (("plain", 0), ("jacobi", 1)):
+           "spmv_GBs": round(spmv_bytes(n, nnz) / t_sp / 1e9, 1),
+           "sell": {"stored": S.stored, "padding": round(S.stored / nnz - 1, 5),
+                    "build_ms": round(t_build * 1e3, 2), "spmv_us": round(t_sell * 1e6, 1),
+                    "spmv_GBs": round(sell_bytes / t_sell / 1e9, 1),
+                    "spmv_GBs_csr_bytes": round(spmv_bytes(n, nnz) / t_sell / 1e9, 1)}}
+    for name, pc, sell in (("plain", 0, None), ("jacobi", 1, None), ("jacobi_sell", 1, S)):
         dx = torch.zeros_like(db)
         opts = cgx.make_opts(rtol=RTOL, precond=pc)
         ws = cgx.cg_workspace(dA, opts)
-        st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
+        st = cgx.cg_solve(dA, db, dx, opts, workspace=ws, sell=sell)
 
         def solve():
             dx.zero_()
-            cgx.cg_solve(dA, db, dx, opts, workspace=ws)
+            cgx.cg_solve(dA, db, dx, opts, workspace=ws, sell=sell)
 
         wall, j = _energy_window(solve, meter, min_s=2.0)
         per_it = spmv_bytes(n, nnz) + (72 * n if pc == 0 else 88 * n)
@@ -269,13 +279,17 @@ def extra_mixed(cgx, synth, meter):
     db = torch.from_numpy(b).cuda()
     out = {"workload": "Q1 192^3 (7,077,888 rows, 189,119,224 nnz) lognormal(0,1.5), "
                        "uniform RHS, rtol 1e-10"}
-    runs = [("fp64_plain", cgx.PRECISION_FP64, 0, 0.0), ("fp64_jacobi", cgx.PRECISION_FP64, 1, 0.0),
-            ("mixed_plain_tau1e-3", cgx.PRECISION_MIXED, 0, 1e-3),
-            ("mixed_jacobi_tau1e-2", cgx.PRECISION_MIXED, 1, 1e-2),
-            ("mixed_jacobi_tau1e-3", cgx.PRECISION_MIXED, 1, 1e-3),
-            ("mixed_jacobi_tau1e-4", cgx.PRECISION_MIXED, 1, 1e-4)]
+    S = cgx.SellMatrix(dA)  # sliced-ELL copy (float64 and binary32 values)
+    runs = [("fp64_plain", cgx.PRECISION_FP64, 0, 0.0, None),
+            ("fp64_jacobi", cgx.PRECISION_FP64, 1, 0.0, None),
+            ("mixed_plain_tau1e-3", cgx.PRECISION_MIXED, 0, 1e-3, None),
+            ("mixed_jacobi_tau1e-2", cgx.PRECISION_MIXED, 1, 1e-2, None),
+            ("mixed_jacobi_tau1e-3", cgx.PRECISION_MIXED, 1, 1e-3, None),
+            ("mixed_jacobi_tau1e-4", cgx.PRECISION_MIXED, 1, 1e-4, None),
+            ("fp64_jacobi_sell", cgx.PRECISION_FP64, 1, 0.0, S),
+            ("mixed_jacobi_tau1e-2_sell", cgx.PRECISION_MIXED, 1, 1e-2, S)]
     ref = None
-    for name, prec, pc, tau in runs:
+    for name, prec, pc, tau, sell in runs:
         opts = cgx.make_opts(rtol=1e-10, precond=pc, precision=prec, inner_rtol=tau,
                              maxit=20000)
         ws = cgx.cg_workspace(dA, opts)
@@ -285,7 +299,7 @@ def extra_mixed(cgx, synth, meter):
         def solve():
             nonlocal st
             dx.zero_()
-            st = cgx.cg_solve(dA, db, dx, opts, workspace=ws)
+            st = cgx.cg_solve(dA, db, dx, opts, workspace=ws, sell=sell)
 
         solve()
         wall, j = _energy_window(solve, meter, min_s=2.0)

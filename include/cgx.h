@@ -172,6 +172,52 @@ size_t cgx_cg_workspace_bytes(int64_t n_rows, int64_t nnz, const cgx_opts *opts)
 int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, void *workspace,
                  size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats);
 
+/* ------------------------------------------------- sliced ELL (SELL) -- */
+
+/* Sliced ELLPACK copy of a CSR matrix (Section 2.3 names ELL among the
+ * sparse storage formats; the paper's measurements use CSR).  Rows in slices
+ * of 64 (one wavefront), each slice stored column-major with the width of
+ * its longest row: entry k of row 64 s + l is at slice_ptr[s] + 64 k + l,
+ * in the row's CSR order; padding entries have column -1 and value 0.  Rows
+ * are not reordered.  All arrays are device memory inside one caller buffer
+ * (see cgx_sell_build); the struct only points into it. */
+typedef struct cgx_sell {
+    int32_t n_rows;
+    int32_t n_cols;
+    int64_t n_slices;          /* ceil(n_rows / 64) */
+    int64_t stored;            /* slice_ptr[n_slices]: entries including padding */
+    const int64_t *slice_ptr;  /* int64[n_slices + 1] */
+    const int32_t *col;        /* int32[stored] */
+    const double *val;         /* float64[stored] */
+    const float *val32;        /* binary32[stored] when A had val32, else NULL */
+} cgx_sell;
+
+/* (sync) Device bytes cgx_sell_build needs for A (one pass over row_ptr). */
+int cgx_sell_bytes(cgx_handle h, const cgx_csr *A, size_t *bytes);
+
+/* (sync) Build the sliced-ELL copy of A into `buffer` (device, 256-byte
+ * aligned, >= cgx_sell_bytes; owned by the caller, which keeps it while
+ * *out is used) and describe it in *out.  Row pointers are clamped as by the
+ * other kernels; A->val32, if set, is copied too.  CGX_ENOMEM if bytes is too
+ * small. */
+int cgx_sell_build(cgx_handle h, const cgx_csr *A, void *buffer, size_t bytes, cgx_sell *out);
+
+/* y = A x from the sliced-ELL copy (Section 5.2, table "SpMV with CSR
+ * format": the same product); float64, each row summed in its CSR order.
+ * x: float64[n_cols], y: float64[n_rows]; y must not overlap x. */
+int cgx_sell_spmv(cgx_handle h, const cgx_sell *S, const double *x, double *y);
+
+/* y = A32 x in binary32 from S->val32; y must not overlap x. */
+int cgx_sell_spmv_f32(cgx_handle h, const cgx_sell *S, const float *x, float *y);
+
+/* (sync) cgx_cg_solve with the SpMV of the iteration (q = A p, and the inner
+ * binary32 SpMV of MIXED, which needs S->val32) run on the sliced-ELL copy S
+ * of A; the setup and residual passes read A.  Same workspace, arguments and
+ * results as cgx_cg_solve. */
+int cgx_cg_solve_sell(cgx_handle h, const cgx_csr *A, const cgx_sell *S, const double *b,
+                      double *x, void *workspace, size_t workspace_bytes, const cgx_opts *opts,
+                      cgx_stats *stats);
+
 /* ------------------------------------------------------------ batched -- */
 
 /* One system of a batch: matrix, right-hand sides and solutions.  B and X

@@ -58,6 +58,13 @@ class Stats(ctypes.Structure):
         return d
 
 
+class _Sell(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32),
+                ("n_slices", ctypes.c_int64), ("stored", ctypes.c_int64),
+                ("slice_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("val32", ctypes.c_void_p)]
+
+
 class _System(ctypes.Structure):
     _fields_ = [("A", _Csr), ("nrhs", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("B", ctypes.c_void_p), ("X", ctypes.c_void_p)]
@@ -67,6 +74,7 @@ EXPORTS = [
     "cgx_create", "cgx_destroy", "cgx_set_stream", "cgx_last_error", "cgx_version",
     "cgx_csr_validate", "cgx_csr_spmv", "cgx_csr_spmv_f32", "cgx_add", "cgx_axpy", "cgx_xmul",
     "cgx_dot", "cgx_demote", "cgx_cg_workspace_bytes", "cgx_cg_solve",
+    "cgx_sell_bytes", "cgx_sell_build", "cgx_sell_spmv", "cgx_sell_spmv_f32", "cgx_cg_solve_sell",
     "cgx_batch_workspace_bytes", "cgx_cg_solve_batched", "cgx_batch_schedule",
     "cgx_serve_start", "cgx_serve_stop", "cgx_serve_request_bytes", "cgx_submit", "cgx_poll",
     "cgx_wait",
@@ -102,6 +110,12 @@ def load_library(path: str = LIB_PATH):
         "cgx_cg_workspace_bytes": ([i64, i64, P(Opts)], ctypes.c_size_t),
         "cgx_cg_solve": ([vp, P(_Csr), vp, vp, vp, ctypes.c_size_t, P(Opts), P(Stats)],
                          ctypes.c_int),
+        "cgx_sell_bytes": ([vp, P(_Csr), P(ctypes.c_size_t)], ctypes.c_int),
+        "cgx_sell_build": ([vp, P(_Csr), vp, ctypes.c_size_t, P(_Sell)], ctypes.c_int),
+        "cgx_sell_spmv": ([vp, P(_Sell), vp, vp], ctypes.c_int),
+        "cgx_sell_spmv_f32": ([vp, P(_Sell), vp, vp], ctypes.c_int),
+        "cgx_cg_solve_sell": ([vp, P(_Csr), P(_Sell), vp, vp, vp, ctypes.c_size_t, P(Opts),
+                               P(Stats)], ctypes.c_int),
         "cgx_batch_workspace_bytes": ([i32, P(_System)], ctypes.c_size_t),
         "cgx_cg_solve_batched": ([vp, i32, P(_System), vp, ctypes.c_size_t, P(Opts), P(Stats)],
                                  ctypes.c_int),
@@ -222,6 +236,49 @@ class DeviceCSR:
         return d
 
 
+class SellMatrix:
+    """Sliced-ELL copy of a DeviceCSR (cgx_sell_build) in a torch-owned
+    buffer; keeps the CSR alive beside it (the CG setup passes read it)."""
+
+    def __init__(self, A: DeviceCSR, handle=None):
+        d = A.desc()
+        nbytes = ctypes.c_size_t()
+        _check(load_library().cgx_sell_bytes(_h(handle), ctypes.byref(d), ctypes.byref(nbytes)))
+        self.csr = A
+        self.buffer = torch.empty(max(nbytes.value, 256), dtype=torch.uint8,
+                                  device=A.row_ptr.device)
+        self._desc = _Sell()
+        _check(load_library().cgx_sell_build(_h(handle), ctypes.byref(d), _ptr(self.buffer),
+                                             self.buffer.numel(), ctypes.byref(self._desc)))
+
+    @property
+    def n_rows(self) -> int:
+        return self._desc.n_rows
+
+    @property
+    def n_slices(self) -> int:
+        return self._desc.n_slices
+
+    @property
+    def stored(self) -> int:
+        return self._desc.stored
+
+    def desc(self) -> _Sell:
+        return self._desc
+
+    def arrays(self):
+        """(slice_ptr int64, col int32, val float64) views of the buffer."""
+        d = self._desc
+        base = self.buffer.data_ptr()
+
+        def view(ptr, count, dtype, size):
+            off = ptr - base
+            return self.buffer[off:off + count * size].view(dtype)
+
+        return (view(d.slice_ptr, d.n_slices + 1, torch.int64, 8),
+                view(d.col, d.stored, torch.int32, 4), view(d.val, d.stored, torch.float64, 8))
+
+
 def _h(handle):
     return (handle or default_handle()).ptr
 
@@ -256,6 +313,30 @@ def csr_spmv_f32(A: DeviceCSR, x: torch.Tensor, y: torch.Tensor | None = None, h
         raise ValueError("x / y length does not match A")
     d = A.desc()
     _check(load_library().cgx_csr_spmv_f32(_h(handle), ctypes.byref(d), _ptr(x), _ptr(y)))
+    return y
+
+
+def sell_spmv(S: SellMatrix, x: torch.Tensor, y: torch.Tensor | None = None, handle=None):
+    _dev_tensor(x, torch.float64, "x")
+    d = S.desc()
+    if y is None:
+        y = torch.empty(d.n_rows, dtype=torch.float64, device=x.device)
+    _dev_tensor(y, torch.float64, "y")
+    if x.numel() != d.n_cols or y.numel() != d.n_rows:
+        raise ValueError("x / y length does not match S")
+    _check(load_library().cgx_sell_spmv(_h(handle), ctypes.byref(d), _ptr(x), _ptr(y)))
+    return y
+
+
+def sell_spmv_f32(S: SellMatrix, x: torch.Tensor, y: torch.Tensor | None = None, handle=None):
+    _dev_tensor(x, torch.float32, "x")
+    d = S.desc()
+    if y is None:
+        y = torch.empty(d.n_rows, dtype=torch.float32, device=x.device)
+    _dev_tensor(y, torch.float32, "y")
+    if x.numel() != d.n_cols or y.numel() != d.n_rows:
+        raise ValueError("x / y length does not match S")
+    _check(load_library().cgx_sell_spmv_f32(_h(handle), ctypes.byref(d), _ptr(x), _ptr(y)))
     return y
 
 
@@ -330,8 +411,9 @@ def cg_workspace(A: DeviceCSR, opts: Opts, device=None) -> torch.Tensor:
 
 
 def cg_solve(A: DeviceCSR, b, x, opts: Opts | None = None, workspace=None, handle=None,
-             raise_on_fail=False) -> Stats:
-    """Solve A x = b in place on x (x holds x0 on entry).  Returns Stats."""
+             raise_on_fail=False, sell: "SellMatrix | None" = None) -> Stats:
+    """Solve A x = b in place on x (x holds x0 on entry).  Returns Stats.
+    With `sell` (a SellMatrix of A) the iteration's SpMV runs on it."""
     opts = opts or make_opts()
     _dev_tensor(b, torch.float64, "b")
     _dev_tensor(x, torch.float64, "x")
@@ -341,9 +423,15 @@ def cg_solve(A: DeviceCSR, b, x, opts: Opts | None = None, workspace=None, handl
         workspace = cg_workspace(A, opts)
     st = Stats()
     d = A.desc()
-    rc = load_library().cgx_cg_solve(_h(handle), ctypes.byref(d), _ptr(b), _ptr(x),
-                                     _ptr(workspace), workspace.numel(), ctypes.byref(opts),
-                                     ctypes.byref(st))
+    if sell is None:
+        rc = load_library().cgx_cg_solve(_h(handle), ctypes.byref(d), _ptr(b), _ptr(x),
+                                         _ptr(workspace), workspace.numel(), ctypes.byref(opts),
+                                         ctypes.byref(st))
+    else:
+        rc = load_library().cgx_cg_solve_sell(_h(handle), ctypes.byref(d),
+                                              ctypes.byref(sell.desc()), _ptr(b), _ptr(x),
+                                              _ptr(workspace), workspace.numel(),
+                                              ctypes.byref(opts), ctypes.byref(st))
     if rc in (EINVAL, ENOMEM, EHIP) or (raise_on_fail and rc != OK):
         _check(rc)
     return st

@@ -247,14 +247,34 @@ size_t cgx_cg_workspace_bytes(int64_t n_rows, int64_t nnz, const cgx_opts *opts)
     }
 }
 
-int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, void *workspace,
-                 size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats)
+static int check_sell(const cgx_sell *S, const cgx_csr *A, bool need_val32)
+{
+    CGX_REQUIRE(S != nullptr, "S is NULL");
+    CGX_REQUIRE(S->n_rows == A->n_rows && S->n_cols == A->n_cols,
+                "sliced-ELL copy does not match A's dimensions");
+    CGX_REQUIRE(S->n_slices == ((int64_t)S->n_rows + 63) / 64, "n_slices must be ceil(n_rows / 64)");
+    CGX_REQUIRE(S->stored >= 0, "negative stored count");
+    CGX_REQUIRE(S->slice_ptr != nullptr, "slice_ptr is NULL");
+    if (S->stored > 0) {
+        CGX_REQUIRE(S->col != nullptr && S->val != nullptr, "col or val is NULL");
+        if (need_val32) CGX_REQUIRE(S->val32 != nullptr, "val32 is NULL");
+    }
+    return CGX_OK;
+}
+
+static int cg_solve_common(cgx_handle h, const cgx_csr *A, const cgx_sell *S, const double *b,
+                           double *x, void *workspace, size_t workspace_bytes, const cgx_opts *opts,
+                           cgx_stats *stats)
 {
     return guarded([&]() -> int {
         CGX_REQUIRE(h != nullptr, "handle is NULL");
         CGX_REQUIRE(opts != nullptr && stats != nullptr, "opts or stats is NULL");
         int rc = check_csr(A, true, opts->precision == CGX_PRECISION_MIXED);
         if (rc) return rc;
+        if (S) {
+            rc = check_sell(S, A, opts->precision == CGX_PRECISION_MIXED);
+            if (rc) return rc;
+        }
         CGX_REQUIRE(A->n_rows == A->n_cols, "matrix must be square");
         CGX_REQUIRE(opts->precond == CGX_PRECOND_NONE || opts->precond == CGX_PRECOND_JACOBI,
                     "unknown preconditioner");
@@ -269,7 +289,75 @@ int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, voi
         CGX_REQUIRE(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
         const size_t nb = (size_t)A->n_rows * 8;
         CGX_REQUIRE(!overlaps(b, nb, x, nb), "x overlaps b");
-        return cgx::run_cg(ctx_of(h), A, b, x, workspace, workspace_bytes, opts, stats);
+        return cgx::run_cg(ctx_of(h), A, S, b, x, workspace, workspace_bytes, opts, stats);
+    });
+}
+
+int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, void *workspace,
+                 size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats)
+{
+    return cg_solve_common(h, A, nullptr, b, x, workspace, workspace_bytes, opts, stats);
+}
+
+int cgx_cg_solve_sell(cgx_handle h, const cgx_csr *A, const cgx_sell *S, const double *b,
+                      double *x, void *workspace, size_t workspace_bytes, const cgx_opts *opts,
+                      cgx_stats *stats)
+{
+    if (!S) {
+        cgx::set_error("S is NULL");
+        return CGX_EINVAL;
+    }
+    return cg_solve_common(h, A, S, b, x, workspace, workspace_bytes, opts, stats);
+}
+
+int cgx_sell_bytes(cgx_handle h, const cgx_csr *A, size_t *bytes)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(bytes != nullptr, "bytes is NULL");
+        int rc = check_csr(A, true, false);
+        if (rc) return rc;
+        return cgx::sell_bytes(ctx_of(h), A, bytes);
+    });
+}
+
+int cgx_sell_build(cgx_handle h, const cgx_csr *A, void *buffer, size_t bytes, cgx_sell *out)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(out != nullptr, "out is NULL");
+        int rc = check_csr(A, true, false);
+        if (rc) return rc;
+        CGX_REQUIRE(buffer != nullptr && ((uintptr_t)buffer & 255) == 0,
+                    "buffer must be 256-byte aligned device memory");
+        return cgx::sell_build(ctx_of(h), A, buffer, bytes, out);
+    });
+}
+
+int cgx_sell_spmv(cgx_handle h, const cgx_sell *S, const double *x, double *y)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr && S != nullptr, "handle or S is NULL");
+        CGX_REQUIRE(S->slice_ptr != nullptr && S->n_rows >= 0 && S->n_cols >= 0, "bad S");
+        CGX_REQUIRE(S->stored == 0 || (S->col != nullptr && S->val != nullptr), "col or val is NULL");
+        if (S->n_rows == 0) return CGX_OK;
+        CGX_REQUIRE(y != nullptr && (x != nullptr || S->n_cols == 0), "x or y is NULL");
+        CGX_REQUIRE(!overlaps(x, (size_t)S->n_cols * 8, y, (size_t)S->n_rows * 8), "y overlaps x");
+        return cgx::launch_sell_spmv(ctx_of(h), S, x, y);
+    });
+}
+
+int cgx_sell_spmv_f32(cgx_handle h, const cgx_sell *S, const float *x, float *y)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr && S != nullptr, "handle or S is NULL");
+        CGX_REQUIRE(S->slice_ptr != nullptr && S->n_rows >= 0 && S->n_cols >= 0, "bad S");
+        CGX_REQUIRE(S->stored == 0 || (S->col != nullptr && S->val32 != nullptr),
+                    "col or val32 is NULL");
+        if (S->n_rows == 0) return CGX_OK;
+        CGX_REQUIRE(y != nullptr && (x != nullptr || S->n_cols == 0), "x or y is NULL");
+        CGX_REQUIRE(!overlaps(x, (size_t)S->n_cols * 4, y, (size_t)S->n_rows * 4), "y overlaps x");
+        return cgx::launch_sell_spmv_f32(ctx_of(h), S, x, y);
     });
 }
 

@@ -281,7 +281,7 @@ int run_batched(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t
         K = (int)(2.0e-3 / t_iter);
         K = K < 2 ? 2 : (K > 32 ? 32 : K);
     }
-    uint64_t key[12] = {(uint64_t)(uintptr_t)ws, (uint64_t)nsys, (uint64_t)P.tiles.size(),
+    uint64_t key[kGraphKey] = {(uint64_t)(uintptr_t)ws, (uint64_t)nsys, (uint64_t)P.tiles.size(),
                         (uint64_t)K, 0x42ull, 0, 0, 0, 0, 0, 0, 0};
     for (int i = 0; i < nsys; ++i) {
         const uint64_t h = ((uint64_t)(uintptr_t)in[i].A.row_ptr * 1000003u) ^
@@ -292,7 +292,7 @@ int run_batched(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t
     }
     GraphSlot &slot = c->graph_batch;
     bool hit = slot.exec != nullptr;
-    for (int i = 0; i < 12 && hit; ++i) hit = slot.key[i] == key[i];
+    for (int i = 0; i < kGraphKey && hit; ++i) hit = slot.key[i] == key[i];
     if (!hit) {
         slot.reset();
         CGX_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -301,7 +301,7 @@ int run_batched(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t
         CGX_HIP_CHECK(hipStreamEndCapture(s, &g));
         slot.graph = g;
         CGX_HIP_CHECK(hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0));
-        for (int i = 0; i < 12; ++i) slot.key[i] = key[i];
+        for (int i = 0; i < kGraphKey; ++i) slot.key[i] = key[i];
     }
     std::vector<int32_t> done(nsys);
     const int64_t max_replays = (int64_t)maxit / K + 2;

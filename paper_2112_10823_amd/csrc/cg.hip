@@ -59,6 +59,9 @@ struct CgArgs {
     T *dinv;  // nullptr without preconditioner
     T *partials;  // kPRegions * kMaxPhaseBlocks values
     T *tpart;     // p.q partial of each SpMV wave tile (region kPPq itself when it fits)
+    const int64_t *sell_sp;  // sliced-ELL copy of A for the SpMV phase (null: CSR wave tiles)
+    const int32_t *sell_col;
+    const T *sell_val;
     CgState *st;
     int ntiles;           // wave tiles of the SpMV phase (= its workgroups)
     int tiles_per_red;    // tile partials added by one reduction workgroup
@@ -190,6 +193,25 @@ __global__ __launch_bounds__(kWave) void cg_spmv_kernel(CgArgs<T> a)
     if (row < 0) return;  // the solve has stopped
     T part = T(0);
     if (threadIdx.x % (kWave / RT) == 0 && row < a.n) {
+        a.q[row] = acc;
+        part = a.p[row] * acc;
+    }
+    part = wave_sum(part);
+    if (threadIdx.x == 0) a.tpart[tile] = part;
+}
+
+// (1) on a sliced-ELL copy of A: one 64-row slice per workgroup, the slice's
+// partial of p.q.
+template <typename T>
+__global__ __launch_bounds__(kWave) void cg_sell_spmv_kernel(CgArgs<T> a)
+{
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    int row;
+    const T acc = sell_rows<8, T>(tile, a.n, a.n_cols, a.sell_sp, a.sell_col, a.sell_val, a.p, row,
+                                  &a.st->done);
+    if (row < 0) return;  // the solve has stopped
+    T part = T(0);
+    if (row < a.n) {
         a.q[row] = acc;
         part = a.p[row] * acc;
     }
@@ -795,11 +817,13 @@ struct Grids {
     int grid_vr;        // workgroups of the vector-CSR setup passes
 };
 
-Grids make_grids(const Context *c, int64_t n, int64_t nnz, bool mixed)
+Grids make_grids(const Context *c, int64_t n, int64_t nnz, bool mixed, bool sell)
 {
     Grids g{};
     g.L = lanes_per_row(n, nnz);
-    g.RT = wave_tile_rows(n, nnz, mixed ? wave_e<float>() : wave_e<double>());
+    // sliced ELL: one 64-row slice per SpMV workgroup (never more tiles than
+    // the wave tiles the workspace is sized for)
+    g.RT = sell ? kWave : wave_tile_rows(n, nnz, mixed ? wave_e<float>() : wave_e<double>());
     g.ntiles = (int)std::max<int64_t>(1, (n + g.RT - 1) / g.RT);
     if (g.ntiles <= kMaxPhaseBlocks) {
         g.grid_red = 0;
@@ -847,6 +871,10 @@ void launch_init(const Grids &g, bool jac, hipStream_t s, const CgArgs<double> &
 template <typename T>
 void launch_spmv_kernel(const Grids &g, hipStream_t s, const CgArgs<T> &a)
 {
+    if (a.sell_sp) {
+        hipLaunchKernelGGL((cg_sell_spmv_kernel<T>), dim3(g.ntiles), dim3(kWave), 0, s, a);
+        return;
+    }
 #define CGX_SP(RR) \
     hipLaunchKernelGGL((cg_spmv_kernel<RR, T>), dim3(g.ntiles), dim3(kWave), 0, s, a)
     CGX_WRT_SWITCH(g.RT, CGX_SP)
@@ -952,11 +980,11 @@ int replay_iters(const cgx_opts *o, double bytes_per_iter)
 // Capture (or reuse) a graph of K iterations and replay it until the state's
 // `done` flag is set, at most max_replays times.
 template <typename T>
-int replay_until_done(Context *c, GraphSlot &slot, const uint64_t (&key)[12], int K, const Grids &g,
+int replay_until_done(Context *c, GraphSlot &slot, const uint64_t (&key)[kGraphKey], int K, const Grids &g,
                       bool jac, hipStream_t s, const CgArgs<T> &a, int64_t max_replays)
 {
     bool hit = slot.exec != nullptr;
-    for (int i = 0; i < 12 && hit; ++i) hit = slot.key[i] == key[i];
+    for (int i = 0; i < kGraphKey && hit; ++i) hit = slot.key[i] == key[i];
     if (!hit) {
         slot.reset();
         CGX_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -965,7 +993,7 @@ int replay_until_done(Context *c, GraphSlot &slot, const uint64_t (&key)[12], in
         CGX_HIP_CHECK(hipStreamEndCapture(s, &graph));
         slot.graph = graph;
         CGX_HIP_CHECK(hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0));
-        for (int i = 0; i < 12; ++i) slot.key[i] = key[i];
+        for (int i = 0; i < kGraphKey; ++i) slot.key[i] = key[i];
     }
     for (int64_t rep = 0; rep < max_replays; ++rep) {
         CGX_HIP_CHECK(hipGraphLaunch(slot.exec, s));
@@ -1011,8 +1039,8 @@ int begin_solve(Context *c, hipStream_t s)
     return CGX_OK;
 }
 
-int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
-             const cgx_opts *o, cgx_stats *st)
+int run_fp64(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, double *x, void *ws,
+             size_t ws_bytes, const cgx_opts *o, cgx_stats *st)
 {
     const int64_t n = A->n_rows;
     const bool jac = o->precond == CGX_PRECOND_JACOBI;
@@ -1022,7 +1050,7 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
         return CGX_ENOMEM;
     }
     char *w = static_cast<char *>(ws);
-    const Grids g = make_grids(c, n, A->nnz, false);
+    const Grids g = make_grids(c, n, A->nnz, false, S != nullptr);
     CgArgs<double> a{};
     a.n = (int)n;
     a.n_cols = A->n_cols;
@@ -1039,6 +1067,11 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
     a.dinv = jac ? reinterpret_cast<double *>(w + lay.dinv) : nullptr;
     a.partials = reinterpret_cast<double *>(w + lay.partials);
     a.st = reinterpret_cast<CgState *>(w + lay.state);
+    if (S) {
+        a.sell_sp = S->slice_ptr;
+        a.sell_col = S->col;
+        a.sell_val = S->val;
+    }
     bind_grids(g, a, w + lay.tpart);
 
     const int maxit = o->maxit > 0 ? o->maxit : (int)std::min<int64_t>(n > 0 ? n : 1, 0x7fffffff);
@@ -1116,12 +1149,12 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
         } else {
             const double bytes = 12.0 * (double)A->nnz + (jac ? 104.0 : 88.0) * (double)n;
             const int K = replay_iters(o, bytes);
-            const uint64_t key[12] = {(uint64_t)(uintptr_t)a.rp, (uint64_t)(uintptr_t)a.ci,
-                                      (uint64_t)(uintptr_t)a.val, (uint64_t)(uintptr_t)b,
-                                      (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)ws,
-                                      (uint64_t)n, (uint64_t)A->nnz, (uint64_t)A->n_cols,
-                                      (uint64_t)(jac ? 1 : 0), (uint64_t)K,
-                                      ((uint64_t)g.n_pq << 32) | (uint64_t)g.grid_ew};
+            const uint64_t key[kGraphKey] = {
+                (uint64_t)(uintptr_t)a.rp, (uint64_t)(uintptr_t)a.ci, (uint64_t)(uintptr_t)a.val,
+                (uint64_t)(uintptr_t)b, (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)ws,
+                (uint64_t)n, (uint64_t)A->nnz, (uint64_t)A->n_cols, (uint64_t)(jac ? 1 : 0),
+                (uint64_t)K, ((uint64_t)g.n_pq << 32) | (uint64_t)g.grid_ew,
+                (uint64_t)(uintptr_t)a.sell_sp, (uint64_t)(uintptr_t)a.sell_val};
             const int64_t max_replays = (int64_t)maxit / K + 2;
             rc = replay_until_done<double>(c, c->graph64, key, K, g, jac, s, a, max_replays);
             if (rc) return rc;
@@ -1151,8 +1184,8 @@ int run_fp64(Context *c, const cgx_csr *A, const double *b, double *x, void *ws,
     return st->status;
 }
 
-int run_mixed(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
-              const cgx_opts *o, cgx_stats *st)
+int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, double *x, void *ws,
+              size_t ws_bytes, const cgx_opts *o, cgx_stats *st)
 {
     const int64_t n = A->n_rows;
     const bool jac = o->precond == CGX_PRECOND_JACOBI;
@@ -1162,7 +1195,7 @@ int run_mixed(Context *c, const cgx_csr *A, const double *b, double *x, void *ws
         return CGX_ENOMEM;
     }
     char *w = static_cast<char *>(ws);
-    const Grids g = make_grids(c, n, A->nnz, true);
+    const Grids g = make_grids(c, n, A->nnz, true, S != nullptr);
 
     MxArgs m{};
     m.n = (int)n;
@@ -1194,6 +1227,11 @@ int run_mixed(Context *c, const cgx_csr *A, const double *b, double *x, void *ws
     in.dinv = m.dinv32;
     in.partials = reinterpret_cast<float *>(w + lay.partials);
     in.st = reinterpret_cast<CgState *>(w + lay.state2);
+    if (S) {
+        in.sell_sp = S->slice_ptr;
+        in.sell_col = S->col;
+        in.sell_val = S->val32;
+    }
     bind_grids(g, in, w + lay.tpart);
 
     const int max_outer = o->max_outer > 0 ? o->max_outer : 100;
@@ -1211,11 +1249,11 @@ int run_mixed(Context *c, const cgx_csr *A, const double *b, double *x, void *ws
 
     const double bytes_in = 8.0 * (double)A->nnz + (jac ? 52.0 : 44.0) * (double)n;
     const int K = replay_iters(o, bytes_in);
-    const uint64_t key[12] = {(uint64_t)(uintptr_t)in.rp, (uint64_t)(uintptr_t)in.ci,
-                              (uint64_t)(uintptr_t)in.val, (uint64_t)(uintptr_t)ws,
-                              (uint64_t)n, (uint64_t)A->nnz, (uint64_t)A->n_cols,
-                              (uint64_t)(jac ? 1 : 0), (uint64_t)K,
-                              ((uint64_t)g.n_pq << 32) | (uint64_t)g.grid_ew, 0x4d58ull, 0};
+    const uint64_t key[kGraphKey] = {
+        (uint64_t)(uintptr_t)in.rp, (uint64_t)(uintptr_t)in.ci, (uint64_t)(uintptr_t)in.val,
+        (uint64_t)(uintptr_t)ws, (uint64_t)n, (uint64_t)A->nnz, (uint64_t)A->n_cols,
+        (uint64_t)(jac ? 1 : 0), (uint64_t)K, ((uint64_t)g.n_pq << 32) | (uint64_t)g.grid_ew,
+        0x4d58ull, 0, (uint64_t)(uintptr_t)in.sell_sp, (uint64_t)(uintptr_t)in.sell_val};
     int64_t inner_total = 0;
     int status = CGX_NOT_CONVERGED;
     for (int step = 0; step <= max_outer + 1; ++step) {
@@ -1277,11 +1315,11 @@ size_t cg_workspace_bytes(int64_t n, int64_t nnz, const cgx_opts *o)
     return make_layout(n, nnz, jac, mixed).total;
 }
 
-int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
-           const cgx_opts *o, cgx_stats *st)
+int run_cg(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, double *x, void *ws,
+           size_t ws_bytes, const cgx_opts *o, cgx_stats *st)
 {
-    if (o->precision == CGX_PRECISION_MIXED) return run_mixed(c, A, b, x, ws, ws_bytes, o, st);
-    return run_fp64(c, A, b, x, ws, ws_bytes, o, st);
+    if (o->precision == CGX_PRECISION_MIXED) return run_mixed(c, A, S, b, x, ws, ws_bytes, o, st);
+    return run_fp64(c, A, S, b, x, ws, ws_bytes, o, st);
 }
 
 }  // namespace cgx

@@ -1,6 +1,6 @@
 // Device building blocks for gfx950: wave64 reductions, XCD-aware block
-// numbering, the vector-CSR and wave-tile row bodies and the fixed-order sum
-// of per-workgroup partials.
+// numbering, the vector-CSR, wave-tile and sliced-ELL row bodies and the
+// fixed-order sum of per-workgroup partials.
 //
 // Grid-wide sums never use a per-workgroup device-scope fence (on this
 // multi-die part such a release writes back the die's L2 and halved the
@@ -262,6 +262,58 @@ __device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t
         }
     }
     return group_sum<TPR>(acc);
+}
+
+// -------------------------------------------------------- sliced ELL rows --
+
+// One wavefront computes the 64 rows of sliced-ELL slice s: lane l owns row
+// 64 s + l and walks its entries k = 0 .. width - 1 at sp[s] + 64 k + l, U
+// at a time (U col / val loads, then U gathers in flight); columns outside
+// [0, n_cols) (the padding's -1) contribute nothing.  Returns the row sum in
+// lane l; `row` receives the row index (>= n_rows past the last row).  The
+// entries of a row are added in storage order.
+// With a non-null `stop`, *stop is read together with the slice bounds; if
+// nonzero the slice is skipped: returns 0 with row = -1 in every lane.
+template <int U, typename T>
+__device__ __forceinline__ T sell_rows(int s, int n_rows, int n_cols,
+                                       const int64_t *__restrict__ sp,
+                                       const int32_t *__restrict__ col,
+                                       const T *__restrict__ val, const T *__restrict__ x,
+                                       int &row, const int *stop = nullptr)
+{
+    const int halt = stop != nullptr ? *stop : 0;
+    const int lane = threadIdx.x % kWave;
+    row = s * kWave + lane;
+    const int64_t b = sp[s];
+    const int w = (int)((sp[s + 1] - b) / kWave);
+    if (halt) {
+        row = -1;
+        return T(0);
+    }
+    const int32_t *c = col + b + lane;
+    const T *v = val + b + lane;
+    T acc = T(0);
+    int k = 0;
+    for (; k + U <= w; k += U) {
+        int cc[U];
+        T vv[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {  // streamed once: non-temporal, keeps x resident in L2
+            cc[u] = __builtin_nontemporal_load(c + (int64_t)(k + u) * kWave);
+            vv[u] = __builtin_nontemporal_load(v + (int64_t)(k + u) * kWave);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = (unsigned)cc[u] < (unsigned)n_cols ? x[cc[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += vv[u] * xv[u];
+    }
+    // the remainder with ordinary loads: measured faster than non-temporal
+    // ones here, and than predicating a last batch of U
+    for (; k < w; ++k) {
+        const int cc = c[(int64_t)k * kWave];
+        if ((unsigned)cc < (unsigned)n_cols) acc += v[(int64_t)k * kWave] * x[cc];
+    }
+    return acc;
 }
 
 // Sum of `count` partials in index order (strided per thread, then a fixed

@@ -87,10 +87,12 @@ struct CgState {
 };
 
 // A captured and instantiated HIP graph plus the key it was built for.
+constexpr int kGraphKey = 14;  // words identifying what a cached graph was captured for
+
 struct GraphSlot {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    uint64_t key[12] = {0};
+    uint64_t key[kGraphKey] = {0};
     void reset()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -130,8 +132,12 @@ int launch_demote(Context *c, int64_t n, const double *src, float *dst);
 int launch_spmv(Context *c, const cgx_csr *A, const double *x, double *y);
 int launch_spmv_f32(Context *c, const cgx_csr *A, const float *x, float *y);
 int run_csr_validate(Context *c, const cgx_csr *A, int64_t *bad_row);
-int run_cg(Context *c, const cgx_csr *A, const double *b, double *x, void *ws, size_t ws_bytes,
-           const cgx_opts *o, cgx_stats *st);
+int sell_bytes(Context *c, const cgx_csr *A, size_t *bytes);
+int sell_build(Context *c, const cgx_csr *A, void *buf, size_t bytes, cgx_sell *out);
+int launch_sell_spmv(Context *c, const cgx_sell *S, const double *x, double *y);
+int launch_sell_spmv_f32(Context *c, const cgx_sell *S, const float *x, float *y);
+int run_cg(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, double *x, void *ws,
+           size_t ws_bytes, const cgx_opts *o, cgx_stats *st);
 size_t cg_workspace_bytes(int64_t n, int64_t nnz, const cgx_opts *o);
 size_t batch_workspace_bytes(int32_t nsys, const cgx_system *in);
 // Whether wave tiles of rt rows are an instantiated schedule for K = the
