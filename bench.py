@@ -483,6 +483,8 @@ def extra_paper_shapes(cgx, synth, meter):
         b = torch.from_numpy(synth.uniform(7, n)).cuda()
         y = torch.empty_like(b)
         sp_s, sp_j = _energy_window(lambda: cgx.csr_spmv(dA, b, y), meter, min_s=2.0, min_reps=50)
+        S = cgx.SellMatrix(dA)
+        sell_s = _timeit(lambda: cgx.sell_spmv(S, b, y), reps=50)
         opts = cgx.make_opts(rtol=1e-6)
         ws = cgx.cg_workspace(dA, opts)
         x = torch.zeros_like(b)
@@ -497,12 +499,14 @@ def extra_paper_shapes(cgx, synth, meter):
                      "spmv_us": round(sp_s * 1e6, 2),
                      "spmv_GBs": round(spmv_bytes(n, nnz) / sp_s / 1e9, 1),
                      "spmv_j": round(sp_j, 5) if sp_j is not None else None,
+                     "sell_spmv_us": round(sell_s * 1e6, 2),
+                     "sell_spmv_GBs_csr_bytes": round(spmv_bytes(n, nnz) / sell_s / 1e9, 1),
                      "paper_spmv_ms": PAPER_SPMV_MS[i], "paper_spmv_j": PAPER_SPMV_J[i],
                      "cg_iters": st.iters, "cg_ms": round(cg_s * 1e3, 3),
                      "cg_j": round(cg_j, 4) if cg_j is not None else None,
                      "paper_cg_iters": PAPER_CG_ITERS[i], "paper_cg_s": PAPER_CG_S[i],
                      "paper_cg_j": PAPER_CG_J[i]})
-        del dA, ws
+        del dA, ws, S
     return {"workload": "the paper's 7 gravity-matrix shapes (Q1, a x a x c nodes, identity "
                         "Dirichlet rows); SpMV, plain CG to 1e-6", "rows": rows}
 
