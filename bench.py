@@ -511,6 +511,33 @@ def extra_paper_shapes(cgx, synth, meter):
                         "Dirichlet rows); SpMV, plain CG to 1e-6", "rows": rows}
 
 
+def extra_transfer(meter):
+    """Host <-> device copies (the paper's transfer figure gives no numbers):
+    float64 buffers of 1 MiB to 1 GiB, pinned and pageable host memory,
+    each direction timed with events and its energy taken over >= 2 s."""
+    import torch
+    rows = []
+    for mib in (1, 16, 256, 1024):
+        nel = mib * (1 << 20) // 8
+        dev_buf = torch.empty(nel, dtype=torch.float64, device="cuda")
+        for pinned in (True, False):
+            host = torch.empty(nel, dtype=torch.float64, pin_memory=pinned)
+            host.fill_(1.0)
+            for direction in ("h2d", "d2h"):
+                if direction == "h2d":
+                    fn = lambda: dev_buf.copy_(host, non_blocking=pinned)  # noqa: E731
+                else:
+                    fn = lambda: host.copy_(dev_buf, non_blocking=pinned)  # noqa: E731
+                t = _timeit(fn, reps=max(3, min(200, 2048 // mib)), warm=2)
+                wall, j = _energy_window(fn, meter, min_s=2.0, min_reps=3)
+                rows.append({"MiB": mib, "pinned": pinned, "dir": direction,
+                             "ms": round(t * 1e3, 4), "GBs": round(mib * (1 << 20) / t / 1e9, 2),
+                             "j_per_GB": round(j / (mib * (1 << 20) / 1e9), 3) if j else None})
+            del host
+        del dev_buf
+    return {"workload": "host<->device copies, float64, pinned / pageable", "rows": rows}
+
+
 def run_extras(which):
     import numpy as _np  # noqa: F401
     import torch
@@ -525,7 +552,8 @@ def run_extras(which):
              "mixed": lambda: extra_mixed(cgx, synth, meter),
              "batched": lambda: extra_batched(cgx, synth, meter),
              "serving": lambda: extra_serving(cgx, synth, meter),
-             "paper": lambda: extra_paper_shapes(cgx, synth, meter)}
+             "paper": lambda: extra_paper_shapes(cgx, synth, meter),
+             "transfer": lambda: extra_transfer(meter)}
     for name in which:
         print(f"# extra {name}", file=sys.stderr, flush=True)
         res = table[name]()
@@ -543,7 +571,8 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="warm-up plus a few solves, for profiler runs")
     ap.add_argument("--extras", default="",
-                    help="comma list of extra workloads (small,blas1,q1,mixed,batched,serving,paper); "
+                    help="comma list of extra workloads (small,blas1,q1,mixed,batched,serving,paper,"
+                         "transfer); "
                          "prints one JSON line each instead of the benchmark line")
     ap.add_argument("--calib", action="store_true",
                     help="with --profile-only: first run cgx_add on 2^26 float64 elements "
