@@ -50,28 +50,20 @@ def jacobi_setup_bytes(n, nnz):
 
 
 class EnergyMeter:
-    """GPU energy accumulator through amdsmi (microjoule counter); None if unavailable."""
+    """GPU energy through the amdsmi accumulator, sampled in the background
+    (it advances about once per second on MI355X): the mean power over an
+    interval comes from the counter updates inside it and their own
+    timestamps, and energy = power x time."""
 
     def __init__(self):
-        self.h = None
-        try:
-            import amdsmi
-            amdsmi.amdsmi_init()
-            hs = amdsmi.amdsmi_get_processor_handles()
-            if hs:
-                self.amdsmi = amdsmi
-                self.h = hs[0]
-                self.read()
-        except Exception:
-            self.h = None
+        from paper_2112_10823_amd.energy import EnergySampler
+        self.sampler = EnergySampler().start()
 
-    def read(self):
-        if self.h is None:
-            return None
-        e = self.amdsmi.amdsmi_get_energy_count(self.h)
-        acc = e.get("energy_accumulator", e.get("power"))
-        res = e.get("counter_resolution", 1.0)
-        return float(acc) * float(res) * 1e-6  # joules
+    def power(self, t0, t1):
+        return self.sampler.power_between(t0, t1) if self.sampler.ok else None
+
+    def updates_between(self, t0, t1):
+        return sum(1 for u in self.sampler.updates if t0 <= u[0] <= t1)
 
 
 def wave_tile_rows(n, nnz, entries_per_lane=8):
@@ -139,23 +131,24 @@ def _timeit(fn, reps=20, warm=3):
     return e0.elapsed_time(e1) / reps * 1e-3  # s
 
 
-def _energy_window(fn, meter, min_s=2.0, min_reps=1):
-    """Run fn repeatedly for at least min_s seconds (the GPU energy counter
-    updates too coarsely for shorter windows); returns (s per call, J per call
-    or None)."""
+def _energy_window(fn, meter, min_s=2.5, min_reps=1):
+    """Run fn repeatedly for at least min_s seconds and until the energy
+    counter has advanced three times inside the window (at most 4 min_s);
+    returns (s per call, J per call or None)."""
     import torch
     torch.cuda.synchronize()
-    e0 = meter.read()
     t0 = time.perf_counter()
     reps = 0
-    while reps < min_reps or time.perf_counter() - t0 < min_s:
+    while (reps < min_reps or time.perf_counter() - t0 < min_s
+           or (meter.sampler.ok and meter.updates_between(t0, time.perf_counter()) < 3
+               and time.perf_counter() - t0 < 4 * min_s)):
         fn()
         reps += 1
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / reps
-    e1 = meter.read()
-    j = (e1 - e0) / reps if (e0 is not None and e1 is not None and e1 > e0) else None
-    return wall, j
+    t1 = time.perf_counter()
+    wall = (t1 - t0) / reps
+    p = meter.power(t0, t1)
+    return wall, (p * wall if p is not None else None)
 
 
 def extra_small_cg(cgx, synth, oracle_mod, meter):
@@ -401,7 +394,6 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
         gaps = rng.exponential(1.0 / qps, n_req) if qps else np.zeros(n_req)
         lat, ok = [], 0
         out = [torch.zeros_like(bs[k]) for k in picks]
-        e0 = meter.read()
         with cgx.Server(pool_t, max_slots=48, handle=h, max_group=max_group) as srv:
             t0 = time.perf_counter()
             tickets = []
@@ -416,7 +408,7 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
                 ok += st.status == cgx.OK
                 lat.append(st.latency_ms)
             wall = time.perf_counter() - t0
-        e1 = meter.read()
+        p = meter.power(t0, t0 + wall)
         lat.sort()
         return {"qps": round(qps, 2) if qps else "burst", "max_group": max_group,
                 "precond": "jacobi" if opts.precond else "none",
@@ -424,7 +416,7 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
                 "p50_ms": round(lat[len(lat) // 2], 2),
                 "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 2),
                 "ok": ok, "wall_s": round(wall, 2),
-                "j_per_solve": round((e1 - e0) / n_req, 3) if e0 is not None and e1 > e0 else None}
+                "j_per_solve": round(p * wall / n_req, 3) if p is not None else None}
 
     def sequential(opts=opts):
         """The same requests solved one after another with the single-system
@@ -434,7 +426,6 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
         out = [torch.zeros_like(bs[k]) for k in picks]
         wss = {k: cgx.cg_workspace(mats[k][1], opts) for k in set(picks.tolist())}
         torch.cuda.synchronize()
-        e0 = meter.read()
         t0 = time.perf_counter()
         ok = 0
         for i, k in enumerate(picks):
@@ -442,9 +433,9 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5):
             ok += st.status == cgx.OK
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        e1 = meter.read()
+        p = meter.power(t0, t0 + wall)
         return {"solves_per_s": round(n_req / wall, 2), "wall_s": round(wall, 2), "ok": ok,
-                "j_per_solve": round((e1 - e0) / n_req, 3) if e0 is not None and e1 > e0 else None}
+                "j_per_solve": round(p * wall / n_req, 3) if p is not None else None}
 
     jac = cgx.make_opts(rtol=1e-8, precond=cgx.PRECOND_JACOBI)
     sat = run(0)  # all requests at once: saturation throughput
@@ -538,6 +529,102 @@ def extra_transfer(meter):
     return {"workload": "host<->device copies, float64, pinned / pageable", "rows": rows}
 
 
+def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
+    """The paper's Section 4 analysis on this GPU's energy counter: runs of
+    idle / add / xmul / axpy / dot / SpMV / Jacobi-CG / idle phases of
+    phase_s seconds each on the Q1 128^3 system and vectors of its length;
+    the power trace of each run is cut into phases by the variance-based
+    step detector (noise from the first idle phase), the runs with the most
+    common phase pattern are averaged, and the per-call energies are used to
+    check the paper's composition claim for one CG iteration."""
+    import torch
+    from paper_2112_10823_amd.energy import detect_steps, most_common_pattern, segments_of
+    A = synth.q1cube(N_GRID, SIGMA, seed=synth.SEED_C2_COEFF)
+    n = A.n_rows
+    dA = cgx.DeviceCSR.from_host(A)
+    x = torch.from_numpy(synth.uniform(synth.SEED_VEC_X, n)).cuda()
+    y = torch.from_numpy(synth.uniform(synth.SEED_VEC_Y, n)).cuda()
+    z = torch.empty_like(x)
+    w = torch.empty_like(x)
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    db = torch.from_numpy(synth.blob_rhs(N_GRID, synth.SEED_C2_BLOBS)).cuda()
+    xs = torch.zeros_like(db)
+    opts = cgx.make_opts(rtol=RTOL, precond=cgx.PRECOND_JACOBI)
+    ws = cgx.cg_workspace(dA, opts)
+    st = cgx.cg_solve(dA, db, xs, opts, workspace=ws)
+
+    def solve():
+        xs.zero_()
+        cgx.cg_solve(dA, db, xs, opts, workspace=ws)
+
+    ops = [("idle", None), ("add", lambda: cgx.add(x, y, z)), ("xmul", lambda: cgx.xmul(x, y, z)),
+           ("axpy", lambda: (w.copy_(y), cgx.axpy(0.5, x, w))), ("dot", lambda: cgx.dot(x, y, out)),
+           ("spmv", lambda: cgx.csr_spmv(dA, x, z)), ("jacobi_cg", solve), ("idle_end", None)]
+    per_run, phase_lists = [], []
+    direct = {name: [] for name, _ in ops}
+    for r in range(runs):
+        torch.cuda.synchronize()
+        time.sleep(2.0)  # back to idle before the run
+        bounds = []
+        for name, fn in ops:
+            t0 = time.perf_counter()
+            calls = 0
+            if fn is None:
+                time.sleep(phase_s)
+            else:
+                while time.perf_counter() - t0 < phase_s:
+                    for _ in range(20):
+                        fn()
+                    calls += 20
+                    torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            bounds.append((name, t0, t1, calls))
+        t, p = meter.sampler.trace()
+        sel = (t >= bounds[0][1]) & (t <= bounds[-1][2])
+        t, p = t[sel], p[sel]
+        # the noise sample: the first idle phase past its first two seconds
+        idle = p[(t >= bounds[0][1] + 2.0) & (t <= bounds[0][2])]
+        noise = max(float(np.std(idle)) if idle.size > 1 else 0.0, 2.0)
+        cuts = detect_steps(p, noise, min_len=2)
+        segs = segments_of(p, cuts)
+        dt = float(np.median(np.diff(t))) if t.size > 1 else 1.0
+        phase_lists.append([((sg.end - sg.start) * dt, sg.level) for sg in segs])
+        for name, t0, t1, calls in bounds:
+            pw = meter.power(t0 + 1.0, t1)  # the first second is the ramp
+            if pw is not None:
+                direct[name].append((pw, (t1 - t0) / calls if calls else None))
+        per_run.append({"samples": int(p.size), "noise_W": round(noise, 2),
+                        "phases": [[round(d, 1), round(lv, 1)] for d, lv in phase_lists[-1]]})
+    pat, keep, phases = most_common_pattern(phase_lists)
+    table = {}
+    for name, vals in direct.items():
+        if not vals:
+            continue
+        pw = float(np.mean([v[0] for v in vals]))
+        per_call = [v[1] for v in vals if v[1] is not None]
+        row = {"W": round(pw, 1)}
+        if per_call:
+            s_call = float(np.mean(per_call))
+            row.update({"s_per_call": s_call, "J_per_call": pw * s_call})
+        table[name] = row
+    comp = None
+    if all(k in table and "J_per_call" in table[k] for k in ("spmv", "dot", "axpy", "xmul", "jacobi_cg")):
+        pred = (table["spmv"]["J_per_call"] + 2 * table["dot"]["J_per_call"]
+                + 3 * table["axpy"]["J_per_call"] + table["xmul"]["J_per_call"])
+        meas = table["jacobi_cg"]["J_per_call"] / st.iters
+        comp = {"iters": st.iters, "predicted_J_per_iter": round(pred, 4),
+                "measured_J_per_iter": round(meas, 4), "measured_over_predicted": round(meas / pred, 3)}
+    for row in table.values():
+        if "J_per_call" in row:
+            row["J_per_call"] = round(row["J_per_call"], 5)
+            row["s_per_call"] = round(row["s_per_call"] * 1e6, 1)  # us
+    return {"workload": f"{runs} runs of {len(ops)} phases x {phase_s:g} s; vectors of {n} float64, "
+                        "Q1 128^3 SpMV and Jacobi-CG", "runs": per_run,
+            "most_common_pattern": list(pat), "runs_kept": keep,
+            "phases_W": [[round(d, 1), round(lv, 1)] for d, lv in phases],
+            "per_op_known_boundaries": table, "composition": comp}
+
+
 def run_extras(which):
     import numpy as _np  # noqa: F401
     import torch
@@ -553,7 +640,8 @@ def run_extras(which):
              "batched": lambda: extra_batched(cgx, synth, meter),
              "serving": lambda: extra_serving(cgx, synth, meter),
              "paper": lambda: extra_paper_shapes(cgx, synth, meter),
-             "transfer": lambda: extra_transfer(meter)}
+             "transfer": lambda: extra_transfer(meter),
+             "energy": lambda: extra_energy_phases(cgx, synth, meter)}
     for name in which:
         print(f"# extra {name}", file=sys.stderr, flush=True)
         res = table[name]()
@@ -563,7 +651,7 @@ def run_extras(which):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=300,
@@ -572,7 +660,7 @@ def main():
                     help="warm-up plus a few solves, for profiler runs")
     ap.add_argument("--extras", default="",
                     help="comma list of extra workloads (small,blas1,q1,mixed,batched,serving,paper,"
-                         "transfer); "
+                         "transfer,energy); "
                          "prints one JSON line each instead of the benchmark line")
     ap.add_argument("--calib", action="store_true",
                     help="with --profile-only: first run cgx_add on 2^26 float64 elements "
@@ -634,7 +722,6 @@ def main():
 
     meter = EnergyMeter()
     torch.cuda.synchronize()
-    e0 = meter.read()
     t0 = time.perf_counter()
     lat, iters = [], []
     for _ in range(args.steps):
@@ -644,7 +731,9 @@ def main():
         iters.append(st.iters)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    e1 = meter.read()
+    # mean power over the counter updates of the timed region, past its first
+    # second (the board's power ramps up over about a second)
+    p_avg = meter.power(t0 + min(1.0, (t1 - t0) / 3), t1)
     wall = t1 - t0
     total_bytes = sum(jacobi_setup_bytes(n, nnz) + k * jacobi_iter_bytes(n, nnz) for k in iters)
     value = total_bytes / wall / 1e9
@@ -672,7 +761,7 @@ def main():
         print("# CPU oracle sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(A, b, n, nnz, args.cpu_iters)
 
-    joules = (e1 - e0) / args.steps if (e0 is not None and e1 is not None and e1 > e0) else None
+    joules = p_avg * wall / args.steps if p_avg is not None else None
     lat_ms = sorted(1e3 * v for v in lat)
     p99 = lat_ms[min(len(lat_ms) - 1, math.ceil(0.99 * len(lat_ms)) - 1)]
     out = {

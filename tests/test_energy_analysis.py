@@ -1,0 +1,73 @@
+"""CPU tests of the power-trace analysis (the paper's Section 4: averaging
+filter, variance-based step detection given a noise sample, most common
+phase pattern over repeated runs) on synthetic traces whose phases are
+known."""
+import numpy as np
+import pytest
+
+from paper_2112_10823_amd.energy import (detect_steps, most_common_pattern, moving_average,
+                                         phase_pattern, segments_of)
+
+LEVELS = [250.0, 800.0, 600.0, 820.0, 260.0]
+LENGTHS = [8, 10, 6, 12, 9]
+
+
+def synthetic(seed, sigma=5.0, levels=LEVELS, lengths=LENGTHS):
+    rng = np.random.default_rng(seed)
+    truth = np.concatenate([np.full(n, v) for v, n in zip(levels, lengths)])
+    return truth + rng.normal(0.0, sigma, truth.size), list(np.cumsum(lengths)[:-1])
+
+
+def test_moving_average_definition():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=37)
+    for w in (1, 3, 5, 9):
+        y = moving_average(x, w)
+        h = w // 2
+        ref = [x[max(0, i - h):i + h + 1].mean() for i in range(x.size)]
+        assert np.allclose(y, ref, rtol=0, atol=1e-12)
+    assert np.array_equal(moving_average(np.full(10, 3.5), 5), np.full(10, 3.5))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_steps_recovered_exactly(seed):
+    x, cuts = synthetic(seed)
+    found = detect_steps(x, noise_std=5.0, min_len=2)
+    assert found == cuts
+    for s, v, n in zip(segments_of(x, found), LEVELS, LENGTHS):
+        assert abs(s.level - v) <= 4 * 5.0 / np.sqrt(n)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_noise_alone_has_no_step(seed):
+    rng = np.random.default_rng(100 + seed)
+    x = 400.0 + rng.normal(0.0, 5.0, 60)
+    assert detect_steps(x, noise_std=5.0) == []
+
+
+def test_underestimated_noise_gives_spurious_steps():
+    """The noise sample matters: told the noise is ten times smaller than it
+    is, the detector cuts the noise itself."""
+    rng = np.random.default_rng(7)
+    x = 400.0 + rng.normal(0.0, 5.0, 60)
+    assert len(detect_steps(x, noise_std=0.5)) > 0
+
+
+def test_min_len_and_single_step_at_the_edge():
+    x = np.concatenate([np.full(3, 100.0), np.full(30, 500.0)])
+    assert detect_steps(x, noise_std=1.0, min_len=2) == [3]
+    assert detect_steps(x, noise_std=1.0, min_len=4) in ([4], [])
+
+
+def test_most_common_pattern_average():
+    a = [(2.0, 250.0), (5.0, 800.0), (3.0, 260.0)]
+    b = [(2.2, 254.0), (4.8, 790.0), (3.1, 262.0)]
+    odd = [(2.0, 250.0), (1.0, 600.0), (4.0, 800.0), (3.0, 255.0)]
+    pat, keep, phases = most_common_pattern([a, odd, b])
+    assert pat == (3, 1, -1) and keep == [0, 2]
+    assert phases == pytest.approx([(2.1, 252.0), (4.9, 795.0), (3.05, 261.0)])
+
+
+def test_phase_pattern_signs():
+    x, cuts = synthetic(1)
+    assert phase_pattern(segments_of(x, cuts)) == (5, 1, -1, 1, -1)
