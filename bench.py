@@ -131,11 +131,18 @@ def _timeit(fn, reps=20, warm=3):
     return e0.elapsed_time(e1) / reps * 1e-3  # s
 
 
-def _energy_window(fn, meter, min_s=2.5, min_reps=1):
+def _energy_window(fn, meter, min_s=2.5, min_reps=1, warm_s=1.0):
     """Run fn repeatedly for at least min_s seconds and until the energy
     counter has advanced three times inside the window (at most 4 min_s);
-    returns (s per call, J per call or None)."""
+    returns (s per call, J per call or None).  With telemetry on, fn first
+    runs untimed for warm_s seconds, so that the board's power has settled
+    at the workload's level (it takes about a second to move between
+    levels) before the window opens."""
     import torch
+    if meter.sampler.ok:
+        tw = time.perf_counter()
+        while time.perf_counter() - tw < warm_s:
+            fn()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = 0
@@ -538,7 +545,8 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
     common phase pattern are averaged, and the per-call energies are used to
     check the paper's composition claim for one CG iteration."""
     import torch
-    from paper_2112_10823_amd.energy import detect_steps, most_common_pattern, segments_of
+    from paper_2112_10823_amd.energy import (Segment, detect_steps, merge_short, most_common_pattern,
+                                             phase_pattern, segments_of)
     A = synth.q1cube(N_GRID, SIGMA, seed=synth.SEED_C2_COEFF)
     n = A.n_rows
     dA = cgx.DeviceCSR.from_host(A)
@@ -579,13 +587,17 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
                     torch.cuda.synchronize()
             t1 = time.perf_counter()
             bounds.append((name, t0, t1, calls))
+            print(f"# energy run {r}: phase {name} done, {calls} calls", file=sys.stderr, flush=True)
         t, p = meter.sampler.trace()
         sel = (t >= bounds[0][1]) & (t <= bounds[-1][2])
         t, p = t[sel], p[sel]
         # the noise sample: the first idle phase past its first two seconds
         idle = p[(t >= bounds[0][1] + 2.0) & (t <= bounds[0][2])]
         noise = max(float(np.std(idle)) if idle.size > 1 else 0.0, 2.0)
-        cuts = detect_steps(p, noise, min_len=2)
+        # one counter sample spans about a second, so the sample taken across a
+        # phase boundary mixes two levels: segments shorter than three samples
+        # are such mixtures and join the closer neighbour
+        cuts = merge_short(p, detect_steps(p, noise, min_len=1), 3)
         segs = segments_of(p, cuts)
         dt = float(np.median(np.diff(t))) if t.size > 1 else 1.0
         phase_lists.append([((sg.end - sg.start) * dt, sg.level) for sg in segs])
@@ -605,7 +617,7 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
         row = {"W": round(pw, 1)}
         if per_call:
             s_call = float(np.mean(per_call))
-            row.update({"s_per_call": s_call, "J_per_call": pw * s_call})
+            row.update({"us_per_call": s_call, "J_per_call": pw * s_call})
         table[name] = row
     comp = None
     if all(k in table and "J_per_call" in table[k] for k in ("spmv", "dot", "axpy", "xmul", "jacobi_cg")):
@@ -617,10 +629,12 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
     for row in table.values():
         if "J_per_call" in row:
             row["J_per_call"] = round(row["J_per_call"], 5)
-            row["s_per_call"] = round(row["s_per_call"] * 1e6, 1)  # us
+            row["us_per_call"] = round(row["us_per_call"] * 1e6, 1)
     return {"workload": f"{runs} runs of {len(ops)} phases x {phase_s:g} s; vectors of {n} float64, "
                         "Q1 128^3 SpMV and Jacobi-CG", "runs": per_run,
             "most_common_pattern": list(pat), "runs_kept": keep,
+            "pattern_of_known_phases": list(phase_pattern(
+                [Segment(0, 0, table[name]["W"]) for name, _ in ops if name in table])),
             "phases_W": [[round(d, 1), round(lv, 1)] for d, lv in phases],
             "per_op_known_boundaries": table, "composition": comp}
 

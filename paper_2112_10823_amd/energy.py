@@ -25,7 +25,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["EnergySampler", "moving_average", "detect_steps", "Segment", "segments_of",
+__all__ = ["EnergySampler", "moving_average", "detect_steps", "merge_short", "Segment", "segments_of",
            "phase_pattern", "most_common_pattern"]
 
 
@@ -161,6 +161,31 @@ def detect_steps(x, noise_std: float, min_len: int = 2, penalty: float | None = 
             todo.append((a, k))
             todo.append((k, b))
     return sorted(cuts)
+
+
+def merge_short(x, cuts, min_len: int):
+    """Fold every segment shorter than `min_len` samples into the neighbour
+    whose level is closer (the shortest first), so that a sample taken across
+    a phase boundary, which reads a mixture of the two levels, joins one of
+    the two phases instead of standing as a phase of its own.  Returns the
+    remaining change indices."""
+    x = np.asarray(x, dtype=np.float64)
+    cuts = sorted(cuts)
+    while cuts:
+        bounds = [0] + cuts + [x.size]
+        lens = [b - a for a, b in zip(bounds, bounds[1:])]
+        k = int(np.argmin(lens))
+        if lens[k] >= min_len:
+            break
+        lv = [float(x[a:b].mean()) for a, b in zip(bounds, bounds[1:])]
+        if k == 0:
+            drop = 0
+        elif k == len(lens) - 1:
+            drop = k - 1
+        else:
+            drop = k - 1 if abs(lv[k] - lv[k - 1]) <= abs(lv[k] - lv[k + 1]) else k
+        del cuts[drop]
+    return cuts
 
 
 def segments_of(x, cuts):

@@ -5,8 +5,8 @@ known."""
 import numpy as np
 import pytest
 
-from paper_2112_10823_amd.energy import (detect_steps, most_common_pattern, moving_average,
-                                         phase_pattern, segments_of)
+from paper_2112_10823_amd.energy import (detect_steps, merge_short, most_common_pattern,
+                                         moving_average, phase_pattern, segments_of)
 
 LEVELS = [250.0, 800.0, 600.0, 820.0, 260.0]
 LENGTHS = [8, 10, 6, 12, 9]
@@ -71,3 +71,32 @@ def test_most_common_pattern_average():
 def test_phase_pattern_signs():
     x, cuts = synthetic(1)
     assert phase_pattern(segments_of(x, cuts)) == (5, 1, -1, 1, -1)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_boundary_samples_do_not_make_phases(seed):
+    """A sensor sample that spans a phase boundary reads a mixture of the two
+    levels; the detector gives it a short segment of its own, and folding
+    segments under three samples into the closer neighbour leaves one step
+    there."""
+    rng = np.random.default_rng(50 + seed)
+    levels, length = [260.0, 680.0, 740.0, 330.0, 1230.0, 1140.0, 270.0], 8
+    x = np.concatenate([np.full(length, v) for v in levels])
+    for i in range(1, len(levels)):
+        f = rng.uniform(0.2, 0.8)
+        x[i * length] = f * levels[i - 1] + (1 - f) * levels[i]
+    x += rng.normal(0.0, 5.0, x.size)
+    raw = detect_steps(x, noise_std=5.0, min_len=1)
+    assert len(raw) > len(levels) - 1
+    cuts = merge_short(x, raw, 3)
+    assert len(cuts) == len(levels) - 1
+    assert all(abs(c - i * length) <= 1 for c, i in zip(cuts, range(1, len(levels))))
+    assert phase_pattern(segments_of(x, cuts)) == (7, 1, 1, -1, 1, -1, -1)
+
+
+def test_merge_short_cases():
+    x = np.array([0.0] * 5 + [3.0] + [10.0] * 5 + [9.0, 1.0] + [1.0] * 4)
+    assert merge_short(x, [5, 6, 11, 12], 3) == [6, 12]
+    assert merge_short(x, [1], 3) == []
+    assert merge_short(x, [5, 11], 3) == [5, 11]
+    assert merge_short(x, [], 3) == []
