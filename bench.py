@@ -546,7 +546,7 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
     check the paper's composition claim for one CG iteration."""
     import torch
     from paper_2112_10823_amd.energy import (Segment, detect_steps, merge_short, most_common_pattern,
-                                             phase_pattern, segments_of)
+                                             noise_from_differences, phase_pattern, segments_of)
     A = synth.q1cube(N_GRID, SIGMA, seed=synth.SEED_C2_COEFF)
     n = A.n_rows
     dA = cgx.DeviceCSR.from_host(A)
@@ -591,9 +591,12 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
         t, p = meter.sampler.trace()
         sel = (t >= bounds[0][1]) & (t <= bounds[-1][2])
         t, p = t[sel], p[sel]
-        # the noise sample: the first idle phase past its first two seconds
+        # the noise sample: the first idle phase past its first two seconds;
+        # the counter is noisier under load than at idle, so the estimate
+        # from the trace's own differences is taken where it is larger
         idle = p[(t >= bounds[0][1] + 2.0) & (t <= bounds[0][2])]
-        noise = max(float(np.std(idle)) if idle.size > 1 else 0.0, 2.0)
+        idle_sd = float(np.std(idle)) if idle.size > 1 else 0.0
+        noise = max(idle_sd, noise_from_differences(p), 2.0)
         # one counter sample spans about a second, so the sample taken across a
         # phase boundary mixes two levels: segments shorter than three samples
         # are such mixtures and join the closer neighbour
@@ -605,7 +608,8 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
             pw = meter.power(t0 + 1.0, t1)  # the first second is the ramp
             if pw is not None:
                 direct[name].append((pw, (t1 - t0) / calls if calls else None))
-        per_run.append({"samples": int(p.size), "noise_W": round(noise, 2),
+        per_run.append({"samples": int(p.size), "noise_W": round(noise, 2), "idle_sd_W": round(idle_sd, 2),
+                        "trace_W": [round(float(v), 1) for v in p],
                         "phases": [[round(d, 1), round(lv, 1)] for d, lv in phase_lists[-1]]})
     pat, keep, phases = most_common_pattern(phase_lists)
     table = {}

@@ -25,7 +25,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["EnergySampler", "moving_average", "detect_steps", "merge_short", "Segment", "segments_of",
+__all__ = ["EnergySampler", "moving_average", "noise_from_differences", "detect_steps", "merge_short",
+           "Segment", "segments_of",
            "phase_pattern", "most_common_pattern"]
 
 
@@ -122,6 +123,18 @@ class Segment:
     start: int   # first sample
     end: int     # one past the last sample
     level: float
+
+
+def noise_from_differences(x):
+    """Standard deviation of the noise on a piecewise-constant signal,
+    estimated from its first differences: away from the few steps each
+    difference is the difference of two independent noise samples, so the
+    median absolute difference, scaled by 1.4826 / sqrt(2), estimates the
+    noise's sigma for Gaussian noise and is not moved by the steps."""
+    d = np.diff(np.asarray(x, dtype=np.float64))
+    if d.size == 0:
+        return 0.0
+    return float(1.4826 * np.median(np.abs(d)) / np.sqrt(2.0))
 
 
 def detect_steps(x, noise_std: float, min_len: int = 2, penalty: float | None = None):

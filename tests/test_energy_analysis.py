@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 from paper_2112_10823_amd.energy import (detect_steps, merge_short, most_common_pattern,
-                                         moving_average, phase_pattern, segments_of)
+                                         moving_average, noise_from_differences, phase_pattern,
+                                         segments_of)
 
 LEVELS = [250.0, 800.0, 600.0, 820.0, 260.0]
 LENGTHS = [8, 10, 6, 12, 9]
@@ -100,3 +101,16 @@ def test_merge_short_cases():
     assert merge_short(x, [1], 3) == []
     assert merge_short(x, [5, 11], 3) == [5, 11]
     assert merge_short(x, [], 3) == []
+
+
+def test_noise_from_differences():
+    """The estimate ignores the steps: on a long trace with a few large steps
+    it lands within 15 % of the noise's sigma, and it is zero without noise."""
+    rng = np.random.default_rng(3)
+    levels = [260.0, 700.0, 350.0, 1250.0, 1160.0, 270.0]
+    x = np.concatenate([np.full(40, v) for v in levels])
+    for sigma in (2.0, 5.0, 20.0):
+        est = noise_from_differences(x + rng.normal(0.0, sigma, x.size))
+        assert abs(est - sigma) <= 0.15 * sigma
+    assert noise_from_differences(x) == 0.0
+    assert noise_from_differences([1.0]) == 0.0
