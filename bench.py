@@ -553,7 +553,7 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
     x = torch.from_numpy(synth.uniform(synth.SEED_VEC_X, n)).cuda()
     y = torch.from_numpy(synth.uniform(synth.SEED_VEC_Y, n)).cuda()
     z = torch.empty_like(x)
-    w = torch.empty_like(x)
+    w = y.clone()  # the axpy phase accumulates into w (|w| stays below 1e7)
     out = torch.empty(1, dtype=torch.float64, device="cuda")
     db = torch.from_numpy(synth.blob_rhs(N_GRID, synth.SEED_C2_BLOBS)).cuda()
     xs = torch.zeros_like(db)
@@ -566,7 +566,7 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
         cgx.cg_solve(dA, db, xs, opts, workspace=ws)
 
     ops = [("idle", None), ("add", lambda: cgx.add(x, y, z)), ("xmul", lambda: cgx.xmul(x, y, z)),
-           ("axpy", lambda: (w.copy_(y), cgx.axpy(0.5, x, w))), ("dot", lambda: cgx.dot(x, y, out)),
+           ("axpy", lambda: cgx.axpy(0.5, x, w)), ("dot", lambda: cgx.dot(x, y, out)),
            ("spmv", lambda: cgx.csr_spmv(dA, x, z)), ("jacobi_cg", solve), ("idle_end", None)]
     per_run, phase_lists = [], []
     direct = {name: [] for name, _ in ops}
