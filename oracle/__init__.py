@@ -15,6 +15,9 @@ Each function follows a passage of the paper (arXiv 2112.10823):
   mixed_ir               mixed-precision iterative refinement (reference cited
                          beside CG in Section 5.3)
   lanczos_extremes       extreme Ritz values from CG coefficients (Saad 6.7)
+  schwarz.solve          CG under an additive Schwarz preconditioner with CG
+                         subdomain solves (domain decomposition, end of
+                         Section 5.3; module `oracle.schwarz`)
 """
 from __future__ import annotations
 
