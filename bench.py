@@ -268,6 +268,69 @@ def extra_spmv_and_cg(cgx, synth, meter):
     return res
 
 
+def extra_schwarz(cgx, synth, oracle_mod, meter):
+    """Additive Schwarz (slabs of the Q1 128^3 grid, overlap in grid layers of
+    N^2 rows) around flexible CG, every subdomain solved by the batched CG
+    solver; against Jacobi-CG on the same system (lognormal(0,1), blob RHS,
+    1e-8).  The subdomain phase's rate uses the batched model bytes per
+    iteration (12 nnz_i + 4 (m_i + 1) + 88 m_i summed over the subdomains),
+    with the largest subdomain iteration count of every outer step."""
+    import torch
+    A = synth.q1cube(N_GRID, SIGMA, seed=synth.SEED_C2_COEFF)
+    b = synth.blob_rhs(N_GRID, synth.SEED_C2_BLOBS)
+    n = A.n_rows
+    layer = N_GRID * N_GRID
+    dA = cgx.DeviceCSR.from_host(A)
+    db = torch.from_numpy(b).cuda()
+    dx = torch.zeros_like(db)
+    res = {"workload": "Q1 128^3 lognormal(0,1), blob RHS, rtol 1e-8; additive Schwarz slabs "
+                       "around flexible CG, subdomains by batched Jacobi-CG"}
+    jopts = cgx.make_opts(rtol=RTOL, precond=cgx.PRECOND_JACOBI)
+    ws = cgx.cg_workspace(dA, jopts)
+    st = cgx.cg_solve(dA, db, dx, jopts, workspace=ws)
+
+    def jsolve():
+        dx.zero_()
+        cgx.cg_solve(dA, db, dx, jopts, workspace=ws)
+
+    wall, j = _energy_window(jsolve, meter, min_s=2.0)
+    res["jacobi_cg"] = {"iters": st.iters, "solve_ms": round(wall * 1e3, 2),
+                        "j_per_solve": round(j, 3) if j is not None else None}
+    rows = []
+    for S, layers, tau, m in ((8, 1, 0.1, 100), (8, 2, 0.1, 100), (32, 1, 0.1, 100),
+                              (32, 1, -1.0, 8), (128, 1, 0.1, 100), (128, 1, -1.0, 8)):
+        t0 = time.perf_counter()
+        D = cgx.SchwarzDecomposition(dA, S, layers * layer)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        opts = cgx.make_opts(rtol=RTOL, maxit=m, inner_rtol=tau, precond=cgx.PRECOND_JACOBI)
+        wsd = torch.empty(D.workspace_bytes(), dtype=torch.uint8, device="cuda")
+        dx.zero_()
+        st = cgx.schwarz_solve(dA, D, db, dx, opts, workspace=wsd)
+        relres = float(np.linalg.norm(b - oracle_mod.spmv(A, dx.cpu().numpy())) / np.linalg.norm(b))
+
+        def solve():
+            dx.zero_()
+            cgx.schwarz_solve(dA, D, db, dx, opts, workspace=wsd)
+
+        wall, j = _energy_window(solve, meter, min_s=2.0)
+        nnz_off = D.arrays()[0].cpu().numpy()
+        lrows = D.local_rows
+        it_bytes = 12 * int(nnz_off[-1]) + 4 * (lrows + S) + 88 * lrows
+        rows.append({"n_sub": S, "overlap_layers": layers,
+                     "inner": f"tau {tau:g}, cap {m}" if tau > 0 else f"{m} iterations",
+                     "status": st.status, "outer": st.outer_iters, "inner_iters": st.iters,
+                     "build_ms": round(build_ms, 1), "solve_ms": round(wall * 1e3, 1),
+                     "local_share": round(st.phase_ms[0] / st.device_ms, 3),
+                     "local_GBs_model": round(it_bytes * st.iters / (st.phase_ms[0] * 1e-3) / 1e9, 1),
+                     "j_per_solve": round(j, 3) if j is not None else None,
+                     "true_relres_by_oracle_spmv": relres})
+        print(f"# schwarz S={S} layers={layers} tau={tau} done", file=sys.stderr, flush=True)
+        del D, wsd
+    res["rows"] = rows
+    return res
+
+
 def extra_mixed(cgx, synth, meter):
     """Q1 192^3 lognormal(0,1.5), uniform RHS, to 1e-10: float64 CG against
     binary32-inner refinement, each plain and Jacobi-preconditioned."""
@@ -655,6 +718,7 @@ def run_extras(which):
              "blas1": lambda: extra_blas1_sweep(cgx, synth),
              "q1": lambda: extra_spmv_and_cg(cgx, synth, meter),
              "mixed": lambda: extra_mixed(cgx, synth, meter),
+             "schwarz": lambda: extra_schwarz(cgx, synth, oracle_mod, meter),
              "batched": lambda: extra_batched(cgx, synth, meter),
              "serving": lambda: extra_serving(cgx, synth, meter),
              "paper": lambda: extra_paper_shapes(cgx, synth, meter),

@@ -139,11 +139,14 @@ typedef struct cgx_opts {
 
 typedef struct cgx_stats {
     int32_t status;      /* CGX_OK, CGX_NOT_CONVERGED, CGX_BREAKDOWN, CGX_NONFINITE */
-    int32_t iters;       /* CG iterations (binary32 inner iterations for MIXED) */
-    int32_t outer_iters; /* MIXED: refinement steps; served requests: requests in its
-                          * slot when it started, itself included (1: alone) */
+    int32_t iters;       /* CG iterations (binary32 inner iterations for MIXED;
+                          * Schwarz: subdomain iterations, summed over the outer
+                          * steps of the largest count among the subdomains) */
+    int32_t outer_iters; /* MIXED: refinement steps; Schwarz: outer iterations;
+                          * served requests: requests in its slot when it
+                          * started, itself included (1: alone) */
     int32_t path;        /* kernel path: 0 phase kernels, 1 single workgroup, 2 mixed
-                          * refinement, 3 batched, 4 served */
+                          * refinement, 3 batched, 4 served, 5 Schwarz */
     double relres;       /* recursive ||r|| / ||b|| at exit (outer residual for MIXED) */
     double relres_true;  /* ||b - A x|| / ||b|| if requested, else -1 */
     double device_ms;    /* GPU time of the solve, from stream events */
@@ -306,6 +309,69 @@ int cgx_poll(cgx_handle h, uint64_t ticket, cgx_stats *stats);
 
 /* (sync) Like cgx_poll but waits for completion. */
 int cgx_wait(cgx_handle h, uint64_t ticket, cgx_stats *stats);
+
+/* ------------------------------------------ domain decomposition -- */
+
+/* Additive Schwarz preconditioner with conjugate-gradient subdomain solves
+ * (end of Section 5.3: domain-decomposition preconditioning of CG, the outer
+ * iteration on the host and every subdomain problem solved by CG on the
+ * GPU).  The rows are cut into n_sub contiguous core blocks [floor(i n /
+ * n_sub), floor((i+1) n / n_sub)); subdomain i is its block extended by
+ * `overlap` rows on each side, clipped to [0, n) (for a grid in
+ * lexicographic order, slabs overlapping by overlap / (rows per layer)
+ * layers).  Its matrix A_i is the principal submatrix of A on those rows and
+ * columns, entries in stored order, columns shifted to start at 0.  All
+ * pointers are device memory inside the caller's buffer. */
+typedef struct cgx_schwarz {
+    int32_t n_rows;            /* rows of A */
+    int32_t n_sub;             /* subdomains, 1 <= n_sub <= n_rows */
+    int32_t overlap;           /* 0 <= overlap <= floor(n_rows / n_sub) */
+    int32_t reserved;
+    int64_t local_rows;        /* sum of the subdomain sizes: n + 2 overlap (n_sub - 1) */
+    int64_t local_nnz;         /* entries of all subdomain matrices */
+    const int64_t *nnz_off;    /* int64[n_sub + 1]: first entry of each subdomain */
+    const int32_t *row_ptr;    /* int32[local_rows + n_sub]: subdomain i's m_i + 1 row
+                                * pointers (from 0) at local row offset + i */
+    const int32_t *col;        /* int32[local_nnz] */
+    const double *val;         /* float64[local_nnz] */
+} cgx_schwarz;
+
+/* (sync) Device bytes cgx_schwarz_build needs (one pass over A).  CGX_EINVAL
+ * unless A is square, 1 <= n_sub <= n_rows and 0 <= overlap <= floor(n_rows /
+ * n_sub). */
+int cgx_schwarz_bytes(cgx_handle h, const cgx_csr *A, int32_t n_sub, int32_t overlap,
+                      size_t *bytes);
+
+/* (sync) Build the subdomain matrices into `buffer` (device, 256-byte
+ * aligned, >= cgx_schwarz_bytes; owned by the caller, which keeps it while
+ * *out is used) and describe them in *out.  CGX_ENOMEM if bytes is too
+ * small; CGX_EINVAL as for cgx_schwarz_bytes. */
+int cgx_schwarz_build(cgx_handle h, const cgx_csr *A, int32_t n_sub, int32_t overlap,
+                      void *buffer, size_t bytes, cgx_schwarz *out);
+
+/* Workspace bytes of cgx_schwarz_solve (0 on invalid S). */
+size_t cgx_schwarz_workspace_bytes(const cgx_schwarz *S);
+
+/* (sync) Solve A x = b (A symmetric positive definite, S built from A) by
+ * flexible conjugate gradient preconditioned by additive Schwarz: with
+ * q = A p, alpha = r.z / p.q, x += alpha p, r -= alpha q, stop when ||r|| <=
+ * opts->rtol ||b||; then z = sum_i R_i^T z_i (subdomains added in increasing
+ * order), z_i from CG on A_i z_i = R_i r started at 0, all subdomains solved
+ * together by the batched solver; beta = -alpha (z.q) / rho, rho = r.z, p =
+ * z + beta p.  Subdomain CG: opts->inner_rtol > 0 its relative tolerance,
+ * 0 for 1e-2, < 0 for none (exactly opts->maxit iterations); opts->maxit
+ * (<= 0: 50) its iteration cap; opts->precond its preconditioner.
+ * opts->max_outer (<= 0: n) caps the outer iterations; opts->true_residual
+ * as for cgx_cg_solve; opts->precision must be FP64.  x holds x0 and
+ * receives the solution; b = 0 gives x = 0.  stats: outer_iters, iters (see
+ * cgx_stats), relres, device_ms (wall time of the call), phase_ms[0] (time
+ * in the subdomain solves) and phase_ms[1] (the rest).  Returns
+ * stats->status: CGX_OK, CGX_NOT_CONVERGED, CGX_BREAKDOWN (p.q <= 0, r.z <=
+ * 0, or a subdomain solve broke down), CGX_NONFINITE; CGX_ENOMEM if the
+ * workspace is too small. */
+int cgx_schwarz_solve(cgx_handle h, const cgx_csr *A, const cgx_schwarz *S, const double *b,
+                      double *x, void *workspace, size_t workspace_bytes, const cgx_opts *opts,
+                      cgx_stats *stats);
 
 #ifdef __cplusplus
 }

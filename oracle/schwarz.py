@@ -153,6 +153,8 @@ def solve(A, b, x0=None, rtol=1e-8, max_outer=0, n_sub=4, overlap=0, inner_rtol=
         if np.sqrt(rr) <= rtol * bnorm:
             status = OK
             break
+        if k >= cap:
+            break
         z, its, worst = apply(rg, subs, r, inner_rtol, inner_maxit, jacobi)
         inner += its
         beta = -alpha * dot(z, q) / rho

@@ -65,6 +65,14 @@ class _Sell(ctypes.Structure):
                 ("val", ctypes.c_void_p), ("val32", ctypes.c_void_p)]
 
 
+class _Schwarz(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("n_sub", ctypes.c_int32),
+                ("overlap", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("local_rows", ctypes.c_int64), ("local_nnz", ctypes.c_int64),
+                ("nnz_off", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
 class _System(ctypes.Structure):
     _fields_ = [("A", _Csr), ("nrhs", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("B", ctypes.c_void_p), ("X", ctypes.c_void_p)]
@@ -77,7 +85,8 @@ EXPORTS = [
     "cgx_sell_bytes", "cgx_sell_build", "cgx_sell_spmv", "cgx_sell_spmv_f32", "cgx_cg_solve_sell",
     "cgx_batch_workspace_bytes", "cgx_cg_solve_batched", "cgx_batch_schedule",
     "cgx_serve_start", "cgx_serve_stop", "cgx_serve_request_bytes", "cgx_submit", "cgx_poll",
-    "cgx_wait",
+    "cgx_wait", "cgx_schwarz_bytes", "cgx_schwarz_build", "cgx_schwarz_workspace_bytes",
+    "cgx_schwarz_solve",
 ]
 
 _lib = None
@@ -126,6 +135,12 @@ def load_library(path: str = LIB_PATH):
         "cgx_submit": ([vp, P(_Csr), vp, vp, P(Opts), P(ctypes.c_uint64)], ctypes.c_int),
         "cgx_poll": ([vp, ctypes.c_uint64, P(Stats)], ctypes.c_int),
         "cgx_wait": ([vp, ctypes.c_uint64, P(Stats)], ctypes.c_int),
+        "cgx_schwarz_bytes": ([vp, P(_Csr), i32, i32, P(ctypes.c_size_t)], ctypes.c_int),
+        "cgx_schwarz_build": ([vp, P(_Csr), i32, i32, vp, ctypes.c_size_t, P(_Schwarz)],
+                              ctypes.c_int),
+        "cgx_schwarz_workspace_bytes": ([P(_Schwarz)], ctypes.c_size_t),
+        "cgx_schwarz_solve": ([vp, P(_Csr), P(_Schwarz), vp, vp, vp, ctypes.c_size_t, P(Opts),
+                               P(Stats)], ctypes.c_int),
     }
     for name, (argt, rest) in sig.items():
         fn = getattr(lib, name)
@@ -277,6 +292,61 @@ class SellMatrix:
 
         return (view(d.slice_ptr, d.n_slices + 1, torch.int64, 8),
                 view(d.col, d.stored, torch.int32, 4), view(d.val, d.stored, torch.float64, 8))
+
+
+class SchwarzDecomposition:
+    """Subdomain matrices of an additive Schwarz preconditioner for a
+    DeviceCSR (cgx_schwarz_build: n_sub contiguous row blocks, each extended
+    by `overlap` rows on both sides) in a torch-owned buffer."""
+
+    def __init__(self, A: DeviceCSR, n_sub: int, overlap: int = 0, handle=None):
+        d = A.desc()
+        nbytes = ctypes.c_size_t()
+        _check(load_library().cgx_schwarz_bytes(_h(handle), ctypes.byref(d), int(n_sub),
+                                                int(overlap), ctypes.byref(nbytes)))
+        self.csr = A
+        self.buffer = torch.empty(max(nbytes.value, 256), dtype=torch.uint8,
+                                  device=A.row_ptr.device)
+        self._desc = _Schwarz()
+        _check(load_library().cgx_schwarz_build(_h(handle), ctypes.byref(d), int(n_sub),
+                                                int(overlap), _ptr(self.buffer),
+                                                self.buffer.numel(), ctypes.byref(self._desc)))
+
+    @property
+    def n_sub(self) -> int:
+        return self._desc.n_sub
+
+    @property
+    def overlap(self) -> int:
+        return self._desc.overlap
+
+    @property
+    def local_rows(self) -> int:
+        return self._desc.local_rows
+
+    @property
+    def local_nnz(self) -> int:
+        return self._desc.local_nnz
+
+    def desc(self) -> _Schwarz:
+        return self._desc
+
+    def workspace_bytes(self) -> int:
+        return int(load_library().cgx_schwarz_workspace_bytes(ctypes.byref(self._desc)))
+
+    def arrays(self):
+        """(nnz_off int64, row_ptr int32, col int32, val float64) views of the buffer."""
+        d = self._desc
+        base = self.buffer.data_ptr()
+
+        def view(ptr, count, dtype, size):
+            off = ptr - base
+            return self.buffer[off:off + count * size].view(dtype)
+
+        return (view(d.nnz_off, d.n_sub + 1, torch.int64, 8),
+                view(d.row_ptr, d.local_rows + d.n_sub, torch.int32, 4),
+                view(d.col, d.local_nnz, torch.int32, 4),
+                view(d.val, d.local_nnz, torch.float64, 8))
 
 
 def _h(handle):
@@ -432,6 +502,28 @@ def cg_solve(A: DeviceCSR, b, x, opts: Opts | None = None, workspace=None, handl
                                               ctypes.byref(sell.desc()), _ptr(b), _ptr(x),
                                               _ptr(workspace), workspace.numel(),
                                               ctypes.byref(opts), ctypes.byref(st))
+    if rc in (EINVAL, ENOMEM, EHIP) or (raise_on_fail and rc != OK):
+        _check(rc)
+    return st
+
+
+def schwarz_solve(A: DeviceCSR, D: SchwarzDecomposition, b, x, opts: Opts | None = None,
+                  workspace=None, handle=None, raise_on_fail=False) -> Stats:
+    """Solve A x = b in place on x by flexible CG under the additive Schwarz
+    preconditioner D (cgx_schwarz_solve; subdomain CG per opts.inner_rtol,
+    opts.maxit, opts.precond; outer cap opts.max_outer)."""
+    opts = opts or make_opts()
+    _dev_tensor(b, torch.float64, "b")
+    _dev_tensor(x, torch.float64, "x")
+    if b.numel() != A.n_rows or x.numel() != A.n_rows:
+        raise ValueError("b / x length does not match A")
+    if workspace is None:
+        workspace = torch.empty(max(D.workspace_bytes(), 1), dtype=torch.uint8, device=x.device)
+    st = Stats()
+    d = A.desc()
+    rc = load_library().cgx_schwarz_solve(_h(handle), ctypes.byref(d), ctypes.byref(D.desc()),
+                                          _ptr(b), _ptr(x), _ptr(workspace), workspace.numel(),
+                                          ctypes.byref(opts), ctypes.byref(st))
     if rc in (EINVAL, ENOMEM, EHIP) or (raise_on_fail and rc != OK):
         _check(rc)
     return st

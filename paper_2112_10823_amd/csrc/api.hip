@@ -361,6 +361,89 @@ int cgx_sell_spmv_f32(cgx_handle h, const cgx_sell *S, const float *x, float *y)
     });
 }
 
+static int check_schwarz_shape(const cgx_csr *A, int32_t n_sub, int32_t overlap)
+{
+    int rc = check_csr(A, true, false);
+    if (rc) return rc;
+    CGX_REQUIRE(A->n_rows == A->n_cols, "matrix must be square");
+    CGX_REQUIRE(n_sub >= 1 && n_sub <= A->n_rows, "n_sub must be in [1, n_rows]");
+    CGX_REQUIRE(overlap >= 0 && overlap <= A->n_rows / n_sub,
+                "overlap must be in [0, floor(n_rows / n_sub)]");
+    return CGX_OK;
+}
+
+static bool schwarz_ok(const cgx_schwarz *S)
+{
+    if (!S || S->n_rows < 1 || S->n_sub < 1 || S->n_sub > S->n_rows) return false;
+    if (S->overlap < 0 || S->overlap > S->n_rows / S->n_sub) return false;
+    if (S->local_rows != (int64_t)S->n_rows + 2 * (int64_t)S->overlap * (S->n_sub - 1))
+        return false;
+    return S->local_nnz >= 0 && S->nnz_off && S->row_ptr &&
+           (S->local_nnz == 0 || (S->col && S->val));
+}
+
+int cgx_schwarz_bytes(cgx_handle h, const cgx_csr *A, int32_t n_sub, int32_t overlap,
+                      size_t *bytes)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(bytes != nullptr, "bytes is NULL");
+        int rc = check_schwarz_shape(A, n_sub, overlap);
+        if (rc) return rc;
+        return cgx::schwarz_bytes(ctx_of(h), A, n_sub, overlap, bytes);
+    });
+}
+
+int cgx_schwarz_build(cgx_handle h, const cgx_csr *A, int32_t n_sub, int32_t overlap,
+                      void *buffer, size_t bytes, cgx_schwarz *out)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(out != nullptr, "out is NULL");
+        int rc = check_schwarz_shape(A, n_sub, overlap);
+        if (rc) return rc;
+        CGX_REQUIRE(buffer != nullptr && ((uintptr_t)buffer & 255) == 0,
+                    "buffer must be 256-byte aligned device memory");
+        return cgx::schwarz_build(ctx_of(h), A, n_sub, overlap, buffer, bytes, out);
+    });
+}
+
+size_t cgx_schwarz_workspace_bytes(const cgx_schwarz *S)
+{
+    if (!schwarz_ok(S)) return 0;
+    try {
+        return cgx::schwarz_workspace_bytes(S);
+    } catch (...) {
+        return 0;
+    }
+}
+
+int cgx_schwarz_solve(cgx_handle h, const cgx_csr *A, const cgx_schwarz *S, const double *b,
+                      double *x, void *workspace, size_t workspace_bytes, const cgx_opts *opts,
+                      cgx_stats *stats)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(opts != nullptr && stats != nullptr, "opts or stats is NULL");
+        int rc = check_csr(A, true, false);
+        if (rc) return rc;
+        CGX_REQUIRE(A->n_rows == A->n_cols, "matrix must be square");
+        CGX_REQUIRE(schwarz_ok(S), "bad Schwarz descriptor");
+        CGX_REQUIRE(S->n_rows == A->n_rows, "Schwarz descriptor does not match A");
+        CGX_REQUIRE(opts->precond == CGX_PRECOND_NONE || opts->precond == CGX_PRECOND_JACOBI,
+                    "unknown preconditioner");
+        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64, "Schwarz solve is float64");
+        CGX_REQUIRE(opts->rtol >= 0.0, "rtol must be >= 0");
+        std::memset(stats, 0, sizeof(*stats));
+        stats->relres_true = -1.0;
+        CGX_REQUIRE(b && x && workspace, "NULL b, x or workspace");
+        CGX_REQUIRE(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
+        const size_t nb = (size_t)A->n_rows * 8;
+        CGX_REQUIRE(!overlaps(b, nb, x, nb), "x overlaps b");
+        return cgx::schwarz_solve(ctx_of(h), A, S, b, x, workspace, workspace_bytes, opts, stats);
+    });
+}
+
 static int check_batch(cgx_handle h, int32_t nsys, const cgx_system *systems)
 {
     CGX_REQUIRE(h != nullptr, "handle is NULL");

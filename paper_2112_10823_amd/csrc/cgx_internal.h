@@ -149,6 +149,12 @@ int batch_autotune(Context *c, int32_t nsys, const cgx_system *in, void *ws, siz
                    std::vector<int> &Ms);
 int tune_one(Context *c, const cgx_system &sys, void *ws, size_t ws_bytes, hipStream_t s,
              int &M_out);
+int schwarz_bytes(Context *c, const cgx_csr *A, int n_sub, int overlap, size_t *bytes);
+int schwarz_build(Context *c, const cgx_csr *A, int n_sub, int overlap, void *buf, size_t bytes,
+                  cgx_schwarz *out);
+size_t schwarz_workspace_bytes(const cgx_schwarz *S);
+int schwarz_solve(Context *c, const cgx_csr *A, const cgx_schwarz *S, const double *b, double *x,
+                  void *ws, size_t ws_bytes, const cgx_opts *o, cgx_stats *st);
 int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots, int32_t max_group);
 int serve_stop(Context *c);
 size_t serve_request_bytes(int64_t n_rows);

@@ -52,6 +52,7 @@ int main(void) {{
   printf("%zu %zu %zu %zu\\n", sizeof(cgx_stats), offsetof(cgx_stats, relres), offsetof(cgx_stats, device_ms), offsetof(cgx_stats, phase_ms));
   printf("%zu %zu %zu %zu\\n", sizeof(cgx_sell), offsetof(cgx_sell, n_slices), offsetof(cgx_sell, slice_ptr), offsetof(cgx_sell, val32));
   printf("%zu %zu %zu\\n", sizeof(cgx_system), offsetof(cgx_system, schedule), offsetof(cgx_system, X));
+  printf("%zu %zu %zu %zu\\n", sizeof(cgx_schwarz), offsetof(cgx_schwarz, local_rows), offsetof(cgx_schwarz, nnz_off), offsetof(cgx_schwarz, val));
   return 0;
 }}
 """)
@@ -67,6 +68,23 @@ int main(void) {{
     L, Y = cgx._Sell, cgx._System
     assert c[3] == [ctypes.sizeof(L), L.n_slices.offset, L.slice_ptr.offset, L.val32.offset]
     assert c[4] == [ctypes.sizeof(Y), Y.schedule.offset, Y.X.offset]
+    W = cgx._Schwarz
+    assert c[5] == [ctypes.sizeof(W), W.local_rows.offset, W.nnz_off.offset, W.val.offset]
+
+
+def test_schwarz_workspace_bytes_host_only():
+    """The workspace size query needs no GPU; a descriptor whose sizes do not
+    add up is refused with 0."""
+    W = cgx._Schwarz
+    d = W(n_rows=1000, n_sub=4, overlap=50, local_rows=1000 + 2 * 50 * 3, local_nnz=0,
+          nnz_off=256, row_ptr=512, col=None, val=None)
+    lib = cgx.load_library()
+    nb = lib.cgx_schwarz_workspace_bytes(ctypes.byref(d))
+    assert nb >= (4 * 1000 + 1300) * 8
+    d.local_rows = 1299
+    assert lib.cgx_schwarz_workspace_bytes(ctypes.byref(d)) == 0
+    d.local_rows, d.overlap = 1300 + 2 * 3 * 200, 251
+    assert lib.cgx_schwarz_workspace_bytes(ctypes.byref(d)) == 0
 
 
 def test_binding_refuses_host_tensors():
