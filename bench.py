@@ -379,7 +379,7 @@ def extra_mixed(cgx, synth, meter):
     return out
 
 
-def extra_batched(cgx, synth, meter):
+def extra_batched(cgx, synth, oracle_mod, meter):
     """64 systems (7-point / Q1 alternating, N ~ U{24..96}, lognormal(0,1)),
     16 RHS each, Jacobi CG to 1e-8: batched against one solve at a time."""
     import torch
@@ -389,7 +389,7 @@ def extra_batched(cgx, synth, meter):
         B = torch.empty(16, A.n_rows, dtype=torch.float64)
         for j in range(16):
             B[j] = torch.from_numpy(synth.uniform(1000 + s * 16 + j, A.n_rows))
-        items.append((cgx.DeviceCSR.from_host(A), B.cuda(),
+        items.append((cgx.DeviceCSR.from_host(A, with_f32=True), B.cuda(),
                       torch.zeros(16, A.n_rows, dtype=torch.float64, device="cuda")))
     opts = cgx.make_opts(rtol=1e-8, precond=1)
     ws = cgx.batch_workspace(items)
@@ -423,8 +423,37 @@ def extra_batched(cgx, synth, meter):
             cgx.cg_solve(dA, B[j].contiguous(), x1, o1, workspace=w1)
         t_single += (time.perf_counter() - t1) / 4 * 16
     t_single *= 64 / len(sample)
+    # the same batch float32-refined: float64 residual and update, binary32
+    # inner batched Jacobi-CG to 1e-2
+    mopts = cgx.make_opts(rtol=1e-8, precond=1, precision=cgx.PRECISION_MIXED, inner_rtol=1e-2)
+    mws = cgx.batch_workspace(items, opts=mopts)
+    for _, _, X in items:
+        X.zero_()
+    mst = cgx.cg_solve_batched(items, mopts, workspace=mws)
+    check = []
+    for s in (0, 21, 42, 63):
+        dA, B, X = items[s]
+        for j in (0, 15):
+            b = B[j].cpu().numpy()
+            x = X[j].cpu().numpy()
+            check.append(float(np.linalg.norm(b - oracle_mod.spmv(mats[s], x)) / np.linalg.norm(b)))
+
+    def msolve():
+        nonlocal mst
+        for _, _, X in items:
+            X.zero_()
+        mst = cgx.cg_solve_batched(items, mopts, workspace=mws)
+
+    mwall, mjb = _energy_window(msolve, meter, min_s=2.0)
+    mixed = {"solves_per_s": round(1024 / mwall, 1), "batch_s": round(mwall, 3),
+             "converged": sum(v.status == cgx.OK for row in mst for v in row),
+             "j_per_solve": round(mjb / 1024, 4) if mjb is not None else None,
+             "inner_iters_mean": round(float(np.mean([v.iters for row in mst for v in row])), 1),
+             "outer_mean": round(float(np.mean([v.outer_iters for row in mst for v in row])), 2),
+             "true_relres_max_sample": max(check)}
     return {"workload": "64 systems N~U{24..96} 7-point/Q1 lognormal(0,1), 16 RHS each, "
                         "Jacobi CG rtol 1e-8",
+            "float32_refined": mixed,
             "solves": 1024, "converged": ok, "batch_s": round(wall, 3),
             "solves_per_s": round(1024 / wall, 1),
             "model_GBs": round(byts / wall / 1e9, 1),
@@ -731,7 +760,7 @@ def run_extras(which):
              "q1": lambda: extra_spmv_and_cg(cgx, synth, meter),
              "mixed": lambda: extra_mixed(cgx, synth, meter),
              "schwarz": lambda: extra_schwarz(cgx, synth, oracle_mod, meter),
-             "batched": lambda: extra_batched(cgx, synth, meter),
+             "batched": lambda: extra_batched(cgx, synth, oracle_mod, meter),
              "serving": lambda: extra_serving(cgx, synth, meter),
              "serving10k": lambda: extra_serving(cgx, synth, meter, n_req=10000, full=False),
              "paper": lambda: extra_paper_shapes(cgx, synth, meter),

@@ -241,6 +241,11 @@ typedef struct cgx_system {
 /* Workspace bytes of cgx_cg_solve_batched for this batch (0 on bad input). */
 size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems);
 
+/* Workspace bytes of cgx_cg_solve_batched with opts->precision MIXED (the
+ * float64 state, the binary32 inner state and the inner right-hand sides
+ * and solutions; 0 on bad input). */
+size_t cgx_batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *systems);
+
 /* (sync) Solve every system of the batch by conjugate gradient (Section 5.3;
  * Jacobi preconditioning optional), all systems and right-hand sides
  * advanced together: each phase of an iteration is one kernel launch over a
@@ -252,8 +257,20 @@ size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems);
  * in the handle (unless the system fixes it).  A system's results do not depend on the
  * other systems in the batch.  stats: array of sum(nrhs) entries in
  * (system, right-hand side) order.  Returns CGX_OK if all converged, else
- * the first non-OK status; argument errors as usual.  opts->precision must
- * be FP64; opts->maxit <= 0 means the largest n. */
+ * the first non-OK status; argument errors as usual.  opts->maxit <= 0
+ * means the largest n.
+ *
+ * opts->precision MIXED (every A.val32 set; workspace from
+ * cgx_batch_mixed_workspace_bytes): the refinement of the single-system
+ * MIXED solve for every (system, right-hand side) at once.  Each outer step
+ * computes r = b - A x in float64 for all of them (right-hand sides with
+ * ||r|| <= rtol ||b|| are done), then solves A32 d = float(r / ||r||) for the
+ * others by batched binary32 CG (binary32 values, vectors, scalars and
+ * sums; Jacobi with float(1 / a_ii) if asked) from d = 0 to inner_rtol (<= 0:
+ * 1e-3) within maxit iterations, and sets x = fma(||r||, double(d), x); at
+ * most max_outer (<= 0: 100) steps.  stats: iters = binary32 iterations
+ * summed over the steps, outer_iters = refinement steps, relres = the last
+ * float64 ||r|| / ||b||. */
 int cgx_cg_solve_batched(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
                          size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats);
 

@@ -85,7 +85,7 @@ EXPORTS = [
     "cgx_sell_bytes", "cgx_sell_build", "cgx_sell_spmv", "cgx_sell_spmv_f32", "cgx_cg_solve_sell",
     "cgx_batch_workspace_bytes", "cgx_cg_solve_batched", "cgx_batch_schedule",
     "cgx_serve_start", "cgx_serve_stop", "cgx_serve_request_bytes", "cgx_submit", "cgx_poll",
-    "cgx_wait", "cgx_schwarz_bytes", "cgx_schwarz_build", "cgx_schwarz_workspace_bytes",
+    "cgx_wait", "cgx_batch_mixed_workspace_bytes", "cgx_schwarz_bytes", "cgx_schwarz_build", "cgx_schwarz_workspace_bytes",
     "cgx_schwarz_solve",
 ]
 
@@ -126,6 +126,7 @@ def load_library(path: str = LIB_PATH):
         "cgx_cg_solve_sell": ([vp, P(_Csr), P(_Sell), vp, vp, vp, ctypes.c_size_t, P(Opts),
                                P(Stats)], ctypes.c_int),
         "cgx_batch_workspace_bytes": ([i32, P(_System)], ctypes.c_size_t),
+        "cgx_batch_mixed_workspace_bytes": ([i32, P(_System)], ctypes.c_size_t),
         "cgx_cg_solve_batched": ([vp, i32, P(_System), vp, ctypes.c_size_t, P(Opts), P(Stats)],
                                  ctypes.c_int),
         "cgx_batch_schedule": ([vp, i32, P(_System), vp, ctypes.c_size_t, P(i32)], ctypes.c_int),
@@ -549,13 +550,18 @@ def _systems(items):
     return arr
 
 
-def batch_workspace_bytes(items) -> int:
+def batch_workspace_bytes(items, opts: Opts | None = None) -> int:
+    """Workspace bytes of cg_solve_batched (float32-refined with
+    opts.precision == PRECISION_MIXED)."""
     arr = _systems(items)
+    if opts is not None and opts.precision == PRECISION_MIXED:
+        return int(load_library().cgx_batch_mixed_workspace_bytes(len(items), arr))
     return int(load_library().cgx_batch_workspace_bytes(len(items), arr))
 
 
-def batch_workspace(items, device="cuda") -> torch.Tensor:
-    return torch.empty(max(batch_workspace_bytes(items), 1), dtype=torch.uint8, device=device)
+def batch_workspace(items, device="cuda", opts: Opts | None = None) -> torch.Tensor:
+    return torch.empty(max(batch_workspace_bytes(items, opts), 1), dtype=torch.uint8,
+                       device=device)
 
 
 def cg_solve_batched(items, opts: Opts | None = None, workspace=None, handle=None):
@@ -565,7 +571,7 @@ def cg_solve_batched(items, opts: Opts | None = None, workspace=None, handle=Non
     opts = opts or make_opts()
     arr = _systems(items)
     if workspace is None:
-        workspace = batch_workspace(items)
+        workspace = batch_workspace(items, opts=opts)
     nstat = sum(int(item[1].shape[0]) for item in items)
     st = (Stats * nstat)()
     rc = load_library().cgx_cg_solve_batched(_h(handle), len(items), arr, _ptr(workspace),

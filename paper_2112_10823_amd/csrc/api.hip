@@ -110,6 +110,7 @@ int cgx_destroy(cgx_handle h)
     c->graph64.reset();
     c->graph32.reset();
     c->graph_batch.reset();
+    c->graph_batch32.reset();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
@@ -444,13 +445,14 @@ int cgx_schwarz_solve(cgx_handle h, const cgx_csr *A, const cgx_schwarz *S, cons
     });
 }
 
-static int check_batch(cgx_handle h, int32_t nsys, const cgx_system *systems)
+static int check_batch(cgx_handle h, int32_t nsys, const cgx_system *systems,
+                       bool need_val32 = false)
 {
     CGX_REQUIRE(h != nullptr, "handle is NULL");
     CGX_REQUIRE(nsys >= 1 && systems != nullptr, "empty batch");
     for (int32_t s = 0; s < nsys; ++s) {
         const cgx_system &q = systems[s];
-        int rc = check_csr(&q.A, true, false);
+        int rc = check_csr(&q.A, true, need_val32);
         if (rc) return rc;
         CGX_REQUIRE(q.A.n_rows == q.A.n_cols, "batched matrices must be square");
         CGX_REQUIRE(q.A.n_rows >= 1, "empty system in batch");
@@ -485,19 +487,35 @@ size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems)
     }
 }
 
+size_t cgx_batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *systems)
+{
+    if (nsys < 1 || systems == nullptr) return 0;
+    try {
+        return cgx::batch_mixed_workspace_bytes(nsys, systems);
+    } catch (...) {
+        return 0;
+    }
+}
+
 int cgx_cg_solve_batched(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
                          size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats)
 {
     return guarded([&]() -> int {
-        int rc = check_batch(h, nsys, systems);
-        if (rc) return rc;
         CGX_REQUIRE(opts != nullptr && stats != nullptr, "opts or stats is NULL");
-        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64, "batched solve is float64");
+        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64 ||
+                        opts->precision == CGX_PRECISION_MIXED,
+                    "unknown precision");
+        const bool mixed = opts->precision == CGX_PRECISION_MIXED;
+        int rc = check_batch(h, nsys, systems, mixed);
+        if (rc) return rc;
         CGX_REQUIRE(opts->precond == CGX_PRECOND_NONE || opts->precond == CGX_PRECOND_JACOBI,
                     "unknown preconditioner");
         CGX_REQUIRE(opts->rtol >= 0.0, "rtol must be >= 0");
         CGX_REQUIRE(workspace != nullptr && ((uintptr_t)workspace & 255) == 0,
                     "workspace must be 256-byte aligned");
+        if (mixed)
+            return cgx::run_batched_mixed(ctx_of(h), nsys, systems, workspace, workspace_bytes,
+                                          opts, stats);
         return cgx::run_batched(ctx_of(h), nsys, systems, workspace, workspace_bytes, opts, stats);
     });
 }

@@ -18,15 +18,18 @@ struct LanePtr {
     double *x;
 };
 
-struct BSys {
+// T: the type of the values, vectors and sums (double, or float for the
+// inner solves of the float32-refined batch).
+template <typename T>
+struct BSysT {
     const int32_t *rp;
     const int32_t *ci;
-    const double *val;
-    const double *B;  // caller right-hand sides, [nrhs][n] (batch call)
-    double *X;        // caller solutions, [nrhs][n] (batch call)
+    const T *val;
+    const T *B;  // caller right-hand sides, [nrhs][n] (batch call)
+    T *X;        // caller solutions, [nrhs][n] (batch call)
     const LanePtr *lanes;  // served groups: per right-hand side b / x (else null)
-    double *x, *r, *p, *q, *z;  // interleaved [n][K]
-    double *dinv;     // [n]
+    T *x, *r, *p, *q, *z;  // interleaved [n][K]
+    T *dinv;     // [n]
     int64_t nnz;
     int n, K, nrhs, M;
     int tile0, ntiles, trows, scal0;
@@ -34,28 +37,33 @@ struct BSys {
     int maxit, pad;
     double rtol2;        // squared relative tolerance of this system
 };
+using BSys = BSysT<double>;
 
 struct BTile {
     int sys, row0, rows, tile;  // tile = index within the whole table
 };
 
-struct BScal {
-    double rho, rho_used, alpha, beta, rr, bb, stop2, pq;
+template <typename T>
+struct BScalT {
+    T rho, rho_used, alpha, beta, rr, bb, stop2, pq;
     int32_t iter, status, active, pad;
 };
+using BScal = BScalT<double>;
 
-struct BArgs {
-    const BSys *sys;
+template <typename T>
+struct BArgsT {
+    const BSysT<T> *sys;
     const BTile *tiles;     // tiles this launch covers (one workgroup each)
     const int32_t *list;    // systems the per-system kernels cover (one workgroup each)
-    BScal *scal;
+    BScalT<T> *scal;
     int32_t *sys_done;      // per system: all right-hand sides finished
-    double *part;           // 3 regions of part_stride doubles
+    T *part;                // 3 regions of part_stride values
     int64_t part_stride;    // (tiles of the whole table) * 16
     int ntiles;
     int nlist;
     int wave_lds;           // dynamic LDS bytes of the SpMM launch (wave-tile staging or 0)
 };
+using BArgs = BArgsT<double>;
 
 namespace bk {
 namespace {  // internal linkage: each translation unit keeps its own copy
@@ -68,15 +76,19 @@ __device__ __forceinline__ int clampk(int v, int64_t nnz)
     return v < 0 ? 0 : (v > nnz ? (int)nnz : v);
 }
 
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Per-RHS block sum: thread t holds a value for right-hand side t % K; the
 // K totals (fixed order) are written to out[0..K) by threads 0..K-1.
-__device__ __forceinline__ void block_sum_by_rhs(double v, int K, double *red, double *out)
+template <typename T>
+__device__ __forceinline__ void block_sum_by_rhs(T v, int K, T *red, T *out)
 {
     __syncthreads();
     red[threadIdx.x] = v;
     __syncthreads();
     if (threadIdx.x < K) {
-        double s = 0.0;
+        T s = T(0);
         for (int i = threadIdx.x; i < kBB; i += K) s += red[i];
         out[threadIdx.x] = s;
     }
@@ -85,7 +97,8 @@ __device__ __forceinline__ void block_sum_by_rhs(double v, int K, double *red, d
 // Slices per row of the setup pass: the tuned M, or for systems whose SpMM
 // runs on wave tiles (M < 0) M = max(1, 8 / K): groups of K * M <= 64 lanes
 // (K <= 16), so every wave holds at least one row group.
-__device__ __forceinline__ int setup_m(const BSys &S) { return S.M > 0 ? S.M : max(1, 8 / S.K); }
+template <typename T>
+__device__ __forceinline__ int setup_m(const BSysT<T> &S) { return S.M > 0 ? S.M : max(1, 8 / S.K); }
 
 // Row sum of one row for right-hand side j over nonzero slice m of M, using
 // interleaved vector v ([n][K]); combined over the M slices by butterfly.
@@ -93,19 +106,20 @@ __device__ __forceinline__ int setup_m(const BSys &S) { return S.M > 0 ? S.M : m
 // The nonzero loop is unrolled four ways (four col/val loads, then four
 // gathers in flight per lane); the accumulation order is k, k + M, ... in
 // both the unrolled and the remainder part.
-__device__ __forceinline__ double row_spmm(const BSys &S, int row, int j, int m, int M,
-                                           double &diag, const double *v)
+template <typename T>
+__device__ __forceinline__ T row_spmm(const BSysT<T> &S, int row, int j, int m, int M, T &diag,
+                                      const T *v)
 {
     int s = S.rp[row], e = S.rp[row + 1];
     s = clampk(s, S.nnz);
     e = clampk(e, S.nnz);
     if (e < s) e = s;
     const int K = S.K;
-    double acc = 0.0, dg = 0.0;
+    T acc = T(0), dg = T(0);
     int k = s + m;
     for (; k + 3 * M < e; k += 4 * M) {
         int c[4];
-        double a[4], pv[4];
+        T a[4], pv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             c[u] = S.ci[k + u * M];
@@ -113,7 +127,7 @@ __device__ __forceinline__ double row_spmm(const BSys &S, int row, int j, int m,
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            pv[u] = (unsigned)c[u] < (unsigned)S.n_cols ? v[(int64_t)c[u] * K + j] : 0.0;
+            pv[u] = (unsigned)c[u] < (unsigned)S.n_cols ? v[(int64_t)c[u] * K + j] : T(0);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if ((unsigned)c[u] < (unsigned)S.n_cols) acc += a[u] * pv[u];
@@ -122,7 +136,7 @@ __device__ __forceinline__ double row_spmm(const BSys &S, int row, int j, int m,
     }
     for (; k < e; k += M) {
         const int c = S.ci[k];
-        const double a = S.val[k];
+        const T a = S.val[k];
         if ((unsigned)c < (unsigned)S.n_cols) acc += a * v[(int64_t)c * K + j];
         if (c == row) dg = a;
     }
@@ -136,14 +150,15 @@ __device__ __forceinline__ double row_spmm(const BSys &S, int row, int j, int m,
 }
 
 // Caller layout -> interleaved x.
-__global__ __launch_bounds__(kBB) void batch_in_kernel(BArgs a)
+template <typename T>
+__global__ __launch_bounds__(kBB) void batch_in_kernel(BArgsT<T> a)
 {
     const BTile t = a.tiles[blockIdx.x];
-    const BSys S = a.sys[t.sys];
+    const BSysT<T> S = a.sys[t.sys];
     const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) {
         const int row = (int)(e / S.K), j = (int)(e % S.K);
-        double v = 0.0;
+        T v = T(0);
         if (j < S.nrhs) {
             if (!S.lanes)
                 v = S.X[(int64_t)j * S.n + row];
@@ -154,38 +169,40 @@ __global__ __launch_bounds__(kBB) void batch_in_kernel(BArgs a)
     }
 }
 
-// r0 = b - A x0, D^-1, z0, p0 and the partials of r.r, r.z, b.b.
-__global__ __launch_bounds__(kBB) void batch_init_kernel(BArgs a)
+// r0 = b - A x0, D^-1, z0, p0 and the partials of r.r, r.z, b.b.  D^-1 is
+// 1 / a_ii rounded once to T from a float64 division.
+template <typename T>
+__global__ __launch_bounds__(kBB) void batch_init_kernel(BArgsT<T> a)
 {
-    __shared__ double red[kBB];
+    __shared__ T red[kBB];
     const int w = xcd_block(blockIdx.x, gridDim.x);
     const BTile t = a.tiles[w];
-    const BSys S = a.sys[t.sys];
+    const BSysT<T> S = a.sys[t.sys];
     const int M = setup_m(S);
     const int G = S.K * M, gpw = kWave / G;
     if (gpw < 1) return;  // not reached: K * M <= 64 is validated on the host
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
-    double prr = 0.0, prz = 0.0, pbb = 0.0;
+    T prr = T(0), prz = T(0), pbb = T(0);
     for (int row = t.row0 + wave * gpw + grp; row < t.row0 + t.rows; row += (kBB / kWave) * gpw) {
-        double dg;
-        const double ax = row_spmm(S, row, j, m, M, dg, S.x);
+        T dg;
+        const T ax = row_spmm(S, row, j, m, M, dg, S.x);
         if (m == 0) {
             const int64_t e = (int64_t)row * S.K + j;
-            double bi = 0.0;
+            T bi = T(0);
             if (j < S.nrhs) {
                 if (!S.lanes)
                     bi = S.B[(int64_t)j * S.n + row];
                 else if (S.lanes[j].b)
                     bi = S.lanes[j].b[row];
             }
-            const double ri = bi - ax;
-            double zi = ri;
+            const T ri = bi - ax;
+            T zi = ri;
             S.r[e] = ri;
             if (S.jac) {
-                const double d = dg > 0.0 ? dg : 1.0;
-                if (!(dg > 0.0)) a.scal[S.scal0 + j].pad = 1;  // same value from every writer
-                const double di = 1.0 / d;
+                const T d = dg > T(0) ? dg : T(1);
+                if (!(dg > T(0))) a.scal[S.scal0 + j].pad = 1;  // same value from every writer
+                const T di = (T)(1.0 / (double)d);
                 if (j == 0) S.dinv[row] = di;
                 zi = di * ri;
                 S.z[e] = zi;
@@ -197,7 +214,7 @@ __global__ __launch_bounds__(kBB) void batch_init_kernel(BArgs a)
         }
     }
     // lanes with m > 0 hold zeros; the lane of (grp, j, m = 0) is lane % K == j
-    double *base = a.part + (int64_t)t.tile * kMaxK;
+    T *base = a.part + (int64_t)t.tile * kMaxK;
     block_sum_by_rhs(prr, S.K, red, base);
     block_sum_by_rhs(prz, S.K, red, base + a.part_stride);
     block_sum_by_rhs(pbb, S.K, red, base + 2 * a.part_stride);
@@ -220,43 +237,45 @@ __device__ __forceinline__ double sum_partials_in_block(double v, double *red)
 
 // Sum of region `reg` partials of system s for right-hand side j (fixed
 // order: tile-strided per thread slice, then slices in order).
-__device__ __forceinline__ double sys_sum(const BArgs &a, const BSys &S, int reg, double *red)
+template <typename T>
+__device__ __forceinline__ T sys_sum(const BArgsT<T> &a, const BSysT<T> &S, int reg, T *red)
 {
     const int K = S.K;
     const int slice = threadIdx.x / K, j = threadIdx.x % K, nsl = kBB / K;
-    double s = 0.0;
-    const double *base = a.part + reg * a.part_stride;
+    T s = T(0);
+    const T *base = a.part + reg * a.part_stride;
     // unrolled: eight loads in flight, still added one by one in tile order
 #pragma unroll 8
     for (int t = S.tile0 + slice; t < S.tile0 + S.ntiles; t += nsl) s += base[(int64_t)t * kMaxK + j];
     __syncthreads();
     red[threadIdx.x] = s;
     __syncthreads();
-    double tot = 0.0;
+    T tot = T(0);
     if (threadIdx.x < K)
         for (int i = 0; i < nsl; ++i) tot += red[i * K + threadIdx.x];
     return tot;  // valid in threads 0..K-1
 }
 
-__global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgs a)
+template <typename T>
+__global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgsT<T> a)
 {
-    __shared__ double red[kBB];
+    __shared__ T red[kBB];
     const int sid = a.list[blockIdx.x];
-    const BSys S = a.sys[sid];
-    const double rr = sys_sum(a, S, 0, red);
-    const double rz = sys_sum(a, S, 1, red);
-    const double bb = sys_sum(a, S, 2, red);
+    const BSysT<T> S = a.sys[sid];
+    const T rr = sys_sum(a, S, 0, red);
+    const T rz = sys_sum(a, S, 1, red);
+    const T bb = sys_sum(a, S, 2, red);
     __shared__ int any_active;
     if (threadIdx.x == 0) any_active = 0;
     __syncthreads();
     if (threadIdx.x < S.K) {
         const int j = threadIdx.x;
-        BScal &c = a.scal[S.scal0 + j];
+        BScalT<T> &c = a.scal[S.scal0 + j];
         const bool badd = c.pad != 0;
         c.rr = rr;
         c.bb = bb;
         c.rho = S.jac ? rz : rr;
-        c.stop2 = S.rtol2 * bb;
+        c.stop2 = (T)S.rtol2 * bb;
         c.iter = 0;
         int status = CGX_PENDING;
         if (j >= S.nrhs)
@@ -265,9 +284,9 @@ __global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgs a)
             status = CGX_BREAKDOWN;
         else if (!isfinite(bb) || !isfinite(rr) || !isfinite(rz))
             status = CGX_NONFINITE;
-        else if (bb == 0.0 || rr <= S.rtol2 * bb)
+        else if (bb == T(0) || rr <= c.stop2)
             status = CGX_OK;
-        else if (S.jac && !(rz > 0.0))
+        else if (S.jac && !(rz > T(0)))
             status = CGX_BREAKDOWN;
         c.status = status;
         c.active = status == CGX_PENDING;
@@ -289,20 +308,20 @@ __global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgs a)
 // vector-CSR schedules keep their occupancy.
 constexpr int kWaveStageBytes = (kBB / kWave) * (kWave * 8 * 12 + 65 * 4 + 8);
 
-template <int RT, int K>
-__device__ __forceinline__ double spmm_wave_tiles(const BSys &S, const BTile &t, double *lds)
+template <int RT, int K, typename T>
+__device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, double *lds)
 {
-    using Sm = WaveSmem<8, RT, double>;
+    using Sm = WaveSmem<8, RT, T>;
     static_assert((kBB / kWave) * sizeof(Sm) <= kWaveStageBytes, "wave staging");
-    constexpr int T = kWave / (RT * K);
-    static_assert(T >= 1 && RT * K * T == kWave, "lanes per row");
+    constexpr int TL = kWave / (RT * K);
+    static_assert(TL >= 1 && RT * K * TL == kWave, "lanes per row");
     constexpr int C = kWave * 8, U = 4;
     Sm &sm = reinterpret_cast<Sm *>(lds)[threadIdx.x / kWave];
     const int lane = threadIdx.x % kWave;
-    const int g = lane / (K * T), sl = (lane / K) % T, j = lane % K;
+    const int g = lane / (K * TL), sl = (lane / K) % TL, j = lane % K;
     const int end = t.row0 + t.rows;
-    const double *__restrict__ p = S.p;
-    double ppq = 0.0;
+    const T *__restrict__ p = S.p;
+    T ppq = T(0);
     for (int r0 = t.row0 + (threadIdx.x / kWave) * RT; r0 < end; r0 += (kBB / kWave) * RT) {
         const int nr = min(RT, end - r0);
         wave_lds_sync();  // the previous tile's readers of sm are done
@@ -314,15 +333,15 @@ __device__ __forceinline__ double spmm_wave_tiles(const BSys &S, const BTile &t,
             s = max(sm.rp[g], k0);
             e = min(max(sm.rp[g + 1], s), k1);
         }
-        double acc = 0.0;
+        T acc = T(0);
         for (int c0 = k0; c0 < k1; c0 += C) {
             int col[8];
-            double a[8];
+            T a[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int k = c0 + lane + kWave * u;
                 col[u] = -1;
-                a[u] = 0.0;
+                a[u] = T(0);
                 if (k < k1) {
                     col[u] = __builtin_nontemporal_load(&S.ci[k]);
                     a[u] = __builtin_nontemporal_load(&S.val[k]);
@@ -336,14 +355,14 @@ __device__ __forceinline__ double spmm_wave_tiles(const BSys &S, const BTile &t,
             }
             wave_lds_sync();
             const int lo = max(s, c0) - c0, hi = min(e, c0 + C) - c0;
-            for (int k = lo + sl; k < hi; k += U * T) {
+            for (int k = lo + sl; k < hi; k += U * TL) {
                 int cc[U];
-                double vv[U], xv[U];
+                T vv[U], xv[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int kk = k + u * T;
+                    const int kk = k + u * TL;
                     cc[u] = -1;
-                    vv[u] = 0.0;
+                    vv[u] = T(0);
                     if (kk < hi) {
                         cc[u] = sm.col[kk];
                         vv[u] = sm.val[kk];
@@ -351,13 +370,13 @@ __device__ __forceinline__ double spmm_wave_tiles(const BSys &S, const BTile &t,
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    xv[u] = (unsigned)cc[u] < (unsigned)S.n_cols ? p[(int64_t)cc[u] * K + j] : 0.0;
+                    xv[u] = (unsigned)cc[u] < (unsigned)S.n_cols ? p[(int64_t)cc[u] * K + j] : T(0);
 #pragma unroll
                 for (int u = 0; u < U; ++u) acc += vv[u] * xv[u];
             }
         }
 #pragma unroll
-        for (int off = T / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off * K);
+        for (int off = TL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off * K);
         const int row = r0 + g;
         if (sl == 0 && g < nr) {
             const int64_t ei = (int64_t)row * K + j;
@@ -369,32 +388,34 @@ __device__ __forceinline__ double spmm_wave_tiles(const BSys &S, const BTile &t,
 }
 
 // Wave-tile schedule (M < 0: RT = -M rows per wave tile) for K = S.K.
-__device__ __forceinline__ double spmm_wave_dispatch(const BSys &S, const BTile &t, double *lds)
+template <typename T>
+__device__ __forceinline__ T spmm_wave_dispatch(const BSysT<T> &S, const BTile &t, double *lds)
 {
     const int rt = -S.M;
 #define CGX_WT(R, KK) \
-    if (rt == R && S.K == KK) return spmm_wave_tiles<R, KK>(S, t, lds);
+    if (rt == R && S.K == KK) return spmm_wave_tiles<R, KK, T>(S, t, lds);
     CGX_WT(1, 1) CGX_WT(2, 1) CGX_WT(4, 1) CGX_WT(8, 1) CGX_WT(16, 1) CGX_WT(32, 1) CGX_WT(64, 1)
     CGX_WT(8, 2) CGX_WT(16, 2) CGX_WT(32, 2)
     CGX_WT(4, 4) CGX_WT(8, 4) CGX_WT(16, 4)
     CGX_WT(2, 8) CGX_WT(4, 8) CGX_WT(8, 8)
     CGX_WT(1, 16) CGX_WT(2, 16) CGX_WT(4, 16)
 #undef CGX_WT
-    return 0.0;  // not reached: schedules are validated on the host
+    return T(0);  // not reached: schedules are validated on the host
 }
 
 // (1) q = A p for every active system, p.q partials per right-hand side.
 // Systems with M > 0 use K * M lanes per row (vector CSR over the
 // interleaved vectors), systems with M < 0 wave tiles of -M rows.
-__global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgs a)
+template <typename T>
+__global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgsT<T> a)
 {
-    __shared__ double red[kBB];
+    __shared__ T red[kBB];
     extern __shared__ double stage[];  // kWaveStageBytes when a system runs on wave tiles
     const int w = xcd_block(blockIdx.x, gridDim.x);
     const BTile t = a.tiles[w];
     if (a.sys_done[t.sys]) return;
-    const BSys S = a.sys[t.sys];
-    double ppq = 0.0;
+    const BSysT<T> S = a.sys[t.sys];
+    T ppq = T(0);
     if (S.M < 0) {
         ppq = spmm_wave_dispatch(S, t, stage);
     } else {
@@ -403,8 +424,8 @@ __global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgs a)
         const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
         for (int row = t.row0 + wave * gpw + grp; gpw >= 1 && row < t.row0 + t.rows;
              row += (kBB / kWave) * gpw) {
-            double dg;
-            const double qv = row_spmm(S, row, j, m, S.M, dg, S.p);
+            T dg;
+            const T qv = row_spmm(S, row, j, m, S.M, dg, S.p);
             if (m == 0) {
                 const int64_t e = (int64_t)row * S.K + j;
                 S.q[e] = qv;
@@ -416,18 +437,19 @@ __global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgs a)
 }
 
 // (R1) alpha per right-hand side; breakdown / non-finite p.q ends it.
-__global__ __launch_bounds__(kBB) void batch_r1_kernel(BArgs a)
+template <typename T>
+__global__ __launch_bounds__(kBB) void batch_r1_kernel(BArgsT<T> a)
 {
-    __shared__ double red[kBB];
+    __shared__ T red[kBB];
     const int sid = a.list[blockIdx.x];
     if (a.sys_done[sid]) return;
-    const BSys S = a.sys[sid];
-    const double pq = sys_sum(a, S, 0, red);
+    const BSysT<T> S = a.sys[sid];
+    const T pq = sys_sum(a, S, 0, red);
     if (threadIdx.x < S.K) {
-        BScal &c = a.scal[S.scal0 + threadIdx.x];
+        BScalT<T> &c = a.scal[S.scal0 + threadIdx.x];
         if (c.active) {
             c.pq = pq;
-            if (!isfinite(pq) || !(pq > 0.0)) {
+            if (!isfinite(pq) || !(pq > T(0))) {
                 c.status = isfinite(pq) ? CGX_BREAKDOWN : CGX_NONFINITE;
                 c.active = 0;
             } else {
@@ -441,60 +463,62 @@ __global__ __launch_bounds__(kBB) void batch_r1_kernel(BArgs a)
 
 // (2) x += alpha p, r -= alpha q, z = D^-1 r for active right-hand sides;
 // r.r and r.z partials.
-__global__ __launch_bounds__(kBB) void batch_update_kernel(BArgs a)
+template <typename T>
+__global__ __launch_bounds__(kBB) void batch_update_kernel(BArgsT<T> a)
 {
-    __shared__ double red[kBB];
+    __shared__ T red[kBB];
     const int w = xcd_block(blockIdx.x, gridDim.x);
     const BTile t = a.tiles[w];
     if (a.sys_done[t.sys]) return;
-    const BSys S = a.sys[t.sys];
+    const BSysT<T> S = a.sys[t.sys];
     const int j = threadIdx.x % S.K;  // fixed per thread: K divides kBB
-    const BScal c = a.scal[S.scal0 + j];
-    double prr = 0.0, prz = 0.0;
+    const BScalT<T> c = a.scal[S.scal0 + j];
+    T prr = T(0), prz = T(0);
     if (c.active) {
-        const double alpha = c.alpha;
+        const T alpha = c.alpha;
         const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
         for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) {
-            const double xi = __builtin_fma(alpha, S.p[e], S.x[e]);
-            const double ri = __builtin_fma(-alpha, S.q[e], S.r[e]);
+            const T xi = fma_t(alpha, S.p[e], S.x[e]);
+            const T ri = fma_t(-alpha, S.q[e], S.r[e]);
             S.x[e] = xi;
             S.r[e] = ri;
             prr += ri * ri;
             if (S.jac) {
-                const double zi = S.dinv[e / S.K] * ri;
+                const T zi = S.dinv[e / S.K] * ri;
                 S.z[e] = zi;
                 prz += ri * zi;
             }
         }
     }
-    double *base = a.part + (int64_t)t.tile * kMaxK;
+    T *base = a.part + (int64_t)t.tile * kMaxK;
     block_sum_by_rhs(prr, S.K, red, base + a.part_stride);
     block_sum_by_rhs(prz, S.K, red, base + 2 * a.part_stride);
 }
 
 // (R2) stopping test and beta per right-hand side; system-done flag.
-__global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgs a)
+template <typename T>
+__global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
 {
-    __shared__ double red[kBB];
+    __shared__ T red[kBB];
     __shared__ int any_active;
     const int sid = a.list[blockIdx.x];
     if (a.sys_done[sid]) return;
-    const BSys S = a.sys[sid];
-    const double rr = sys_sum(a, S, 1, red);
-    const double rz0 = sys_sum(a, S, 2, red);
+    const BSysT<T> S = a.sys[sid];
+    const T rr = sys_sum(a, S, 1, red);
+    const T rz0 = sys_sum(a, S, 2, red);
     if (threadIdx.x == 0) any_active = 0;
     __syncthreads();
     if (threadIdx.x < S.K) {
-        BScal &c = a.scal[S.scal0 + threadIdx.x];
+        BScalT<T> &c = a.scal[S.scal0 + threadIdx.x];
         if (c.active) {
-            const double rz = S.jac ? rz0 : rr;
+            const T rz = S.jac ? rz0 : rr;
             c.rr = rr;
             int status = CGX_PENDING;
             if (!isfinite(rr) || !isfinite(rz))
                 status = CGX_NONFINITE;
             else if (rr <= c.stop2)
                 status = CGX_OK;
-            else if (!(rz > 0.0))
+            else if (!(rz > T(0)))
                 status = CGX_BREAKDOWN;
             else if (c.iter >= S.maxit)
                 status = CGX_NOT_CONVERGED;
@@ -513,32 +537,34 @@ __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgs a)
 }
 
 // (3) p = z + beta p for active right-hand sides.
-__global__ __launch_bounds__(kBB) void batch_direction_kernel(BArgs a)
+template <typename T>
+__global__ __launch_bounds__(kBB) void batch_direction_kernel(BArgsT<T> a)
 {
     const int w = xcd_block(blockIdx.x, gridDim.x);
     const BTile t = a.tiles[w];
     if (a.sys_done[t.sys]) return;
-    const BSys S = a.sys[t.sys];
+    const BSysT<T> S = a.sys[t.sys];
     const int j = threadIdx.x % S.K;
-    const BScal c = a.scal[S.scal0 + j];
+    const BScalT<T> c = a.scal[S.scal0 + j];
     if (!c.active) return;
-    const double beta = c.beta;
-    const double *z = S.jac ? S.z : S.r;
+    const T beta = c.beta;
+    const T *z = S.jac ? S.z : S.r;
     const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) S.p[e] = __builtin_fma(beta, S.p[e], z[e]);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) S.p[e] = fma_t(beta, S.p[e], z[e]);
 }
 
 // Interleaved x -> caller layout (x = 0 where b = 0).
-__global__ __launch_bounds__(kBB) void batch_out_kernel(BArgs a)
+template <typename T>
+__global__ __launch_bounds__(kBB) void batch_out_kernel(BArgsT<T> a)
 {
     const BTile t = a.tiles[blockIdx.x];
-    const BSys S = a.sys[t.sys];
+    const BSysT<T> S = a.sys[t.sys];
     const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) {
         const int row = (int)(e / S.K), j = (int)(e % S.K);
         if (j < S.nrhs) {
-            const BScal &c = a.scal[S.scal0 + j];
-            S.X[(int64_t)j * S.n + row] = (c.bb == 0.0 && c.status == CGX_OK) ? 0.0 : S.x[e];
+            const BScalT<T> &c = a.scal[S.scal0 + j];
+            S.X[(int64_t)j * S.n + row] = (c.bb == T(0) && c.status == CGX_OK) ? T(0) : S.x[e];
         }
     }
 }
@@ -642,10 +668,11 @@ __global__ __launch_bounds__(kBB) void lane_out_kernel(const BSys *sys, int si, 
         x[i] = zero ? 0.0 : S.x[i * S.K + j];
 }
 
-__global__ void batch_scal_init_kernel(BScal *scal, int64_t n, int32_t *done, int nsys)
+template <typename T>
+__global__ void batch_scal_init_kernel(BScalT<T> *scal, int64_t n, int32_t *done, int nsys)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) scal[i] = BScal{};
+    if (i < n) scal[i] = BScalT<T>{};
     if (i < nsys) done[i] = 0;
 }
 
@@ -656,13 +683,14 @@ __global__ void batch_zero_kernel(double *x, int64_t n)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = 0.0;
 }
 
-void launch_batch_iteration(const BArgs &a, hipStream_t s)
+template <typename T>
+void launch_batch_iteration(const BArgsT<T> &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(batch_spmm_kernel, dim3(a.ntiles), dim3(kBB), a.wave_lds, s, a);
-    hipLaunchKernelGGL(batch_r1_kernel, dim3(a.nlist), dim3(kBB), 0, s, a);
-    hipLaunchKernelGGL(batch_update_kernel, dim3(a.ntiles), dim3(kBB), 0, s, a);
-    hipLaunchKernelGGL(batch_r2_kernel, dim3(a.nlist), dim3(kBB), 0, s, a);
-    hipLaunchKernelGGL(batch_direction_kernel, dim3(a.ntiles), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL((batch_spmm_kernel<T>), dim3(a.ntiles), dim3(kBB), a.wave_lds, s, a);
+    hipLaunchKernelGGL((batch_r1_kernel<T>), dim3(a.nlist), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL((batch_update_kernel<T>), dim3(a.ntiles), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL((batch_r2_kernel<T>), dim3(a.nlist), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL((batch_direction_kernel<T>), dim3(a.ntiles), dim3(kBB), 0, s, a);
 }
 
 int pad_k(int nrhs)

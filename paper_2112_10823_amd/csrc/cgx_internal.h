@@ -116,6 +116,7 @@ struct Context {
     GraphSlot graph64;  // float64 CG iterations
     GraphSlot graph32;  // binary32 inner iterations of the refinement
     GraphSlot graph_batch;  // batched CG iterations
+    GraphSlot graph_batch32;  // binary32 inner iterations of the refined batch
     // batched-SpMM autotuner: (K, mean row length, log2 rows) -> slice count M
     std::mutex tune_mu;
     std::map<std::tuple<int, int, int>, int> batch_tune;
@@ -145,6 +146,9 @@ size_t batch_workspace_bytes(int32_t nsys, const cgx_system *in);
 bool batch_wave_schedule_ok(int rt, int K);
 int run_batched(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t ws_bytes,
                 const cgx_opts *o, cgx_stats *stats);
+size_t batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *in);
+int run_batched_mixed(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t ws_bytes,
+                      const cgx_opts *o, cgx_stats *stats);
 int batch_autotune(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t ws_bytes,
                    std::vector<int> &Ms);
 int tune_one(Context *c, const cgx_system &sys, void *ws, size_t ws_bytes, hipStream_t s,

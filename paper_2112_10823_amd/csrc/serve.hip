@@ -300,9 +300,9 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
                     if (sl.state[j] == kLaneJoining) sl.state[j] = kLaneRunning;
             }
             const BArgs f = engine_args(E, true, (int)tiles2.size(), (int)list2.size());
-            hipLaunchKernelGGL(batch_in_kernel, dim3(f.ntiles), dim3(kBB), 0, s, f);
-            hipLaunchKernelGGL(batch_init_kernel, dim3(f.ntiles), dim3(kBB), 0, s, f);
-            hipLaunchKernelGGL(batch_r0_kernel, dim3(f.nlist), dim3(kBB), 0, s, f);
+            hipLaunchKernelGGL((batch_in_kernel<double>), dim3(f.ntiles), dim3(kBB), 0, s, f);
+            hipLaunchKernelGGL((batch_init_kernel<double>), dim3(f.ntiles), dim3(kBB), 0, s, f);
+            hipLaunchKernelGGL((batch_r0_kernel<double>), dim3(f.nlist), dim3(kBB), 0, s, f);
             ENG_CHECK(hipGetLastError());
             for (int i : list2) E.slots[i].fresh = false;
         }
