@@ -650,7 +650,8 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
     check the paper's composition claim for one CG iteration."""
     import torch
     from paper_2112_10823_amd.energy import (Segment, detect_steps, merge_short, most_common_pattern,
-                                             noise_from_differences, phase_pattern, segments_of)
+                                             noise_from_differences, phase_pattern, robust_spread,
+                                             segments_of)
     A = synth.q1cube(N_GRID, SIGMA, seed=synth.SEED_C2_COEFF)
     n = A.n_rows
     dA = cgx.DeviceCSR.from_host(A)
@@ -695,12 +696,14 @@ def extra_energy_phases(cgx, synth, meter, phase_s=8.0, runs=3):
         t, p = meter.sampler.trace()
         sel = (t >= bounds[0][1]) & (t <= bounds[-1][2])
         t, p = t[sel], p[sel]
-        # the noise sample: the first idle phase past its first two seconds;
-        # the counter is noisier under load than at idle, so the estimate
-        # from the trace's own differences is taken where it is larger
+        # the noise sample: the first idle phase past its first two seconds
+        # (its spread by median absolute deviation: the last sample may reach
+        # into the next phase); the estimate from the trace's own differences
+        # where it is larger; at least 10 W, the drift of the board's power
+        # within one steady phase, so that drift is not cut into phases
         idle = p[(t >= bounds[0][1] + 2.0) & (t <= bounds[0][2])]
-        idle_sd = float(np.std(idle)) if idle.size > 1 else 0.0
-        noise = max(idle_sd, noise_from_differences(p), 2.0)
+        idle_sd = robust_spread(idle)
+        noise = max(idle_sd, noise_from_differences(p), 10.0)
         # one counter sample spans about a second, so the sample taken across a
         # phase boundary mixes two levels: segments shorter than three samples
         # are such mixtures and join the closer neighbour

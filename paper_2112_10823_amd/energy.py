@@ -25,7 +25,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["EnergySampler", "moving_average", "noise_from_differences", "detect_steps", "merge_short",
+__all__ = ["EnergySampler", "moving_average", "robust_spread", "noise_from_differences",
+           "detect_steps", "merge_short",
            "Segment", "segments_of",
            "phase_pattern", "most_common_pattern"]
 
@@ -123,6 +124,16 @@ class Segment:
     start: int   # first sample
     end: int     # one past the last sample
     level: float
+
+
+def robust_spread(x):
+    """Standard deviation of a noise sample estimated from its median
+    absolute deviation (1.4826 MAD, exact for Gaussian noise), so that a
+    sample taken across the end of the window does not inflate it."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.size == 0:
+        return 0.0
+    return float(1.4826 * np.median(np.abs(x - np.median(x))))
 
 
 def noise_from_differences(x):

@@ -7,7 +7,7 @@ import pytest
 
 from paper_2112_10823_amd.energy import (detect_steps, merge_short, most_common_pattern,
                                          moving_average, noise_from_differences, phase_pattern,
-                                         segments_of)
+                                         robust_spread, segments_of)
 
 LEVELS = [250.0, 800.0, 600.0, 820.0, 260.0]
 LENGTHS = [8, 10, 6, 12, 9]
@@ -114,3 +114,14 @@ def test_noise_from_differences():
         assert abs(est - sigma) <= 0.15 * sigma
     assert noise_from_differences(x) == 0.0
     assert noise_from_differences([1.0]) == 0.0
+
+
+def test_robust_spread_ignores_an_edge_sample():
+    """A noise sample whose last value already belongs to the next phase: the
+    standard deviation jumps, the MAD-based spread stays near sigma."""
+    rng = np.random.default_rng(5)
+    x = 269.0 + rng.normal(0.0, 1.0, 200)
+    assert abs(robust_spread(x) - 1.0) <= 0.15
+    y = np.append(x[:6], 437.0)
+    assert np.std(y) > 50.0 and robust_spread(y) < 3.0
+    assert robust_spread([]) == 0.0
