@@ -320,7 +320,7 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
     static_assert((kBB / kWave) * sizeof(Sm) <= kWaveStageBytes, "wave staging");
     constexpr int TL = kWave / (RT * K);
     static_assert(TL >= 1 && RT * K * TL == kWave, "lanes per row");
-    constexpr int C = kWave * 8, U = 4, NW = kBB / kWave;
+    constexpr int C = kWave * 8, U = K >= 8 ? 8 : 4, NW = kBB / kWave;
     Sm &sm = reinterpret_cast<Sm *>(lds)[threadIdx.x / kWave];
     const int lane = threadIdx.x % kWave;
     const int g = lane / (K * TL), sl = (lane / K) % TL, j = lane % K;
@@ -748,7 +748,7 @@ int pad_k(int nrhs)
     return K;
 }
 
-int tile_rows_for(int K) { return K >= 16 ? 128 : 2048 / K; }
+int tile_rows_for(int K) { return K >= 8 ? 8192 / K : 2048 / K; }
 
 // Wave-tile schedules the kernels instantiate: RT rows per wave with
 // RT * K <= 64 (K = 1: any power of two; K > 1: 1, 2 or 4 lanes per
