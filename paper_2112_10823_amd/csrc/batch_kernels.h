@@ -525,14 +525,18 @@ __global__ __launch_bounds__(kBB) void batch_update_kernel(BArgsT<T> a)
     if (c.active) {
         const T alpha = c.alpha;
         const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) {
+        // K divides kBB: the thread's row advances by kBB / K per step
+        const int drow = kBB / S.K;
+        int row = t.row0 + (int)threadIdx.x / S.K;
+#pragma unroll 4
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB, row += drow) {
             const T xi = fma_t(alpha, S.p[e], S.x[e]);
             const T ri = fma_t(-alpha, S.q[e], S.r[e]);
             S.x[e] = xi;
             S.r[e] = ri;
             prr += ri * ri;
             if (S.jac) {
-                const T zi = S.dinv[e / S.K] * ri;
+                const T zi = S.dinv[row] * ri;
                 S.z[e] = zi;
                 prz += ri * zi;
             }
@@ -598,6 +602,7 @@ __global__ __launch_bounds__(kBB) void batch_direction_kernel(BArgsT<T> a)
     const T beta = c.beta;
     const T *z = S.jac ? S.z : S.r;
     const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
+#pragma unroll 4
     for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) S.p[e] = fma_t(beta, S.p[e], z[e]);
 }
 
