@@ -301,14 +301,17 @@ __global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgsT<T> a)
 // t K + j for row g, right-hand side j and entry slice t.  Every lane walks
 // its row's entries t, t + T, ... four at a time from LDS, gathering
 // p[col][j] from the interleaved vector; the T slices are then combined by
-// butterfly.  For K = 1 this is the single-system wave tile.  The four waves
-// of the workgroup take contiguous quarters of the work tile.  Staging: a
-// wave reads the row starts of up to 64 of its rows at once and streams the
+// butterfly.  For K = 1 this is the single-system wave tile.  For K >= 8 the
+// four waves of the workgroup take contiguous quarters of the work tile, and
+// a wave reads the row starts of up to 64 of its rows at once and streams the
 // col_idx / val of as many whole groups of RT rows as fit one 64 x 8 chunk
 // into LDS (coalesced, non-temporal), then computes them group by group, so
 // that the dependent loads (row starts, then entries, then gathers) are paid
-// once per chunk, not once per RT rows.  A group of RT rows longer than a
-// chunk is streamed chunk by chunk.  The staging is dynamic LDS, requested
+// once per chunk, not once per RT rows (RT is at most 4 there).  For K < 8
+// the waves take groups of RT rows in turn, one group per chunk, so that
+// neighbouring groups run at the same time and share their gathers in the
+// cache (measured faster for one right-hand side).  A group of RT rows
+// longer than a chunk is streamed chunk by chunk.  The staging is dynamic LDS, requested
 // only by launches that contain such a system, so that the vector-CSR
 // schedules keep their occupancy.
 constexpr int kWaveStageBytes = (kBB / kWave) * (kWave * 8 * 12 + 65 * 4 + 8);
@@ -321,12 +324,14 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
     constexpr int TL = kWave / (RT * K);
     static_assert(TL >= 1 && RT * K * TL == kWave, "lanes per row");
     constexpr int C = kWave * 8, U = K >= 8 ? 8 : 4, NW = kBB / kWave;
+    constexpr bool kContig = K >= 8;
     Sm &sm = reinterpret_cast<Sm *>(lds)[threadIdx.x / kWave];
     const int lane = threadIdx.x % kWave;
     const int g = lane / (K * TL), sl = (lane / K) % TL, j = lane % K;
-    const int per = ((t.rows + NW - 1) / NW + RT - 1) / RT * RT;  // rows per wave
-    const int wr0 = t.row0 + (threadIdx.x / kWave) * per;
-    const int wend = min(t.row0 + t.rows, wr0 + per);
+    const int w = threadIdx.x / kWave;
+    const int per = ((t.rows + NW - 1) / NW + RT - 1) / RT * RT;  // rows per wave (kContig)
+    const int wr0 = kContig ? t.row0 + w * per : t.row0 + w * RT;
+    const int wend = kContig ? min(t.row0 + t.rows, wr0 + per) : t.row0 + t.rows;
     const T *__restrict__ p = S.p;
     T ppq = T(0);
 
@@ -386,7 +391,7 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
     };
 
     for (int r0 = wr0; r0 < wend;) {
-        const int na = min(kWave, wend - r0);
+        const int na = min(kContig ? kWave : RT, wend - r0);
         wave_lds_sync();  // the previous range's readers of sm are done
         for (int i = lane; i <= na; i += kWave) sm.rp[i] = clampk(S.rp[r0 + i], S.nnz);
         wave_lds_sync();
@@ -414,7 +419,7 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
                 walk(s, e, k0, acc);
                 finish(r0 + gr, gr < rs, acc);
             }
-            r0 += rs;
+            r0 += kContig ? rs : NW * RT;
         } else {  // one group of RT rows longer than a chunk
             const int nr = min(RT, na);
             const int k1 = max(k0, sm.rp[nr]);
@@ -429,7 +434,7 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
                 walk(max(s, c0), min(e, c0 + C), c0, acc);
             }
             finish(r0 + g, g < nr, acc);
-            r0 += nr;
+            r0 += kContig ? nr : NW * RT;
         }
     }
     return ppq;
