@@ -67,7 +67,8 @@ int build_plan(int32_t nsys, const cgx_system *in, const int *Ms, const cgx_opts
         S.nrhs = q.nrhs;
         S.K = pad_k(q.nrhs);
         S.M = Ms ? Ms[s] : default_m(S.K, S.n ? (double)S.nnz / S.n : 1.0);
-        S.trows = tile_rows_for(S.K);
+        S.staged = 1;
+        S.trows = tile_rows_for(S.K, true);
         S.scal0 = (int)scal;
         S.jac = o && o->precond == CGX_PRECOND_JACOBI ? 1 : 0;
         S.rtol2 = o ? o->rtol * o->rtol : 0.0;

@@ -34,7 +34,8 @@ struct BSysT {
     int n, K, nrhs, M;
     int tile0, ntiles, trows, scal0;
     int n_cols, jac;     // jac: Jacobi preconditioning for this system
-    int maxit, pad;
+    int maxit;
+    int staged;          // SpMM wave tiles for K >= 8 staged per wave (batch call; see below)
     double rtol2;        // squared relative tolerance of this system
 };
 using BSys = BSysT<double>;
@@ -301,30 +302,33 @@ __global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgsT<T> a)
 // t K + j for row g, right-hand side j and entry slice t.  Every lane walks
 // its row's entries t, t + T, ... four at a time from LDS, gathering
 // p[col][j] from the interleaved vector; the T slices are then combined by
-// butterfly.  For K = 1 this is the single-system wave tile.  For K >= 8 the
-// four waves of the workgroup take contiguous quarters of the work tile, and
-// a wave reads the row starts of up to 64 of its rows at once and streams the
-// col_idx / val of as many whole groups of RT rows as fit one 64 x 8 chunk
-// into LDS (coalesced, non-temporal), then computes them group by group, so
-// that the dependent loads (row starts, then entries, then gathers) are paid
-// once per chunk, not once per RT rows (RT is at most 4 there).  For K < 8
-// the waves take groups of RT rows in turn, one group per chunk, so that
+// butterfly.  For K = 1 this is the single-system wave tile.  Staged (kStaged
+// and K >= 8): the four waves of the workgroup take contiguous quarters of
+// the work tile, and a wave reads the row starts of up to 64 of its rows at
+// once and streams the col_idx / val of as many whole groups of RT rows as
+// fit one 64 x 8 chunk into LDS (coalesced, non-temporal), then computes them
+// group by group with eight gathers in flight, so that the dependent loads
+// (row starts, then entries, then gathers) are paid once per chunk, not once
+// per RT rows (RT is at most 4 there).  Otherwise the waves take groups of RT
+// rows in turn, one group per chunk, four gathers in flight, so that
 // neighbouring groups run at the same time and share their gathers in the
-// cache (measured faster for one right-hand side).  A group of RT rows
-// longer than a chunk is streamed chunk by chunk.  The staging is dynamic LDS, requested
+// cache.  The batch call stages (faster on its systems of up to 96^3 rows);
+// the solve server does not (faster on its larger systems, whose neighbouring
+// planes are further apart).  A group of RT rows longer than a chunk is
+// streamed chunk by chunk.  The staging is dynamic LDS, requested
 // only by launches that contain such a system, so that the vector-CSR
 // schedules keep their occupancy.
 constexpr int kWaveStageBytes = (kBB / kWave) * (kWave * 8 * 12 + 65 * 4 + 8);
 
-template <int RT, int K, typename T>
+template <int RT, int K, typename T, bool kStaged>
 __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, double *lds)
 {
     using Sm = WaveSmem<8, kWave, T>;  // row starts of up to 64 rows
     static_assert((kBB / kWave) * sizeof(Sm) <= kWaveStageBytes, "wave staging");
     constexpr int TL = kWave / (RT * K);
     static_assert(TL >= 1 && RT * K * TL == kWave, "lanes per row");
-    constexpr int C = kWave * 8, U = K >= 8 ? 8 : 4, NW = kBB / kWave;
-    constexpr bool kContig = K >= 8;
+    constexpr bool kContig = kStaged && K >= 8;
+    constexpr int C = kWave * 8, U = kContig ? 8 : 4, NW = kBB / kWave;
     Sm &sm = reinterpret_cast<Sm *>(lds)[threadIdx.x / kWave];
     const int lane = threadIdx.x % kWave;
     const int g = lane / (K * TL), sl = (lane / K) % TL, j = lane % K;
@@ -445,8 +449,10 @@ template <typename T>
 __device__ __forceinline__ T spmm_wave_dispatch(const BSysT<T> &S, const BTile &t, double *lds)
 {
     const int rt = -S.M;
-#define CGX_WT(R, KK) \
-    if (rt == R && S.K == KK) return spmm_wave_tiles<R, KK, T>(S, t, lds);
+#define CGX_WT(R, KK)                                                 \
+    if (rt == R && S.K == KK)                                         \
+        return S.staged ? spmm_wave_tiles<R, KK, T, true>(S, t, lds)  \
+                        : spmm_wave_tiles<R, KK, T, false>(S, t, lds);
     CGX_WT(1, 1) CGX_WT(2, 1) CGX_WT(4, 1) CGX_WT(8, 1) CGX_WT(16, 1) CGX_WT(32, 1) CGX_WT(64, 1)
     CGX_WT(8, 2) CGX_WT(16, 2) CGX_WT(32, 2)
     CGX_WT(4, 4) CGX_WT(8, 4) CGX_WT(16, 4)
@@ -758,7 +764,7 @@ int pad_k(int nrhs)
     return K;
 }
 
-int tile_rows_for(int K) { return K >= 8 ? 8192 / K : 2048 / K; }
+int tile_rows_for(int K, bool staged) { return staged && K >= 8 ? 8192 / K : 2048 / K; }
 
 // Wave-tile schedules the kernels instantiate: RT rows per wave with
 // RT * K <= 64 (K = 1: any power of two; K > 1: 1, 2 or 4 lanes per

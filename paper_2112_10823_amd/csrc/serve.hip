@@ -156,7 +156,7 @@ namespace {
 
 int tiles_of(int64_t n, int nrhs)
 {
-    const int tr = tile_rows_for(pad_k(nrhs));
+    const int tr = tile_rows_for(pad_k(nrhs), false);
     return (int)((n + tr - 1) / tr);
 }
 
@@ -204,7 +204,7 @@ BSys slot_sys(const Engine &E, int si, int tile0)
     S.K = s.K;
     S.nrhs = s.K;
     S.M = s.M;
-    S.trows = tile_rows_for(s.K);
+    S.trows = tile_rows_for(s.K, false);
     S.tile0 = tile0;
     S.ntiles = s.ntiles;
     S.scal0 = si * kMaxK;
@@ -553,7 +553,7 @@ int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots, in
     E->max_slots = max_slots;
     E->max_group = max_group;
     // arena: tables sized for the most tiles the heap can hold
-    E->max_tiles = (int64_t)(pool_bytes / (40.0 * tile_rows_for(1))) + max_slots + 1;
+    E->max_tiles = (int64_t)(pool_bytes / (40.0 * tile_rows_for(1, false))) + max_slots + 1;
     size_t off = 0;
     E->off_sys = off;
     off += a256(sizeof(BSys) * max_slots);
