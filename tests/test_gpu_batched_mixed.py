@@ -108,3 +108,29 @@ def test_refined_batch_caps_and_errors():
         cgx.cg_solve_batched([(dA64, dev(b[None]), X)],
                              cgx.make_opts(precision=cgx.PRECISION_MIXED),
                              workspace=torch.empty(1 << 20, dtype=torch.uint8, device="cuda"))
+
+
+def test_refined_64_systems_16_rhs_full_size():
+    """The batched configuration float32-refined (binary32 inner Jacobi-CG to
+    1e-2): every (system, right-hand side) converges to 1e-8 in float64, gated
+    on a sample through the oracle's SpMV of the GPU solution."""
+    mats = synth.batch_systems(64)
+    items = []
+    for s, A in enumerate(mats):
+        B = torch.empty(16, A.n_rows, dtype=torch.float64)
+        for j in range(16):
+            B[j] = torch.from_numpy(synth.uniform(1000 + s * 16 + j, A.n_rows))
+        items.append((cgx.DeviceCSR.from_host(A, with_f32=True), B.cuda(),
+                      torch.zeros(16, A.n_rows, dtype=torch.float64, device="cuda")))
+    print("[batched mixed] 64 x 16 full size", flush=True)
+    st = cgx.cg_solve_batched(items, cgx.make_opts(rtol=1e-8, precond=1,
+                                                   precision=cgx.PRECISION_MIXED,
+                                                   inner_rtol=1e-2))
+    assert all(v.status == cgx.OK for row in st for v in row)
+    assert all(v.relres <= 1e-8 for row in st for v in row)
+    rng = np.random.default_rng(1)
+    for s in rng.choice(64, 8, replace=False):
+        for j in rng.choice(16, 2, replace=False):
+            b = items[s][1][j].cpu().numpy()
+            x = items[s][2][j].cpu().numpy()
+            assert true_relres(mats[s], b, x) <= 1e-8 * 1.01

@@ -185,3 +185,23 @@ def test_argument_errors():
     with pytest.raises(cgx.CgxError):
         cgx.schwarz_solve(B, D, torch.ones(125, dtype=torch.float64, device="cuda"),
                           torch.zeros(125, dtype=torch.float64, device="cuda"))
+
+
+def test_q1_128_full_size():
+    """The Q1 128^3 system of the benchmark (lognormal(0,1), blob right-hand
+    side) in 8 slabs overlapping by one grid layer, Jacobi-CG subdomain
+    solves to 0.1: the oracle's SpMV of the GPU solution gives the true
+    residual (the oracle's own Schwarz solve at this size takes minutes)."""
+    A = synth.q1cube(128, 1.0, seed=synth.SEED_C2_COEFF)
+    b = synth.blob_rhs(128, synth.SEED_C2_BLOBS)
+    dA = cgx.DeviceCSR.from_host(A)
+    D = cgx.SchwarzDecomposition(dA, 8, 128 * 128)
+    assert D.local_rows == A.n_rows + 2 * 128 * 128 * 7
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    print("[schwarz] Q1 128^3 full size", flush=True)
+    st = cgx.schwarz_solve(dA, D, dev(b), x,
+                           cgx.make_opts(rtol=1e-8, maxit=100, inner_rtol=0.1,
+                                         precond=cgx.PRECOND_JACOBI, true_residual=True))
+    assert st.status == cgx.OK and 0 < st.outer_iters < 356
+    rr = true_relres(A, x.cpu().numpy(), b)
+    assert rr <= 1.5e-8 and abs(rr - st.relres_true) <= 1e-10
