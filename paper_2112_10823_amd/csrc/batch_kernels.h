@@ -6,6 +6,7 @@
 #include <cmath>
 #include <map>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "cgx_device.h"
@@ -444,22 +445,190 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
     return ppq;
 }
 
+// Staged wave tiles with vector gathers (batch call, K >= 8): as the staged
+// form of spmm_wave_tiles, but every lane serves V = 16 / sizeof(T)
+// consecutive right-hand sides with one 16-byte gather per entry, so a wave
+// covers V times the rows per pass (RT V) and keeps twice (float64) or four
+// times (binary32) the bytes in flight per instruction.  Each (row, right-
+// hand side) still sums its entries in the same order.  The p.q partials
+// come back per lane and right-hand side: pp[v] for right-hand side
+// (lane % (K / V)) V + v.
+template <int RT, int K, typename T>
+__device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTile &t,
+                                                    double *lds, T (&pp)[16 / sizeof(T)])
+{
+    constexpr int V = 16 / (int)sizeof(T), KV = K / V;
+    using Sm = WaveSmem<8, kWave, T>;
+    static_assert((kBB / kWave) * sizeof(Sm) <= kWaveStageBytes, "wave staging");
+    constexpr int TL = kWave / (RT * K);  // entry slices per (row, right-hand side)
+    constexpr int RTV = RT * V;           // rows per pass
+    static_assert(TL >= 1 && RTV * KV * TL == kWave, "lanes per row");
+    constexpr int C = kWave * 8, U = 8, NW = kBB / kWave;
+    using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    Sm &sm = reinterpret_cast<Sm *>(lds)[threadIdx.x / kWave];
+    const int lane = threadIdx.x % kWave;
+    const int g = lane / (KV * TL), sl = (lane / KV) % TL, j0 = (lane % KV) * V;
+    const int per = ((t.rows + NW - 1) / NW + RTV - 1) / RTV * RTV;  // rows per wave
+    const int wr0 = t.row0 + (threadIdx.x / kWave) * per;
+    const int wend = min(t.row0 + t.rows, wr0 + per);
+    const T *__restrict__ p = S.p;
+#pragma unroll
+    for (int v = 0; v < V; ++v) pp[v] = T(0);
+
+    auto walk = [&](int s, int e, int c0, T (&acc)[V]) {
+        const int lo = s - c0, hi = e - c0;
+        for (int k = lo + sl; k < hi; k += U * TL) {
+            int cc[U];
+            T vv[U];
+            VT xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int kk = k + u * TL;
+                cc[u] = -1;
+                vv[u] = T(0);
+                if (kk < hi) {
+                    cc[u] = sm.col[kk];
+                    vv[u] = sm.val[kk];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                xv[u] = VT{};
+                if ((unsigned)cc[u] < (unsigned)S.n_cols)
+                    xv[u] = *reinterpret_cast<const VT *>(p + (int64_t)cc[u] * K + j0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                T xs[V];
+                __builtin_memcpy(xs, &xv[u], sizeof(VT));
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] += vv[u] * xs[v];
+            }
+        }
+    };
+    auto stage = [&](int c0, int k1) {
+        int col[8];
+        T a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = c0 + lane + kWave * u;
+            col[u] = -1;
+            a[u] = T(0);
+            if (k < k1) {
+                col[u] = __builtin_nontemporal_load(&S.ci[k]);
+                a[u] = __builtin_nontemporal_load(&S.val[k]);
+            }
+        }
+        wave_lds_sync();  // earlier readers of the chunk are done
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sm.col[lane + kWave * u] = col[u];
+            sm.val[lane + kWave * u] = a[u];
+        }
+        wave_lds_sync();
+    };
+    auto finish = [&](int row, bool valid, T (&acc)[V]) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int off = TL / 2; off > 0; off >>= 1) acc[v] += __shfl_xor(acc[v], off * KV);
+        if (sl == 0 && valid) {
+            const int64_t ei = (int64_t)row * K + j0;
+            VT qv;
+            __builtin_memcpy(&qv, acc, sizeof(VT));
+            *reinterpret_cast<VT *>(S.q + ei) = qv;
+            const VT pvv = *reinterpret_cast<const VT *>(p + ei);
+            T ps[V];
+            __builtin_memcpy(ps, &pvv, sizeof(VT));
+#pragma unroll
+            for (int v = 0; v < V; ++v) pp[v] += ps[v] * acc[v];
+        }
+    };
+
+    for (int r0 = wr0; r0 < wend;) {
+        const int na = min(kWave, wend - r0);
+        wave_lds_sync();  // the previous range's readers of sm are done
+        for (int i = lane; i <= na; i += kWave) sm.rp[i] = clampk(S.rp[r0 + i], S.nnz);
+        wave_lds_sync();
+        const int k0 = sm.rp[0];
+        int rs = 0;
+        {
+            const int l = lane + 1;
+            if (l <= na && (l % RTV == 0 || l == na) && sm.rp[l] - k0 <= C) rs = l;
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) rs = max(rs, __shfl_xor(rs, off));
+        }
+        if (rs > 0) {
+            const int k1 = max(k0, sm.rp[rs]);
+            stage(k0, k1);
+            for (int g0 = 0; g0 < rs; g0 += RTV) {
+                const int gr = g0 + g;
+                int s = k0, e = k0;
+                if (gr < rs) {
+                    s = max(sm.rp[gr], k0);
+                    e = min(max(sm.rp[gr + 1], s), k1);
+                }
+                T acc[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] = T(0);
+                walk(s, e, k0, acc);
+                finish(r0 + gr, gr < rs, acc);
+            }
+            r0 += rs;
+        } else {  // one group of RTV rows longer than a chunk
+            const int nr = min(RTV, na);
+            const int k1 = max(k0, sm.rp[nr]);
+            int s = k0, e = k0;
+            if (g < nr) {
+                s = max(sm.rp[g], k0);
+                e = min(max(sm.rp[g + 1], s), k1);
+            }
+            T acc[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] = T(0);
+            for (int c0 = k0; c0 < k1; c0 += C) {
+                stage(c0, k1);
+                walk(max(s, c0), min(e, c0 + C), c0, acc);
+            }
+            finish(r0 + g, g < nr, acc);
+            r0 += nr;
+        }
+    }
+}
+
 // Wave-tile schedule (M < 0: RT = -M rows per wave tile) for K = S.K.
+// Returns the number of p.q values in pp: 1 (pp[0], right-hand side
+// threadIdx.x % K) or V = 16 / sizeof(T) (the vector-gather form, see
+// spmm_wave_tiles_vec).
 template <typename T>
-__device__ __forceinline__ T spmm_wave_dispatch(const BSysT<T> &S, const BTile &t, double *lds)
+__device__ __forceinline__ int spmm_wave_dispatch(const BSysT<T> &S, const BTile &t, double *lds,
+                                                  T (&pp)[16 / sizeof(T)])
 {
     const int rt = -S.M;
-#define CGX_WT(R, KK)                                                 \
-    if (rt == R && S.K == KK)                                         \
-        return S.staged ? spmm_wave_tiles<R, KK, T, true>(S, t, lds)  \
-                        : spmm_wave_tiles<R, KK, T, false>(S, t, lds);
+#define CGX_WT(R, KK)                                                          \
+    if (rt == R && S.K == KK) {                                                \
+        pp[0] = S.staged ? spmm_wave_tiles<R, KK, T, true>(S, t, lds)          \
+                         : spmm_wave_tiles<R, KK, T, false>(S, t, lds);        \
+        return 1;                                                              \
+    }
+#define CGX_WV(R, KK)                                                          \
+    if (rt == R && S.K == KK) {                                                \
+        if (S.staged) {                                                        \
+            spmm_wave_tiles_vec<R, KK, T>(S, t, lds, pp);                      \
+            return 16 / (int)sizeof(T);                                        \
+        }                                                                      \
+        pp[0] = spmm_wave_tiles<R, KK, T, false>(S, t, lds);                   \
+        return 1;                                                              \
+    }
     CGX_WT(1, 1) CGX_WT(2, 1) CGX_WT(4, 1) CGX_WT(8, 1) CGX_WT(16, 1) CGX_WT(32, 1) CGX_WT(64, 1)
     CGX_WT(8, 2) CGX_WT(16, 2) CGX_WT(32, 2)
     CGX_WT(4, 4) CGX_WT(8, 4) CGX_WT(16, 4)
-    CGX_WT(2, 8) CGX_WT(4, 8) CGX_WT(8, 8)
-    CGX_WT(1, 16) CGX_WT(2, 16) CGX_WT(4, 16)
+    CGX_WV(2, 8) CGX_WV(4, 8) CGX_WV(8, 8)
+    CGX_WV(1, 16) CGX_WV(2, 16) CGX_WV(4, 16)
 #undef CGX_WT
-    return T(0);  // not reached: schedules are validated on the host
+#undef CGX_WV
+    pp[0] = T(0);  // not reached: schedules are validated on the host
+    return 1;
 }
 
 // (1) q = A p for every active system, p.q partials per right-hand side.
@@ -476,7 +645,26 @@ __global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgsT<T> a)
     const BSysT<T> S = a.sys[t.sys];
     T ppq = T(0);
     if (S.M < 0) {
-        ppq = spmm_wave_dispatch(S, t, stage);
+        constexpr int V = 16 / (int)sizeof(T);
+        T pp[V];
+        const int nv = spmm_wave_dispatch(S, t, stage, pp);
+        if (nv > 1) {
+            // thread t's value v belongs to right-hand side (t V + v) mod K:
+            // the staging LDS (free now) holds them in that order, and each
+            // right-hand side's values are added in index order
+            __syncthreads();
+            T *vred = reinterpret_cast<T *>(stage);
+#pragma unroll
+            for (int v = 0; v < V; ++v) vred[threadIdx.x * V + v] = pp[v];
+            __syncthreads();
+            if (threadIdx.x < S.K) {
+                T sum = T(0);
+                for (int i = threadIdx.x; i < kBB * V; i += S.K) sum += vred[i];
+                a.part[(int64_t)t.tile * kMaxK + threadIdx.x] = sum;
+            }
+            return;
+        }
+        ppq = pp[0];
     } else {
         const int G = S.K * S.M, gpw = kWave / G;
         const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
