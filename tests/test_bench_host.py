@@ -1,0 +1,57 @@
+"""Host-side checks of the benchmark driver (no GPU): the byte models it
+reports against counts of the arrays they stand for, the wave-tile rows it
+names against the library's rule, the byte-counter lookup keyed by the
+kernel sources, and the refusal of more than one GPU."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import bench
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.parametrize("make", [lambda: synth.fd7(7), lambda: synth.q1cube(6, 1.0, 1)])
+def test_byte_models_count_the_arrays(make):
+    """SpMV: every stored value and column index once, the row pointers, x
+    and y once.  Jacobi-CG iteration: the SpMV plus the vectors the update
+    (x, r read and written, p, q, D^-1 read, z written) and the p update (z
+    and p read, p written) touch."""
+    A = make()
+    n, nnz = A.n_rows, A.nnz
+    arrays = A.val.nbytes + A.col_idx.nbytes + A.row_ptr.nbytes + 2 * 8 * n
+    assert bench.spmv_bytes(n, nnz) == arrays
+    assert bench.jacobi_iter_bytes(n, nnz) == arrays + 8 * n * (2 * 2 + 3 + 1) + 8 * n * 3
+    assert bench.jacobi_setup_bytes(n, nnz) == arrays + 8 * n + 8 * n * 4
+
+
+def test_wave_tile_rows_rule():
+    """The largest power of two up to 64 whose expected entries fill at most
+    90 % of 64 x 8: 16 rows for the 27-point Q1 rows, 64 for the 7-point
+    rows, one row when a mean row exceeds the chunk."""
+    assert bench.wave_tile_rows(2_097_152, 55_742_968) == 16
+    assert bench.wave_tile_rows(4096, 27136) == 64
+    assert bench.wave_tile_rows(100, 100 * 600) == 1
+    for rt in (1, 2, 4, 8, 16, 32, 64):
+        mean = 0.9 * 64 * 8 / rt
+        assert bench.wave_tile_rows(1000, int(1000 * mean)) == rt
+
+
+def test_traffic_lookup_is_keyed_by_the_sources():
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and int(h, 16) >= 0
+    t = bench.measured_traffic(h)
+    if t is not None:  # the committed counters were taken on these sources
+        alg = bench.spmv_bytes(2_097_152, 55_742_968)
+        assert 0.9 * alg <= t <= 1.2 * alg
+    assert bench.measured_traffic("0" * 16) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
