@@ -734,9 +734,8 @@ __global__ __launch_bounds__(kBB) void batch_update_kernel(BArgsT<T> a)
             S.x[e] = xi;
             S.r[e] = ri;
             prr += ri * ri;
-            if (S.jac) {
+            if (S.jac) {  // z = D^-1 r is not stored: the p update forms it again
                 const T zi = S.dinv[row] * ri;
-                S.z[e] = zi;
                 prz += ri * zi;
             }
         }
@@ -787,7 +786,10 @@ __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
     if (threadIdx.x == 0 && !any_active) a.sys_done[sid] = 1;
 }
 
-// (3) p = z + beta p for active right-hand sides.
+// (3) p = z + beta p for active right-hand sides, z = D^-1 r formed here
+// (the same product as in the update, so the same bits) instead of being
+// stored by the update and read back: D^-1 has one value per row, z one per
+// (row, right-hand side).
 template <typename T>
 __global__ __launch_bounds__(kBB) void batch_direction_kernel(BArgsT<T> a)
 {
@@ -799,10 +801,17 @@ __global__ __launch_bounds__(kBB) void batch_direction_kernel(BArgsT<T> a)
     const BScalT<T> c = a.scal[S.scal0 + j];
     if (!c.active) return;
     const T beta = c.beta;
-    const T *z = S.jac ? S.z : S.r;
     const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
+    if (S.jac) {
+        const int drow = kBB / S.K;
+        int row = t.row0 + (int)threadIdx.x / S.K;
 #pragma unroll 4
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) S.p[e] = fma_t(beta, S.p[e], z[e]);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB, row += drow)
+            S.p[e] = fma_t(beta, S.p[e], S.dinv[row] * S.r[e]);
+    } else {
+#pragma unroll 4
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) S.p[e] = fma_t(beta, S.p[e], S.r[e]);
+    }
 }
 
 // Interleaved x -> caller layout (x = 0 where b = 0).
