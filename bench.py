@@ -794,7 +794,7 @@ def main():
                          "(reads 1 GiB, writes 0.5 GiB) to calibrate byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only; the multi-GPU path is a design "
+        print("bench.py: the solver is measured on one GPU only; the multi-GPU path is a design "
               "(independent systems per GPU, row-slab halo exchange for one big system) "
               "and is not run. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
