@@ -125,3 +125,40 @@ def test_robust_spread_ignores_an_edge_sample():
     y = np.append(x[:6], 437.0)
     assert np.std(y) > 50.0 and robust_spread(y) < 3.0
     assert robust_spread([]) == 0.0
+
+
+def test_sampler_power_from_counter_updates(monkeypatch):
+    """The background sampler against a stand-in energy counter that advances
+    once every 0.1 s by exactly 300 W x 0.1 s (timestamps in ns, energy in
+    units of 15.3 uJ): the mean power between updates and the trace are
+    300 W, and an interval with fewer than two updates gives None."""
+    import sys
+    import threading
+    import time
+    import types
+    from paper_2112_10823_amd.energy import EnergySampler
+
+    res = 15.3e-6  # J per counter unit
+    t_start = time.perf_counter()
+    lock = threading.Lock()
+
+    def energy_count(_h):
+        with lock:
+            steps = int((time.perf_counter() - t_start) / 0.1)
+        ts = steps * 0.1
+        return {"energy_accumulator": int(round(300.0 * ts / res)), "counter_resolution": res * 1e6,
+                "timestamp": int(ts * 1e9)}
+
+    fake = types.SimpleNamespace(amdsmi_init=lambda: None,
+                                 amdsmi_get_processor_handles=lambda: [0],
+                                 amdsmi_get_energy_count=energy_count)
+    monkeypatch.setitem(sys.modules, "amdsmi", fake)
+    s = EnergySampler(period_s=0.005).start()
+    time.sleep(0.75)
+    s.stop()
+    assert s.ok and len(s.updates) >= 5
+    p = s.power_between(s.updates[0][0], s.updates[-1][0])
+    assert abs(p - 300.0) <= 300.0 * 1e-3
+    t, w = s.trace()
+    assert len(w) >= 4 and np.all(np.abs(w - 300.0) <= 300.0 * 1e-3)
+    assert s.power_between(s.updates[-1][0] + 1.0, s.updates[-1][0] + 2.0) is None
