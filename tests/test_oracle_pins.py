@@ -367,3 +367,85 @@ def test_f32_kernels_are_binary32():
     y32 = oracle.spmv_f32(A, A.val.astype(np.float32), np.ones(A.n_rows, np.float32))
     assert y32.dtype == np.float32
     assert np.array_equal(y32, oracle.spmv(A, np.ones(A.n_rows)).astype(np.float32))
+
+
+def _power_of_two_diagonal(n):
+    """diag(a) with a_i cycling through 1/2, 2, 8: three distinct eigenvalues,
+    every entry and its reciprocal exact in binary32."""
+    a = np.resize(np.array([0.5, 2.0, 8.0]), n)
+    return a, CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), a.copy())
+
+
+def test_mixed_ir_diagonal_closed_form():
+    """Refinement on a diagonal matrix, where each step has a closed form.
+    Jacobi-preconditioned, the binary32 inner CG is exact after one step
+    (z = D^-1 c, q = c, alpha = 1), so one refinement step gives
+    x_i = s * float(b_i / s) / a_i with s = ||b||: only the rounding of the
+    scaled residual to binary32 remains, a relative residual of at most
+    2^-24, and a second step squares it.  Unpreconditioned, the inner CG
+    takes exactly three steps (three distinct eigenvalues, a generic
+    right-hand side) whenever the inner tolerance lies above the binary32
+    floor."""
+    n = 300
+    a, A = _power_of_two_diagonal(n)
+    v32 = A.val.astype(np.float32)
+    b = synth.uniform(41, n)
+    s = np.linalg.norm(b)
+    one = oracle.mixed_ir(A, v32, b, rtol=1e-10, tau=1e-3, max_outer=1, jacobi=True)
+    assert one.status == oracle.NOT_CONVERGED and one.outer_iters == 1 and one.iters == 1
+    x1 = s * (b / s).astype(np.float32).astype(np.float64) / a
+    assert np.all(np.abs(one.x - x1) <= 4 * U * np.abs(x1))
+    assert 0.0 < one.relres <= 2.0 ** -24 * 1.001
+    full = oracle.mixed_ir(A, v32, b, rtol=1e-10, tau=1e-3, jacobi=True)
+    assert full.status == oracle.OK and full.outer_iters == 2 and full.iters == 2
+    assert full.relres <= 1e-14
+    assert np.linalg.norm(full.x - b / a) <= 1e-14 * np.linalg.norm(b / a)
+    plain = oracle.mixed_ir(A, v32, b, rtol=1e-10, tau=1e-3)
+    assert plain.status == oracle.OK and 2 <= plain.outer_iters <= 3
+    assert plain.iters == 3 * plain.outer_iters
+    assert np.linalg.norm(plain.x - b / a) <= 1e-9 * np.linalg.norm(b / a)
+
+
+def test_mixed_ir_trivial_cases():
+    """A zero right-hand side gives x = 0 without a step; an exact starting
+    guess gives no step and leaves x untouched."""
+    a, A = _power_of_two_diagonal(30)
+    v32 = A.val.astype(np.float32)
+    z = oracle.mixed_ir(A, v32, np.zeros(30), x0=np.ones(30))
+    assert z.status == oracle.OK and z.outer_iters == 0 and not z.x.any()
+    x = synth.uniform(3, 30)
+    b = a * x  # exact: every a_i is a power of two
+    e = oracle.mixed_ir(A, v32, b, x0=x)
+    assert e.status == oracle.OK and e.outer_iters == 0 and e.iters == 0
+    assert np.array_equal(e.x, x)
+
+
+def test_mixed_ir_jacobi_inner_sees_two_eigenvalues():
+    """A = S B S with B block-diagonal in identical 2x2 blocks [[1, t], [t, 1]]
+    (eigenvalues 1 - t and 1 + t) and S diagonal in powers of two, so that A,
+    its diagonal S^2 and the scaling are exact in binary32.  Jacobi-PCG on A is
+    CG on B, which ends in two steps for any right-hand side: every inner solve
+    of the Jacobi refinement takes exactly two steps, while the unpreconditioned
+    inner CG sees the many distinct eigenvalues of A and takes more."""
+    rng = np.random.default_rng(8)
+    nb, t = 200, 0.5
+    s = 2.0 ** rng.integers(-2, 3, 2 * nb)
+    rows, cols, vals = [], [], []
+    for k in range(nb):
+        i, j = 2 * k, 2 * k + 1
+        for r, c, v in ((i, i, 1.0), (i, j, t), (j, i, t), (j, j, 1.0)):
+            rows.append(r)
+            cols.append(c)
+            vals.append(s[r] * v * s[c])
+    n = 2 * nb
+    A = CSR(n, n, np.arange(0, 2 * n + 1, 2, dtype=np.int32), np.array(cols, np.int32),
+            np.array(vals))
+    assert np.array_equal(A.val.astype(np.float32).astype(np.float64), A.val)
+    b = synth.uniform(77, n)
+    xs = np.linalg.solve(A.to_dense(), b)
+    jac = oracle.mixed_ir(A, A.val.astype(np.float32), b, rtol=1e-10, tau=1e-3, jacobi=True)
+    assert jac.status == oracle.OK and 2 <= jac.outer_iters <= 3
+    assert jac.iters == 2 * jac.outer_iters
+    assert np.linalg.norm(jac.x - xs) <= 1e-9 * np.linalg.norm(xs)
+    plain = oracle.mixed_ir(A, A.val.astype(np.float32), b, rtol=1e-10, tau=1e-3)
+    assert plain.status == oracle.OK and plain.iters > 2 * plain.outer_iters
