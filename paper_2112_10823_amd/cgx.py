@@ -171,6 +171,17 @@ def _dev_tensor(t, dtype, name):
     return t
 
 
+def _buffer(t, name):
+    """A caller-supplied workspace or pool: contiguous GPU memory of any
+    dtype, passed on with its size in bytes (a host tensor would hand a host
+    address to the kernels, so it is refused here)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.numel() * t.element_size()
+
+
 class Handle:
     """A libcgx handle bound to a device and a stream."""
 
@@ -492,16 +503,17 @@ def cg_solve(A: DeviceCSR, b, x, opts: Opts | None = None, workspace=None, handl
         raise ValueError("b / x length does not match A")
     if workspace is None:
         workspace = cg_workspace(A, opts)
+    ws_bytes = _buffer(workspace, "workspace")
     st = Stats()
     d = A.desc()
     if sell is None:
         rc = load_library().cgx_cg_solve(_h(handle), ctypes.byref(d), _ptr(b), _ptr(x),
-                                         _ptr(workspace), workspace.numel(), ctypes.byref(opts),
+                                         _ptr(workspace), ws_bytes, ctypes.byref(opts),
                                          ctypes.byref(st))
     else:
         rc = load_library().cgx_cg_solve_sell(_h(handle), ctypes.byref(d),
                                               ctypes.byref(sell.desc()), _ptr(b), _ptr(x),
-                                              _ptr(workspace), workspace.numel(),
+                                              _ptr(workspace), ws_bytes,
                                               ctypes.byref(opts), ctypes.byref(st))
     if rc in (EINVAL, ENOMEM, EHIP) or (raise_on_fail and rc != OK):
         _check(rc)
@@ -520,10 +532,11 @@ def schwarz_solve(A: DeviceCSR, D: SchwarzDecomposition, b, x, opts: Opts | None
         raise ValueError("b / x length does not match A")
     if workspace is None:
         workspace = torch.empty(max(D.workspace_bytes(), 1), dtype=torch.uint8, device=x.device)
+    ws_bytes = _buffer(workspace, "workspace")
     st = Stats()
     d = A.desc()
     rc = load_library().cgx_schwarz_solve(_h(handle), ctypes.byref(d), ctypes.byref(D.desc()),
-                                          _ptr(b), _ptr(x), _ptr(workspace), workspace.numel(),
+                                          _ptr(b), _ptr(x), _ptr(workspace), ws_bytes,
                                           ctypes.byref(opts), ctypes.byref(st))
     if rc in (EINVAL, ENOMEM, EHIP) or (raise_on_fail and rc != OK):
         _check(rc)
@@ -572,10 +585,11 @@ def cg_solve_batched(items, opts: Opts | None = None, workspace=None, handle=Non
     arr = _systems(items)
     if workspace is None:
         workspace = batch_workspace(items, opts=opts)
+    ws_bytes = _buffer(workspace, "workspace")
     nstat = sum(int(item[1].shape[0]) for item in items)
     st = (Stats * nstat)()
     rc = load_library().cgx_cg_solve_batched(_h(handle), len(items), arr, _ptr(workspace),
-                                             workspace.numel(), ctypes.byref(opts), st)
+                                             ws_bytes, ctypes.byref(opts), st)
     if rc in (EINVAL, ENOMEM, EHIP):
         _check(rc)
     out, k = [], 0
@@ -592,9 +606,10 @@ def batch_schedule(items, workspace=None, handle=None):
     arr = _systems(items)
     if workspace is None:
         workspace = batch_workspace(items)
+    ws_bytes = _buffer(workspace, "workspace")
     m = (ctypes.c_int32 * len(items))()
     _check(load_library().cgx_batch_schedule(_h(handle), len(items), arr, _ptr(workspace),
-                                             workspace.numel(), m))
+                                             ws_bytes, m))
     return list(m)
 
 
@@ -611,10 +626,12 @@ class Server:
 
     def __init__(self, pool: torch.Tensor, max_slots: int = 64, handle: Handle | None = None,
                  max_group: int = 16):
+        pool_bytes = _buffer(pool, "pool")
         self.handle = handle or Handle()
         self.pool = pool
         self._keep = {}
-        _check(load_library().cgx_serve_start(self.handle.ptr, _ptr(pool), pool.numel(),
+        self.running = False
+        _check(load_library().cgx_serve_start(self.handle.ptr, _ptr(pool), pool_bytes,
                                               int(max_slots), int(max_group)))
         self.running = True
 

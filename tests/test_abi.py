@@ -91,3 +91,38 @@ def test_binding_refuses_host_tensors():
     import torch
     with pytest.raises(TypeError):
         cgx._dev_tensor(torch.zeros(3, dtype=torch.float64), torch.float64, "x")
+
+
+def test_binding_refuses_host_workspaces(monkeypatch):
+    """A host workspace or pool is refused before the library is reached: the
+    vector checks are waved through here (there is no GPU), and any library
+    call fails the test."""
+    import torch
+
+    def no_library(*a, **k):
+        raise AssertionError("library reached with a host workspace")
+
+    monkeypatch.setattr(cgx, "_dev_tensor", lambda t, dtype, name: t)
+    monkeypatch.setattr(cgx, "load_library", no_library)
+
+    class FakeCSR:
+        n_rows = 4
+        nnz = 4
+
+        def desc(self):
+            return cgx._Csr()
+
+    A = FakeCSR()
+    v = torch.zeros(4, dtype=torch.float64)
+    host_ws = torch.zeros(1024, dtype=torch.uint8)
+    with pytest.raises(TypeError, match="workspace"):
+        cgx.cg_solve(A, v, v.clone(), workspace=host_ws)
+    with pytest.raises(TypeError, match="workspace"):
+        cgx.schwarz_solve(A, None, v, v.clone(), workspace=host_ws)
+    B = torch.zeros(2, 4, dtype=torch.float64)
+    with pytest.raises(TypeError, match="workspace"):
+        cgx.cg_solve_batched([(A, B, B.clone())], workspace=host_ws)
+    with pytest.raises(TypeError, match="workspace"):
+        cgx.batch_schedule([(A, B, B.clone())], workspace=host_ws)
+    with pytest.raises(TypeError, match="pool"):
+        cgx.Server(host_ws, handle=object())
