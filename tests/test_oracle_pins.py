@@ -449,3 +449,27 @@ def test_mixed_ir_jacobi_inner_sees_two_eigenvalues():
     assert np.linalg.norm(jac.x - xs) <= 1e-9 * np.linalg.norm(xs)
     plain = oracle.mixed_ir(A, A.val.astype(np.float32), b, rtol=1e-10, tau=1e-3)
     assert plain.status == oracle.OK and plain.iters > 2 * plain.outer_iters
+
+
+def test_rounding_is_per_operation_in_each_precision():
+    """Inputs whose results follow by hand from IEEE round-to-nearest-even.
+    With e = 2^-12 (binary32) or 2^-27 (float64), (1+e)^2 = 1 + 2e + e^2
+    rounds to 1 + 2e, so -1 + (1+e)(1+e) is 2e; an SpMV that fuses the
+    product into its sum, or a dot carried wholly in a wider type, gives
+    2e + e^2.  And 1 + u + u with u half an ulp of 1 stays 1 when added in
+    order (ties to even), where a wider SpMV accumulator reaches the next
+    float.  (The compensated dot's own correction term is zero on these
+    inputs, so how that step is rounded is left to the dot's error-bound
+    pins.)"""
+    for e, u, f32 in ((2.0 ** -12, 2.0 ** -24, True), (2.0 ** -27, 2.0 ** -53, False)):
+        A = CSR(2, 4, np.array([0, 2, 5], np.int32), np.array([0, 1, 0, 2, 3], np.int32),
+                np.array([-1.0, 1 + e, 1.0, u, u]))
+        x = np.array([1.0, 1 + e, 1.0, 1.0])
+        if f32:
+            y = oracle.spmv_f32(A, A.val.astype(np.float32), x.astype(np.float32))
+            d = oracle.dot_f32(np.array([1 + e, -1], np.float32), np.array([1 + e, 1], np.float32))
+        else:
+            y = oracle.spmv(A, x)
+            d = oracle.dot(np.array([1 + e, -1.0]), np.array([1 + e, 1.0]))
+        assert y[0] == 2 * e and y[1] == 1.0, (f32, y)
+        assert d == 2 * e, (f32, d)
