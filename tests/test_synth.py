@@ -96,3 +96,77 @@ def test_blob_rhs_reproducible():
     b2 = synth.blob_rhs(10, 11)
     assert np.array_equal(b1, b2) and np.linalg.norm(b1) > 0
     assert not np.array_equal(b1, synth.blob_rhs(10, 12))
+
+
+def _q1_element_stiffness(h):
+    """int over [0, h]^3 of grad phi_a . grad phi_b for the eight trilinear
+    basis functions (vertex a = (ax, ay, az) in {0,1}^3, a = ax + 2 ay + 4 az),
+    by two-point Gauss quadrature per axis, exact for these integrands."""
+    g = h * (0.5 + np.array([-0.5, 0.5]) / np.sqrt(3.0))
+    w = h / 2.0
+    K = np.zeros((8, 8))
+    for qx in g:
+        for qy in g:
+            for qz in g:
+                q = (qx, qy, qz)
+                grads = []
+                for a in range(8):
+                    bits = ((a >> 0) & 1, (a >> 1) & 1, (a >> 2) & 1)
+                    f = [q[d] / h if bits[d] else 1.0 - q[d] / h for d in range(3)]
+                    df = [(1.0 if bits[d] else -1.0) / h for d in range(3)]
+                    grads.append([df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]])
+                G = np.array(grads)
+                K += w ** 3 * G @ G.T
+    return K
+
+
+@pytest.mark.parametrize("elem", [(2, 1, 3), (0, 2, 4), (5, 5, 0)])
+def test_q1_single_element_matches_quadrature(elem):
+    """One element with coefficient 1.7, every other zero: the assembled
+    matrix is 1.7 times the element stiffness matrix on the element's
+    vertices that are unknowns (grid nodes 1..N; 0 and N+1 are the Dirichlet
+    boundary), and zero elsewhere.  Element (ex, ey, ez) spans grid nodes
+    ex..ex+1 along x (and likewise y, z) and its coefficient sits at
+    ex + (N+1) (ey + (N+1) ez)."""
+    N = 5
+    h = 1.0 / (N + 1)
+    ex, ey, ez = elem
+    k = np.zeros((N + 1) ** 3)
+    k[ex + (N + 1) * (ey + (N + 1) * ez)] = 1.7
+    A = synth.q1cube_from_coeffs(N, k).to_dense()
+    K = 1.7 * _q1_element_stiffness(h)
+    expect = np.zeros_like(A)
+    verts = []
+    for a in range(8):
+        x, y, z = ex + (a & 1), ey + ((a >> 1) & 1), ez + ((a >> 2) & 1)
+        if 1 <= x <= N and 1 <= y <= N and 1 <= z <= N:
+            verts.append((a, (x - 1) + N * ((y - 1) + N * (z - 1))))
+    for a, i in verts:
+        for b, j in verts:
+            expect[i, j] = K[a, b]
+    assert len(verts) == {(2, 1, 3): 8, (0, 2, 4): 4, (5, 5, 0): 1}[elem]
+    assert np.allclose(A, expect, rtol=0, atol=1e-14 * np.abs(K).max())
+
+
+def test_fd7_var_face_weights_are_series_conductances():
+    """The 7-point operator's node coefficients are k = exp(sigma Z) from the
+    normal stream of the same seed.  A face joins two half cells in series,
+    so its weight w = -a_ij lies between min(k_i, k_j) and 2 min(k_i, k_j)
+    (an arithmetic mean leaves that range once the contrast exceeds 3, which
+    many faces here do); each diagonal is its face weights plus k_i for every
+    face on the Dirichlet boundary."""
+    N, sigma, seed = 6, 1.0, 3
+    A = synth.fd7_var(N, sigma, seed)
+    k = np.exp(sigma * synth.normal(seed, N ** 3))
+    contrast = 0
+    for i in range(A.n_rows):
+        cols = A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]]
+        vals = A.val[A.row_ptr[i]:A.row_ptr[i + 1]]
+        off = cols != i
+        w, kj = -vals[off], k[cols[off]]
+        m = np.minimum(k[i], kj)
+        assert np.all(w >= m * (1 - 1e-15)) and np.all(w <= 2 * m * (1 + 1e-15)), i
+        contrast += int(np.sum(np.maximum(k[i], kj) > 3 * m))
+        diag = vals[~off][0]
+        assert diag == pytest.approx(w.sum() + k[i] * (6 - off.sum()), rel=1e-14), i
+    assert contrast > 100
