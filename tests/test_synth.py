@@ -98,25 +98,27 @@ def test_blob_rhs_reproducible():
     assert not np.array_equal(b1, synth.blob_rhs(10, 12))
 
 
-def _q1_element_stiffness(h):
-    """int over [0, h]^3 of grad phi_a . grad phi_b for the eight trilinear
-    basis functions (vertex a = (ax, ay, az) in {0,1}^3, a = ax + 2 ay + 4 az),
-    by two-point Gauss quadrature per axis, exact for these integrands."""
-    g = h * (0.5 + np.array([-0.5, 0.5]) / np.sqrt(3.0))
-    w = h / 2.0
+def _q1_element_stiffness(h, hy=None, hz=None):
+    """int over [0, hx] x [0, hy] x [0, hz] of grad phi_a . grad phi_b for the
+    eight trilinear basis functions (vertex a = (ax, ay, az) in {0,1}^3,
+    a = ax + 2 ay + 4 az), by two-point Gauss quadrature per axis, exact for
+    these integrands.  One side length gives the cube."""
+    hs = (h, h if hy is None else hy, h if hz is None else hz)
+    pts = [hd * (0.5 + np.array([-0.5, 0.5]) / np.sqrt(3.0)) for hd in hs]
+    w = hs[0] * hs[1] * hs[2] / 8.0
     K = np.zeros((8, 8))
-    for qx in g:
-        for qy in g:
-            for qz in g:
+    for qx in pts[0]:
+        for qy in pts[1]:
+            for qz in pts[2]:
                 q = (qx, qy, qz)
                 grads = []
                 for a in range(8):
                     bits = ((a >> 0) & 1, (a >> 1) & 1, (a >> 2) & 1)
-                    f = [q[d] / h if bits[d] else 1.0 - q[d] / h for d in range(3)]
-                    df = [(1.0 if bits[d] else -1.0) / h for d in range(3)]
+                    f = [q[d] / hs[d] if bits[d] else 1.0 - q[d] / hs[d] for d in range(3)]
+                    df = [(1.0 if bits[d] else -1.0) / hs[d] for d in range(3)]
                     grads.append([df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]])
                 G = np.array(grads)
-                K += w ** 3 * G @ G.T
+                K += w * G @ G.T
     return K
 
 
@@ -170,3 +172,37 @@ def test_fd7_var_face_weights_are_series_conductances():
         diag = vals[~off][0]
         assert diag == pytest.approx(w.sum() + k[i] * (6 - off.sum()), rel=1e-14), i
     assert contrast > 100
+
+
+def test_q1box_rows_match_quadrature():
+    """The paper-shape box (a x a x c nodes over 200 x 200 x 10 km): a node
+    whose neighbours are all unknowns has the row the eight bricks around it
+    assemble, each brick's stiffness integrated by quadrature with sides
+    hx = hy = 200/(a-1), hz = 10/(c-1); Dirichlet nodes are identity rows."""
+    a, c = 9, 7
+    A = synth.q1box(a, c)
+    hx, hz = 200.0 / (a - 1), 10.0 / (c - 1)
+    K = _q1_element_stiffness(hx, hx, hz)
+
+    def node(x, y, z):
+        return x + a * (y + a * z)
+
+    for (x, y, z) in [(2, 2, 2), (4, 3, 3), (6, 6, 4)]:
+        i = node(x, y, z)
+        expect = {}
+        for ez in (z - 1, z):
+            for ey in (y - 1, y):
+                for ex in (x - 1, x):
+                    la = (x - ex) + 2 * (y - ey) + 4 * (z - ez)
+                    for lb in range(8):
+                        j = node(ex + (lb & 1), ey + ((lb >> 1) & 1), ez + ((lb >> 2) & 1))
+                        expect[j] = expect.get(j, 0.0) + K[la, lb]
+        got = dict(zip(A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]].tolist(),
+                       A.val[A.row_ptr[i]:A.row_ptr[i + 1]].tolist()))
+        assert sorted(got) == sorted(expect)
+        scale = max(abs(v) for v in expect.values())
+        for j in expect:
+            assert abs(got[j] - expect[j]) <= 1e-13 * scale, (x, y, z, j)
+    for i in (node(0, 3, 3), node(4, 8, 2), node(5, 5, 0), node(3, 3, c - 1)):
+        assert A.row_ptr[i + 1] - A.row_ptr[i] == 1
+        assert A.col_idx[A.row_ptr[i]] == i and A.val[A.row_ptr[i]] == 1.0
