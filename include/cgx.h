@@ -238,12 +238,16 @@ typedef struct cgx_system {
     double *X;
 } cgx_system;
 
-/* Workspace bytes of cgx_cg_solve_batched for this batch (0 on bad input). */
+/* Workspace bytes of cgx_cg_solve_batched for this batch; 0 when nsys < 1
+ * or systems is NULL.  The size follows each descriptor's n_rows and nrhs as
+ * given: the descriptors are validated by cgx_cg_solve_batched (square,
+ * n_rows >= 1, nrhs in [1, 16], ...), not by this query. */
 size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems);
 
 /* Workspace bytes of cgx_cg_solve_batched with opts->precision MIXED (the
  * float64 state, the binary32 inner state and the inner right-hand sides
- * and solutions; 0 on bad input). */
+ * and solutions); 0 when nsys < 1 or systems is NULL, the descriptors
+ * validated by the solve as above. */
 size_t cgx_batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *systems);
 
 /* (sync) Solve every system of the batch by conjugate gradient (Section 5.3;

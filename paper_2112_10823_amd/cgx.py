@@ -556,6 +556,9 @@ def _systems(items):
         _dev_tensor(X, torch.float64, "X")
         if B.dim() != 2 or B.shape != X.shape or B.shape[1] != A.n_rows:
             raise ValueError("B and X must be (nrhs, n_rows)")
+        if not 1 <= B.shape[0] <= 16 or A.n_rows < 1 or A.n_rows != A.n_cols:
+            raise ValueError("each system needs a square matrix with n_rows >= 1 and 1 to 16 "
+                             "right-hand sides")
         arr[i].A = A.desc()
         arr[i].nrhs = B.shape[0]
         arr[i].B = B.data_ptr()

@@ -106,7 +106,7 @@ def test_binding_refuses_host_workspaces(monkeypatch):
     monkeypatch.setattr(cgx, "load_library", no_library)
 
     class FakeCSR:
-        n_rows = 4
+        n_rows = n_cols = 4
         nnz = 4
 
         def desc(self):
@@ -126,3 +126,30 @@ def test_binding_refuses_host_workspaces(monkeypatch):
         cgx.batch_schedule([(A, B, B.clone())], workspace=host_ws)
     with pytest.raises(TypeError, match="pool"):
         cgx.Server(host_ws, handle=object())
+
+
+def test_binding_checks_batch_descriptors(monkeypatch):
+    """The workspace-size queries take descriptors as given; the binding
+    refuses a system with no or more than 16 right-hand sides, or a
+    non-square or empty matrix, before it sizes or solves the batch."""
+    import torch
+
+    def no_library(*a, **k):
+        raise AssertionError("library reached with a bad batch")
+
+    monkeypatch.setattr(cgx, "_dev_tensor", lambda t, dtype, name: t)
+    monkeypatch.setattr(cgx, "load_library", no_library)
+
+    class FakeCSR:
+        def __init__(self, n_rows, n_cols):
+            self.n_rows, self.n_cols, self.nnz = n_rows, n_cols, max(n_rows, 0)
+
+        def desc(self):
+            return cgx._Csr()
+
+    for A, k in ((FakeCSR(4, 4), 0), (FakeCSR(4, 4), 17), (FakeCSR(4, 5), 1), (FakeCSR(0, 0), 1)):
+        B = torch.zeros(k, A.n_rows, dtype=torch.float64)
+        with pytest.raises(ValueError):
+            cgx.batch_workspace_bytes([(A, B, B.clone())])
+        with pytest.raises(ValueError):
+            cgx.cg_solve_batched([(A, B, B.clone())])
