@@ -160,8 +160,10 @@ typedef struct cgx_stats {
 
 /* Bytes of device workspace cg_solve needs for a system of n_rows rows and
  * nnz stored entries (the SpMV tile count depends on the mean row length)
- * and `opts` (0 on invalid arguments).  The caller allocates it (256-byte aligned) and
- * keeps it alive for the duration of the call. */
+ * and `opts` (its precond and precision); 0 when n_rows or nnz is negative or
+ * opts is NULL.  Option values themselves are checked by the solve.  The
+ * caller allocates it (256-byte aligned) and keeps it alive for the duration
+ * of the call. */
 size_t cgx_cg_workspace_bytes(int64_t n_rows, int64_t nnz, const cgx_opts *opts);
 
 /* (sync) Solve A x = b, A symmetric positive definite, by conjugate gradient
