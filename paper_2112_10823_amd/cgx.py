@@ -171,6 +171,22 @@ def _dev_tensor(t, dtype, name):
     return t
 
 
+_I32_MAX = 2 ** 31 - 1
+
+
+def _host_i32(a, name):
+    """A host index array as contiguous int32, refused if an entry would not
+    fit (a cast would wrap it)."""
+    a = np.asarray(a)
+    if not np.issubdtype(a.dtype, np.integer):
+        raise TypeError(f"{name} must hold integers, got {a.dtype}")
+    if a.dtype != np.int32 and a.size and (int(a.min()) < -_I32_MAX - 1 or int(a.max()) > _I32_MAX):
+        raise ValueError(f"{name} has entries beyond the 32-bit range")
+    if a.size > _I32_MAX:
+        raise ValueError(f"{name} has more than 2^31 - 1 entries")
+    return np.ascontiguousarray(a, np.int32)
+
+
 def _buffer(t, name):
     """A caller-supplied workspace or pool: contiguous GPU memory of any
     dtype, passed on with its size in bytes (a host tensor would hand a host
@@ -250,10 +266,22 @@ class DeviceCSR:
 
     @classmethod
     def from_host(cls, A, device="cuda", with_f32=False, validate=True, handle=None):
-        """Upload a host CSR (row_ptr, col_idx, val numpy arrays) and validate it on the GPU."""
-        rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, np.int32)).to(device)
-        ci = torch.from_numpy(np.ascontiguousarray(A.col_idx, np.int32)).to(device)
-        v = torch.from_numpy(np.ascontiguousarray(A.val, np.float64)).to(device)
+        """Upload a host CSR (row_ptr, col_idx, val numpy arrays) and validate it on the GPU.
+        Sizes and indices must fit the library's 32-bit CSR; they are checked
+        here before anything is copied, so that no index wraps in the cast."""
+        n_rows, n_cols = int(A.n_rows), int(A.n_cols)
+        if not (0 <= n_rows <= _I32_MAX and 0 <= n_cols <= _I32_MAX):
+            raise ValueError("n_rows and n_cols must lie in [0, 2^31 - 1]")
+        rp_h = _host_i32(A.row_ptr, "row_ptr")
+        ci_h = _host_i32(A.col_idx, "col_idx")
+        v_h = np.ascontiguousarray(A.val, np.float64)
+        if rp_h.size != n_rows + 1:
+            raise ValueError("row_ptr must hold n_rows + 1 entries")
+        if ci_h.size != v_h.size:
+            raise ValueError("col_idx and val must have the same length")
+        rp = torch.from_numpy(rp_h).to(device)
+        ci = torch.from_numpy(ci_h).to(device)
+        v = torch.from_numpy(v_h).to(device)
         d = cls(int(A.n_rows), int(A.n_cols), rp, ci, v)
         if with_f32:
             d.val32 = torch.empty(d.nnz, dtype=torch.float32, device=device)

@@ -153,3 +153,31 @@ def test_binding_checks_batch_descriptors(monkeypatch):
             cgx.batch_workspace_bytes([(A, B, B.clone())])
         with pytest.raises(ValueError):
             cgx.cg_solve_batched([(A, B, B.clone())])
+
+
+def test_from_host_checks_sizes_before_copying():
+    """Index arrays that would wrap in the cast to 32 bits, a row-pointer
+    array of the wrong length or mismatched entry arrays are refused before
+    anything is copied; a valid int64 CSR converts exactly."""
+    import numpy as np
+    import synth
+
+    A = synth.fd7(3)
+    bad_rp = A.row_ptr.astype(np.int64)
+    bad_rp[-1] = 2 ** 31
+    cases = [
+        synth.CSR(A.n_rows, A.n_cols, bad_rp, A.col_idx, A.val),
+        synth.CSR(A.n_rows, A.n_cols, A.row_ptr[:-1], A.col_idx, A.val),
+        synth.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, A.val[:-1]),
+        synth.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx.astype(np.int64) - 2 ** 32, A.val),
+        synth.CSR(2 ** 31, A.n_cols, A.row_ptr, A.col_idx, A.val),
+    ]
+    for bad in cases:
+        with pytest.raises(ValueError):
+            cgx.DeviceCSR.from_host(bad, device="cpu", validate=False)
+    with pytest.raises(TypeError):
+        cgx.DeviceCSR.from_host(synth.CSR(A.n_rows, A.n_cols, A.row_ptr.astype(float), A.col_idx,
+                                          A.val), device="cpu", validate=False)
+    ok = synth.CSR(A.n_rows, A.n_cols, A.row_ptr.astype(np.int64), A.col_idx.astype(np.int64), A.val)
+    d = cgx.DeviceCSR.from_host(ok, device="cpu", validate=False)
+    assert np.array_equal(d.row_ptr.numpy(), A.row_ptr) and np.array_equal(d.col_idx.numpy(), A.col_idx)
