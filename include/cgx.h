@@ -306,7 +306,10 @@ int cgx_batch_schedule(cgx_handle h, int32_t nsys, const cgx_system *systems, vo
  * at least 65536 rows keep one spare lane for such late arrivals.  With max_group = 1 a request's result is
  * bit-identical alone and in any mix; with grouping it is the same within
  * the solve tolerance.  The handle must not run other solves while the
- * server runs. */
+ * server runs.  Threads: cgx_submit, cgx_poll and cgx_wait may be called
+ * from several host threads at once, each ticket collected by one caller
+ * only; cgx_serve_stop (and cgx_destroy) must not overlap any other call on
+ * the handle. */
 int cgx_serve_start(cgx_handle h, void *pool, size_t pool_bytes, int32_t max_slots,
                     int32_t max_group);
 
