@@ -55,3 +55,31 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_host_residual_matches_the_oracle():
+    """The residual the extras report (scipy's CSR product on the host) is
+    the oracle's ||b - A x|| / ||b|| up to rounding."""
+    import oracle
+    A = synth.q1cube(8, 1.0, 3)
+    b = synth.uniform(4, A.n_rows)
+    x = oracle.cg(A, b, rtol=1e-6).x
+    ref = float(np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b))
+    assert abs(bench.host_relres(A, b, x) - ref) <= 1e-9 * ref
+    assert bench.host_relres(A, b, np.zeros(A.n_rows)) == 1.0
+
+
+def test_only_the_cpu_baseline_uses_the_oracle():
+    """Apart from the CPU baseline, no part of the benchmark imports the
+    oracle."""
+    import ast
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    users = set()
+    for fn in ast.walk(tree):
+        if isinstance(fn, ast.FunctionDef):
+            for node in ast.walk(fn):
+                if isinstance(node, (ast.Import, ast.ImportFrom)):
+                    names = [a.name for a in node.names] + [getattr(node, "module", None) or ""]
+                    if any(n == "oracle" or n.startswith("oracle.") for n in names):
+                        users.add(fn.name)
+    assert users == {"cpu_baseline"}
