@@ -473,3 +473,21 @@ def test_rounding_is_per_operation_in_each_precision():
             d = oracle.dot(np.array([1 + e, -1.0]), np.array([1 + e, 1.0]))
         assert y[0] == 2 * e and y[1] == 1.0, (f32, y)
         assert d == 2 * e, (f32, d)
+
+
+def test_degenerate_systems():
+    """n = 0: nothing to do, OK after no iteration; an empty dot is +0.0.
+    1 x 1 (4 x = 3): one step of CG, Jacobi-CG or refinement lands on 3/4,
+    which every precision holds exactly."""
+    A0 = CSR(0, 0, np.array([0], np.int32), np.array([], np.int32), np.array([], np.float64))
+    assert oracle.spmv(A0, np.zeros(0)).size == 0
+    r0 = oracle.cg(A0, np.zeros(0))
+    assert r0.status == oracle.OK and r0.iters == 0 and r0.x.size == 0
+    d0 = oracle.dot(np.zeros(0), np.zeros(0))
+    assert d0 == 0.0 and math.copysign(1.0, d0) == 1.0
+    A1 = CSR(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0]))
+    b = np.array([3.0])
+    for r in (oracle.cg(A1, b, rtol=1e-14), oracle.cg(A1, b, rtol=1e-14, jacobi=True)):
+        assert r.status == oracle.OK and r.iters == 1 and r.x[0] == 0.75
+    ir = oracle.mixed_ir(A1, np.array([4.0], np.float32), b, rtol=1e-14)
+    assert ir.status == oracle.OK and ir.outer_iters == 1 and ir.iters == 1 and ir.x[0] == 0.75
