@@ -114,6 +114,12 @@ int cgx_xmul(cgx_handle h, int64_t n, const double *x, const double *y, double *
  * well-conditioned data.  n = 0 gives +0.0. */
 int cgx_dot(cgx_handle h, int64_t n, const double *x, const double *y, double *result);
 
+/* (sync) The dot product of cgx_dot returned to the host: *result_host (a
+ * host pointer) receives the same bits cgx_dot writes, after the handle's
+ * stream has finished the reduction (the host-side result the paper's dot
+ * product table times). */
+int cgx_dot_sync(cgx_handle h, int64_t n, const double *x, const double *y, double *result_host);
+
 /* dst[i] = (float)src[i], round to nearest even (e.g. to build val32). */
 int cgx_demote(cgx_handle h, int64_t n, const double *src, float *dst);
 
@@ -156,6 +162,16 @@ typedef struct cgx_stats {
                           * plus the x/r/z update and its dots, (3) the p update */
     double queue_ms;     /* served requests: submission to admission, wall clock */
     double latency_ms;   /* served requests: submission to completion, wall clock */
+    double kappa_est;    /* cgx_cg_solve / _sell: ritz_max / ritz_min, the condition
+                          * number estimate of the operator CG ran on (A, or D^-1 A
+                          * with Jacobi; MIXED: the first refinement step's binary32
+                          * inner solve); 0 when no iteration ran or not recorded */
+    double ritz_min;     /* extreme eigenvalues of the Lanczos tridiagonal T_k built */
+    double ritz_max;     /* from the first k = min(iterations, 4096) CG steps' alpha,
+                          * beta (Saad, Sec. 6.7.3, the textbook the paper cites for
+                          * CG): T[j][j] = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+                          * T[j][j+1] = sqrt(beta_j)/alpha_j; they lie inside the
+                          * operator's spectrum and approach its ends as k grows */
 } cgx_stats;
 
 /* Bytes of device workspace cg_solve needs for a system of n_rows rows and
@@ -240,16 +256,16 @@ typedef struct cgx_system {
     double *X;
 } cgx_system;
 
-/* Workspace bytes of cgx_cg_solve_batched for this batch; 0 when nsys < 1
- * or systems is NULL.  The size follows each descriptor's n_rows and nrhs as
- * given: the descriptors are validated by cgx_cg_solve_batched (square,
- * n_rows >= 1, nrhs in [1, 16], ...), not by this query. */
+/* Workspace bytes of cgx_cg_solve_batched for this batch; 0 when nsys < 1,
+ * systems is NULL or a descriptor's sizes are invalid (not square, n_rows <
+ * 1, nnz outside [0, 2^31), nrhs outside [1, 16]).  Pointers are checked by
+ * the solve. */
 size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems);
 
 /* Workspace bytes of cgx_cg_solve_batched with opts->precision MIXED (the
  * float64 state, the binary32 inner state and the inner right-hand sides
- * and solutions); 0 when nsys < 1 or systems is NULL, the descriptors
- * validated by the solve as above. */
+ * and solutions); 0 for the invalid batches cgx_batch_workspace_bytes
+ * rejects. */
 size_t cgx_batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *systems);
 
 /* (sync) Solve every system of the batch by conjugate gradient (Section 5.3;
@@ -398,6 +414,14 @@ size_t cgx_schwarz_workspace_bytes(const cgx_schwarz *S);
 int cgx_schwarz_solve(cgx_handle h, const cgx_csr *A, const cgx_schwarz *S, const double *b,
                       double *x, void *workspace, size_t workspace_bytes, const cgx_opts *opts,
                       cgx_stats *stats);
+
+/* ---------------------------------------------------------- test hooks -- */
+
+/* For tests of the failure paths: the next `count` calls of the batched
+ * schedule autotuner on this handle (cgx_batch_schedule, the batched solves,
+ * a served slot's first cycle) fail with CGX_EHIP before launching anything,
+ * whether or not the shape class was tuned before.  count = 0 clears it. */
+int cgx_debug_fail_tuning(cgx_handle h, int32_t count);
 
 #ifdef __cplusplus
 }

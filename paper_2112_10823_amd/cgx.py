@@ -50,7 +50,9 @@ class Stats(ctypes.Structure):
                 ("outer_iters", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
                 ("device_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 3),
-                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("kappa_est", ctypes.c_double), ("ritz_min", ctypes.c_double),
+                ("ritz_max", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,7 +88,7 @@ EXPORTS = [
     "cgx_batch_workspace_bytes", "cgx_cg_solve_batched", "cgx_batch_schedule",
     "cgx_serve_start", "cgx_serve_stop", "cgx_serve_request_bytes", "cgx_submit", "cgx_poll",
     "cgx_wait", "cgx_batch_mixed_workspace_bytes", "cgx_schwarz_bytes", "cgx_schwarz_build", "cgx_schwarz_workspace_bytes",
-    "cgx_schwarz_solve",
+    "cgx_schwarz_solve", "cgx_dot_sync", "cgx_debug_fail_tuning",
 ]
 
 _lib = None
@@ -115,6 +117,8 @@ def load_library(path: str = LIB_PATH):
         "cgx_axpy": ([vp, i64, dbl, vp, vp], ctypes.c_int),
         "cgx_xmul": ([vp, i64, vp, vp, vp], ctypes.c_int),
         "cgx_dot": ([vp, i64, vp, vp, vp], ctypes.c_int),
+        "cgx_dot_sync": ([vp, i64, vp, vp, P(dbl)], ctypes.c_int),
+        "cgx_debug_fail_tuning": ([vp, i32], ctypes.c_int),
         "cgx_demote": ([vp, i64, vp, vp], ctypes.c_int),
         "cgx_cg_workspace_bytes": ([i64, i64, P(Opts)], ctypes.c_size_t),
         "cgx_cg_solve": ([vp, P(_Csr), vp, vp, vp, ctypes.c_size_t, P(Opts), P(Stats)],
@@ -490,6 +494,19 @@ def dot(x, y, out=None, handle=None):
     _dev_tensor(out, torch.float64, "out")
     _check(load_library().cgx_dot(_h(handle), x.numel(), _ptr(x), _ptr(y), _ptr(out)))
     return out
+
+
+def dot_sync(x, y, handle=None) -> float:
+    """x . y returned to the host (cgx_dot_sync: waits for the handle's stream)."""
+    _vec_args(x, y)
+    out = ctypes.c_double()
+    _check(load_library().cgx_dot_sync(_h(handle), x.numel(), _ptr(x), _ptr(y), ctypes.byref(out)))
+    return out.value
+
+
+def debug_fail_tuning(count: int, handle=None):
+    """Test hook: the next `count` autotuner calls on the handle fail (cgx_debug_fail_tuning)."""
+    _check(load_library().cgx_debug_fail_tuning(_h(handle), int(count)))
 
 
 def demote(src, dst=None, handle=None):

@@ -81,6 +81,7 @@ int cgx_create(cgx_handle *out, int device, void *stream)
         const size_t scratch_bytes = (size_t)2 * cgx::kReduceBlocks * sizeof(double) + 256;
         hipError_t e = hipMalloc(&c->scratch, scratch_bytes);
         if (e == hipSuccess) e = hipHostMalloc(&c->host_state, sizeof(cgx::CgState));
+        if (e == hipSuccess) e = hipHostMalloc(&c->host_scalar, sizeof(double));
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreate(&c->ev0);
         if (e == hipSuccess) e = hipEventCreate(&c->ev1);
@@ -119,6 +120,7 @@ int cgx_destroy(cgx_handle h)
         if (c->ev_phase[i]) (void)hipEventDestroy(c->ev_phase[i]);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     if (c->host_state) (void)hipHostFree(c->host_state);
+    if (c->host_scalar) (void)hipHostFree(c->host_scalar);
     if (c->scratch) (void)hipFree(c->scratch);
     delete c;
     return CGX_OK;
@@ -223,6 +225,26 @@ int cgx_dot(cgx_handle h, int64_t n, const double *x, const double *y, double *r
         CGX_REQUIRE(result != nullptr, "result is NULL");
         CGX_REQUIRE(n == 0 || (x && y), "NULL vector");
         return cgx::launch_dot(ctx_of(h), n, x, y, result);
+    });
+}
+
+int cgx_dot_sync(cgx_handle h, int64_t n, const double *x, const double *y, double *result_host)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(n >= 0, "negative length");
+        CGX_REQUIRE(result_host != nullptr, "result_host is NULL");
+        CGX_REQUIRE(n == 0 || (x && y), "NULL vector");
+        Context *c = ctx_of(h);
+        // the result word sits after the reduction partials in the handle's scratch
+        double *dres = c->scratch + 2 * cgx::kReduceBlocks;
+        int rc = cgx::launch_dot(c, n, x, y, dres);
+        if (rc) return rc;
+        CGX_HIP_CHECK(hipMemcpyAsync(c->host_scalar, dres, sizeof(double), hipMemcpyDeviceToHost,
+                                     c->stream));
+        CGX_HIP_CHECK(hipStreamSynchronize(c->stream));
+        *result_host = *c->host_scalar;
+        return CGX_OK;
     });
 }
 
@@ -445,18 +467,31 @@ int cgx_schwarz_solve(cgx_handle h, const cgx_csr *A, const cgx_schwarz *S, cons
     });
 }
 
+// The sizes and schedules of a batch's descriptors (what the workspace
+// layout follows); pointers are checked by check_batch.
+static int check_batch_shapes(int32_t nsys, const cgx_system *systems)
+{
+    CGX_REQUIRE(nsys >= 1 && systems != nullptr, "empty batch");
+    for (int32_t s = 0; s < nsys; ++s) {
+        const cgx_system &q = systems[s];
+        CGX_REQUIRE(q.A.n_rows >= 1, "empty system in batch");
+        CGX_REQUIRE(q.A.n_rows == q.A.n_cols, "batched matrices must be square");
+        CGX_REQUIRE(q.A.nnz >= 0 && q.A.nnz < ((int64_t)1 << 31), "nnz must be in [0, 2^31)");
+        CGX_REQUIRE(q.nrhs >= 1 && q.nrhs <= 16, "nrhs must be in [1, 16]");
+    }
+    return CGX_OK;
+}
+
 static int check_batch(cgx_handle h, int32_t nsys, const cgx_system *systems,
                        bool need_val32 = false)
 {
     CGX_REQUIRE(h != nullptr, "handle is NULL");
-    CGX_REQUIRE(nsys >= 1 && systems != nullptr, "empty batch");
+    int rc = check_batch_shapes(nsys, systems);
+    if (rc) return rc;
     for (int32_t s = 0; s < nsys; ++s) {
         const cgx_system &q = systems[s];
-        int rc = check_csr(&q.A, true, need_val32);
+        rc = check_csr(&q.A, true, need_val32);
         if (rc) return rc;
-        CGX_REQUIRE(q.A.n_rows == q.A.n_cols, "batched matrices must be square");
-        CGX_REQUIRE(q.A.n_rows >= 1, "empty system in batch");
-        CGX_REQUIRE(q.nrhs >= 1 && q.nrhs <= 16, "nrhs must be in [1, 16]");
         CGX_REQUIRE(q.B != nullptr && q.X != nullptr, "NULL B or X");
         const size_t nb = (size_t)q.A.n_rows * q.nrhs * 8;
         CGX_REQUIRE(!overlaps(q.B, nb, q.X, nb), "X overlaps B");
@@ -479,7 +514,7 @@ static int check_batch(cgx_handle h, int32_t nsys, const cgx_system *systems,
 
 size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems)
 {
-    if (nsys < 1 || systems == nullptr) return 0;
+    if (check_batch_shapes(nsys, systems) != CGX_OK) return 0;
     try {
         return cgx::batch_workspace_bytes(nsys, systems);
     } catch (...) {
@@ -489,7 +524,7 @@ size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems)
 
 size_t cgx_batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *systems)
 {
-    if (nsys < 1 || systems == nullptr) return 0;
+    if (check_batch_shapes(nsys, systems) != CGX_OK) return 0;
     try {
         return cgx::batch_mixed_workspace_bytes(nsys, systems);
     } catch (...) {
@@ -607,6 +642,18 @@ int cgx_wait(cgx_handle h, uint64_t ticket, cgx_stats *stats)
     return guarded([&]() -> int {
         CGX_REQUIRE(h != nullptr, "handle is NULL");
         return cgx::serve_poll(ctx_of(h), ticket, stats, true);
+    });
+}
+
+int cgx_debug_fail_tuning(cgx_handle h, int32_t count)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(count >= 0, "count must be >= 0");
+        Context *c = ctx_of(h);
+        std::lock_guard<std::mutex> lk(c->tune_mu);
+        c->fail_tune = count;
+        return CGX_OK;
     });
 }
 

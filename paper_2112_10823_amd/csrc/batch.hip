@@ -247,6 +247,49 @@ int mixed_layout(int32_t nsys, const cgx_system *in, const int *Ms, const cgx_op
     return CGX_OK;
 }
 
+// Key of a graph of K batched iterations: the captured launches take
+// exactly the fields of `a` (grid sizes ntiles / nlist, dynamic LDS
+// wave_lds), so those and K identify it; the per-system tables they read are
+// uploaded before every solve.
+template <typename T>
+GraphKey batch_key(int K, const BArgsT<T> &a)
+{
+    GraphKey k;
+    k.add(0x42ull).add(sizeof(T)).add((uint64_t)K);
+    k.ptr(a.sys).ptr(a.tiles).ptr(a.list).ptr(a.scal).ptr(a.sys_done).ptr(a.part);
+    k.add((uint64_t)a.part_stride).add((uint64_t)a.ntiles).add((uint64_t)a.nlist);
+    k.add((uint64_t)a.wave_lds);
+    return k;
+}
+
+// Capture K batched iterations over `a` into `slot` unless its graph was
+// captured for the same key.
+template <typename T>
+int ensure_batch_graph(GraphSlot &slot, int K, const BArgsT<T> &a, hipStream_t s)
+{
+    const GraphKey key = batch_key<T>(K, a);
+    if (slot.matches(key)) return CGX_OK;
+    slot.reset();
+    CGX_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < K; ++k) launch_batch_iteration(a, s);
+    hipGraph_t g = nullptr;
+    CGX_HIP_CHECK(hipStreamEndCapture(s, &g));
+    slot.graph = g;
+    CGX_HIP_CHECK(hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0));
+    slot.key = key.w;
+    return CGX_OK;
+}
+
+// Two timing events destroyed on every exit path.
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~EventPair()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 }  // namespace
 
 bool batch_wave_schedule_ok(int rt, int K) { return wave_schedule_ok(rt, K); }
@@ -261,6 +304,11 @@ int tune_one(Context *c, const cgx_system &sys, void *ws, size_t ws_bytes, hipSt
     const auto key = shape_key(K, sys.A.n_rows, sys.A.nnz);
     {
         std::lock_guard<std::mutex> lk(c->tune_mu);
+        if (c->fail_tune > 0) {  // test hook: fail before any launch
+            --c->fail_tune;
+            set_error("autotuning failed (forced)");
+            return CGX_EHIP;
+        }
         auto it = c->batch_tune.find(key);
         if (it != c->batch_tune.end()) {
             M_out = it->second;
@@ -270,9 +318,10 @@ int tune_one(Context *c, const cgx_system &sys, void *ws, size_t ws_bytes, hipSt
     const double mean = sys.A.n_rows ? (double)sys.A.nnz / sys.A.n_rows : 1.0;
     float best_ms = 1e30f;
     int best_m = default_m(K, mean);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    CGX_HIP_CHECK(hipEventCreate(&e0));
-    CGX_HIP_CHECK(hipEventCreate(&e1));
+    EventPair ev;
+    CGX_HIP_CHECK(hipEventCreate(&ev.e0));
+    CGX_HIP_CHECK(hipEventCreate(&ev.e1));
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     for (int M : m_candidates(K, sys.A.n_rows, sys.A.nnz)) {
         int Mv[1] = {M};
         Plan P;
@@ -299,8 +348,6 @@ int tune_one(Context *c, const cgx_system &sys, void *ws, size_t ws_bytes, hipSt
             best_m = M;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     std::lock_guard<std::mutex> lk(c->tune_mu);
     c->batch_tune[key] = best_m;
     M_out = best_m;
@@ -374,28 +421,9 @@ int run_batched(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t
         K = (int)(2.0e-3 / t_iter);
         K = K < 2 ? 2 : (K > 32 ? 32 : K);
     }
-    uint64_t key[kGraphKey] = {(uint64_t)(uintptr_t)ws, (uint64_t)nsys, (uint64_t)P.tiles.size(),
-                        (uint64_t)K, 0x42ull, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = 0; i < nsys; ++i) {
-        const uint64_t h = ((uint64_t)(uintptr_t)in[i].A.row_ptr * 1000003u) ^
-                           ((uint64_t)(uintptr_t)in[i].X << 1) ^
-                           ((uint64_t)(uintptr_t)in[i].B << 3) ^ ((uint64_t)P.sys[i].M << 7) ^
-                           (uint64_t)i;
-        key[5 + (i % 7)] = key[5 + (i % 7)] * 31u + h;
-    }
+    rc = ensure_batch_graph(c->graph_batch, K, a, s);
+    if (rc) return rc;
     GraphSlot &slot = c->graph_batch;
-    bool hit = slot.exec != nullptr;
-    for (int i = 0; i < kGraphKey && hit; ++i) hit = slot.key[i] == key[i];
-    if (!hit) {
-        slot.reset();
-        CGX_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < K; ++k) launch_batch_iteration(a, s);
-        hipGraph_t g = nullptr;
-        CGX_HIP_CHECK(hipStreamEndCapture(s, &g));
-        slot.graph = g;
-        CGX_HIP_CHECK(hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0));
-        for (int i = 0; i < kGraphKey; ++i) slot.key[i] = key[i];
-    }
     std::vector<int32_t> done(nsys);
     const int64_t max_replays = (int64_t)maxit / K + 2;
     for (int64_t rep = 0; rep < max_replays; ++rep) {
@@ -512,27 +540,9 @@ int run_batched_mixed(Context *c, int32_t nsys, const cgx_system *in, void *ws, 
         K = (int)(2.0e-3 / t_iter);
         K = K < 2 ? 2 : (K > 32 ? 32 : K);
     }
-    uint64_t key[kGraphKey] = {(uint64_t)(uintptr_t)ws, (uint64_t)nsys, (uint64_t)L.P32.tiles.size(),
-                               (uint64_t)K, 0x43ull, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = 0; i < nsys; ++i) {
-        const uint64_t h = ((uint64_t)(uintptr_t)in[i].A.row_ptr * 1000003u) ^
-                           ((uint64_t)(uintptr_t)in[i].A.val32 << 1) ^
-                           ((uint64_t)L.P32.sys[i].M << 7) ^ (uint64_t)i;
-        key[5 + (i % 7)] = key[5 + (i % 7)] * 31u + h;
-    }
+    rc = ensure_batch_graph(c->graph_batch32, K, a32, s);
+    if (rc) return rc;
     GraphSlot &slot = c->graph_batch32;
-    bool hit = slot.exec != nullptr;
-    for (int i = 0; i < kGraphKey && hit; ++i) hit = slot.key[i] == key[i];
-    if (!hit) {
-        slot.reset();
-        CGX_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < K; ++k) launch_batch_iteration(a32, s);
-        hipGraph_t g = nullptr;
-        CGX_HIP_CHECK(hipStreamEndCapture(s, &g));
-        slot.graph = g;
-        CGX_HIP_CHECK(hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0));
-        for (int i = 0; i < kGraphKey; ++i) slot.key[i] = key[i];
-    }
 
     std::vector<BScalT<double>> h64(L.P64.nscal);
     std::vector<BScalT<float>> h32(L.P32.nscal);

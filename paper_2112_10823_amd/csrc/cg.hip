@@ -22,6 +22,7 @@
 // (one launch, workgroup barriers between phases): at that size the cost is
 // launches and grid synchronisation, not bandwidth.
 #include <cmath>
+#include <vector>
 
 #include "cgx_device.h"
 
@@ -63,6 +64,7 @@ struct CgArgs {
     const int32_t *sell_col;
     const T *sell_val;
     CgState *st;
+    double *coef;         // alpha_j at 2 j, beta_j at 2 j + 1, j < kCoefRec (while st->rec)
     int ntiles;           // wave tiles of the SpMV phase (= its workgroups)
     int tiles_per_red;    // tile partials added by one reduction workgroup
     int n_pq;             // p.q partials in region kPPq
@@ -81,6 +83,7 @@ __global__ void cg_state_init_kernel(CgState *st, int maxit)
         CgState s = {};
         s.maxit = maxit;
         s.status = CGX_PENDING;
+        s.rec = 1;
         *st = s;
     }
 }
@@ -188,13 +191,15 @@ __global__ __launch_bounds__(kWave) void cg_spmv_kernel(CgArgs<T> a)
     __shared__ WaveSmem<wave_e<T>(), RT, T> sm;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     int row;
-    const T acc = wave_rows<wave_e<T>(), RT, 4, T>(tile * RT, a.n, a.n_cols, a.nnz, a.rp, a.ci,
-                                                   a.val, a.p, sm, row, &a.st->done);
+    T prow;  // p[row], from the gather of the diagonal entry
+    const T acc = wave_rows<wave_e<T>(), RT, 4, T, true>(tile * RT, a.n, a.n_cols, a.nnz, a.rp,
+                                                         a.ci, a.val, a.p, sm, row, &a.st->done,
+                                                         &prow);
     if (row < 0) return;  // the solve has stopped
     T part = T(0);
     if (threadIdx.x % (kWave / RT) == 0 && row < a.n) {
         a.q[row] = acc;
-        part = a.p[row] * acc;
+        part = prow * acc;
     }
     part = wave_sum(part);
     if (threadIdx.x == 0) a.tpart[tile] = part;
@@ -207,13 +212,14 @@ __global__ __launch_bounds__(kWave) void cg_sell_spmv_kernel(CgArgs<T> a)
 {
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     int row;
-    const T acc = sell_rows<8, T>(tile, a.n, a.n_cols, a.sell_sp, a.sell_col, a.sell_val, a.p, row,
-                                  &a.st->done);
+    T prow;  // p[row], from the gather of the diagonal entry
+    const T acc = sell_rows<8, T, true>(tile, a.n, a.n_cols, a.sell_sp, a.sell_col, a.sell_val,
+                                        a.p, row, &a.st->done, &prow);
     if (row < 0) return;  // the solve has stopped
     T part = T(0);
     if (row < a.n) {
         a.q[row] = acc;
-        part = a.p[row] * acc;
+        part = prow * acc;
     }
     part = wave_sum(part);
     if (threadIdx.x == 0) a.tpart[tile] = part;
@@ -257,10 +263,12 @@ __global__ __launch_bounds__(kPB) void cg_update_kernel(CgArgs<T> a)
     }
     const T alpha = rho / pq;
     if (lead) {
+        const int it = st->iter;
+        if (st->rec && it < kCoefRec) a.coef[2 * it] = (double)alpha;
         st->pq = pq;
         st->alpha = alpha;
         st->rho_used = rho;
-        st->iter = st->iter + 1;
+        st->iter = it + 1;
     }
     T *__restrict__ x = a.x;
     T *__restrict__ r = a.r;
@@ -321,6 +329,8 @@ __global__ __launch_bounds__(kPB) void cg_direction_kernel(CgArgs<T> a)
     }
     const T beta = rz / (T)st->rho_used;
     if (lead) {
+        const int j = st->iter - 1;  // the iteration whose alpha the update kernel formed
+        if (st->rec && j >= 0 && j < kCoefRec) a.coef[2 * j + 1] = (double)beta;
         st->rr = rr;
         st->rho = rz;
         st->beta = beta;
@@ -367,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(int64_t n, double *x)
 }
 
 // Status after p.q (single-workgroup path); forms alpha.
-__device__ void small_finish_pq(CgState *st, double pq)
+__device__ void small_finish_pq(CgState *st, double pq, double *coef)
 {
     st->pq = pq;
     if (!isfinite(pq) || !(pq > 0.0)) {
@@ -375,11 +385,12 @@ __device__ void small_finish_pq(CgState *st, double pq)
         st->done = 1;
     } else {
         st->alpha = st->rho / pq;
+        if (st->rec && st->iter < kCoefRec) coef[2 * st->iter] = st->alpha;
     }
 }
 
 // Status after the update (single-workgroup path); forms beta.
-__device__ void small_finish_update(CgState *st, double rr, double rz)
+__device__ void small_finish_update(CgState *st, double rr, double rz, double *coef)
 {
     const int iter = st->iter + 1;
     st->iter = iter;
@@ -396,6 +407,7 @@ __device__ void small_finish_update(CgState *st, double rr, double rz)
     if (status == CGX_PENDING) {
         st->beta = rz / st->rho;
         st->rho = rz;
+        if (st->rec && iter - 1 < kCoefRec) coef[2 * (iter - 1) + 1] = st->beta;
     } else {
         st->status = status;
         st->done = 1;
@@ -537,7 +549,7 @@ __global__ __launch_bounds__(kSmallBlock) void cg_res_kernel(CgArgs<double> a, d
             if (t + BS * j < n) p1[0] += sp[t + BS * j] * q[j];
         block_sum<1, BS>(p1, red);
         if (t == 0) {
-            small_finish_pq(st, p1[0]);
+            small_finish_pq(st, p1[0], a.coef);
             sh_done = st->done;
             sh_alpha = st->alpha;
         }
@@ -558,7 +570,7 @@ __global__ __launch_bounds__(kSmallBlock) void cg_res_kernel(CgArgs<double> a, d
         }
         block_sum<2, BS>(p2, red);
         if (t == 0) {
-            small_finish_update(st, p2[0], kJac ? p2[1] : p2[0]);
+            small_finish_update(st, p2[0], kJac ? p2[1] : p2[0], a.coef);
             sh_done = st->done;
             sh_beta = st->beta;
         }
@@ -724,6 +736,7 @@ __global__ __launch_bounds__(kPB) void mx_inner_init_finish_kernel(MxArgs m, CgA
     s->stop2 = (double)(tau2 * cc);
     s->iter = 0;
     s->maxit = inner_maxit;
+    s->rec = m.ost->iter == 0 ? 1 : 0;  // coefficients of the first refinement step
     const bool bad = !isfinite(cc) || !isfinite(cz) || !(cz > 0.0f);
     s->status = bad ? CGX_NONFINITE : CGX_PENDING;
     s->done = bad ? 1 : 0;
@@ -748,7 +761,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 // Mixed: outer state | inner state | r64 | r32 p32 q32 [z32 dinv32] | d32 | partials.
 struct Layout {
     size_t state = 0, state2 = 0, r64 = 0, r = 0, p = 0, q = 0, z = 0, dinv = 0, d = 0;
-    size_t partials = 0, tpart = 0, total = 0;
+    size_t partials = 0, tpart = 0, coef = 0, total = 0;
 };
 
 // Wave tiles of the SpMV phase for a system of n rows and nnz entries.
@@ -792,6 +805,8 @@ Layout make_layout(int64_t n, int64_t nnz, bool jac, bool mixed)
     off += align_up((size_t)kPRegions * kMaxPhaseBlocks * sizeof(double));
     L.tpart = off;
     off += align_up((size_t)std::max<int64_t>(spmv_tiles(n, nnz, mixed), 1) * sizeof(double));
+    L.coef = off;
+    off += align_up((size_t)2 * kCoefRec * sizeof(double));
     L.total = off;
     return L;
 }
@@ -979,13 +994,29 @@ int replay_iters(const cgx_opts *o, double bytes_per_iter)
 
 // Capture (or reuse) a graph of K iterations and replay it until the state's
 // `done` flag is set, at most max_replays times.
+// Key of a graph of K iterations: every argument and launch shape the
+// captured launches take.
 template <typename T>
-int replay_until_done(Context *c, GraphSlot &slot, const uint64_t (&key)[kGraphKey], int K, const Grids &g,
-                      bool jac, hipStream_t s, const CgArgs<T> &a, int64_t max_replays)
+GraphKey iteration_key(int K, const Grids &g, bool jac, const CgArgs<T> &a)
 {
-    bool hit = slot.exec != nullptr;
-    for (int i = 0; i < kGraphKey && hit; ++i) hit = slot.key[i] == key[i];
-    if (!hit) {
+    GraphKey k;
+    k.add(sizeof(T)).add((uint64_t)K).add(jac ? 1 : 0);
+    k.add((uint64_t)g.RT).add((uint64_t)g.ntiles).add((uint64_t)g.grid_red);
+    k.add((uint64_t)g.tiles_per_red).add((uint64_t)g.n_pq).add((uint64_t)g.grid_ew);
+    k.add((uint64_t)a.n).add((uint64_t)a.n_cols).add((uint64_t)a.nnz);
+    k.ptr(a.rp).ptr(a.ci).ptr(a.val).ptr(a.b).ptr(a.x).ptr(a.r).ptr(a.p).ptr(a.q).ptr(a.z);
+    k.ptr(a.dinv).ptr(a.partials).ptr(a.tpart).ptr(a.sell_sp).ptr(a.sell_col).ptr(a.sell_val);
+    k.ptr(a.st).ptr(a.coef).add((uint64_t)a.ntiles).add((uint64_t)a.tiles_per_red).add((uint64_t)a.n_pq);
+    k.add((uint64_t)a.grid_ew);
+    return k;
+}
+
+template <typename T>
+int replay_until_done(Context *c, GraphSlot &slot, int K, const Grids &g, bool jac, hipStream_t s,
+                      const CgArgs<T> &a, int64_t max_replays)
+{
+    const GraphKey key = iteration_key<T>(K, g, jac, a);
+    if (!slot.matches(key)) {
         slot.reset();
         CGX_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < K; ++k) launch_iteration<T>(g, jac, s, a);
@@ -993,7 +1024,7 @@ int replay_until_done(Context *c, GraphSlot &slot, const uint64_t (&key)[kGraphK
         CGX_HIP_CHECK(hipStreamEndCapture(s, &graph));
         slot.graph = graph;
         CGX_HIP_CHECK(hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0));
-        for (int i = 0; i < kGraphKey; ++i) slot.key[i] = key[i];
+        slot.key = key.w;
     }
     for (int64_t rep = 0; rep < max_replays; ++rep) {
         CGX_HIP_CHECK(hipGraphLaunch(slot.exec, s));
@@ -1028,6 +1059,26 @@ int zero_if_needed(Context *c, hipStream_t s, bool zero, int64_t n, double *x)
     CGX_HIP_CHECK(hipEventRecord(c->ev_out, s));
     CGX_HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_out, 0));
     if (zero) CGX_HIP_CHECK(hipStreamSynchronize(s));  // else finish_solve has waited
+    return CGX_OK;
+}
+
+// Ritz extremes and condition estimate from the first k recorded
+// coefficients (k = 0: left at 0).
+int fill_kappa(hipStream_t s, const double *coef_dev, int64_t iters, cgx_stats *st)
+{
+    const int k = (int)std::min<int64_t>(iters, kCoefRec);
+    st->kappa_est = st->ritz_min = st->ritz_max = 0.0;
+    if (k <= 0) return CGX_OK;
+    std::vector<double> coef(2 * (size_t)k);
+    CGX_HIP_CHECK(hipMemcpyAsync(coef.data(), coef_dev, coef.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+    CGX_HIP_CHECK(hipStreamSynchronize(s));
+    double lo = 0.0, hi = 0.0;
+    if (lanczos_extremes(coef.data(), k, lo, hi)) {
+        st->ritz_min = lo;
+        st->ritz_max = hi;
+        st->kappa_est = lo > 0.0 ? hi / lo : 0.0;
+    }
     return CGX_OK;
 }
 
@@ -1067,6 +1118,7 @@ int run_fp64(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, d
     a.dinv = jac ? reinterpret_cast<double *>(w + lay.dinv) : nullptr;
     a.partials = reinterpret_cast<double *>(w + lay.partials);
     a.st = reinterpret_cast<CgState *>(w + lay.state);
+    a.coef = reinterpret_cast<double *>(w + lay.coef);
     if (S) {
         a.sell_sp = S->slice_ptr;
         a.sell_col = S->col;
@@ -1149,14 +1201,8 @@ int run_fp64(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, d
         } else {
             const double bytes = 12.0 * (double)A->nnz + (jac ? 104.0 : 88.0) * (double)n;
             const int K = replay_iters(o, bytes);
-            const uint64_t key[kGraphKey] = {
-                (uint64_t)(uintptr_t)a.rp, (uint64_t)(uintptr_t)a.ci, (uint64_t)(uintptr_t)a.val,
-                (uint64_t)(uintptr_t)b, (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)ws,
-                (uint64_t)n, (uint64_t)A->nnz, (uint64_t)A->n_cols, (uint64_t)(jac ? 1 : 0),
-                (uint64_t)K, ((uint64_t)g.n_pq << 32) | (uint64_t)g.grid_ew,
-                (uint64_t)(uintptr_t)a.sell_sp, (uint64_t)(uintptr_t)a.sell_val};
             const int64_t max_replays = (int64_t)maxit / K + 2;
-            rc = replay_until_done<double>(c, c->graph64, key, K, g, jac, s, a, max_replays);
+            rc = replay_until_done<double>(c, c->graph64, K, g, jac, s, a, max_replays);
             if (rc) return rc;
         }
     }
@@ -1181,6 +1227,8 @@ int run_fp64(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, d
     if (o->true_residual) st->relres_true = hs.bb > 0.0 ? std::sqrt(hs.rr_true / hs.bb) : 0.0;
     if (zero_b) st->relres_true = 0.0, st->relres = 0.0;
     st->device_ms = ms;
+    rc = fill_kappa(s, a.coef, hs.iter, st);
+    if (rc) return rc;
     return st->status;
 }
 
@@ -1227,6 +1275,7 @@ int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, 
     in.dinv = m.dinv32;
     in.partials = reinterpret_cast<float *>(w + lay.partials);
     in.st = reinterpret_cast<CgState *>(w + lay.state2);
+    in.coef = reinterpret_cast<double *>(w + lay.coef);
     if (S) {
         in.sell_sp = S->slice_ptr;
         in.sell_col = S->col;
@@ -1249,12 +1298,7 @@ int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, 
 
     const double bytes_in = 8.0 * (double)A->nnz + (jac ? 52.0 : 44.0) * (double)n;
     const int K = replay_iters(o, bytes_in);
-    const uint64_t key[kGraphKey] = {
-        (uint64_t)(uintptr_t)in.rp, (uint64_t)(uintptr_t)in.ci, (uint64_t)(uintptr_t)in.val,
-        (uint64_t)(uintptr_t)ws, (uint64_t)n, (uint64_t)A->nnz, (uint64_t)A->n_cols,
-        (uint64_t)(jac ? 1 : 0), (uint64_t)K, ((uint64_t)g.n_pq << 32) | (uint64_t)g.grid_ew,
-        0x4d58ull, 0, (uint64_t)(uintptr_t)in.sell_sp, (uint64_t)(uintptr_t)in.sell_val};
-    int64_t inner_total = 0;
+    int64_t inner_total = 0, first_inner = 0;
     int status = CGX_NOT_CONVERGED;
     for (int step = 0; step <= max_outer + 1; ++step) {
         launch_mx_residual(g, step == 0, jac, s, m, rtol2);
@@ -1276,9 +1320,10 @@ int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, 
                            (float)(tau * tau), inner_maxit, jac ? 1 : 0);
         CGX_HIP_CHECK(hipGetLastError());
         const int64_t max_replays = (int64_t)inner_maxit / K + 2;
-        rc = replay_until_done<float>(c, c->graph32, key, K, g, jac, s, in, max_replays);
+        rc = replay_until_done<float>(c, c->graph32, K, g, jac, s, in, max_replays);
         if (rc) return rc;
         const CgState inner = *c->host_state;
+        if (step == 0) first_inner = inner.iter;
         inner_total += inner.iter;
         if (inner.status == CGX_NONFINITE) {
             status = CGX_NONFINITE;
@@ -1302,10 +1347,76 @@ int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, 
     st->relres = hs.bb > 0.0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
     st->relres_true = st->relres;
     st->device_ms = ms;
+    rc = fill_kappa(s, in.coef, first_inner, st);
+    if (rc) return rc;
     return st->status;
 }
 
 }  // namespace
+
+// Sturm count: eigenvalues of the symmetric tridiagonal (d, off-diagonal
+// squares e2) below x.
+static int sturm_below(const std::vector<double> &d, const std::vector<double> &e2, double x,
+                       double pivmin)
+{
+    int c = 0;
+    double q = d[0] - x;
+    for (size_t i = 0;; ++i) {
+        if (std::fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) ++c;
+        if (i + 1 == d.size()) break;
+        q = d[i + 1] - x - e2[i] / q;
+    }
+    return c;
+}
+
+bool lanczos_extremes(const double *coef, int k, double &lo, double &hi)
+{
+    if (k <= 0) return false;
+    // T[j][j] = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T[j][j+1]^2 = beta_j / alpha_j^2
+    std::vector<double> d(k), e2(k > 1 ? k - 1 : 0), e(k > 1 ? k - 1 : 0);
+    for (int j = 0; j < k; ++j) {
+        const double al = coef[2 * j];
+        if (!std::isfinite(al) || !(al > 0.0)) return false;
+        d[j] = 1.0 / al;
+        if (j > 0) d[j] += coef[2 * (j - 1) + 1] / coef[2 * (j - 1)];
+        if (j + 1 < k) {
+            const double be = coef[2 * j + 1];
+            if (!std::isfinite(be) || be < 0.0) return false;
+            e2[j] = be / (al * al);
+            e[j] = std::sqrt(e2[j]);
+        }
+    }
+    // Gershgorin interval, then bisection on the Sturm count for the two ends
+    double g0 = HUGE_VAL, g1 = -HUGE_VAL, emax2 = 0.0;
+    for (int j = 0; j < k; ++j) {
+        const double r = (j > 0 ? e[j - 1] : 0.0) + (j + 1 < k ? e[j] : 0.0);
+        g0 = std::min(g0, d[j] - r);
+        g1 = std::max(g1, d[j] + r);
+        if (j + 1 < k) emax2 = std::max(emax2, e2[j]);
+    }
+    if (!std::isfinite(g0) || !std::isfinite(g1)) return false;
+    const double span = std::max(std::fabs(g0), std::fabs(g1));
+    const double pivmin = std::max(1e-300, 1e-290 * std::max(1.0, emax2));
+    g0 -= 1e-15 * span + pivmin;
+    g1 += 1e-15 * span + pivmin;
+    auto bisect = [&](int target) {  // smallest x with sturm_below(x) >= target
+        double a = g0, b = g1;
+        for (int it = 0; it < 200; ++it) {
+            const double m = 0.5 * (a + b);
+            if (m <= a || m >= b) break;
+            if (sturm_below(d, e2, m, pivmin) >= target)
+                b = m;
+            else
+                a = m;
+            if (b - a <= 2e-16 * std::max(std::fabs(a), std::fabs(b))) break;
+        }
+        return 0.5 * (a + b);
+    };
+    lo = bisect(1);
+    hi = bisect(k);
+    return std::isfinite(lo) && std::isfinite(hi);
+}
 
 size_t cg_workspace_bytes(int64_t n, int64_t nnz, const cgx_opts *o)
 {

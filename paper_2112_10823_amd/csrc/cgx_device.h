@@ -186,13 +186,16 @@ struct WaveSmem {
 // With a non-null `stop`, *stop is read together with the row starts (its
 // latency hidden behind theirs); if nonzero the tile is skipped: returns 0
 // with row = -1 in every lane.
-template <int E, int RT, int U, typename T>
+// kDiag: *xdiag receives x[row] in all TPR lanes of the row, taken from the
+// gather of the row's diagonal entry (no load of its own), or loaded when
+// the row stores no diagonal.
+template <int E, int RT, int U, typename T, bool kDiag = false>
 __device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t nnz,
                                        const int32_t *__restrict__ rp,
                                        const int32_t *__restrict__ ci,
                                        const T *__restrict__ val, const T *__restrict__ x,
                                        WaveSmem<E, RT, T> &sm, int &row,
-                                       const int *stop = nullptr)
+                                       const int *stop = nullptr, T *xdiag = nullptr)
 {
     constexpr int TPR = kWave / RT;
     constexpr int C = kWave * E;
@@ -220,7 +223,8 @@ __device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t
         s = max(sm.rp[g], k0);
         e = min(max(sm.rp[g + 1], s), k1);
     }
-    T acc = T(0);
+    T acc = T(0), xd = T(0);
+    int seen = 0;
     for (int c0 = k0; c0 < k1; c0 += C) {
         int col[E];
         T a[E];
@@ -258,8 +262,21 @@ __device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t
 #pragma unroll
             for (int u = 0; u < U; ++u) xv[u] = (unsigned)cc[u] < (unsigned)n_cols ? x[cc[u]] : T(0);
 #pragma unroll
-            for (int u = 0; u < U; ++u) acc += vv[u] * xv[u];
+            for (int u = 0; u < U; ++u) {
+                acc += vv[u] * xv[u];
+                if (kDiag && cc[u] == row) {
+                    xd = xv[u];
+                    seen = 1;
+                }
+            }
         }
+    }
+    if (kDiag) {
+        // one lane of the row holds the diagonal's value, the others 0
+        xd = group_sum<TPR>(xd);
+        seen = group_sum<TPR>(seen);
+        if (!seen && (unsigned)row < (unsigned)min(n_rows, n_cols)) xd = x[row];
+        *xdiag = xd;
     }
     return group_sum<TPR>(acc);
 }
@@ -274,12 +291,14 @@ __device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t
 // entries of a row are added in storage order.
 // With a non-null `stop`, *stop is read together with the slice bounds; if
 // nonzero the slice is skipped: returns 0 with row = -1 in every lane.
-template <int U, typename T>
+// kDiag: *xdiag receives x[row], taken from the gather of the row's diagonal
+// entry, or loaded when the row stores no diagonal.
+template <int U, typename T, bool kDiag = false>
 __device__ __forceinline__ T sell_rows(int s, int n_rows, int n_cols,
                                        const int64_t *__restrict__ sp,
                                        const int32_t *__restrict__ col,
                                        const T *__restrict__ val, const T *__restrict__ x,
-                                       int &row, const int *stop = nullptr)
+                                       int &row, const int *stop = nullptr, T *xdiag = nullptr)
 {
     const int halt = stop != nullptr ? *stop : 0;
     const int lane = threadIdx.x % kWave;
@@ -292,7 +311,8 @@ __device__ __forceinline__ T sell_rows(int s, int n_rows, int n_cols,
     }
     const int32_t *c = col + b + lane;
     const T *v = val + b + lane;
-    T acc = T(0);
+    T acc = T(0), xd = T(0);
+    bool seen = false;
     int k = 0;
     for (; k + U <= w; k += U) {
         int cc[U];
@@ -305,13 +325,30 @@ __device__ __forceinline__ T sell_rows(int s, int n_rows, int n_cols,
 #pragma unroll
         for (int u = 0; u < U; ++u) xv[u] = (unsigned)cc[u] < (unsigned)n_cols ? x[cc[u]] : T(0);
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc += vv[u] * xv[u];
+        for (int u = 0; u < U; ++u) {
+            acc += vv[u] * xv[u];
+            if (kDiag && cc[u] == row) {
+                xd = xv[u];
+                seen = true;
+            }
+        }
     }
     // the remainder with ordinary loads: measured faster than non-temporal
     // ones here, and than predicating a last batch of U
     for (; k < w; ++k) {
         const int cc = c[(int64_t)k * kWave];
-        if ((unsigned)cc < (unsigned)n_cols) acc += v[(int64_t)k * kWave] * x[cc];
+        if ((unsigned)cc < (unsigned)n_cols) {
+            const T xv = x[cc];
+            acc += v[(int64_t)k * kWave] * xv;
+            if (kDiag && cc == row) {
+                xd = xv;
+                seen = true;
+            }
+        }
+    }
+    if (kDiag) {
+        if (!seen && (unsigned)row < (unsigned)min(n_rows, n_cols)) xd = x[row];
+        *xdiag = xd;
     }
     return acc;
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -82,23 +83,53 @@ struct CgState {
     int32_t status;// CGX_* status; CGX_PENDING while iterating
     int32_t done;  // nonzero once converged or failed: later kernels return at once
     int32_t bad;   // set by any thread meeting a non-positive / missing diagonal
-    int32_t pad;
+    int32_t rec;   // nonzero: record alpha_j, beta_j of iterations j < kCoefRec
     int32_t pad2[4];
 };
 
-// A captured and instantiated HIP graph plus the key it was built for.
-constexpr int kGraphKey = 14;  // words identifying what a cached graph was captured for
+// CG coefficients recorded per solve (alpha_j, beta_j of the first kCoefRec
+// iterations): they define the Lanczos tridiagonal whose extreme eigenvalues
+// estimate the spectrum of the (preconditioned) operator.
+constexpr int kCoefRec = 4096;
 
+// Extreme eigenvalues of the k x k Lanczos tridiagonal defined by CG
+// coefficients coef[2 j] = alpha_j (j < k), coef[2 j + 1] = beta_j (j < k - 1);
+// false when k = 0 or a coefficient is not finite and positive.
+bool lanczos_extremes(const double *coef, int k, double &lo, double &hi);
+
+// Words identifying what a captured graph bakes in: every kernel argument of
+// the captured launches (pointers, sizes, offsets), the launch shapes and the
+// number of captured iterations.  A cached graph is replayed only when the
+// whole key matches.
+struct GraphKey {
+    std::vector<uint64_t> w;
+    GraphKey &add(uint64_t v)
+    {
+        w.push_back(v);
+        return *this;
+    }
+    GraphKey &ptr(const void *p) { return add((uint64_t)(uintptr_t)p); }
+    GraphKey &f64(double v)
+    {
+        uint64_t b;
+        std::memcpy(&b, &v, sizeof b);
+        return add(b);
+    }
+};
+
+// A captured and instantiated HIP graph plus the key it was built for.
 struct GraphSlot {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    uint64_t key[kGraphKey] = {0};
+    std::vector<uint64_t> key;
+    bool matches(const GraphKey &k) const { return exec != nullptr && key == k.w; }
     void reset()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
+        key.clear();
     }
 };
 
@@ -110,6 +141,7 @@ struct Context {
     int num_cu = 256;
     double *scratch = nullptr;     // device: reduction partials of the standalone calls
     CgState *host_state = nullptr; // pinned host copy of the solver state
+    double *host_scalar = nullptr; // pinned host word for results returned to the host
     hipEvent_t ev0 = nullptr, ev1 = nullptr;      // timing of a solve
     hipEvent_t ev_in = nullptr, ev_out = nullptr; // ordering between the two streams
     hipEvent_t ev_phase[4 * kProfWindow] = {};  // profile mode: 4 per iteration of a window
@@ -120,6 +152,7 @@ struct Context {
     // batched-SpMM autotuner: (K, mean row length, log2 rows) -> slice count M
     std::mutex tune_mu;
     std::map<std::tuple<int, int, int>, int> batch_tune;
+    int fail_tune = 0;  // test hook: the next fail_tune tuning calls fail (under tune_mu)
     struct Engine *engine = nullptr;  // solve server, while running
 };
 

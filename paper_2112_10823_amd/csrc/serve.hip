@@ -462,9 +462,11 @@ void engine_loop(Engine *Ep)
             sys.nrhs = sl.K;
             int M = 1;
             if (tune_one(E.c, sys, E.pool + sl.off, sl.bytes, E.stream, M) != CGX_OK) {
+                // every waiter wakes and every unfinished ticket reports the failure
                 std::lock_guard<std::mutex> lk(E.mu);
                 E.fail = CGX_EHIP;
                 E.fail_msg = "autotuning failed";
+                E.cv_done.notify_all();
                 return;
             }
             sl.M = M;

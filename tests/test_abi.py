@@ -49,7 +49,7 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {{
   printf("%zu %zu %zu %zu\\n", sizeof(cgx_csr), offsetof(cgx_csr, row_ptr), offsetof(cgx_csr, val32), offsetof(cgx_csr, nnz));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(cgx_opts), offsetof(cgx_opts, inner_rtol), offsetof(cgx_opts, max_outer), offsetof(cgx_opts, true_residual), offsetof(cgx_opts, profile));
-  printf("%zu %zu %zu %zu\\n", sizeof(cgx_stats), offsetof(cgx_stats, relres), offsetof(cgx_stats, device_ms), offsetof(cgx_stats, phase_ms));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(cgx_stats), offsetof(cgx_stats, relres), offsetof(cgx_stats, device_ms), offsetof(cgx_stats, phase_ms), offsetof(cgx_stats, kappa_est), offsetof(cgx_stats, ritz_max));
   printf("%zu %zu %zu %zu\\n", sizeof(cgx_sell), offsetof(cgx_sell, n_slices), offsetof(cgx_sell, slice_ptr), offsetof(cgx_sell, val32));
   printf("%zu %zu %zu\\n", sizeof(cgx_system), offsetof(cgx_system, schedule), offsetof(cgx_system, X));
   printf("%zu %zu %zu %zu\\n", sizeof(cgx_schwarz), offsetof(cgx_schwarz, local_rows), offsetof(cgx_schwarz, nnz_off), offsetof(cgx_schwarz, val));
@@ -64,7 +64,8 @@ int main(void) {{
     assert c[0] == [ctypes.sizeof(S), S.row_ptr.offset, S.val32.offset, S.nnz.offset]
     assert c[1] == [ctypes.sizeof(O), O.inner_rtol.offset, O.max_outer.offset, O.true_residual.offset,
                     O.profile.offset]
-    assert c[2] == [ctypes.sizeof(T), T.relres.offset, T.device_ms.offset, T.phase_ms.offset]
+    assert c[2] == [ctypes.sizeof(T), T.relres.offset, T.device_ms.offset, T.phase_ms.offset,
+                    T.kappa_est.offset, T.ritz_max.offset]
     L, Y = cgx._Sell, cgx._System
     assert c[3] == [ctypes.sizeof(L), L.n_slices.offset, L.slice_ptr.offset, L.val32.offset]
     assert c[4] == [ctypes.sizeof(Y), Y.schedule.offset, Y.X.offset]
@@ -181,3 +182,79 @@ def test_from_host_checks_sizes_before_copying():
     ok = synth.CSR(A.n_rows, A.n_cols, A.row_ptr.astype(np.int64), A.col_idx.astype(np.int64), A.val)
     d = cgx.DeviceCSR.from_host(ok, device="cpu", validate=False)
     assert np.array_equal(d.row_ptr.numpy(), A.row_ptr) and np.array_equal(d.col_idx.numpy(), A.col_idx)
+
+
+def test_batch_workspace_bytes_rejects_bad_descriptors():
+    """The batched size queries validate the descriptor sizes they lay out
+    (host code, no GPU): a non-square matrix, an empty system, nnz out of
+    range or nrhs outside [1, 16] give 0; a valid batch a positive size."""
+    lib = cgx.load_library()
+
+    def sys(n=100, m=100, nnz=500, nrhs=4):
+        y = cgx._System()
+        y.A = cgx._Csr(n, m, nnz, 256, 512, 768, None)
+        y.nrhs = nrhs
+        y.schedule = 0
+        y.B = 1024
+        y.X = 2048
+        return y
+
+    for q in (cgx.load_library().cgx_batch_workspace_bytes,
+              cgx.load_library().cgx_batch_mixed_workspace_bytes):
+        good = (cgx._System * 2)(sys(), sys(n=50, m=50, nnz=200, nrhs=16))
+        assert q(2, good) > 0
+        for bad in (sys(m=99), sys(n=0, m=0), sys(nnz=-1), sys(nnz=1 << 31), sys(nrhs=0),
+                    sys(nrhs=17)):
+            arr = (cgx._System * 2)(sys(), bad)
+            assert q(2, arr) == 0
+        assert q(0, good) == 0
+    assert lib.cgx_batch_workspace_bytes(1, None) == 0
+
+
+def test_lanczos_extremes_host():
+    """The library's Ritz-value routine (host C++ behind cgx_stats.kappa_est)
+    against the oracle's dense eigvalsh of the same Lanczos tridiagonal: on
+    the oracle's own CG coefficients of the 7-point 16^3 solve (whose
+    extremes are the analytic spectrum ends) and on random positive
+    coefficient sequences; non-positive alpha is refused."""
+    import numpy as np
+    import oracle
+    import synth
+    lib = cgx.load_library()
+    fn = getattr(lib, "_ZN3cgx16lanczos_extremesEPKdiRdS2_")
+    fn.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    fn.restype = ctypes.c_bool
+
+    def ext(alpha, beta):
+        k = len(alpha)
+        coef = np.zeros(2 * k)
+        coef[0::2] = alpha
+        coef[1:2 * k - 1:2] = beta[:k - 1]
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        ok = fn(coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), k, ctypes.byref(lo),
+                ctypes.byref(hi))
+        return ok, lo.value, hi.value
+
+    N = 16
+    A = synth.fd7(N)
+    xs = synth.uniform(0, A.n_rows, -1.0, 1.0)
+    b = oracle.spmv(A, xs)
+    ref = oracle.cg(A, b, rtol=1e-10, history=True)
+    ok, lo, hi = ext(ref.alpha, ref.beta)
+    rlo, rhi = oracle.lanczos_extremes(ref.alpha, ref.beta)
+    assert ok
+    assert abs(lo - rlo) <= 1e-12 * rhi and abs(hi - rhi) <= 1e-12 * rhi
+    th = np.pi / (N + 1)
+    lmin, lmax = 12 * np.sin(th / 2) ** 2, 12 * np.sin(N * th / 2) ** 2
+    assert abs(lo - lmin) <= 1e-8 * lmax and abs(hi - lmax) <= 1e-8 * lmax
+    rng = np.random.default_rng(7)
+    for k in (1, 2, 3, 17, 200):
+        al = rng.uniform(0.1, 2.0, k)
+        be = rng.uniform(0.0, 1.5, k)
+        ok, lo, hi = ext(al, be)
+        rlo, rhi = oracle.lanczos_extremes(al, be[:k - 1])
+        assert ok
+        assert abs(lo - rlo) <= 1e-11 * abs(rhi) and abs(hi - rhi) <= 1e-11 * abs(rhi)
+    ok, _, _ = ext(np.array([1.0, -0.5]), np.array([0.3, 0.0]))
+    assert not ok

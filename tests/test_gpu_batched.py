@@ -168,3 +168,33 @@ def test_batched_64_systems_16_rhs_full_size():
             b = items[s][1][j].cpu().numpy()
             x = items[s][2][j].cpu().numpy()
             assert true_relres(mats[s], b, x) <= 1.5e-8
+
+
+@pytest.mark.parametrize("schedule", [2, 4])
+def test_batched_graph_reused_only_for_same_layout(schedule):
+    """Regression for the cached iteration graph: the same matrices, B / X
+    pointers, workspace, schedule and replay length with 4 and then 16
+    right-hand sides give equal tile counts but another scalar and partial
+    layout, so the second solve must capture its own graph.  Both runs are
+    checked against the oracle (and a rerun with 4 reuses the first layout)."""
+    mats = [synth.q1cube(9, 1.0, 41), synth.fd7_var(8, 1.0, 42)]
+    B16 = [np.stack([synth.uniform(5000 + 31 * s + j, A.n_rows) for j in range(16)])
+           for s, A in enumerate(mats)]
+    dA = [cgx.DeviceCSR.from_host(A) for A in mats]
+    dB = [dev(B) for B in B16]
+    dX = [torch.zeros_like(B) for B in dB]
+    full = [(dA[s], dB[s], dX[s], schedule) for s in range(2)]
+    ws = cgx.batch_workspace(full)
+    opts = cgx.make_opts(rtol=1e-9, precond=1, check_every=4)
+    for k in (4, 16, 4):
+        for X in dX:
+            X.zero_()
+        items = [(dA[s], dB[s][:k], dX[s][:k], schedule) for s in range(2)]
+        st = cgx.cg_solve_batched(items, opts, workspace=ws)
+        for s, A in enumerate(mats):
+            X = dX[s][:k].cpu().numpy()
+            for j in range(k):
+                ref = oracle.cg(A, B16[s][j], rtol=1e-9, jacobi=True)
+                assert st[s][j].status == cgx.OK, (k, s, j, st[s][j].as_dict())
+                assert abs(st[s][j].iters - ref.iters) <= 2, (k, s, j, st[s][j].iters, ref.iters)
+                assert true_relres(A, B16[s][j], X[j]) <= 1.5e-9, (k, s, j)

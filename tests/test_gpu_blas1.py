@@ -135,3 +135,27 @@ def test_demote_round_to_nearest():
     x = specials(20001, 8)
     assert same_bits(cgx.demote(dev(x)).cpu().numpy().astype(np.float64),
                      x.astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("n", [0, 1, 4096, 1000003])
+def test_dot_sync_equals_dot(n):
+    """cgx_dot_sync returns to the host exactly the bits cgx_dot writes to the
+    device, and is within the dot bar of the oracle's compensated sum."""
+    x = synth.uniform(31, n)
+    y = synth.uniform(32, n)
+    dx, dy = dev(x), dev(y)
+    ds = cgx.dot_sync(dx, dy)
+    dd = cgx.dot(dx, dy).item()
+    assert np.float64(ds).view(np.int64) == np.float64(dd).view(np.int64)
+    if n:
+        ref = oracle.dot(x, y)
+        assert abs(ds - ref) <= 1e-13 * max(abs(ref), 1e-3 * float(np.sum(np.abs(x * y))))
+    else:
+        assert ds == 0.0
+
+
+def test_dot_sync_integer_exact():
+    rng = np.random.default_rng(5)
+    x = rng.integers(-1000, 1000, 100000).astype(np.float64)
+    y = rng.integers(-1000, 1000, 100000).astype(np.float64)
+    assert cgx.dot_sync(dev(x), dev(y)) == float(np.dot(x.astype(np.int64), y.astype(np.int64)))

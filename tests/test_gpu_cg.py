@@ -241,3 +241,76 @@ def test_q1_128_jacobi_full_size_true_residual():
     assert tr <= 1.5e-8
     assert abs(st.relres_true - tr) <= 1e-2 * tr
     assert 100 < st.iters < 2000
+
+
+# ------------------------------------------- condition estimate (kappa_est) --
+
+def fd7_extremes(N):
+    th = math.pi / (N + 1)
+    return 12 * math.sin(th / 2) ** 2, 12 * math.sin(N * th / 2) ** 2
+
+
+@pytest.mark.parametrize("N,jacobi", [(16, False), (16, True), (24, False), (24, True)])
+def test_kappa_est_fd7(N, jacobi):
+    """Ritz extremes of the Lanczos tridiagonal from the GPU's recorded CG
+    coefficients (Saad 6.7.3) against the oracle's own coefficients and the
+    analytic spectrum ends of the 7-point operator (D = 6 I, so Jacobi leaves
+    the spectrum scaled by 1/6).  16^3 runs the single-workgroup kernel, 24^3
+    the phase kernels in a HIP graph."""
+    A = synth.fd7(N)
+    xs = synth.uniform(synth.SEED_C1_XSTAR, A.n_rows)
+    b = oracle.spmv(A, xs)
+    rtol = 1e-10
+    ref = oracle.cg(A, b, rtol=rtol, jacobi=jacobi, history=True)
+    rlo, rhi = oracle.lanczos_extremes(ref.alpha, ref.beta)
+    st, _ = solve(A, b, rtol=rtol, precond=cgx.PRECOND_JACOBI if jacobi else cgx.PRECOND_NONE)
+    assert st.status == cgx.OK and st.path == (1 if N == 16 else 0)
+    lo, hi = fd7_extremes(N)
+    if jacobi:
+        lo, hi = lo / 6, hi / 6
+    assert abs(st.ritz_min - rlo) <= 1e-8 * rhi and abs(st.ritz_max - rhi) <= 1e-8 * rhi
+    assert abs(st.ritz_min - lo) <= 1e-6 * hi and abs(st.ritz_max - hi) <= 1e-6 * hi
+    assert abs(st.kappa_est - hi / lo) <= 1e-6 * hi / lo
+    if N == 16:
+        assert abs(st.kappa_est - 116.46) < 0.01
+
+
+def test_kappa_est_q1_lognormal_inside_spectrum():
+    """Q1 with lognormal coefficients (no closed form): the GPU's Ritz
+    extremes equal the oracle's from its own coefficients, and they lie
+    inside [lambda_min, lambda_max] of D^-1 A (dense eigenvalues)."""
+    N = 12
+    A = synth.q1cube(N, sigma=1.0, seed=synth.SEED_C2_COEFF)
+    b = synth.uniform(3, A.n_rows)
+    ref = oracle.cg(A, b, rtol=1e-10, jacobi=True, history=True)
+    rlo, rhi = oracle.lanczos_extremes(ref.alpha, ref.beta)
+    st, _ = solve(A, b, rtol=1e-10, precond=cgx.PRECOND_JACOBI)
+    assert st.status == cgx.OK
+    assert abs(st.ritz_min - rlo) <= 1e-7 * rhi and abs(st.ritz_max - rhi) <= 1e-7 * rhi
+    D = np.zeros((A.n_rows, A.n_rows))
+    for i in range(A.n_rows):
+        D[i, A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]]] = A.val[A.row_ptr[i]:A.row_ptr[i + 1]]
+    d = np.sqrt(np.diag(D))
+    ev = np.linalg.eigvalsh(D / d[:, None] / d[None, :])
+    assert ev[0] * (1 - 1e-10) <= st.ritz_min and st.ritz_max <= ev[-1] * (1 + 1e-10)
+
+
+def test_kappa_est_mixed_first_inner_solve():
+    """MIXED records the first refinement step's binary32 inner coefficients:
+    their Ritz values lie inside the spectrum (binary32 rounding aside)."""
+    N = 20
+    A = synth.fd7(N)
+    b = synth.uniform(4, A.n_rows)
+    dA = cgx.DeviceCSR.from_host(A, with_f32=True)
+    dx = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    st = cgx.cg_solve(dA, dev(b), dx, cgx.make_opts(rtol=1e-10, precision=cgx.PRECISION_MIXED,
+                                                     inner_rtol=1e-3))
+    assert st.status == cgx.OK and st.kappa_est > 1.0
+    lo, hi = fd7_extremes(N)
+    assert lo * (1 - 1e-4) <= st.ritz_min <= st.ritz_max <= hi * (1 + 1e-4)
+
+
+def test_kappa_est_zero_rhs():
+    A = synth.fd7(6)
+    st, x = solve(A, np.zeros(A.n_rows), rtol=1e-10)
+    assert st.status == cgx.OK and st.iters == 0 and st.kappa_est == 0.0
