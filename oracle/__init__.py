@@ -50,6 +50,7 @@ class SolveResult:
     relres_true: float
     alpha: np.ndarray | None = None
     beta: np.ndarray | None = None
+    relres_hist: np.ndarray | None = None  # ||r_k|| / ||b||, k = 0 .. iters
 
 
 def _load():
@@ -77,7 +78,8 @@ def _load():
         lib.oracle_inv_diag.argtypes = [i64, i32p, i32p, f64p, f64p]
         lib.oracle_inv_diag.restype = i64
         lib.oracle_cg.argtypes = [i64, i32p, i32p, f64p, f64p, f64p, dbl, i32, i32,
-                                  ctypes.POINTER(_Stats), ctypes.c_void_p, ctypes.c_void_p]
+                                  ctypes.POINTER(_Stats), ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]
         lib.oracle_cg.restype = ctypes.c_int
         lib.oracle_mixed_ir.argtypes = [i64, i32p, i32p, f64p, f32p, f64p, f64p, dbl, dbl, i32,
                                         i32, i32, ctypes.POINTER(_Stats)]
@@ -177,13 +179,16 @@ def cg(A, b, x0=None, rtol=1e-8, maxit=0, jacobi=False, history=False) -> SolveR
     cap = maxit if maxit > 0 else A.n_rows
     ah = np.zeros(max(cap, 1)) if history else None
     bh = np.zeros(max(cap, 1)) if history else None
+    rh = np.full(max(cap, 1) + 1, np.nan) if history else None
     _load().oracle_cg(A.n_rows, _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val), b, x, float(rtol),
                       int(maxit), int(bool(jacobi)), ctypes.byref(st),
-                      ah.ctypes.data if history else None, bh.ctypes.data if history else None)
+                      ah.ctypes.data if history else None, bh.ctypes.data if history else None,
+                      rh.ctypes.data if history else None)
     res = SolveResult(x, st.status, st.iters, 0, st.relres, st.relres_true)
     if history:
         res.alpha = ah[:st.iters].copy()
         res.beta = bh[:max(st.iters - 1, 0)].copy()
+        res.relres_hist = rh[:st.iters + 1].copy()
     return res
 
 

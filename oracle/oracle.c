@@ -187,10 +187,13 @@ int64_t oracle_inv_diag(int64_t n, const int32_t *rp, const int32_t *ci, const d
  *     beta = rho_{k+1} / rho_k,  p_{k+1} = z + beta p_k
  * b = 0 returns x = 0 after 0 iterations.  maxit <= 0 means n.
  * alpha_hist / beta_hist (length >= maxit, nullable) receive the coefficients
- * of every completed iteration (beta of the last one is not formed). */
+ * of every completed iteration (beta of the last one is not formed).
+ * res_hist (length >= maxit + 1, nullable) receives ||r_k|| / ||b|| of the
+ * recursively updated residual for k = 0 .. iters (output only: the values
+ * the stopping test compares). */
 int oracle_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *val,
               const double *b, double *x, double rtol, int32_t maxit, int32_t jacobi,
-              oracle_stats *st, double *alpha_hist, double *beta_hist)
+              oracle_stats *st, double *alpha_hist, double *beta_hist, double *res_hist)
 {
     memset(st, 0, sizeof(*st));
     if (maxit <= 0) maxit = (int32_t)(n > 0x7fffffff ? 0x7fffffff : n);
@@ -220,6 +223,7 @@ int oracle_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *val
     memcpy(p, z, (size_t)n * sizeof(double));
     double rho = oracle_dot(n, r, z);
     rr = jacobi ? oracle_dot(n, r, r) : rho;
+    if (res_hist) res_hist[0] = sqrt(rr) / bnorm;
     if (!isfinite(rr)) { status = ORC_NONFINITE; goto done; }
     if (sqrt(rr) <= rtol * bnorm) { status = ORC_OK; goto done; }
 
@@ -236,6 +240,7 @@ int oracle_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *val
         rr = jacobi ? oracle_dot(n, r, r) : rho_new;
         if (alpha_hist) alpha_hist[k] = alpha;
         ++k;
+        if (res_hist) res_hist[k] = sqrt(rr) / bnorm;
         if (!isfinite(rr) || !isfinite(rho_new)) { status = ORC_NONFINITE; break; }
         if (sqrt(rr) <= rtol * bnorm) { status = ORC_OK; break; }
         if (!(rho_new > 0.0)) { status = ORC_BREAKDOWN; break; }

@@ -491,3 +491,75 @@ def test_degenerate_systems():
         assert r.status == oracle.OK and r.iters == 1 and r.x[0] == 0.75
     ir = oracle.mixed_ir(A1, np.array([4.0], np.float32), b, rtol=1e-14)
     assert ir.status == oracle.OK and ir.outer_iters == 1 and ir.iters == 1 and ir.x[0] == 0.75
+
+
+# ------------------------------------------------- CG residual history --
+
+def _exact_cg_residuals(Ad, b, iters, jacobi):
+    """CG (Saad's recurrences, the paper's cited textbook) carried out in exact
+    rational arithmetic on an integer matrix: ||r_k|| / ||b|| for k = 0..iters."""
+    n = len(b)
+    A = [[Fraction(int(v)) for v in row] for row in Ad]
+    dinv = [Fraction(1) / A[i][i] if jacobi else Fraction(1) for i in range(n)]
+    r = [Fraction(int(v)) for v in b]
+    z = [dinv[i] * r[i] for i in range(n)]
+    p = list(z)
+    rho = sum(ri * zi for ri, zi in zip(r, z))
+    bb = sum(v * v for v in r)
+    out = [1.0]
+    for _ in range(iters):
+        q = [sum(A[i][j] * p[j] for j in range(n)) for i in range(n)]
+        alpha = rho / sum(pi * qi for pi, qi in zip(p, q))
+        r = [ri - alpha * qi for ri, qi in zip(r, q)]
+        rr = sum(v * v for v in r)
+        out.append(math.sqrt(rr / bb))
+        if rr == 0:
+            break
+        z = [dinv[i] * r[i] for i in range(n)]
+        rho_new = sum(ri * zi for ri, zi in zip(r, z))
+        p = [zi + (rho_new / rho) * pi for zi, pi in zip(z, p)]
+        rho = rho_new
+    return out
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_cg_residual_history_exact_rational(jacobi):
+    """The recorded ||r_k|| / ||b|| of every step against CG in exact rational
+    arithmetic on a small integer SPD system (a well-conditioned case, so
+    finite precision follows the exact iterates closely); the last entry is
+    the reported relres, at or below rtol, and the one before it above."""
+    rng = np.random.default_rng(11)
+    n = 8
+    M = rng.integers(-3, 4, (n, n))
+    Ad = M @ M.T + np.diag(rng.integers(4, 12, n))
+    rp = np.arange(0, n * n + 1, n, dtype=np.int32)
+    ci = np.tile(np.arange(n, dtype=np.int32), n)
+    A = CSR(n, n, rp, ci, Ad.astype(np.float64).ravel())
+    b = rng.integers(-5, 6, n).astype(np.float64)
+    rtol = 1e-10
+    res = oracle.cg(A, b, rtol=rtol, jacobi=jacobi, history=True)
+    h = res.relres_hist
+    assert res.status == oracle.OK and len(h) == res.iters + 1
+    exact = _exact_cg_residuals(Ad, b, res.iters, jacobi)
+    assert h[0] == 1.0
+    for k in range(1, res.iters):
+        assert abs(h[k] - exact[k]) <= 1e-9 * max(exact[k], 1e-6), (k, h[k], exact[k])
+    assert h[-1] == res.relres and h[-1] <= rtol < h[-2]
+
+
+def test_cg_residual_history_plain_matches_coefficients():
+    """Plain CG: ||r_k||^2 = rho_k = rho_0 * beta_0 ... beta_{k-1} (beta_j =
+    rho_{j+1} / rho_j), so the history and the coefficient record agree; the
+    manufactured eigenvector's history is [1, ~0]."""
+    N = 12
+    A = synth.fd7(N)
+    b = synth.uniform(21, A.n_rows)
+    res = oracle.cg(A, b, rtol=1e-9, history=True)
+    h = res.relres_hist
+    prod = np.concatenate([[1.0], np.cumprod(res.beta)])
+    np.testing.assert_allclose(h[:-1] ** 2, prod, rtol=1e-12)
+    i = np.arange(1, N + 1)
+    v = np.einsum("k,j,i->kji", *[np.sin(j * math.pi * i / (N + 1)) for j in (4, 2, 1)]).ravel()
+    lam = sum(4 * math.sin(j * math.pi / (2 * (N + 1))) ** 2 for j in (1, 2, 4))
+    e = oracle.cg(A, lam * v, rtol=1e-12, history=True)
+    assert e.iters == 1 and e.relres_hist[0] == 1.0 and e.relres_hist[1] < 1e-13
