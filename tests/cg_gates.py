@@ -1,0 +1,49 @@
+"""Gates on where a GPU CG run stopped, derived from the oracle alone.
+
+Two correct finite-precision CG runs on the same system stop at the first
+step whose own recursive residual ||r_k|| / ||b|| is at or below rtol.  Their
+residual histories are not equal: each rounding order perturbs the recurrences
+(CG's residual norm is not even monotone), so the crossing can move by a few
+steps.  How far depends on the system, not on any kernel: the oracle measures
+it by running the same CG on the reversed-order system P A P^T, P b (exact in
+exact arithmetic, every sum in another order).  If the oracle's two histories
+differ at the same step by at most a factor (1 + delta), a third correct run
+(the GPU's) differs from the oracle's by at most F = (1 + delta)^2 (each
+deviates from the exact history by up to (1 + delta)).  At the GPU's stopping
+step k the oracle's residual must then satisfy h[k] <= F rtol, and at the
+step before h[k - 1] > rtol / F.
+"""
+import numpy as np
+
+import oracle
+from synth import CSR
+
+
+def reversed_system(A, b):
+    """P A P^T and P b for the reversal permutation i -> n - 1 - i (rows and
+    the entries inside each row in reverse order)."""
+    n = A.n_rows
+    rp = np.asarray(A.row_ptr, np.int64)
+    lens = np.diff(rp)[::-1]
+    new_rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = (n - 1 - np.asarray(A.col_idx, np.int64))[::-1].astype(np.int32)
+    val = np.asarray(A.val)[::-1].copy()
+    return CSR(n, n, new_rp, ci, val), np.asarray(b)[::-1].copy()
+
+
+def residual_band(A, b, rtol, jacobi=False):
+    """The oracle's residual history h (run past rtol, to rtol / 100) and the
+    band factor F = (1 + delta)^2 from its reversed-order run."""
+    h = oracle.cg(A, b, rtol=rtol / 100, jacobi=jacobi, history=True).relres_hist
+    Ar, br = reversed_system(A, b)
+    hr = oracle.cg(Ar, br, rtol=rtol / 100, jacobi=jacobi, history=True).relres_hist
+    m = min(len(h), len(hr))
+    ratio = hr[:m] / h[:m]
+    delta = float(np.max(np.maximum(ratio, 1.0 / ratio)) - 1.0)
+    return h, (1.0 + delta) ** 2
+
+
+def assert_stop_in_band(h, F, k, rtol, what=""):
+    assert 1 <= k < len(h), (what, k, len(h))
+    assert h[k] <= F * rtol, (what, k, h[k] / rtol, F)
+    assert h[k - 1] > rtol / F, (what, k, h[k - 1] / rtol, F)
