@@ -29,7 +29,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_lib = None
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")  # timing build (all cores)
+_libs: dict = {}
 
 OK, EINVAL, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, -1, -4, -5, -6
 
@@ -53,13 +54,12 @@ class SolveResult:
     relres_hist: np.ndarray | None = None  # ||r_k|| / ||b||, k = 0 .. iters
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+def _load(path: str = _LIB_PATH):
+    if path not in _libs:
+        if not os.path.exists(path):
             from . import build as _b
             _b.build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        lib = ctypes.CDLL(path)
         i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
         f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
@@ -84,8 +84,15 @@ def _load():
         lib.oracle_mixed_ir.argtypes = [i64, i32p, i32p, f64p, f32p, f64p, f64p, dbl, dbl, i32,
                                         i32, i32, ctypes.POINTER(_Stats)]
         lib.oracle_mixed_ir.restype = ctypes.c_int
-        _lib = lib
-    return _lib
+        for name, lp in (("oracle_mixed_ru", f32p), ("oracle_mixed_ru_f64", f64p)):
+            fn = getattr(lib, name)
+            fn.argtypes = [i64, i32p, i32p, f64p, lp, f64p, f64p, dbl, dbl, i32, i32,
+                           ctypes.POINTER(_Stats), ctypes.c_void_p]
+            fn.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
+        _libs[path] = lib
+    return _libs[path]
 
 
 def _f64(a):
@@ -171,6 +178,24 @@ def inv_diag(A):
     return d
 
 
+def timing_threads() -> int:
+    """Threads of the all-cores timing build (OpenMP; OMP_NUM_THREADS applies)."""
+    return int(_load(_OMP_PATH).oracle_threads())
+
+
+def cg_timing(A, b, rtol=1e-8, maxit=0, jacobi=False) -> SolveResult:
+    """The same CG from the all-cores timing build of oracle.c (rows and
+    elements in parallel, per-thread compensated dot partials): for the CPU
+    baseline's timing only, never for parity."""
+    b = _f64(b)
+    x = np.zeros(A.n_rows)
+    st = _Stats()
+    _load(_OMP_PATH).oracle_cg(A.n_rows, _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val), b, x,
+                               float(rtol), int(maxit), int(bool(jacobi)), ctypes.byref(st),
+                               None, None, None)
+    return SolveResult(x, st.status, st.iters, 0, st.relres, st.relres_true)
+
+
 def cg(A, b, x0=None, rtol=1e-8, maxit=0, jacobi=False, history=False) -> SolveResult:
     """Classical (optionally Jacobi-preconditioned) CG; see oracle.c."""
     b = _f64(b)
@@ -188,6 +213,34 @@ def cg(A, b, x0=None, rtol=1e-8, maxit=0, jacobi=False, history=False) -> SolveR
     if history:
         res.alpha = ah[:st.iters].copy()
         res.beta = bh[:max(st.iters - 1, 0)].copy()
+        res.relres_hist = rh[:st.iters + 1].copy()
+    return res
+
+
+def mixed_ru(A, val32, b, x0=None, rtol=1e-10, delta=0.1, maxit=0, jacobi=False,
+             history=False, inner_f64=False) -> SolveResult:
+    """CG iterating in binary32 with float64 reliable updates (the true
+    residual, the solution and the stopping test in float64, the Krylov space
+    kept across updates); see mixed_ru.inc.  outer_iters = reliable updates.
+    inner_f64: the same steps iterating in float64 (val32 ignored), for tests."""
+    b = _f64(b)
+    x = np.zeros(A.n_rows) if x0 is None else _f64(x0).copy()
+    st = _Stats()
+    cap = maxit if maxit > 0 else A.n_rows
+    rh = np.full(cap + 1, np.nan) if history else None
+    lib = _load()
+    if inner_f64:
+        lib.oracle_mixed_ru_f64(A.n_rows, _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val),
+                                _f64(A.val), b, x, float(rtol), float(delta), int(maxit),
+                                int(bool(jacobi)), ctypes.byref(st),
+                                rh.ctypes.data if history else None)
+    else:
+        lib.oracle_mixed_ru(A.n_rows, _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val),
+                            _f32(val32), b, x, float(rtol), float(delta), int(maxit),
+                            int(bool(jacobi)), ctypes.byref(st),
+                            rh.ctypes.data if history else None)
+    res = SolveResult(x, st.status, st.iters, st.outer_iters, st.relres, st.relres_true)
+    if history:
         res.relres_hist = rh[:st.iters + 1].copy()
     return res
 

@@ -31,6 +31,27 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Timing build only (gcc -fopenmp, used for the all-cores CPU baseline): the
+ * row and element loops run in parallel, each row / element computed as
+ * below; the compensated dot then sums per-thread partials.  The default
+ * build (no -fopenmp) ignores these and is the sequential code as written. */
+#ifdef _OPENMP
+#include <omp.h>
+#define ORC_PARALLEL_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define ORC_PARALLEL_FOR
+#endif
+
+/* Threads the timing build runs with (1 for the default build). */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 enum {
     ORC_OK = 0,
     ORC_EINVAL = -1,
@@ -73,32 +94,65 @@ int64_t oracle_csr_check(int64_t n_rows, int64_t n_cols, int64_t nnz, const int3
 
 void oracle_add(int64_t n, const double *x, const double *y, double *z)
 {
+    ORC_PARALLEL_FOR
     for (int64_t i = 0; i < n; ++i) z[i] = x[i] + y[i];
 }
 
 void oracle_axpy(int64_t n, double alpha, const double *x, double *y)
 {
+    ORC_PARALLEL_FOR
     for (int64_t i = 0; i < n; ++i) y[i] = fma(alpha, x[i], y[i]);
 }
 
 void oracle_xmul(int64_t n, const double *x, const double *y, double *z)
 {
+    ORC_PARALLEL_FOR
     for (int64_t i = 0; i < n; ++i) z[i] = x[i] * y[i];
 }
 
 /* ------------------------------------------------------------------ dot -- */
 
 /* Kahan-compensated sum of the rounded products x_i*y_i, in index order. */
-double oracle_dot(int64_t n, const double *x, const double *y)
+static double kahan_dot(int64_t i0, int64_t i1, const double *x, const double *y)
 {
     double s = 0.0, c = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = i0; i < i1; ++i) {
         double t = x[i] * y[i] - c;
         double u = s + t;
         c = (u - s) - t;
         s = u;
     }
     return s;
+}
+
+double oracle_dot(int64_t n, const double *x, const double *y)
+{
+#ifdef _OPENMP
+    /* timing build: a compensated sum per thread over contiguous index
+     * ranges, the partials then added in thread order with compensation */
+    enum { kMaxThreads = 1024 };
+    double part[kMaxThreads];
+    int nt = omp_get_max_threads();
+    if (nt > kMaxThreads) nt = kMaxThreads;
+#pragma omp parallel num_threads(nt)
+    {
+        const int t = omp_get_thread_num(), T = omp_get_num_threads();
+        part[t] = kahan_dot(n * t / T, n * (t + 1) / T, x, y);
+#pragma omp barrier
+#pragma omp single
+        nt = T;
+    }
+    double s = 0.0, c = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        double v = part[t] - c;
+        double u = s + v;
+        c = (u - s) - v;
+        s = u;
+    }
+    return s;
+#else
+    return kahan_dot(0, n, x, y);
+#endif
 }
 
 /* The same compensated sum carried out entirely in binary32. */
@@ -121,6 +175,7 @@ float oracle_dot_f32(int64_t n, const float *x, const float *y)
 void oracle_spmv(int64_t n_rows, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
                  const double *x, double *y)
 {
+    ORC_PARALLEL_FOR
     for (int64_t i = 0; i < n_rows; ++i) {
         double s = 0.0;
         for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) s = s + val[k] * x[col_idx[k]];
@@ -217,6 +272,7 @@ int oracle_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *val
     if (jacobi && oracle_inv_diag(n, rp, ci, val, dinv) != 0) { status = ORC_BREAKDOWN; goto done; }
 
     oracle_spmv(n, rp, ci, val, x, q);
+    ORC_PARALLEL_FOR
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
     have_r = 1;
     if (jacobi) oracle_xmul(n, dinv, r, z);
@@ -247,6 +303,7 @@ int oracle_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *val
         double beta = rho_new / rho;
         if (beta_hist) beta_hist[k - 1] = beta;
         rho = rho_new;
+        ORC_PARALLEL_FOR
         for (int64_t i = 0; i < n; ++i) p[i] = fma(beta, p[i], z[i]);
     }
 
@@ -371,3 +428,37 @@ int oracle_mixed_ir(int64_t n, const int32_t *rp, const int32_t *ci, const doubl
     free(dinv32);
     return status;
 }
+
+/* --------------------------- mixed precision with reliable updates -- */
+
+/* oracle_mixed_ru: the method, iteration in binary32 (val_lp = val32). */
+#define RU_T float
+#define RU_NAME oracle_mixed_ru
+#define RU_DOT oracle_dot_f32
+#define RU_SPMV oracle_spmv_f32
+#define RU_FMA fmaf
+#define RU_SQRT sqrtf
+#include "mixed_ru.inc"
+#undef RU_T
+#undef RU_NAME
+#undef RU_DOT
+#undef RU_SPMV
+#undef RU_FMA
+#undef RU_SQRT
+
+/* oracle_mixed_ru_f64: the same steps with a float64 iteration (val_lp = val),
+ * for the tests: in exact arithmetic the method is CG, so with float64
+ * everywhere it must follow float64 CG. */
+#define RU_T double
+#define RU_NAME oracle_mixed_ru_f64
+#define RU_DOT oracle_dot
+#define RU_SPMV oracle_spmv
+#define RU_FMA fma
+#define RU_SQRT sqrt
+#include "mixed_ru.inc"
+#undef RU_T
+#undef RU_NAME
+#undef RU_DOT
+#undef RU_SPMV
+#undef RU_FMA
+#undef RU_SQRT

@@ -563,3 +563,98 @@ def test_cg_residual_history_plain_matches_coefficients():
     lam = sum(4 * math.sin(j * math.pi / (2 * (N + 1))) ** 2 for j in (1, 2, 4))
     e = oracle.cg(A, lam * v, rtol=1e-12, history=True)
     assert e.iters == 1 and e.relres_hist[0] == 1.0 and e.relres_hist[1] < 1e-13
+
+
+# ---------------------------- mixed precision with reliable updates --
+
+def _dense_of(A):
+    D = np.zeros((A.n_rows, A.n_cols))
+    for i in range(A.n_rows):
+        s, e = A.row_ptr[i], A.row_ptr[i + 1]
+        D[i, A.col_idx[s:e]] = A.val[s:e]
+    return D
+
+
+@pytest.mark.parametrize("delta", [0.3, 1e-2])
+@pytest.mark.parametrize("case", ["fd7_plain", "q1_jacobi", "fd7var_jacobi"])
+def test_mixed_ru_float64_steps_are_cg(case, delta):
+    """In exact arithmetic the reliable-update method is CG (the replaced
+    residual equals the recursive one, the rescaled beta is CG's beta).  Its
+    steps carried out in float64 therefore follow float64 CG: the same
+    iteration count and residual history, across several updates.  (On
+    well-conditioned operators: where CG's residual history is itself
+    rounding-sensitive, as plain CG on the lognormal matrices, it differs from
+    the oracle's own reversed-order run by tens of percent, and no history
+    comparison is meaningful.)"""
+    A = {"fd7_plain": lambda: synth.fd7(12), "q1_jacobi": lambda: synth.q1cube(12, 1.0, 4),
+         "fd7var_jacobi": lambda: synth.fd7_var(12, 1.0, 4)}[case]()
+    jacobi = case.endswith("jacobi")
+    b = synth.uniform(12, A.n_rows)
+    ref = oracle.cg(A, b, rtol=1e-10, jacobi=jacobi, history=True)
+    ru = oracle.mixed_ru(A, None, b, rtol=1e-10, delta=delta, jacobi=jacobi, history=True,
+                         inner_f64=True)
+    assert ru.status == oracle.OK and ru.outer_iters >= 3
+    assert ru.iters == ref.iters
+    np.testing.assert_allclose(ru.relres_hist, ref.relres_hist, rtol=1e-5)
+    assert np.linalg.norm(ru.x - ref.x) / np.linalg.norm(ref.x) <= 1e-9
+
+
+def test_mixed_ru_diagonal_closed_form():
+    """Power-of-two diagonal with Jacobi: D^-1 A = I, so each binary32 step
+    solves its scaled residual up to the rounding of float(r / s) (relative
+    2^-24), the recursive residual is exactly 0 and an update follows; two
+    steps and two updates reach 1e-10, x = b / a."""
+    n = 64
+    d = 2.0 ** (np.arange(n) % 7 - 3)
+    A = CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b = synth.uniform(3, n)
+    ru = oracle.mixed_ru(A, d.astype(np.float32), b, rtol=1e-10, delta=0.1, jacobi=True,
+                         history=True)
+    assert ru.status == oracle.OK and ru.iters == 2 and ru.outer_iters == 2
+    assert ru.relres_hist[1] <= 2.0 ** -24
+    np.testing.assert_allclose(ru.x, b / d, rtol=2.0 ** -46)
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_mixed_ru_keeps_the_krylov_space(jacobi):
+    """Binary32 iteration with float64 updates converges like float64 CG
+    (within 10 % of its iterations with Jacobi, 20 % without), where
+    refinement that restarts the
+    inner CG at every correction needs markedly more; the solution is within
+    kappa rtol of a dense solve and its true residual meets rtol."""
+    A = synth.q1cube(14, 1.0, 7)
+    b = synth.uniform(8, A.n_rows)
+    v32 = A.val.astype(np.float32)
+    ref = oracle.cg(A, b, rtol=1e-10, jacobi=jacobi)
+    ru = oracle.mixed_ru(A, v32, b, rtol=1e-10, delta=0.01, jacobi=jacobi)
+    ir = oracle.mixed_ir(A, v32, b, rtol=1e-10, tau=0.01, jacobi=jacobi)
+    assert ru.status == oracle.OK
+    assert ru.iters <= (1.1 if jacobi else 1.2) * ref.iters + 2
+    assert ir.iters >= 1.15 * ru.iters
+    D = _dense_of(A)
+    xs = np.linalg.solve(D, b)
+    ev = np.linalg.eigvalsh(D)
+    assert np.linalg.norm(ru.x - xs) / np.linalg.norm(xs) <= (ev[-1] / ev[0]) * 1e-10
+    assert np.linalg.norm(b - oracle.spmv(A, ru.x)) / np.linalg.norm(b) <= 1e-10
+    assert ru.relres == np.linalg.norm(b - oracle.spmv(A, ru.x)) / np.linalg.norm(b) or \
+        abs(ru.relres / (np.linalg.norm(b - oracle.spmv(A, ru.x)) / np.linalg.norm(b)) - 1) < 1e-6
+
+
+def test_mixed_ru_status_cases():
+    A = synth.fd7(6)
+    v32 = A.val.astype(np.float32)
+    n = A.n_rows
+    z = oracle.mixed_ru(A, v32, np.zeros(n), rtol=1e-10)
+    assert z.status == oracle.OK and z.iters == 0 and not z.x.any()
+    xs = synth.uniform(2, n)
+    e = oracle.mixed_ru(A, v32, oracle.spmv(A, xs), x0=xs, rtol=1e-10)
+    assert e.status == oracle.OK and e.iters == 0
+    neg = CSR(n, n, A.row_ptr, A.col_idx, -A.val)
+    assert oracle.mixed_ru(neg, -v32, synth.uniform(3, n), jacobi=True).status == oracle.BREAKDOWN
+    assert oracle.mixed_ru(neg, -v32, synth.uniform(3, n)).status == oracle.BREAKDOWN
+    b = synth.uniform(4, n)
+    cap = oracle.mixed_ru(A, v32, b, rtol=1e-14, maxit=5)
+    assert cap.status == oracle.NOT_CONVERGED and cap.iters == 5
+    # the correction of the unfinished cycle is kept: reported residual = true residual
+    true = np.linalg.norm(b - oracle.spmv(A, cap.x)) / np.linalg.norm(b)
+    assert abs(cap.relres - true) <= 1e-12 * true and true < 0.5
