@@ -70,8 +70,8 @@ def test_host_residual_matches_the_oracle():
 
 
 def test_only_the_cpu_baseline_uses_the_oracle():
-    """Apart from the CPU baseline, no part of the benchmark imports the
-    oracle."""
+    """Apart from the CPU baselines (one core, all cores), no part of the
+    benchmark imports the oracle."""
     import ast
     tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
     users = set()
@@ -82,4 +82,20 @@ def test_only_the_cpu_baseline_uses_the_oracle():
                     names = [a.name for a in node.names] + [getattr(node, "module", None) or ""]
                     if any(n == "oracle" or n.startswith("oracle.") for n in names):
                         users.add(fn.name)
-    assert users == {"cpu_baseline"}
+    assert users == {"cpu_baseline", "cpu_baseline_all_cores"}
+
+
+def test_oracle_timing_build_matches_the_oracle():
+    """The all-cores timing build of oracle.c runs the same CG (rows and
+    elements in parallel, dot partials per thread): the same iterates up to
+    rounding; the default build stays sequential."""
+    import oracle
+    import synth
+    assert oracle._load().oracle_threads() == 1
+    assert oracle.timing_threads() >= 1
+    A = synth.q1cube(14, 1.0, 3)
+    b = synth.uniform(9, A.n_rows)
+    ref = oracle.cg(A, b, rtol=1e-9, jacobi=True)
+    tim = oracle.cg_timing(A, b, rtol=1e-9, jacobi=True)
+    assert tim.status == oracle.OK and abs(tim.iters - ref.iters) <= 2
+    assert np.linalg.norm(tim.x - ref.x) / np.linalg.norm(ref.x) <= 1e-7
