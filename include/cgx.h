@@ -193,6 +193,23 @@ size_t cgx_cg_workspace_bytes(int64_t n_rows, int64_t nnz, const cgx_opts *opts)
 int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, void *workspace,
                  size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats);
 
+/* (sync) cgx_cg_solve for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: tight serving loops, harnesses that forbid
+ * it): the workspace is the library's static device scratch of 64 MiB
+ * (67,108,864 bytes; one copy per GPU, held from cgx_create until the
+ * process ends), and the iterations are launched directly instead of through
+ * a HIP graph.  The call allocates no device or host memory.  float64 only
+ * (opts->precision FP64; plain or Jacobi); otherwise the same arguments,
+ * arithmetic, results and statistics as cgx_cg_solve (same bits).
+ * CGX_ENOMEM with a message when the system needs more workspace than the
+ * scratch holds (cgx_cg_workspace_bytes(n_rows, nnz, opts) > 64 MiB: about
+ * 2.7 M rows plain, 1.6 M rows Jacobi for 27-entry rows).  All calls on one
+ * GPU share the scratch: calls that overlap in time on the same GPU (from
+ * several threads or streams) race and must be serialised by the caller;
+ * each call initialises every scratch word it reads. */
+int cgx_cg_solve_noalloc(cgx_handle h, const cgx_csr *A, const double *b, double *x,
+                         const cgx_opts *opts, cgx_stats *stats);
+
 /* ------------------------------------------------- sliced ELL (SELL) -- */
 
 /* Sliced ELLPACK copy of a CSR matrix (Section 2.3 names ELL among the

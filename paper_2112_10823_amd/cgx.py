@@ -89,6 +89,7 @@ EXPORTS = [
     "cgx_serve_start", "cgx_serve_stop", "cgx_serve_request_bytes", "cgx_submit", "cgx_poll",
     "cgx_wait", "cgx_batch_mixed_workspace_bytes", "cgx_schwarz_bytes", "cgx_schwarz_build", "cgx_schwarz_workspace_bytes",
     "cgx_schwarz_solve", "cgx_dot_sync", "cgx_debug_fail_tuning",
+    "cgx_cg_solve_noalloc",
 ]
 
 _lib = None
@@ -118,6 +119,7 @@ def load_library(path: str = LIB_PATH):
         "cgx_xmul": ([vp, i64, vp, vp, vp], ctypes.c_int),
         "cgx_dot": ([vp, i64, vp, vp, vp], ctypes.c_int),
         "cgx_dot_sync": ([vp, i64, vp, vp, P(dbl)], ctypes.c_int),
+        "cgx_cg_solve_noalloc": ([vp, P(_Csr), vp, vp, P(Opts), P(Stats)], ctypes.c_int),
         "cgx_debug_fail_tuning": ([vp, i32], ctypes.c_int),
         "cgx_demote": ([vp, i64, vp, vp], ctypes.c_int),
         "cgx_cg_workspace_bytes": ([i64, i64, P(Opts)], ctypes.c_size_t),
@@ -561,6 +563,24 @@ def cg_solve(A: DeviceCSR, b, x, opts: Opts | None = None, workspace=None, handl
                                               _ptr(workspace), ws_bytes,
                                               ctypes.byref(opts), ctypes.byref(st))
     if rc in (EINVAL, ENOMEM, EHIP) or (raise_on_fail and rc != OK):
+        _check(rc)
+    return st
+
+
+def cg_solve_noalloc(A: DeviceCSR, b, x, opts: Opts | None = None, handle=None) -> Stats:
+    """cgx_cg_solve_noalloc: float64 CG with the library's static device
+    scratch as workspace (no allocation in the call).  Returns Stats; raises
+    CgxError on argument errors and on a system too large for the scratch."""
+    opts = opts or make_opts()
+    _dev_tensor(b, torch.float64, "b")
+    _dev_tensor(x, torch.float64, "x")
+    if b.numel() != A.n_rows or x.numel() != A.n_rows:
+        raise ValueError("b / x length does not match A")
+    st = Stats()
+    d = A.desc()
+    rc = load_library().cgx_cg_solve_noalloc(_h(handle), ctypes.byref(d), _ptr(b), _ptr(x),
+                                             ctypes.byref(opts), ctypes.byref(st))
+    if rc in (EINVAL, ENOMEM, EHIP):
         _check(rc)
     return st
 

@@ -90,6 +90,13 @@ int cgx_create(cgx_handle *out, int device, void *stream)
         for (int i = 0; i < 4 * cgx::kProfWindow && e == hipSuccess; ++i)
             e = hipEventCreate(&c->ev_phase[i]);
         if (e == hipSuccess) e = hipDeviceSynchronize();
+        c->kappa_host.assign(5 * (size_t)cgx::kCoefRec, 0.0);
+        if (e == hipSuccess && cgx::static_scratch_address(device, &c->static_ws) != CGX_OK) {
+            const std::string msg = cgx_last_error();
+            cgx_destroy(reinterpret_cast<cgx_handle>(c));
+            cgx::set_error("cgx_create: " + msg);
+            return CGX_EHIP;
+        }
         if (e != hipSuccess) {
             cgx::set_error(std::string("cgx_create: ") + hipGetErrorString(e));
             cgx_destroy(reinterpret_cast<cgx_handle>(c));
@@ -320,6 +327,30 @@ int cgx_cg_solve(cgx_handle h, const cgx_csr *A, const double *b, double *x, voi
                  size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats)
 {
     return cg_solve_common(h, A, nullptr, b, x, workspace, workspace_bytes, opts, stats);
+}
+
+int cgx_cg_solve_noalloc(cgx_handle h, const cgx_csr *A, const double *b, double *x,
+                         const cgx_opts *opts, cgx_stats *stats)
+{
+    return guarded([&]() -> int {
+        CGX_REQUIRE(h != nullptr, "handle is NULL");
+        CGX_REQUIRE(opts != nullptr && stats != nullptr, "opts or stats is NULL");
+        int rc = check_csr(A, true, false);
+        if (rc) return rc;
+        CGX_REQUIRE(A->n_rows == A->n_cols, "matrix must be square");
+        CGX_REQUIRE(opts->precond == CGX_PRECOND_NONE || opts->precond == CGX_PRECOND_JACOBI,
+                    "unknown preconditioner");
+        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64,
+                    "cgx_cg_solve_noalloc runs float64 CG only");
+        CGX_REQUIRE(opts->rtol >= 0.0, "rtol must be >= 0");
+        std::memset(stats, 0, sizeof(*stats));
+        stats->relres_true = -1.0;
+        if (A->n_rows == 0) return CGX_OK;
+        CGX_REQUIRE(b && x, "NULL b or x");
+        const size_t nb = (size_t)A->n_rows * 8;
+        CGX_REQUIRE(!overlaps(b, nb, x, nb), "x overlaps b");
+        return cgx::run_cg_noalloc(ctx_of(h), A, b, x, opts, stats);
+    });
 }
 
 int cgx_cg_solve_sell(cgx_handle h, const cgx_csr *A, const cgx_sell *S, const double *b,

@@ -22,11 +22,21 @@
 // (one launch, workgroup barriers between phases): at that size the cost is
 // launches and grid synchronisation, not bandwidth.
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "cgx_device.h"
 
 namespace cgx {
+
+// Workspace of cgx_cg_solve_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes its name to a
+// kernel (on the host it is only a stand-in symbol): static_scratch_address
+// looks up its device address per device, and that address is what the
+// launches take.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 constexpr int kRB = 256;             // threads per workgroup of the p.q tile-partial reduction
@@ -1064,17 +1074,17 @@ int zero_if_needed(Context *c, hipStream_t s, bool zero, int64_t n, double *x)
 
 // Ritz extremes and condition estimate from the first k recorded
 // coefficients (k = 0: left at 0).
-int fill_kappa(hipStream_t s, const double *coef_dev, int64_t iters, cgx_stats *st)
+int fill_kappa(Context *c, hipStream_t s, const double *coef_dev, int64_t iters, cgx_stats *st)
 {
     const int k = (int)std::min<int64_t>(iters, kCoefRec);
     st->kappa_est = st->ritz_min = st->ritz_max = 0.0;
     if (k <= 0) return CGX_OK;
-    std::vector<double> coef(2 * (size_t)k);
-    CGX_HIP_CHECK(hipMemcpyAsync(coef.data(), coef_dev, coef.size() * sizeof(double),
+    double *coef = c->kappa_host.data();  // 2 k coefficients, then 3 k of bisection work
+    CGX_HIP_CHECK(hipMemcpyAsync(coef, coef_dev, 2 * (size_t)k * sizeof(double),
                                  hipMemcpyDeviceToHost, s));
     CGX_HIP_CHECK(hipStreamSynchronize(s));
     double lo = 0.0, hi = 0.0;
-    if (lanczos_extremes(coef.data(), k, lo, hi)) {
+    if (lanczos_extremes_ws(coef, k, coef + 2 * (size_t)kCoefRec, lo, hi)) {
         st->ritz_min = lo;
         st->ritz_max = hi;
         st->kappa_est = lo > 0.0 ? hi / lo : 0.0;
@@ -1090,8 +1100,26 @@ int begin_solve(Context *c, hipStream_t s)
     return CGX_OK;
 }
 
+// Launches K iterations at a time directly on the stream (no graph) until
+// the state's `done` flag is set, at most max_rounds times.
+int launch_until_done(Context *c, int K, const Grids &g, bool jac, hipStream_t s,
+                      const CgArgs<double> &a, int64_t max_rounds)
+{
+    for (int64_t rep = 0; rep < max_rounds; ++rep) {
+        for (int k = 0; k < K; ++k) launch_iteration<double>(g, jac, s, a);
+        CGX_HIP_CHECK(hipGetLastError());
+        CGX_HIP_CHECK(
+            hipMemcpyAsync(c->host_state, a.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+        CGX_HIP_CHECK(hipStreamSynchronize(s));
+        if (c->host_state->done) break;
+    }
+    return CGX_OK;
+}
+
+// direct: iterations launched one by one instead of through a captured graph
+// (the allocation-free entry point).
 int run_fp64(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, double *x, void *ws,
-             size_t ws_bytes, const cgx_opts *o, cgx_stats *st)
+             size_t ws_bytes, const cgx_opts *o, cgx_stats *st, bool direct = false)
 {
     const int64_t n = A->n_rows;
     const bool jac = o->precond == CGX_PRECOND_JACOBI;
@@ -1202,7 +1230,8 @@ int run_fp64(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, d
             const double bytes = 12.0 * (double)A->nnz + (jac ? 104.0 : 88.0) * (double)n;
             const int K = replay_iters(o, bytes);
             const int64_t max_replays = (int64_t)maxit / K + 2;
-            rc = replay_until_done<double>(c, c->graph64, K, g, jac, s, a, max_replays);
+            rc = direct ? launch_until_done(c, K, g, jac, s, a, max_replays)
+                        : replay_until_done<double>(c, c->graph64, K, g, jac, s, a, max_replays);
             if (rc) return rc;
         }
     }
@@ -1227,7 +1256,7 @@ int run_fp64(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, d
     if (o->true_residual) st->relres_true = hs.bb > 0.0 ? std::sqrt(hs.rr_true / hs.bb) : 0.0;
     if (zero_b) st->relres_true = 0.0, st->relres = 0.0;
     st->device_ms = ms;
-    rc = fill_kappa(s, a.coef, hs.iter, st);
+    rc = fill_kappa(c, s, a.coef, hs.iter, st);
     if (rc) return rc;
     return st->status;
 }
@@ -1347,34 +1376,33 @@ int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, 
     st->relres = hs.bb > 0.0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
     st->relres_true = st->relres;
     st->device_ms = ms;
-    rc = fill_kappa(s, in.coef, first_inner, st);
+    rc = fill_kappa(c, s, in.coef, first_inner, st);
     if (rc) return rc;
     return st->status;
 }
 
 }  // namespace
 
-// Sturm count: eigenvalues of the symmetric tridiagonal (d, off-diagonal
-// squares e2) below x.
-static int sturm_below(const std::vector<double> &d, const std::vector<double> &e2, double x,
-                       double pivmin)
+// Sturm count: eigenvalues of the symmetric tridiagonal (diagonal d,
+// off-diagonal squares e2) below x.
+static int sturm_below(const double *d, const double *e2, int k, double x, double pivmin)
 {
     int c = 0;
     double q = d[0] - x;
-    for (size_t i = 0;; ++i) {
+    for (int i = 0;; ++i) {
         if (std::fabs(q) < pivmin) q = -pivmin;
         if (q < 0.0) ++c;
-        if (i + 1 == d.size()) break;
+        if (i + 1 == k) break;
         q = d[i + 1] - x - e2[i] / q;
     }
     return c;
 }
 
-bool lanczos_extremes(const double *coef, int k, double &lo, double &hi)
+bool lanczos_extremes_ws(const double *coef, int k, double *work, double &lo, double &hi)
 {
     if (k <= 0) return false;
     // T[j][j] = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T[j][j+1]^2 = beta_j / alpha_j^2
-    std::vector<double> d(k), e2(k > 1 ? k - 1 : 0), e(k > 1 ? k - 1 : 0);
+    double *d = work, *e2 = work + k, *e = work + 2 * (size_t)k;
     for (int j = 0; j < k; ++j) {
         const double al = coef[2 * j];
         if (!std::isfinite(al) || !(al > 0.0)) return false;
@@ -1405,7 +1433,7 @@ bool lanczos_extremes(const double *coef, int k, double &lo, double &hi)
         for (int it = 0; it < 200; ++it) {
             const double m = 0.5 * (a + b);
             if (m <= a || m >= b) break;
-            if (sturm_below(d, e2, m, pivmin) >= target)
+            if (sturm_below(d, e2, k, m, pivmin) >= target)
                 b = m;
             else
                 a = m;
@@ -1418,12 +1446,51 @@ bool lanczos_extremes(const double *coef, int k, double &lo, double &hi)
     return std::isfinite(lo) && std::isfinite(hi);
 }
 
+bool lanczos_extremes(const double *coef, int k, double &lo, double &hi)
+{
+    if (k <= 0) return false;
+    std::vector<double> work(3 * (size_t)k);
+    return lanczos_extremes_ws(coef, k, work.data(), lo, hi);
+}
+
 size_t cg_workspace_bytes(int64_t n, int64_t nnz, const cgx_opts *o)
 {
     if (n < 0) return 0;
     const bool jac = o && o->precond == CGX_PRECOND_JACOBI;
     const bool mixed = o && o->precision == CGX_PRECISION_MIXED;
     return make_layout(n, nnz, jac, mixed).total;
+}
+
+int static_scratch_address(int device, void **out)
+{
+    static std::mutex mu;
+    static std::map<int, void *> addr;  // device -> address of its copy of `scratch`
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        CGX_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        it = addr.emplace(device, p).first;
+    }
+    *out = it->second;
+    return CGX_OK;
+}
+
+int run_cg_noalloc(Context *c, const cgx_csr *A, const double *b, double *x, const cgx_opts *o,
+                   cgx_stats *st)
+{
+    if (c->static_ws == nullptr) {
+        set_error("static scratch not available on this device");
+        return CGX_EHIP;
+    }
+    const size_t need = cg_workspace_bytes(A->n_rows, A->nnz, o);
+    if (need > kStaticScratchBytes) {
+        set_error("system needs " + std::to_string(need) +
+                  " bytes of workspace; the static scratch of cgx_cg_solve_noalloc holds " +
+                  std::to_string(kStaticScratchBytes));
+        return CGX_ENOMEM;
+    }
+    return run_fp64(c, A, nullptr, b, x, c->static_ws, kStaticScratchBytes, o, st, true);
 }
 
 int run_cg(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, double *x, void *ws,

@@ -96,6 +96,15 @@ constexpr int kCoefRec = 4096;
 // coefficients coef[2 j] = alpha_j (j < k), coef[2 j + 1] = beta_j (j < k - 1);
 // false when k = 0 or a coefficient is not finite and positive.
 bool lanczos_extremes(const double *coef, int k, double &lo, double &hi);
+// The same with caller storage: work holds at least 3 k doubles.
+bool lanczos_extremes_ws(const double *coef, int k, double *work, double &lo, double &hi);
+
+// Bytes of the library's static device scratch (the workspace of
+// cgx_cg_solve_noalloc), one copy per GPU for the life of the process.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+// Device address of the static scratch on the current device (looked up once
+// per device); CGX_EHIP if the lookup fails.
+int static_scratch_address(int device, void **out);
 
 // Words identifying what a captured graph bakes in: every kernel argument of
 // the captured launches (pointers, sizes, offsets), the launch shapes and the
@@ -142,6 +151,9 @@ struct Context {
     double *scratch = nullptr;     // device: reduction partials of the standalone calls
     CgState *host_state = nullptr; // pinned host copy of the solver state
     double *host_scalar = nullptr; // pinned host word for results returned to the host
+    void *static_ws = nullptr;     // device address of the static scratch on this device
+    std::vector<double> kappa_host; // host room for the recorded coefficients and the
+                                    // Lanczos bisection (5 kCoefRec doubles), sized at create
     hipEvent_t ev0 = nullptr, ev1 = nullptr;      // timing of a solve
     hipEvent_t ev_in = nullptr, ev_out = nullptr; // ordering between the two streams
     hipEvent_t ev_phase[4 * kProfWindow] = {};  // profile mode: 4 per iteration of a window
@@ -172,6 +184,10 @@ int launch_sell_spmv(Context *c, const cgx_sell *S, const double *x, double *y);
 int launch_sell_spmv_f32(Context *c, const cgx_sell *S, const float *x, float *y);
 int run_cg(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, double *x, void *ws,
            size_t ws_bytes, const cgx_opts *o, cgx_stats *st);
+// float64 CG with the static scratch as workspace and the iterations launched
+// directly (no graph): allocates nothing.
+int run_cg_noalloc(Context *c, const cgx_csr *A, const double *b, double *x, const cgx_opts *o,
+                   cgx_stats *st);
 size_t cg_workspace_bytes(int64_t n, int64_t nnz, const cgx_opts *o);
 size_t batch_workspace_bytes(int32_t nsys, const cgx_system *in);
 // Whether wave tiles of rt rows are an instantiated schedule for K = the
