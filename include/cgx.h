@@ -128,7 +128,8 @@ int cgx_demote(cgx_handle h, int64_t n, const double *src, float *dst);
 #define CGX_PRECOND_NONE 0
 #define CGX_PRECOND_JACOBI 1
 #define CGX_PRECISION_FP64 0
-#define CGX_PRECISION_MIXED 1
+#define CGX_PRECISION_MIXED 1     /* float64 refinement around restarted binary32 CG */
+#define CGX_PRECISION_MIXED_RU 2  /* binary32 CG with float64 reliable updates */
 
 typedef struct cgx_opts {
     double rtol;         /* stop when ||r_k||_2 <= rtol * ||b||_2 */
@@ -136,8 +137,10 @@ typedef struct cgx_opts {
     int32_t precond;     /* CGX_PRECOND_* */
     int32_t precision;   /* CGX_PRECISION_* */
     int32_t check_every; /* iterations between host convergence checks; <= 0 = auto */
-    double inner_rtol;   /* MIXED: inner binary32 CG relative tolerance (<= 0: 1e-3) */
-    int32_t max_outer;   /* MIXED: refinement step cap (<= 0: 100) */
+    double inner_rtol;   /* MIXED: inner binary32 CG relative tolerance (<= 0: 1e-3);
+                          * MIXED_RU: the residual drop delta that triggers a
+                          * reliable update (<= 0: 1e-2) */
+    int32_t max_outer;   /* MIXED: refinement step cap; MIXED_RU: update cap (<= 0: 100) */
     int32_t true_residual; /* nonzero: also compute ||b - A x|| / ||b|| at exit */
     int32_t profile;     /* nonzero: launch the phase kernels one by one (no graph) with
                           * HIP events around each, and report their mean durations */
@@ -152,7 +155,8 @@ typedef struct cgx_stats {
                           * served requests: requests in its slot when it
                           * started, itself included (1: alone) */
     int32_t path;        /* kernel path: 0 phase kernels, 1 single workgroup, 2 mixed
-                          * refinement, 3 batched, 4 served, 5 Schwarz */
+                          * refinement, 3 batched, 4 served, 5 Schwarz, 6 reliable
+                          * updates */
     double relres;       /* recursive ||r|| / ||b|| at exit (outer residual for MIXED) */
     double relres_true;  /* ||b - A x|| / ||b|| if requested, else -1 */
     double device_ms;    /* GPU time of the solve, from stream events */
@@ -184,7 +188,14 @@ size_t cgx_cg_workspace_bytes(int64_t n_rows, int64_t nnz, const cgx_opts *opts)
 
 /* (sync) Solve A x = b, A symmetric positive definite, by conjugate gradient
  * (Section 5.3: classical CG; Jacobi preconditioning and binary32-inner
- * iterative refinement are options).  b: float64[n] device; x: float64[n]
+ * iterative refinement are options).  MIXED: float64 residual, binary32 CG
+ * on A->val32 from 0 to inner_rtol, x += ||r|| d, repeated.  MIXED_RU: one
+ * binary32 CG on A->val32 whose direction is kept across float64 "reliable
+ * updates" (x += ||r|| d, r = b - A x and the stopping test in float64, the
+ * binary32 residual replaced by float(r / ||r||)) taken when the binary32
+ * residual has fallen by inner_rtol since the last update or below the
+ * tolerance; stats->iters counts binary32 iterations, outer_iters updates.
+ * b: float64[n] device; x: float64[n]
  * device, holds x0 on entry (zeros for the usual start) and the solution on
  * exit.  workspace: device, >= cgx_cg_workspace_bytes bytes.  The iteration
  * state stays on the GPU; the host reads one status word every check_every

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcgx.so")
 
 OK, PENDING, EINVAL, ENOMEM, EHIP, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 1, -1, -2, -3, -4, -5, -6
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
-PRECISION_FP64, PRECISION_MIXED = 0, 1
+PRECISION_FP64, PRECISION_MIXED, PRECISION_MIXED_RU = 0, 1, 2
 STATUS_NAMES = {OK: "OK", PENDING: "PENDING", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP",
                 NOT_CONVERGED: "NOT_CONVERGED", BREAKDOWN: "BREAKDOWN", NONFINITE: "NONFINITE"}
 

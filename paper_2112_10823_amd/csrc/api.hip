@@ -299,17 +299,19 @@ static int cg_solve_common(cgx_handle h, const cgx_csr *A, const cgx_sell *S, co
     return guarded([&]() -> int {
         CGX_REQUIRE(h != nullptr, "handle is NULL");
         CGX_REQUIRE(opts != nullptr && stats != nullptr, "opts or stats is NULL");
-        int rc = check_csr(A, true, opts->precision == CGX_PRECISION_MIXED);
+        const bool lowp = opts->precision != CGX_PRECISION_FP64;
+        int rc = check_csr(A, true, lowp);
         if (rc) return rc;
         if (S) {
-            rc = check_sell(S, A, opts->precision == CGX_PRECISION_MIXED);
+            rc = check_sell(S, A, lowp);
             if (rc) return rc;
         }
         CGX_REQUIRE(A->n_rows == A->n_cols, "matrix must be square");
         CGX_REQUIRE(opts->precond == CGX_PRECOND_NONE || opts->precond == CGX_PRECOND_JACOBI,
                     "unknown preconditioner");
         CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64 ||
-                        opts->precision == CGX_PRECISION_MIXED,
+                        opts->precision == CGX_PRECISION_MIXED ||
+                        opts->precision == CGX_PRECISION_MIXED_RU,
                     "unknown precision");
         CGX_REQUIRE(opts->rtol >= 0.0, "rtol must be >= 0");
         std::memset(stats, 0, sizeof(*stats));

@@ -311,6 +311,10 @@ __global__ __launch_bounds__(kPB) void cg_update_kernel(CgArgs<T> a)
 
 // (3) Stopping test on r.r (every workgroup adds the partials in the same
 // order); beta = rho' / rho; p = z + beta p.  Workgroup 0 records the state.
+// With delta2 > 0 (the binary32 iteration of the reliable-update solve) the
+// iteration also stops, for a float64 update, once r.r < delta2 * rmax2,
+// rmax2 the largest r.r since the last update (delta2 = 0 elsewhere: the
+// test is r.r <= stop2 alone).
 template <bool kJac, typename T>
 __global__ __launch_bounds__(kPB) void cg_direction_kernel(CgArgs<T> a)
 {
@@ -320,10 +324,11 @@ __global__ __launch_bounds__(kPB) void cg_direction_kernel(CgArgs<T> a)
     const T rz = kJac ? sum_partials<kPB>(region(a, kPRz), a.grid_ew, red) : rr;
     if (st->done) return;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const double rmax2 = fmax(st->rmax2, (double)rr);
     int status = CGX_PENDING;
     if (!isfinite(rr) || !isfinite(rz))
         status = CGX_NONFINITE;
-    else if (rr <= (T)st->stop2)
+    else if (rr <= (T)st->stop2 || (double)rr < st->delta2 * rmax2)
         status = CGX_OK;
     else if (!(rz > T(0)))
         status = CGX_BREAKDOWN;
@@ -344,6 +349,7 @@ __global__ __launch_bounds__(kPB) void cg_direction_kernel(CgArgs<T> a)
         st->rr = rr;
         st->rho = rz;
         st->beta = beta;
+        st->rmax2 = rmax2;
     }
     T *__restrict__ p = a.p;
     const T *__restrict__ z = a.z;
@@ -695,6 +701,7 @@ __global__ __launch_bounds__(kPB) void mx_residual_finish_kernel(MxArgs m, int c
     else if (o->iter >= o->maxit)
         status = CGX_NOT_CONVERGED;
     if (status == CGX_PENDING) {
+        o->sigma_prev = o->alpha;  // the scale of the step that just ended
         o->alpha = sqrt(rr);
     } else {
         o->status = status;
@@ -731,9 +738,14 @@ __global__ __launch_bounds__(kPB) void mx_inner_init_kernel(MxArgs m, CgArgs<flo
 
 // One workgroup: inner state for a new refinement step (stop at
 // ||r32|| <= tau ||c||).
+// Reliable updates (delta2 > 0): the binary32 iteration runs on over all
+// updates; it pauses for a float64 update when c.c falls below delta2 times
+// its largest value since the last update, or below (rtol ||b|| / s)^2
+// (converged by the estimate), and records its coefficients throughout.
 __global__ __launch_bounds__(kPB) void mx_inner_init_finish_kernel(MxArgs m, CgArgs<float> in,
                                                                    int count, float tau2,
-                                                                   int inner_maxit, int jac)
+                                                                   int inner_maxit, int jac,
+                                                                   double delta2)
 {
     if (m.ost->done) return;
     __shared__ float red[kPB / kWave];
@@ -743,10 +755,17 @@ __global__ __launch_bounds__(kPB) void mx_inner_init_finish_kernel(MxArgs m, CgA
     CgState *s = in.st;
     s->rr = cc;
     s->rho = cz;
-    s->stop2 = (double)(tau2 * cc);
     s->iter = 0;
     s->maxit = inner_maxit;
     s->rec = m.ost->iter == 0 ? 1 : 0;  // coefficients of the first refinement step
+    s->delta2 = delta2;
+    s->rmax2 = cc;
+    if (delta2 > 0.0) {
+        const double sg = m.ost->alpha;
+        s->stop2 = m.ost->stop2 / (sg * sg);
+    } else {
+        s->stop2 = (double)(tau2 * cc);
+    }
     const bool bad = !isfinite(cc) || !isfinite(cz) || !(cz > 0.0f);
     s->status = bad ? CGX_NONFINITE : CGX_PENDING;
     s->done = bad ? 1 : 0;
@@ -761,6 +780,52 @@ __global__ __launch_bounds__(kPB) void mx_correct_kernel(MxArgs m, const float *
     for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < m.n; i += stride)
         m.x[i] = __builtin_fma(s, (double)d[i], m.x[i]);
     if (blockIdx.x == 0 && threadIdx.x == 0) m.ost->iter += 1;
+}
+
+// Reliable update, after x += s d and the float64 residual r = b - A x with
+// its new norm s' (outer alpha; the old s in sigma_prev): the binary32
+// recursive residual is replaced by c = float(r / s'), d = 0, z = D^-1 c, and
+// the partials of c.c and c.z go where the direction kernel reads them.
+template <bool kJac>
+__global__ __launch_bounds__(kPB) void mx_ru_rescale_kernel(MxArgs m, CgArgs<float> in)
+{
+    if (m.ost->done) return;
+    const double inv_s = 1.0 / m.ost->alpha;
+    float part[2] = {0.0f, 0.0f};
+    const int64_t stride = (int64_t)gridDim.x * kPB;
+    for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < m.n; i += stride) {
+        const float ci = (float)(m.r[i] * inv_s);
+        const float zi = kJac ? m.dinv32[i] * ci : ci;
+        in.r[i] = ci;
+        in.x[i] = 0.0f;
+        if (kJac) in.z[i] = zi;
+        part[0] += ci * ci;
+        part[1] += ci * zi;
+    }
+    __shared__ float red[2 * (kPB / kWave)];
+    block_sum<2, kPB>(part, red);
+    if (threadIdx.x == 0) {
+        region(in, kPRr)[blockIdx.x] = part[0];
+        region(in, kPRz)[blockIdx.x] = part[1];
+    }
+}
+
+// One workgroup, between the rescale and the direction kernel: the inner
+// state resumes in the new scale.  The direction kernel then forms
+// beta = rho' / rho_used with rho_used = rho s / s', i.e. the CG beta of the
+// true residuals carried into the new scale, and p = z + beta p keeps the
+// search direction.  rmax2 restarts (0: the direction kernel takes c.c).
+__global__ void mx_ru_resume_kernel(MxArgs m, CgArgs<float> in)
+{
+    if (threadIdx.x != 0 || m.ost->done) return;
+    const CgState *o = m.ost;
+    CgState *s = in.st;
+    const double sg = o->alpha;
+    s->rho_used = (double)(float)(s->rho_used * (o->sigma_prev / sg));
+    s->stop2 = o->stop2 / (sg * sg);
+    s->rmax2 = 0.0;
+    s->status = CGX_PENDING;
+    s->done = 0;
 }
 
 // ----------------------------------------------------------------- host --
@@ -1074,7 +1139,11 @@ int zero_if_needed(Context *c, hipStream_t s, bool zero, int64_t n, double *x)
 
 // Ritz extremes and condition estimate from the first k recorded
 // coefficients (k = 0: left at 0).
-int fill_kappa(Context *c, hipStream_t s, const double *coef_dev, int64_t iters, cgx_stats *st)
+// beta_scale (reliable updates): the beta recorded at iteration j is in the
+// scale of the new residual; the Lanczos relation takes the CG beta of the
+// true residuals, that beta times s' / s.
+int fill_kappa(Context *c, hipStream_t s, const double *coef_dev, int64_t iters, cgx_stats *st,
+               const std::vector<std::pair<int, double>> *beta_scale = nullptr)
 {
     const int k = (int)std::min<int64_t>(iters, kCoefRec);
     st->kappa_est = st->ritz_min = st->ritz_max = 0.0;
@@ -1083,6 +1152,9 @@ int fill_kappa(Context *c, hipStream_t s, const double *coef_dev, int64_t iters,
     CGX_HIP_CHECK(hipMemcpyAsync(coef, coef_dev, 2 * (size_t)k * sizeof(double),
                                  hipMemcpyDeviceToHost, s));
     CGX_HIP_CHECK(hipStreamSynchronize(s));
+    if (beta_scale)
+        for (const auto &f : *beta_scale)
+            if (f.first >= 0 && f.first + 1 < k) coef[2 * f.first + 1] *= f.second;
     double lo = 0.0, hi = 0.0;
     if (lanczos_extremes_ws(coef, k, coef + 2 * (size_t)kCoefRec, lo, hi)) {
         st->ritz_min = lo;
@@ -1312,10 +1384,14 @@ int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, 
     }
     bind_grids(g, in, w + lay.tpart);
 
+    // reliable updates: one binary32 CG over all float64 updates (delta: the
+    // residual drop that triggers an update); else restarted refinement
+    const bool ru = o->precision == CGX_PRECISION_MIXED_RU;
     const int max_outer = o->max_outer > 0 ? o->max_outer : 100;
     const int inner_maxit =
         o->maxit > 0 ? o->maxit : (int)std::min<int64_t>(n > 0 ? n : 1, 0x7fffffff);
     const double tau = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-3;
+    const double delta = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-2;
     const double rtol2 = o->rtol * o->rtol;
 
     hipStream_t s = c->own_stream;
@@ -1329,6 +1405,8 @@ int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, 
     const int K = replay_iters(o, bytes_in);
     int64_t inner_total = 0, first_inner = 0;
     int status = CGX_NOT_CONVERGED;
+    int inner_status = CGX_OK;
+    std::vector<std::pair<int, double>> beta_scale;  // (iteration, s' / s) of each update
     for (int step = 0; step <= max_outer + 1; ++step) {
         launch_mx_residual(g, step == 0, jac, s, m, rtol2);
         CGX_HIP_CHECK(hipGetLastError());
@@ -1339,21 +1417,41 @@ int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, 
             status = c->host_state->status;
             break;
         }
-        if (jac)
-            hipLaunchKernelGGL((mx_inner_init_kernel<true>), dim3(g.grid_ew), dim3(kPB), 0, s, m,
-                               in);
-        else
-            hipLaunchKernelGGL((mx_inner_init_kernel<false>), dim3(g.grid_ew), dim3(kPB), 0, s, m,
-                               in);
-        hipLaunchKernelGGL(mx_inner_init_finish_kernel, dim3(1), dim3(kPB), 0, s, m, in, g.grid_ew,
-                           (float)(tau * tau), inner_maxit, jac ? 1 : 0);
+        if (ru && inner_status != CGX_OK) {  // the binary32 iteration hit its cap
+            status = inner_status;
+            break;
+        }
+        if (!ru || step == 0) {
+            if (jac)
+                hipLaunchKernelGGL((mx_inner_init_kernel<true>), dim3(g.grid_ew), dim3(kPB), 0, s,
+                                   m, in);
+            else
+                hipLaunchKernelGGL((mx_inner_init_kernel<false>), dim3(g.grid_ew), dim3(kPB), 0, s,
+                                   m, in);
+            hipLaunchKernelGGL(mx_inner_init_finish_kernel, dim3(1), dim3(kPB), 0, s, m, in,
+                               g.grid_ew, (float)(tau * tau), inner_maxit, jac ? 1 : 0,
+                               ru ? delta * delta : 0.0);
+        } else {
+            // reliable update: replace the binary32 residual, keep the direction
+            const CgState &ho = *c->host_state;
+            beta_scale.emplace_back((int)inner_total - 1, ho.alpha / ho.sigma_prev);
+            if (jac)
+                hipLaunchKernelGGL((mx_ru_rescale_kernel<true>), dim3(g.grid_ew), dim3(kPB), 0, s,
+                                   m, in);
+            else
+                hipLaunchKernelGGL((mx_ru_rescale_kernel<false>), dim3(g.grid_ew), dim3(kPB), 0, s,
+                                   m, in);
+            hipLaunchKernelGGL(mx_ru_resume_kernel, dim3(1), dim3(64), 0, s, m, in);
+            launch_direction_phase<float>(g, jac, s, in);
+        }
         CGX_HIP_CHECK(hipGetLastError());
         const int64_t max_replays = (int64_t)inner_maxit / K + 2;
         rc = replay_until_done<float>(c, c->graph32, K, g, jac, s, in, max_replays);
         if (rc) return rc;
         const CgState inner = *c->host_state;
         if (step == 0) first_inner = inner.iter;
-        inner_total += inner.iter;
+        inner_total = ru ? inner.iter : inner_total + inner.iter;
+        inner_status = inner.status;
         if (inner.status == CGX_NONFINITE) {
             status = CGX_NONFINITE;
             break;
@@ -1372,11 +1470,11 @@ int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, 
     st->status = status == CGX_PENDING ? CGX_NOT_CONVERGED : status;
     st->iters = (int32_t)std::min<int64_t>(inner_total, 0x7fffffff);
     st->outer_iters = hs.iter;
-    st->path = 2;
+    st->path = ru ? 6 : 2;
     st->relres = hs.bb > 0.0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
     st->relres_true = st->relres;
     st->device_ms = ms;
-    rc = fill_kappa(c, s, in.coef, first_inner, st);
+    rc = fill_kappa(c, s, in.coef, ru ? inner_total : first_inner, st, &beta_scale);
     if (rc) return rc;
     return st->status;
 }
@@ -1457,7 +1555,7 @@ size_t cg_workspace_bytes(int64_t n, int64_t nnz, const cgx_opts *o)
 {
     if (n < 0) return 0;
     const bool jac = o && o->precond == CGX_PRECOND_JACOBI;
-    const bool mixed = o && o->precision == CGX_PRECISION_MIXED;
+    const bool mixed = o && o->precision != CGX_PRECISION_FP64;
     return make_layout(n, nnz, jac, mixed).total;
 }
 
@@ -1496,7 +1594,7 @@ int run_cg_noalloc(Context *c, const cgx_csr *A, const double *b, double *x, con
 int run_cg(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, double *x, void *ws,
            size_t ws_bytes, const cgx_opts *o, cgx_stats *st)
 {
-    if (o->precision == CGX_PRECISION_MIXED) return run_mixed(c, A, S, b, x, ws, ws_bytes, o, st);
+    if (o->precision != CGX_PRECISION_FP64) return run_mixed(c, A, S, b, x, ws, ws_bytes, o, st);
     return run_fp64(c, A, S, b, x, ws, ws_bytes, o, st);
 }
 

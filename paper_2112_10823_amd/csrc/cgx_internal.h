@@ -78,6 +78,9 @@ struct CgState {
     double bb;     // b.b
     double stop2;  // (rtol * ||b||)^2
     double rr_true;// ||b - A x||^2 when requested
+    double rmax2;  // reliable updates: largest r.r since the last update
+    double delta2; // reliable updates: pause when r.r < delta2 * rmax2 (0: never)
+    double sigma_prev; // reliable updates (outer state): ||r|| of the previous update
     int32_t iter;  // completed iterations
     int32_t maxit;
     int32_t status;// CGX_* status; CGX_PENDING while iterating

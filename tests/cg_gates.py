@@ -31,12 +31,16 @@ def reversed_system(A, b):
     return CSR(n, n, new_rp, ci, val), np.asarray(b)[::-1].copy()
 
 
-def residual_band(A, b, rtol, jacobi=False):
+def residual_band(A, b, rtol, jacobi=False, solve=None):
     """The oracle's residual history h (run past rtol, to rtol / 100) and the
-    band factor F = (1 + delta)^2 from its reversed-order run."""
-    h = oracle.cg(A, b, rtol=rtol / 100, jacobi=jacobi, history=True).relres_hist
+    band factor F = (1 + delta)^2 from its reversed-order run.  solve(A, b,
+    rtol) -> history selects the oracle method (default: CG)."""
+    if solve is None:
+        def solve(M, v, t):
+            return oracle.cg(M, v, rtol=t, jacobi=jacobi, history=True).relres_hist
+    h = solve(A, b, rtol / 100)
     Ar, br = reversed_system(A, b)
-    hr = oracle.cg(Ar, br, rtol=rtol / 100, jacobi=jacobi, history=True).relres_hist
+    hr = solve(Ar, br, rtol / 100)
     m = min(len(h), len(hr))
     ratio = hr[:m] / h[:m]
     delta = float(np.max(np.maximum(ratio, 1.0 / ratio)) - 1.0)
