@@ -145,6 +145,54 @@ def calib_gather_matrix(n):
     return synth.CSR(n, n, np.arange(n + 1, dtype=np.int32), col, np.ones(n))
 
 
+def mixed_path(cgx, synth, meter, reps=3):
+    """The mixed-precision configuration beside the headline: Q1 192^3
+    (7,077,888 rows, 189,119,224 nnz), lognormal(0, 1.5), uniform RHS,
+    Jacobi, to 1e-10: float64 Jacobi-CG against binary32 CG with float64
+    reliable updates (delta 1e-2), wall time per solve (best of `reps`),
+    J/solve from the energy counter, and the mixed solution's distance to the
+    float64 one."""
+    import torch
+    N = 192
+    A = synth.q1cube(N, 1.5, seed=synth.SEED_C3_COEFF)
+    b = synth.uniform(synth.SEED_C3_RHS, A.n_rows)
+    dA = cgx.DeviceCSR.from_host(A, with_f32=True)
+    db = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(db)
+    out = {"workload": f"Q1 hex FEM {N}^3 ({A.n_rows:,} rows, {A.nnz:,} nnz), lognormal(0,1.5), "
+                       "uniform RHS, Jacobi, rtol 1e-10"}
+    sol = {}
+    for name, o in (("fp64_jacobi", cgx.make_opts(rtol=1e-10, precond=1)),
+                    ("mixed_ru", cgx.make_opts(rtol=1e-10, precond=1, inner_rtol=1e-2,
+                                               precision=cgx.PRECISION_MIXED_RU))):
+        ws = cgx.cg_workspace(dA, o)
+
+        def solve():
+            x.zero_()
+            return cgx.cg_solve(dA, db, x, o, workspace=ws)
+        st = solve()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            st = solve()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        _, j = _energy_window(solve, meter, min_s=2.0)
+        sol[name] = x.clone()
+        out[f"{name}_ms"] = round(best * 1e3, 2)
+        out[f"{name}_iters"] = st.iters
+        out[f"{name}_j_per_solve"] = round(j, 2) if j is not None else None
+        out[f"{name}_relres"] = st.relres
+        if name == "mixed_ru":
+            out["mixed_ru_updates"] = st.outer_iters
+        del ws
+    out["time_ratio"] = round(out["mixed_ru_ms"] / out["fp64_jacobi_ms"], 4)
+    out["mixed_vs_fp64_rel_error"] = float(torch.linalg.norm(sol["mixed_ru"] - sol["fp64_jacobi"])
+                                           / torch.linalg.norm(sol["fp64_jacobi"]))
+    return out
+
+
 def host_relres(A, b, x):
     """||b - A x|| / ||b|| with scipy's CSR product on the host: a library
     routine independent of the GPU library, used to check the solutions the
@@ -653,13 +701,13 @@ def extra_paper_shapes(cgx, synth, meter):
                         "Dirichlet rows); SpMV, plain CG to 1e-6", "rows": rows}
 
 
-def extra_transfer(meter):
+def extra_transfer(meter, sizes_mib=(1, 16, 256, 1024), min_s=2.0):
     """Host <-> device copies (the paper's transfer figure gives no numbers):
     float64 buffers of 1 MiB to 1 GiB, pinned and pageable host memory,
-    each direction timed with events and its energy taken over >= 2 s."""
+    each direction timed with events and its energy taken over >= min_s."""
     import torch
     rows = []
-    for mib in (1, 16, 256, 1024):
+    for mib in sizes_mib:
         nel = mib * (1 << 20) // 8
         dev_buf = torch.empty(nel, dtype=torch.float64, device="cuda")
         for pinned in (True, False):
@@ -671,7 +719,7 @@ def extra_transfer(meter):
                 else:
                     fn = lambda: host.copy_(dev_buf, non_blocking=pinned)  # noqa: E731
                 t = _timeit(fn, reps=max(3, min(200, 2048 // mib)), warm=2)
-                wall, j = _energy_window(fn, meter, min_s=2.0, min_reps=3)
+                wall, j = _energy_window(fn, meter, min_s=min_s, min_reps=3)
                 rows.append({"MiB": mib, "pinned": pinned, "dir": direction,
                              "ms": round(t * 1e3, 4), "GBs": round(mib * (1 << 20) / t / 1e9, 2),
                              "j_per_GB": round(j / (mib * (1 << 20) / 1e9), 3) if j else None})
@@ -820,6 +868,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision comparison on Q1 192^3 in the default line")
     ap.add_argument("--cpu-iters", type=int, default=300,
                     help="Jacobi-CG iterations of the CPU oracle sample (about 10-15 s)")
     ap.add_argument("--profile-only", action="store_true",
@@ -983,6 +1033,12 @@ def main():
                  "padding": round(sell.stored / nnz - 1, 5)}
     del sell
     print(f"# sliced-ELL path {sell_path['ms_per_step']} ms per solve", file=sys.stderr, flush=True)
+    del ws
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_path(cgx, synth, meter)
+        print(f"# mixed path {mixed['mixed_ru_ms']} ms vs float64 {mixed['fp64_jacobi_ms']} ms",
+              file=sys.stderr, flush=True)
 
     cpu = cpu_all = None
     if not args.no_cpu_baseline:
@@ -1028,6 +1084,7 @@ def main():
         "cpu_baseline": cpu,
         "cpu_baseline_all_cores": cpu_all,
         "sell_path": sell_path,
+        "mixed_path": mixed,
     }
     print(json.dumps(out), flush=True)
 
