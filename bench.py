@@ -569,7 +569,7 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5, full=Tr
                 break
         N = max(2, round(r ** (1 / 3)))
         A = synth.q1cube(N, 1.0, 2000 + i)
-        mats.append((A, cgx.DeviceCSR.from_host(A)))
+        mats.append((A, cgx.DeviceCSR.from_host(A, with_f32=full)))
     opts = cgx.make_opts(rtol=1e-8)
     picks = rng.integers(0, pool_systems, n_req)
     max_n = max(A.n_rows for A, _ in mats)
@@ -606,6 +606,7 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5, full=Tr
         lat.sort()
         return {"qps": round(qps, 2) if qps else "burst", "max_group": max_group,
                 "precond": "jacobi" if opts.precond else "none",
+                "precision": "mixed" if opts.precision == cgx.PRECISION_MIXED else "fp64",
                 "solves_per_s": round(n_req / wall, 2),
                 "p50_ms": round(lat[len(lat) // 2], 2),
                 "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 2),
@@ -642,6 +643,12 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5, full=Tr
     for f in (0.5, 0.8, 0.95):
         rows.append(run(f * sat["solves_per_s"]))
     rows.append(run(0, opts=jac))
+    # binary32-refined requests (float64 residual, update and stopping test;
+    # binary32 inner Jacobi-CG to 1e-2), burst and Poisson at 0.8 of it
+    mix = cgx.make_opts(rtol=1e-8, precond=cgx.PRECOND_JACOBI, precision=cgx.PRECISION_MIXED,
+                        inner_rtol=1e-2)
+    msat = run(0, opts=mix)
+    rows += [msat, run(0.8 * msat["solves_per_s"], opts=mix)]
     return {"workload": f"{n_req} Poisson-arrival requests on {pool_systems} resident Q1 systems "
                         f"(rows lognormal in [1e4, 4e6]), lognormal(0,1), rtol 1e-8",
             "rows": rows, "one_at_a_time_fp64_cg": sequential(),

@@ -151,9 +151,9 @@ typedef struct cgx_stats {
     int32_t iters;       /* CG iterations (binary32 inner iterations for MIXED;
                           * Schwarz: subdomain iterations, summed over the outer
                           * steps of the largest count among the subdomains) */
-    int32_t outer_iters; /* MIXED: refinement steps; Schwarz: outer iterations;
-                          * served requests: requests in its slot when it
-                          * started, itself included (1: alone) */
+    int32_t outer_iters; /* MIXED: refinement steps (served MIXED requests too);
+                          * Schwarz: outer iterations; served float64
+                          * requests: as slot_requests */
     int32_t path;        /* kernel path: 0 phase kernels, 1 single workgroup, 2 mixed
                           * refinement, 3 batched, 4 served, 5 Schwarz, 6 reliable
                           * updates */
@@ -176,6 +176,9 @@ typedef struct cgx_stats {
                           * CG): T[j][j] = 1/alpha_j + beta_{j-1}/alpha_{j-1},
                           * T[j][j+1] = sqrt(beta_j)/alpha_j; they lie inside the
                           * operator's spectrum and approach its ends as k grows */
+    int32_t slot_requests; /* served requests: requests in its slot when it
+                            * started, itself included (1: alone); else 0 */
+    int32_t reserved;
 } cgx_stats;
 
 /* Bytes of device workspace cg_solve needs for a system of n_rows rows and
@@ -360,15 +363,23 @@ int cgx_serve_start(cgx_handle h, void *pool, size_t pool_bytes, int32_t max_slo
 /* (sync) Finish every queued and running request, then stop the server. */
 int cgx_serve_stop(cgx_handle h);
 
-/* Pool bytes one request of n_rows needs while admitted alone (a group of
- * g requests on one matrix needs less than g times this). */
+/* Pool bytes one request of n_rows needs while admitted alone, float64 or
+ * MIXED (a group of g requests on one matrix needs less than g times this). */
 size_t cgx_serve_request_bytes(int64_t n_rows);
 
 /* Queue a solve of A x = b (A resident and square, b / x device float64[n],
  * x holds x0 and receives the solution; all must stay valid until the
- * request completes).  opts: rtol, maxit, precond are used.  Non-blocking;
- * *ticket identifies the request.  CGX_ENOMEM at once if the request can
- * never fit the pool. */
+ * request completes).  opts: rtol, maxit, precond, precision are used, and
+ * for CGX_PRECISION_MIXED inner_rtol and max_outer.  FP64: CG (Section 5.3)
+ * in float64.  MIXED (needs A->val32): the refinement of cgx_cg_solve's
+ * MIXED, step by step per request: float64 r = b - A x, ||r|| <= rtol ||b||
+ * ends it, else binary32 CG on A->val32 (Jacobi from val32's diagonal with
+ * precond) from 0 on float(r / ||r||) to inner_rtol (default 1e-3) or maxit
+ * iterations, then x += ||r|| d in float64; at most max_outer (default 100)
+ * inner solves, then CGX_NOT_CONVERGED.  The inner solves of all MIXED
+ * requests advance together in the batched binary32 kernels; each request
+ * takes its float64 steps on its own.  Non-blocking; *ticket identifies the
+ * request.  CGX_ENOMEM at once if the request can never fit the pool. */
 int cgx_submit(cgx_handle h, const cgx_csr *A, const double *b, double *x, const cgx_opts *opts,
                uint64_t *ticket);
 

@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
                 ("device_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 3),
                 ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
                 ("kappa_est", ctypes.c_double), ("ritz_min", ctypes.c_double),
-                ("ritz_max", ctypes.c_double)]
+                ("ritz_max", ctypes.c_double), ("slot_requests", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -648,7 +648,10 @@ int cgx_submit(cgx_handle h, const cgx_csr *A, const double *b, double *x, const
     return guarded([&]() -> int {
         CGX_REQUIRE(h != nullptr, "handle is NULL");
         CGX_REQUIRE(opts != nullptr && ticket != nullptr, "opts or ticket is NULL");
-        int rc = check_csr(A, true, false);
+        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64 || opts->precision == CGX_PRECISION_MIXED,
+                    "served solves are float64 or MIXED");
+        const bool mixed = opts->precision == CGX_PRECISION_MIXED;
+        int rc = check_csr(A, true, mixed);
         if (rc) return rc;
         CGX_REQUIRE(A->n_rows == A->n_cols && A->n_rows >= 1, "matrix must be square, n >= 1");
         CGX_REQUIRE(b != nullptr && x != nullptr, "NULL b or x");
@@ -656,8 +659,8 @@ int cgx_submit(cgx_handle h, const cgx_csr *A, const double *b, double *x, const
         CGX_REQUIRE(!overlaps(b, nb, x, nb), "x overlaps b");
         CGX_REQUIRE(opts->precond == CGX_PRECOND_NONE || opts->precond == CGX_PRECOND_JACOBI,
                     "unknown preconditioner");
-        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64, "served solves are float64");
         CGX_REQUIRE(opts->rtol >= 0.0, "rtol must be >= 0");
+        CGX_REQUIRE(!mixed || opts->inner_rtol < 1.0, "inner_rtol must be < 1");
         return cgx::serve_submit(ctx_of(h), A, b, x, opts, ticket);
     });
 }

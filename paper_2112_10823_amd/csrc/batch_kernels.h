@@ -839,13 +839,15 @@ __global__ __launch_bounds__(kBB) void lane_init_kernel(BArgs a, int si, int j)
 {
     __shared__ double red[3 * (kBB / kWave)];
     const BSys S = a.sys[si];
-    const BTile t = a.tiles[S.tile0 + blockIdx.x];
+    // tile blockIdx.x of the system: rows [b trows, (b + 1) trows), partials
+    // at S.tile0 + b (the work table may hold other systems' tiles between)
+    const int row0 = blockIdx.x * S.trows, row1 = min(S.n, row0 + S.trows);
     const double *x0 = S.lanes[j].x;
     const double *b = S.lanes[j].b;
     const int K = S.K;
     double part[3] = {0.0, 0.0, 0.0};
     bool bad = false;
-    for (int row = t.row0 + threadIdx.x; row < t.row0 + t.rows; row += kBB) {
+    for (int row = row0 + threadIdx.x; row < row1; row += kBB) {
         const int s0 = clampk(S.rp[row], S.nnz);
         const int s1 = max(s0, clampk(S.rp[row + 1], S.nnz));
         double ax = 0.0, dg = 0.0;
@@ -874,7 +876,7 @@ __global__ __launch_bounds__(kBB) void lane_init_kernel(BArgs a, int si, int j)
     block_sum<3, kBB>(part, red);
     if (threadIdx.x == 0)
         for (int r = 0; r < 3; ++r)
-            a.part[r * a.part_stride + (int64_t)t.tile * kMaxK + j] = part[r];
+            a.part[r * a.part_stride + (int64_t)(S.tile0 + blockIdx.x) * kMaxK + j] = part[r];
 }
 
 // One workgroup: lane j's initial state from its tile partials (tile order),

@@ -13,8 +13,16 @@
 // them (the batched solver's multi-right-hand-side SpMM).  Each request keeps
 // its own scalars and stopping test and is retired as soon as it finishes.
 //
+// Binary32-refined requests (MIXED) get slots of their own: float64 x and
+// residual, binary32 inner vectors and D^-1.  Their inner CG iterations run
+// in the batched binary32 kernels, all such slots in one launch per phase;
+// each lane's float64 step (fold the inner solution into x, r = b - A x,
+// stopping test, next inner right-hand side r / ||r||) is a short sequence
+// of one-lane kernels the engine issues at the start of the cycle after the
+// lane's inner solve ended.
+//
 // Device memory comes only from the caller's pool: a fixed arena (system
-// table, lane table, work table, scalars, reduction partials) at its start
+// tables, lane table, work tables, scalars, reduction partials) at its start
 // and a first-fit heap for per-slot Krylov vectors.  A request's arithmetic
 // depends only on its slot's rows, tiles, right-hand-side count and
 // schedule: alone and in any mix it gets the same bits when it is served
@@ -52,6 +60,9 @@ struct Request {
     double *x = nullptr;
     int jac = 0, maxit = 0;
     double rtol = 0.0;
+    int mixed = 0;            // binary32 inner solves inside float64 refinement
+    double inner_rtol = 0.0;  // MIXED: inner stopping tolerance
+    int max_outer = 0;        // MIXED: inner solves at most
     double t_submit = 0.0;
     size_t bytes = 0;  // heap bytes: Krylov vectors plus a one-system tuning plan
 };
@@ -65,7 +76,13 @@ struct Slot {
     std::vector<uint8_t> state;     // LaneState per lane
     std::vector<double> t_start;    // admission / join time per lane
     std::vector<int> sharing;       // per lane: requests in the slot when it started
+    // MIXED slots, per lane: float64 step due at the next cycle, first step
+    // (x = caller x0), step issued this cycle, inner solves started, inner
+    // iterations so far
+    std::vector<uint8_t> need_outer, first, outer_ran;
+    std::vector<int> outer, inner_sum;
     size_t off = 0, bytes = 0;      // heap block of the slot's vectors
+    bool mixed = false;
     int M = 1;
     int K = 1;
     int ntiles = 0;
@@ -100,6 +117,10 @@ struct Engine {
     int64_t max_tiles = 0;
     size_t off_sys = 0, off_lanes = 0, off_list = 0, off_list2 = 0, off_scal = 0, off_done = 0,
            off_tiles = 0, off_tiles2 = 0, off_part = 0, heap0 = 0;
+    // binary32 tables of the MIXED slots (indexed by slot like the float64
+    // ones; the work-table entries number tiles in one space with them)
+    size_t off_sys32 = 0, off_list32 = 0, off_scal32 = 0, off_done32 = 0, off_tiles32 = 0,
+           off_part32 = 0, off_bad = 0;
     std::map<size_t, size_t> free_list;  // heap offset -> size
     std::vector<Slot> slots;
     std::deque<Request> queue;
@@ -113,9 +134,12 @@ struct Engine {
     std::string fail_msg;
     BScal *h_scal = nullptr;
     int32_t *h_done = nullptr;
+    BScalT<float> *h_scal32 = nullptr;
     double head_wait_limit = 0.25;  // s a blocked head may wait before backfilling stops
     uint64_t completed = 0;
-    int active_tiles = 0;  // entries of the device work table (engine thread only)
+    int active_tiles = 0;    // entries of the float64 work table (engine thread only)
+    int active_tiles32 = 0;  // entries of the binary32 work table
+    int nlist64 = 0, nlist32 = 0;  // float64 / MIXED slots in the per-system lists
 
     // --------------------------------------------------------- pool heap --
     bool alloc(size_t bytes, size_t &off)
@@ -178,12 +202,210 @@ bool same_group(const Request &a, const Request &b)
 {
     return a.A.row_ptr == b.A.row_ptr && a.A.col_idx == b.A.col_idx && a.A.val == b.A.val &&
            a.A.n_rows == b.A.n_rows && a.A.nnz == b.A.nnz && a.jac == b.jac &&
-           a.maxit == b.maxit && a.rtol == b.rtol;
+           a.maxit == b.maxit && a.rtol == b.rtol && a.mixed == b.mixed &&
+           (!a.mixed || (a.A.val32 == b.A.val32 && a.inner_rtol == b.inner_rtol &&
+                         a.max_outer == b.max_outer));
+}
+
+// ------------------------------------------------ MIXED slot kernels --
+// One lane j of MIXED slot si; S / F are the slot's float64 / binary32
+// descriptors, a workgroup per tile of trows rows (tile index S.tile0 +
+// blockIdx.x in the partials).
+
+// D^-1 of the slot from val32's diagonal, 1 / a_ii rounded once to binary32
+// from a float64 division (as the float32-refined batch forms it); a
+// diagonal entry <= 0 or missing marks the slot (Jacobi breakdown).
+__global__ __launch_bounds__(kBB) void mixed_setup_kernel(const BSysT<float> *sys32, int32_t *bad,
+                                                          int si)
+{
+    const BSysT<float> &F = sys32[si];
+    const int row0 = blockIdx.x * F.trows, row1 = min(F.n, row0 + F.trows);
+    bool b = false;
+    for (int row = row0 + threadIdx.x; row < row1; row += kBB) {
+        const int s0 = clampk(F.rp[row], F.nnz), s1 = max(s0, clampk(F.rp[row + 1], F.nnz));
+        float dg = 0.0f;
+        for (int k = s0; k < s1; ++k)
+            if (F.ci[k] == row) dg = F.val[k];
+        b = b || !(dg > 0.0f);
+        F.dinv[row] = (float)(1.0 / (double)(dg > 0.0f ? dg : 1.0f));
+    }
+    if (b) bad[si] = 1;  // same value from every writer
+}
+
+// x[:, j] = caller x0 (first step) or fma(||r_prev||, double(d[:, j]),
+// x[:, j]): the inner solution folded into the float64 iterate.
+__global__ __launch_bounds__(kBB) void mixed_lane_x_kernel(BArgs a64, BArgsT<float> a32, int si,
+                                                           int j, int first)
+{
+    const BSys &S = a64.sys[si];
+    const BSysT<float> &F = a32.sys[si];
+    const int row0 = blockIdx.x * S.trows, row1 = min(S.n, row0 + S.trows);
+    const double sigma = sqrt(a64.scal[S.scal0 + j].rr);
+    const double *x0 = S.lanes[j].x;
+    for (int row = row0 + threadIdx.x; row < row1; row += kBB) {
+        const int64_t e = (int64_t)row * S.K + j;
+        S.x[e] = first ? x0[row] : __builtin_fma(sigma, (double)F.x[e], S.x[e]);
+    }
+}
+
+// r[:, j] = b - A x[:, j] in float64 (8 lanes per row, each summing entries
+// m, m + 8, ..., then a butterfly) and the tile partials of r.r and b.b.
+__global__ __launch_bounds__(kBB) void mixed_lane_residual_kernel(BArgs a64, int si, int j)
+{
+    constexpr int L = 8;
+    __shared__ double red[2 * (kBB / kWave)];
+    const BSys &S = a64.sys[si];
+    const int row0 = blockIdx.x * S.trows, row1 = min(S.n, row0 + S.trows);
+    const int m = threadIdx.x % L;
+    const double *b = S.lanes[j].b;
+    double part[2] = {0.0, 0.0};
+    for (int row = row0 + (int)threadIdx.x / L; row < row1; row += kBB / L) {
+        const int s0 = clampk(S.rp[row], S.nnz), s1 = max(s0, clampk(S.rp[row + 1], S.nnz));
+        double acc = 0.0;
+        for (int k = s0 + m; k < s1; k += L) {
+            const int c = S.ci[k];
+            if ((unsigned)c < (unsigned)S.n_cols) acc += S.val[k] * S.x[(int64_t)c * S.K + j];
+        }
+        acc = group_sum<L>(acc);
+        if (m == 0) {
+            const double bi = b[row];
+            const double ri = bi - acc;
+            S.r[(int64_t)row * S.K + j] = ri;
+            part[0] += ri * ri;
+            part[1] += bi * bi;
+        }
+    }
+    block_sum<2, kBB>(part, red);
+    if (threadIdx.x == 0) {
+        const int64_t t = (int64_t)(S.tile0 + blockIdx.x) * kMaxK + j;
+        a64.part[t] = part[0];
+        a64.part[a64.part_stride + t] = part[1];
+    }
+}
+
+// One workgroup: ||r||^2 and ||b||^2 of lane j from its tile partials (tile
+// order) and the float64 stopping test: b = 0 or ||r|| <= rtol ||b|| ends
+// it (CGX_OK), a bad Jacobi diagonal ends it (CGX_BREAKDOWN), and so does
+// the step after max_outer inner solves (`last`: CGX_NOT_CONVERGED).
+__global__ __launch_bounds__(kBB) void mixed_lane_outer_kernel(BArgs a64, const int32_t *bad, int si,
+                                                               int j, int last)
+{
+    __shared__ double red[kBB / kWave];
+    const BSys &S = a64.sys[si];
+    double v[2];
+    for (int r = 0; r < 2; ++r) {
+        const double *base = a64.part + r * a64.part_stride;
+        double s = 0.0;
+        for (int q = threadIdx.x; q < S.ntiles; q += kBB) s += base[(int64_t)(S.tile0 + q) * kMaxK + j];
+        v[r] = sum_partials_in_block(s, red);
+    }
+    if (threadIdx.x == 0) {
+        BScal &c = a64.scal[S.scal0 + j];
+        const double rr = v[0], bb = v[1];
+        c.rr = rr;
+        c.bb = bb;
+        int status = CGX_PENDING;
+        if (!isfinite(bb) || !isfinite(rr))
+            status = CGX_NONFINITE;
+        else if (bb == 0.0 || rr <= S.rtol2 * bb)
+            status = CGX_OK;
+        else if (S.jac && bad[si])
+            status = CGX_BREAKDOWN;
+        else if (last)
+            status = CGX_NOT_CONVERGED;
+        c.status = status;
+        c.active = status == CGX_PENDING;
+    }
+}
+
+// Start of lane j's next inner solve (float64 status still pending): c =
+// float(r / ||r||) is its right-hand side and, from d = 0, its residual;
+// z = D^-1 c, p = z; tile partials of c.c and c.z in binary32.
+__global__ __launch_bounds__(kBB) void mixed_lane_start_kernel(BArgs a64, BArgsT<float> a32, int si,
+                                                               int j)
+{
+    __shared__ float red[2 * (kBB / kWave)];
+    const BSys &S = a64.sys[si];
+    const BSysT<float> &F = a32.sys[si];
+    const BScal c64 = a64.scal[S.scal0 + j];
+    if (c64.status != CGX_PENDING) return;  // the whole grid returns
+    const double sigma = sqrt(c64.rr);
+    const int row0 = blockIdx.x * S.trows, row1 = min(S.n, row0 + S.trows);
+    float part[2] = {0.0f, 0.0f};
+    for (int row = row0 + threadIdx.x; row < row1; row += kBB) {
+        const int64_t e = (int64_t)row * S.K + j;
+        const float ci = (float)(S.r[e] / sigma);
+        const float zi = F.jac ? F.dinv[row] * ci : ci;
+        F.r[e] = ci;
+        F.x[e] = 0.0f;
+        F.p[e] = zi;
+        part[0] += ci * ci;
+        part[1] += ci * zi;
+    }
+    block_sum<2, kBB>(part, red);
+    if (threadIdx.x == 0) {
+        const int64_t t = (int64_t)(F.tile0 + blockIdx.x) * kMaxK + j;
+        a32.part[t] = part[0];
+        a32.part[a32.part_stride + t] = part[1];
+    }
+}
+
+// One workgroup: lane j's binary32 scalars for its next inner solve (or an
+// inactive lane when its float64 status is final), as batch_r0_kernel sets
+// them for a whole system: stop when ||c - A d|| <= inner_rtol ||c||.
+__global__ __launch_bounds__(kBB) void mixed_lane_inner_r0_kernel(BArgs a64, BArgsT<float> a32,
+                                                                  int si, int j)
+{
+    __shared__ float red[kBB / kWave];
+    const BSys &S = a64.sys[si];
+    const BSysT<float> &F = a32.sys[si];
+    float v[2];
+    for (int r = 0; r < 2; ++r) {
+        const float *base = a32.part + r * a32.part_stride;
+        float s[1] = {0.0f};
+        for (int q = threadIdx.x; q < F.ntiles; q += kBB) s[0] += base[(int64_t)(F.tile0 + q) * kMaxK + j];
+        block_sum<1, kBB>(s, red);
+        v[r] = s[0];
+        __syncthreads();  // red is reused by the next region
+    }
+    if (threadIdx.x == 0) {
+        BScalT<float> &c = a32.scal[F.scal0 + j];
+        c = BScalT<float>{};
+        if (a64.scal[S.scal0 + j].status != CGX_PENDING) {
+            c.status = CGX_OK;  // no inner solve: the lane is finished
+            return;
+        }
+        const float rr = v[0], rz = v[1];
+        c.rr = rr;
+        c.bb = rr;
+        c.rho = F.jac ? rz : rr;
+        c.stop2 = (float)F.rtol2 * rr;
+        int status = CGX_PENDING;
+        if (!isfinite(rr) || !isfinite(rz))
+            status = CGX_NONFINITE;
+        else if (rr == 0.0f || rr <= c.stop2)
+            status = CGX_OK;
+        else if (F.jac && !(rz > 0.0f))
+            status = CGX_BREAKDOWN;
+        c.status = status;
+        c.active = status == CGX_PENDING;
+        if (c.active) a32.sys_done[si] = 0;
+    }
+}
+
+// Heap block of a MIXED slot: float64 x, r, then binary32 d (the inner
+// solution, the binary32 system's x), r, p, q, all interleaved [n][K], and
+// binary32 D^-1 [n].  No larger than the float64 slot's block (x r p q z,
+// D^-1), which also holds the tuner's one-system plan.
+size_t mixed_slot_bytes(int64_t n, int K)
+{
+    return 2 * a256((size_t)n * K * sizeof(double)) + 4 * a256((size_t)n * K * sizeof(float)) +
+           a256((size_t)n * sizeof(float));
 }
 
 // Device descriptor of slot `si`: interleaved x r p q z of its K lanes and
-// dinv at the start of its heap block; b / x of each request through the
-// slot's lane table (null for a free lane).
+// dinv at the start of its heap block (MIXED slot: x and r only); b / x of
+// each request through the slot's lane table (null for a free lane).
 BSys slot_sys(const Engine &E, int si, int tile0)
 {
     const Slot &s = E.slots[si];
@@ -195,9 +417,14 @@ BSys slot_sys(const Engine &E, int si, int tile0)
     S.lanes = reinterpret_cast<const LanePtr *>(E.pool + E.off_lanes) + (size_t)si * kMaxK;
     const size_t vb = a256((size_t)q.A.n_rows * s.K * sizeof(double));
     char *base = E.pool + s.off;
-    double **vecs[5] = {&S.x, &S.r, &S.p, &S.q, &S.z};
-    for (int v = 0; v < 5; ++v) *vecs[v] = reinterpret_cast<double *>(base + v * vb);
-    S.dinv = reinterpret_cast<double *>(base + 5 * vb);
+    if (s.mixed) {
+        S.x = reinterpret_cast<double *>(base);
+        S.r = reinterpret_cast<double *>(base + vb);
+    } else {
+        double **vecs[5] = {&S.x, &S.r, &S.p, &S.q, &S.z};
+        for (int v = 0; v < 5; ++v) *vecs[v] = reinterpret_cast<double *>(base + v * vb);
+        S.dinv = reinterpret_cast<double *>(base + 5 * vb);
+    }
     S.nnz = q.A.nnz;
     S.n = q.A.n_rows;
     S.n_cols = q.A.n_cols;
@@ -214,6 +441,57 @@ BSys slot_sys(const Engine &E, int si, int tile0)
     return S;
 }
 
+// Binary32 descriptor of MIXED slot `si` (the inner solves): values val32,
+// vectors after the float64 x and r of its heap block, tolerance inner_rtol,
+// iteration cap maxit per inner solve.
+BSysT<float> slot_sys32(const Engine &E, int si, int tile0)
+{
+    const Slot &s = E.slots[si];
+    const Request &q = s.key;
+    BSysT<float> F{};
+    F.rp = q.A.row_ptr;
+    F.ci = q.A.col_idx;
+    F.val = q.A.val32;
+    const size_t n = (size_t)q.A.n_rows;
+    const size_t vb64 = a256(n * s.K * sizeof(double)), vb = a256(n * s.K * sizeof(float));
+    char *base = E.pool + s.off + 2 * vb64;
+    float **vecs[4] = {&F.x, &F.r, &F.p, &F.q};
+    for (int v = 0; v < 4; ++v) *vecs[v] = reinterpret_cast<float *>(base + v * vb);
+    F.dinv = reinterpret_cast<float *>(base + 4 * vb);
+    F.nnz = q.A.nnz;
+    F.n = q.A.n_rows;
+    F.n_cols = q.A.n_cols;
+    F.K = s.K;
+    F.nrhs = s.K;
+    F.M = s.M;
+    F.trows = tile_rows_for(s.K, false);
+    F.tile0 = tile0;
+    F.ntiles = s.ntiles;
+    F.scal0 = si * kMaxK;
+    F.jac = q.jac;
+    F.maxit = q.maxit;
+    F.rtol2 = q.inner_rtol * q.inner_rtol;
+    return F;
+}
+
+BArgsT<float> engine_args32(const Engine &E)
+{
+    BArgsT<float> a{};
+    a.sys = reinterpret_cast<const BSysT<float> *>(E.pool + E.off_sys32);
+    a.tiles = reinterpret_cast<const BTile *>(E.pool + E.off_tiles32);
+    a.list = reinterpret_cast<const int32_t *>(E.pool + E.off_list32);
+    a.scal = reinterpret_cast<BScalT<float> *>(E.pool + E.off_scal32);
+    a.sys_done = reinterpret_cast<int32_t *>(E.pool + E.off_done32);
+    a.part = reinterpret_cast<float *>(E.pool + E.off_part32);
+    a.part_stride = E.max_tiles * kMaxK;
+    a.ntiles = E.active_tiles32;
+    a.nlist = E.nlist32;
+    a.wave_lds = 0;
+    for (const Slot &sl : E.slots)
+        if (sl.used && sl.mixed && sl.M < 0) a.wave_lds = kWaveStageBytes;
+    return a;
+}
+
 BArgs engine_args(const Engine &E, bool fresh, int ntiles, int nlist)
 {
     BArgs a{};
@@ -228,7 +506,7 @@ BArgs engine_args(const Engine &E, bool fresh, int ntiles, int nlist)
     a.nlist = nlist;
     a.wave_lds = 0;
     for (const Slot &sl : E.slots)
-        if (sl.used && sl.M < 0) a.wave_lds = kWaveStageBytes;
+        if (sl.used && !sl.mixed && sl.M < 0) a.wave_lds = kWaveStageBytes;
     return a;
 }
 
@@ -243,57 +521,83 @@ BArgs engine_args(const Engine &E, bool fresh, int ntiles, int nlist)
     } while (0)
 
 // One cycle's device work: rebuild tables if membership changed, initialise
-// fresh slots and the lanes requests joined, run `iters` iterations, read
-// back the slot states.
+// fresh slots and the lanes requests joined, take the float64 steps of the
+// MIXED lanes whose inner solve ended, run `iters` iterations (float64 slots
+// and binary32 inner solves), read back the slot states.  `active` receives
+// every used slot.
 bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
 {
     hipStream_t s = E.stream;
     if (changed) {
         std::vector<BSys> sys(E.max_slots);
-        std::vector<BTile> tiles, tiles2;
-        std::vector<int32_t> list, list2;
+        std::vector<BSysT<float>> sys32(E.max_slots);
+        std::vector<BTile> tiles, tiles2, tiles32;
+        std::vector<int32_t> list, list2, list32, fresh32;
+        int next_tile = 0;  // one numbering for the tiles of both tables
+        active.clear();
         for (int i = 0; i < E.max_slots; ++i) {
             const Slot &sl = E.slots[i];
             if (!sl.used) continue;
-            const int tile0 = (int)tiles.size();
+            const int tile0 = next_tile;
+            next_tile += sl.ntiles;
             sys[i] = slot_sys(E, i, tile0);
+            if (sl.mixed) sys32[i] = slot_sys32(E, i, tile0);
             for (int t = 0; t < sl.ntiles; ++t) {
                 BTile bt{};
                 bt.sys = i;
                 bt.row0 = t * sys[i].trows;
                 bt.rows = std::min(sys[i].trows, sys[i].n - bt.row0);
-                bt.tile = (int)tiles.size();
-                tiles.push_back(bt);
-                if (sl.fresh) tiles2.push_back(bt);
+                bt.tile = tile0 + t;
+                (sl.mixed ? tiles32 : tiles).push_back(bt);
+                if (sl.fresh && !sl.mixed) tiles2.push_back(bt);
             }
-            list.push_back(i);
-            if (sl.fresh) list2.push_back(i);
+            (sl.mixed ? list32 : list).push_back(i);
+            if (sl.fresh) (sl.mixed ? fresh32 : list2).push_back(i);
+            active.push_back(i);
         }
         ENG_CHECK(hipMemcpyAsync(E.pool + E.off_sys, sys.data(), sizeof(BSys) * sys.size(),
                                  hipMemcpyHostToDevice, s));
+        if (!list32.empty())
+            ENG_CHECK(hipMemcpyAsync(E.pool + E.off_sys32, sys32.data(),
+                                     sizeof(BSysT<float>) * sys32.size(), hipMemcpyHostToDevice, s));
         if (!tiles.empty())
             ENG_CHECK(hipMemcpyAsync(E.pool + E.off_tiles, tiles.data(), sizeof(BTile) * tiles.size(),
                                      hipMemcpyHostToDevice, s));
         if (!list.empty())
             ENG_CHECK(hipMemcpyAsync(E.pool + E.off_list, list.data(), sizeof(int32_t) * list.size(),
                                      hipMemcpyHostToDevice, s));
+        if (!tiles32.empty())
+            ENG_CHECK(hipMemcpyAsync(E.pool + E.off_tiles32, tiles32.data(),
+                                     sizeof(BTile) * tiles32.size(), hipMemcpyHostToDevice, s));
+        if (!list32.empty())
+            ENG_CHECK(hipMemcpyAsync(E.pool + E.off_list32, list32.data(),
+                                     sizeof(int32_t) * list32.size(), hipMemcpyHostToDevice, s));
+        E.active_tiles = (int)tiles.size();
+        E.active_tiles32 = (int)tiles32.size();
+        E.nlist64 = (int)list.size();
+        E.nlist32 = (int)list32.size();
+        const std::vector<BScal> zero(kMaxK);
+        const std::vector<BScalT<float>> zero32(kMaxK);
+        const int32_t zd = 0, one = 1;
+        auto upload_lanes = [&](int i) -> bool {
+            LanePtr lanes[kMaxK] = {};
+            const Slot &sl = E.slots[i];
+            for (int j = 0; j < sl.K; ++j)
+                if (sl.state[j] != kLaneFree) lanes[j] = {sl.lane[j].b, sl.lane[j].x};
+            ENG_CHECK(hipMemcpyAsync(E.pool + E.off_lanes + sizeof(LanePtr) * kMaxK * i, lanes,
+                                     sizeof(lanes), hipMemcpyHostToDevice, s));
+            ENG_CHECK(hipMemcpyAsync(E.pool + E.off_scal + sizeof(BScal) * kMaxK * i, zero.data(),
+                                     sizeof(BScal) * kMaxK, hipMemcpyHostToDevice, s));
+            return true;
+        };
         if (!list2.empty()) {
             ENG_CHECK(hipMemcpyAsync(E.pool + E.off_tiles2, tiles2.data(),
                                      sizeof(BTile) * tiles2.size(), hipMemcpyHostToDevice, s));
             ENG_CHECK(hipMemcpyAsync(E.pool + E.off_list2, list2.data(),
                                      sizeof(int32_t) * list2.size(), hipMemcpyHostToDevice, s));
-            const std::vector<BScal> zero(kMaxK);
-            const int32_t zd = 0;
             for (int i : list2) {
-                LanePtr lanes[kMaxK] = {};
                 Slot &sl = E.slots[i];
-                for (int j = 0; j < sl.K; ++j)
-                    if (sl.state[j] != kLaneFree) lanes[j] = {sl.lane[j].b, sl.lane[j].x};
-                ENG_CHECK(hipMemcpyAsync(E.pool + E.off_lanes + sizeof(LanePtr) * kMaxK * i, lanes,
-                                         sizeof(lanes), hipMemcpyHostToDevice, s));
-                ENG_CHECK(hipMemcpyAsync(E.pool + E.off_scal + sizeof(BScal) * kMaxK * i,
-                                         zero.data(), sizeof(BScal) * kMaxK,
-                                         hipMemcpyHostToDevice, s));
+                if (!upload_lanes(i)) return false;
                 ENG_CHECK(hipMemcpyAsync(E.pool + E.off_done + sizeof(int32_t) * i, &zd,
                                          sizeof(int32_t), hipMemcpyHostToDevice, s));
                 for (int j = 0; j < sl.K; ++j)
@@ -306,11 +610,35 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
             ENG_CHECK(hipGetLastError());
             for (int i : list2) E.slots[i].fresh = false;
         }
-        active.assign(list.begin(), list.end());
-        E.active_tiles = (int)tiles.size();
+        // fresh MIXED slots: D^-1 in binary32; every lane starts with its
+        // first float64 step below
+        for (int i : fresh32) {
+            Slot &sl = E.slots[i];
+            if (!upload_lanes(i)) return false;
+            ENG_CHECK(hipMemcpyAsync(E.pool + E.off_scal32 + sizeof(BScalT<float>) * kMaxK * i,
+                                     zero32.data(), sizeof(BScalT<float>) * kMaxK,
+                                     hipMemcpyHostToDevice, s));
+            ENG_CHECK(hipMemcpyAsync(E.pool + E.off_done32 + sizeof(int32_t) * i, &one,
+                                     sizeof(int32_t), hipMemcpyHostToDevice, s));
+            ENG_CHECK(hipMemcpyAsync(E.pool + E.off_bad + sizeof(int32_t) * i, &zd, sizeof(int32_t),
+                                     hipMemcpyHostToDevice, s));
+            if (sl.key.jac)
+                hipLaunchKernelGGL(mixed_setup_kernel, dim3(sl.ntiles), dim3(kBB), 0, s,
+                                   reinterpret_cast<const BSysT<float> *>(E.pool + E.off_sys32),
+                                   reinterpret_cast<int32_t *>(E.pool + E.off_bad), i);
+            for (int j = 0; j < sl.K; ++j)
+                if (sl.state[j] == kLaneJoining) {
+                    sl.state[j] = kLaneRunning;
+                    sl.need_outer[j] = 1;
+                    sl.first[j] = 1;
+                }
+            sl.fresh = false;
+        }
+        ENG_CHECK(hipGetLastError());
     }
     // requests that joined a free lane of a running slot: set that lane up
-    const BArgs m = engine_args(E, false, E.active_tiles, (int)active.size());
+    const BArgs m = engine_args(E, false, E.active_tiles, E.nlist64);
+    const BArgsT<float> m32 = engine_args32(E);
     for (int i : active) {
         Slot &sl = E.slots[i];
         for (int j = 0; j < sl.K; ++j) {
@@ -321,22 +649,50 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
                                      sizeof(lp), hipMemcpyHostToDevice, s));
             ENG_CHECK(hipMemcpyAsync(E.pool + E.off_scal + sizeof(BScal) * (kMaxK * i + j), &zero,
                                      sizeof(zero), hipMemcpyHostToDevice, s));
+            sl.state[j] = kLaneRunning;
+            if (sl.mixed) {
+                sl.need_outer[j] = 1;
+                sl.first[j] = 1;
+                continue;
+            }
             hipLaunchKernelGGL(lane_init_kernel, dim3(sl.ntiles), dim3(kBB), 0, s, m, i, j);
             hipLaunchKernelGGL(lane_r0_kernel, dim3(1), dim3(kBB), 0, s, m, i, j);
             ENG_CHECK(hipGetLastError());
-            sl.state[j] = kLaneRunning;
         }
     }
-    const int ntiles = E.active_tiles;
-    if (!active.empty() && ntiles > 0) {
-        const BArgs a = engine_args(E, false, ntiles, (int)active.size());
-        for (int k = 0; k < iters; ++k) launch_batch_iteration(a, s);
-        ENG_CHECK(hipGetLastError());
+    // float64 steps of MIXED lanes: fold d into x (or take x0), r = b - A x,
+    // stopping test, next inner solve's start
+    const int32_t *bad = reinterpret_cast<const int32_t *>(E.pool + E.off_bad);
+    for (int i : active) {
+        Slot &sl = E.slots[i];
+        if (!sl.mixed) continue;
+        for (int j = 0; j < sl.K; ++j) {
+            if (sl.state[j] != kLaneRunning || !sl.need_outer[j]) continue;
+            const dim3 g(sl.ntiles);
+            hipLaunchKernelGGL(mixed_lane_x_kernel, g, dim3(kBB), 0, s, m, m32, i, j, (int)sl.first[j]);
+            hipLaunchKernelGGL(mixed_lane_residual_kernel, g, dim3(kBB), 0, s, m, i, j);
+            hipLaunchKernelGGL(mixed_lane_outer_kernel, dim3(1), dim3(kBB), 0, s, m, bad, i, j,
+                               (int)(sl.outer[j] >= sl.key.max_outer));
+            hipLaunchKernelGGL(mixed_lane_start_kernel, g, dim3(kBB), 0, s, m, m32, i, j);
+            hipLaunchKernelGGL(mixed_lane_inner_r0_kernel, dim3(1), dim3(kBB), 0, s, m, m32, i, j);
+            ENG_CHECK(hipGetLastError());
+            sl.need_outer[j] = 0;
+            sl.first[j] = 0;
+            sl.outer_ran[j] = 1;
+        }
     }
+    if (E.nlist64 > 0 && E.active_tiles > 0)
+        for (int k = 0; k < iters; ++k) launch_batch_iteration(m, s);
+    if (E.nlist32 > 0 && E.active_tiles32 > 0)
+        for (int k = 0; k < iters; ++k) launch_batch_iteration(m32, s);
+    ENG_CHECK(hipGetLastError());
     ENG_CHECK(hipMemcpyAsync(E.h_done, E.pool + E.off_done, sizeof(int32_t) * E.max_slots,
                              hipMemcpyDeviceToHost, s));
     ENG_CHECK(hipMemcpyAsync(E.h_scal, E.pool + E.off_scal, sizeof(BScal) * kMaxK * E.max_slots,
                              hipMemcpyDeviceToHost, s));
+    if (E.nlist32 > 0)
+        ENG_CHECK(hipMemcpyAsync(E.h_scal32, E.pool + E.off_scal32,
+                                 sizeof(BScalT<float>) * kMaxK * E.max_slots, hipMemcpyDeviceToHost, s));
     ENG_CHECK(hipStreamSynchronize(s));
     return true;
 }
@@ -362,13 +718,16 @@ bool admit(Engine &E, int &ntiles_active)
     for (size_t h = 0; h < pending.size(); ++h)
         for (int i = 0; i < E.max_slots; ++i) {
             Slot &sl = E.slots[i];
-            if (!sl.used || sl.fresh || E.h_done[i] || !same_group(sl.key, pending[h])) continue;
+            const bool finishing = sl.mixed ? sl.running() == 0 : E.h_done[i] != 0;
+            if (!sl.used || sl.fresh || finishing || !same_group(sl.key, pending[h])) continue;
             const int j = sl.free_lane();
             if (j < 0 || sl.running() >= E.max_group) continue;
             sl.lane[j] = pending[h];
             sl.state[j] = kLaneJoining;
             sl.t_start[j] = t;
             sl.sharing[j] = sl.running();
+            sl.need_outer[j] = sl.first[j] = sl.outer_ran[j] = 0;
+            sl.outer[j] = sl.inner_sum[j] = 0;
             taken[h] = 1;
             joined = true;
             break;
@@ -395,6 +754,7 @@ bool admit(Engine &E, int &ntiles_active)
             K = pad_k(g);
             if (K == g && spare) K = pad_k(g + 1);
             bytes = group_bytes(pending[h].A.n_rows, K);
+            if (pending[h].mixed) bytes = std::max(bytes, mixed_slot_bytes(pending[h].A.n_rows, K));
             nt = tiles_of(pending[h].A.n_rows, K);
             if (ntiles_active + nt <= E.max_tiles && E.alloc(bytes, off)) {
                 fits = true;
@@ -412,10 +772,16 @@ bool admit(Engine &E, int &ntiles_active)
         sl.fresh = true;
         sl.K = K;
         sl.key = pending[h];
+        sl.mixed = pending[h].mixed != 0;
         sl.lane.assign(K, Request{});
         sl.state.assign(K, kLaneFree);
         sl.t_start.assign(K, t);
         sl.sharing.assign(K, (int)members.size());
+        sl.need_outer.assign(K, 0);
+        sl.first.assign(K, 0);
+        sl.outer_ran.assign(K, 0);
+        sl.outer.assign(K, 0);
+        sl.inner_sum.assign(K, 0);
         for (size_t q = 0; q < members.size(); ++q) {
             sl.lane[q] = pending[members[q]];
             sl.state[q] = kLaneJoining;
@@ -474,7 +840,9 @@ void engine_loop(Engine *Ep)
         // iterations this cycle: about 1 ms of device work
         double bytes = 0.0;
         for (const Slot &sl : E.slots)
-            if (sl.used) bytes += 12.0 * sl.key.A.nnz + 88.0 * sl.K * sl.key.A.n_rows;
+            if (sl.used)
+                bytes += sl.mixed ? 8.0 * sl.key.A.nnz + 44.0 * sl.K * sl.key.A.n_rows
+                                  : 12.0 * sl.key.A.nnz + 88.0 * sl.K * sl.key.A.n_rows;
         int iters = (int)(1.0e-3 / (bytes / 4.0e12 + 25.0e-6));
         iters = iters < 1 ? 1 : (iters > 16 ? 16 : iters);
         if (!device_cycle(E, changed, iters, active)) {
@@ -489,29 +857,57 @@ void engine_loop(Engine *Ep)
         std::vector<std::pair<uint64_t, cgx_stats>> finished;
         const BSys *dsys = reinterpret_cast<const BSys *>(E.pool + E.off_sys);
         const BScal *dscal = reinterpret_cast<const BScal *>(E.pool + E.off_scal);
+        auto retire = [&](int i, int j, const BScal &v, int iters, int outer) {
+            Slot &sl = E.slots[i];
+            const Request &q = sl.lane[j];
+            cgx_stats st{};
+            st.status = v.status == CGX_PENDING ? CGX_NOT_CONVERGED : v.status;
+            st.iters = iters;
+            st.outer_iters = outer;
+            st.slot_requests = sl.sharing[j];
+            st.path = 4;
+            st.relres = v.bb > 0.0 ? std::sqrt(v.rr / v.bb) : 0.0;
+            if (v.bb == 0.0 && v.status == CGX_OK) st.relres = 0.0;
+            st.relres_true = -1.0;
+            st.queue_ms = 1e3 * (sl.t_start[j] - q.t_submit);
+            st.latency_ms = 1e3 * (t - q.t_submit);
+            hipLaunchKernelGGL(lane_out_kernel, dim3(256), dim3(kBB), 0, E.stream, dsys, i, j, dscal);
+            finished.emplace_back(q.ticket, st);
+            sl.state[j] = kLaneFree;
+        };
         for (int i : active) {
             Slot &sl = E.slots[i];
             if (!sl.used) continue;
-            for (int j = 0; j < sl.K; ++j) {
-                const BScal &v = E.h_scal[(size_t)i * kMaxK + j];
-                if (sl.state[j] != kLaneRunning || (v.active && !E.h_done[i])) continue;
-                const Request &q = sl.lane[j];
-                cgx_stats st{};
-                st.status = v.status == CGX_PENDING ? CGX_NOT_CONVERGED : v.status;
-                st.iters = v.iter;
-                st.outer_iters = sl.sharing[j];
-                st.path = 4;
-                st.relres = v.bb > 0.0 ? std::sqrt(v.rr / v.bb) : 0.0;
-                if (v.bb == 0.0 && v.status == CGX_OK) st.relres = 0.0;
-                st.relres_true = -1.0;
-                st.queue_ms = 1e3 * (sl.t_start[j] - q.t_submit);
-                st.latency_ms = 1e3 * (t - q.t_submit);
-                hipLaunchKernelGGL(lane_out_kernel, dim3(256), dim3(kBB), 0, E.stream, dsys, i, j,
-                                   dscal);
-                finished.emplace_back(q.ticket, st);
-                sl.state[j] = kLaneFree;
+            if (sl.mixed) {
+                // a lane whose float64 step ran this cycle is finished if its
+                // status is final; a lane whose inner solve ended takes its
+                // next float64 step at the next cycle
+                for (int j = 0; j < sl.K; ++j) {
+                    if (sl.state[j] != kLaneRunning) continue;
+                    const BScal &v = E.h_scal[(size_t)i * kMaxK + j];
+                    if (sl.outer_ran[j]) {
+                        sl.outer_ran[j] = 0;
+                        if (v.status != CGX_PENDING) {
+                            retire(i, j, v, sl.inner_sum[j], sl.outer[j]);
+                            continue;
+                        }
+                        ++sl.outer[j];
+                    }
+                    const BScalT<float> &f = E.h_scal32[(size_t)i * kMaxK + j];
+                    if (!f.active) {
+                        sl.inner_sum[j] += f.iter;
+                        sl.need_outer[j] = 1;
+                    }
+                }
+                if (sl.running() > 0) continue;
+            } else {
+                for (int j = 0; j < sl.K; ++j) {
+                    const BScal &v = E.h_scal[(size_t)i * kMaxK + j];
+                    if (sl.state[j] != kLaneRunning || (v.active && !E.h_done[i])) continue;
+                    retire(i, j, v, v.iter, sl.sharing[j]);
+                }
+                if (!E.h_done[i]) continue;
             }
-            if (!E.h_done[i]) continue;
             E.release(sl.off, sl.bytes);
             ntiles_active -= sl.ntiles;
             sl.used = false;
@@ -575,6 +971,20 @@ int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots, in
     off += a256(sizeof(BTile) * E->max_tiles);
     E->off_part = off;
     off += a256(sizeof(double) * 3 * E->max_tiles * kMaxK);
+    E->off_sys32 = off;
+    off += a256(sizeof(BSysT<float>) * max_slots);
+    E->off_list32 = off;
+    off += a256(sizeof(int32_t) * max_slots);
+    E->off_scal32 = off;
+    off += a256(sizeof(BScalT<float>) * kMaxK * max_slots);
+    E->off_done32 = off;
+    off += a256(sizeof(int32_t) * max_slots);
+    E->off_bad = off;
+    off += a256(sizeof(int32_t) * max_slots);
+    E->off_tiles32 = off;
+    off += a256(sizeof(BTile) * E->max_tiles);
+    E->off_part32 = off;
+    off += a256(sizeof(float) * 3 * E->max_tiles * kMaxK);
     E->heap0 = off;
     if (off >= pool_bytes) {
         delete E;
@@ -585,10 +995,12 @@ int serve_start(Context *c, void *pool, size_t pool_bytes, int32_t max_slots, in
     E->slots.resize(max_slots);
     hipError_t e = hipHostMalloc(&E->h_scal, sizeof(BScal) * kMaxK * max_slots);
     if (e == hipSuccess) e = hipHostMalloc(&E->h_done, sizeof(int32_t) * max_slots);
+    if (e == hipSuccess) e = hipHostMalloc(&E->h_scal32, sizeof(BScalT<float>) * kMaxK * max_slots);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         if (E->h_scal) (void)hipHostFree(E->h_scal);
         if (E->h_done) (void)hipHostFree(E->h_done);
+        if (E->h_scal32) (void)hipHostFree(E->h_scal32);
         delete E;
         set_error(std::string("serve_start: ") + hipGetErrorString(e));
         return CGX_EHIP;
@@ -617,6 +1029,7 @@ int serve_stop(Context *c)
     (void)hipStreamDestroy(E->stream);
     (void)hipHostFree(E->h_scal);
     (void)hipHostFree(E->h_done);
+    (void)hipHostFree(E->h_scal32);
     delete E;
     c->engine = nullptr;
     if (fail) {
@@ -643,6 +1056,9 @@ int serve_submit(Context *c, const cgx_csr *A, const double *b, double *x, const
     q.jac = o->precond == CGX_PRECOND_JACOBI ? 1 : 0;
     q.maxit = o->maxit > 0 ? o->maxit : std::max(A->n_rows, 1);
     q.rtol = o->rtol;
+    q.mixed = o->precision == CGX_PRECISION_MIXED ? 1 : 0;
+    q.inner_rtol = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-3;
+    q.max_outer = o->max_outer > 0 ? o->max_outer : 100;
     q.bytes = request_bytes(A->n_rows);
     std::lock_guard<std::mutex> lk(E->mu);
     if (E->fail) {

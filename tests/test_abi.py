@@ -49,7 +49,7 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {{
   printf("%zu %zu %zu %zu\\n", sizeof(cgx_csr), offsetof(cgx_csr, row_ptr), offsetof(cgx_csr, val32), offsetof(cgx_csr, nnz));
   printf("%zu %zu %zu %zu %zu\\n", sizeof(cgx_opts), offsetof(cgx_opts, inner_rtol), offsetof(cgx_opts, max_outer), offsetof(cgx_opts, true_residual), offsetof(cgx_opts, profile));
-  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(cgx_stats), offsetof(cgx_stats, relres), offsetof(cgx_stats, device_ms), offsetof(cgx_stats, phase_ms), offsetof(cgx_stats, kappa_est), offsetof(cgx_stats, ritz_max));
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cgx_stats), offsetof(cgx_stats, relres), offsetof(cgx_stats, device_ms), offsetof(cgx_stats, phase_ms), offsetof(cgx_stats, kappa_est), offsetof(cgx_stats, ritz_max), offsetof(cgx_stats, slot_requests));
   printf("%zu %zu %zu %zu\\n", sizeof(cgx_sell), offsetof(cgx_sell, n_slices), offsetof(cgx_sell, slice_ptr), offsetof(cgx_sell, val32));
   printf("%zu %zu %zu\\n", sizeof(cgx_system), offsetof(cgx_system, schedule), offsetof(cgx_system, X));
   printf("%zu %zu %zu %zu\\n", sizeof(cgx_schwarz), offsetof(cgx_schwarz, local_rows), offsetof(cgx_schwarz, nnz_off), offsetof(cgx_schwarz, val));
@@ -65,7 +65,7 @@ int main(void) {{
     assert c[1] == [ctypes.sizeof(O), O.inner_rtol.offset, O.max_outer.offset, O.true_residual.offset,
                     O.profile.offset]
     assert c[2] == [ctypes.sizeof(T), T.relres.offset, T.device_ms.offset, T.phase_ms.offset,
-                    T.kappa_est.offset, T.ritz_max.offset]
+                    T.kappa_est.offset, T.ritz_max.offset, T.slot_requests.offset]
     L, Y = cgx._Sell, cgx._System
     assert c[3] == [ctypes.sizeof(L), L.n_slices.offset, L.slice_ptr.offset, L.val32.offset]
     assert c[4] == [ctypes.sizeof(Y), Y.schedule.offset, Y.X.offset]
