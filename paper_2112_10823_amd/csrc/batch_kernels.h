@@ -48,7 +48,8 @@ struct BTile {
 template <typename T>
 struct BScalT {
     T rho, rho_used, alpha, beta, rr, bb, stop2, pq;
-    int32_t iter, status, active, pad;
+    int32_t iter, status, active, pad;  // pad: a diagonal entry <= 0 met at setup
+    int32_t xstep, pad2;                // xstep: x += alpha p due in this iteration's p update
 };
 using BScal = BScalT<double>;
 
@@ -58,7 +59,8 @@ struct BArgsT {
     const BTile *tiles;     // tiles this launch covers (one workgroup each)
     const int32_t *list;    // systems the per-system kernels cover (one workgroup each)
     BScalT<T> *scal;
-    int32_t *sys_done;      // per system: all right-hand sides finished
+    int32_t *sys_done;      // per system: 0 running; 2 all right-hand sides finished, the
+                            // last x steps pending in this iteration's p update; 1 done
     T *part;                // 3 regions of part_stride values
     int64_t part_stride;    // (tiles of the whole table) * 16
     int ntiles;
@@ -683,17 +685,25 @@ __global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgsT<T> a)
     block_sum_by_rhs(ppq, S.K, red, a.part + (int64_t)t.tile * kMaxK);
 }
 
-// (R1) alpha per right-hand side; breakdown / non-finite p.q ends it.
+// (R1) alpha per right-hand side; breakdown / non-finite p.q ends it.  A
+// system whose last x steps were taken (state 2) becomes done (1).
 template <typename T>
 __global__ __launch_bounds__(kBB) void batch_r1_kernel(BArgsT<T> a)
 {
     __shared__ T red[kBB];
+    __shared__ int any_active;
     const int sid = a.list[blockIdx.x];
-    if (a.sys_done[sid]) return;
+    const int done = a.sys_done[sid];
+    if (done) {
+        if (done == 2 && threadIdx.x == 0) a.sys_done[sid] = 1;
+        return;
+    }
     const BSysT<T> S = a.sys[sid];
-    const T pq = sys_sum(a, S, 0, red);
+    if (threadIdx.x == 0) any_active = 0;
+    const T pq = sys_sum(a, S, 0, red);  // its barriers order any_active's reset
     if (threadIdx.x < S.K) {
         BScalT<T> &c = a.scal[S.scal0 + threadIdx.x];
+        c.xstep = 0;
         if (c.active) {
             c.pq = pq;
             if (!isfinite(pq) || !(pq > T(0))) {
@@ -703,13 +713,18 @@ __global__ __launch_bounds__(kBB) void batch_r1_kernel(BArgsT<T> a)
                 c.alpha = c.rho / pq;
                 c.rho_used = c.rho;
                 c.iter += 1;
+                c.xstep = 1;
+                atomicOr(&any_active, 1);
             }
         }
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && !any_active) a.sys_done[sid] = 1;  // no x step left either
 }
 
-// (2) x += alpha p, r -= alpha q, z = D^-1 r for active right-hand sides;
-// r.r and r.z partials.
+// (2) r -= alpha q, z = D^-1 r for active right-hand sides; r.r and r.z
+// partials.  x += alpha p is taken in the p update (3), which reads p
+// anyway, so that p is read once per iteration outside the SpMM.
 template <typename T>
 __global__ __launch_bounds__(kBB) void batch_update_kernel(BArgsT<T> a)
 {
@@ -729,9 +744,7 @@ __global__ __launch_bounds__(kBB) void batch_update_kernel(BArgsT<T> a)
         int row = t.row0 + (int)threadIdx.x / S.K;
 #pragma unroll 4
         for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB, row += drow) {
-            const T xi = fma_t(alpha, S.p[e], S.x[e]);
             const T ri = fma_t(-alpha, S.q[e], S.r[e]);
-            S.x[e] = xi;
             S.r[e] = ri;
             prr += ri * ri;
             if (S.jac) {  // z = D^-1 r is not stored: the p update forms it again
@@ -745,7 +758,8 @@ __global__ __launch_bounds__(kBB) void batch_update_kernel(BArgsT<T> a)
     block_sum_by_rhs(prz, S.K, red, base + 2 * a.part_stride);
 }
 
-// (R2) stopping test and beta per right-hand side; system-done flag.
+// (R2) stopping test and beta per right-hand side; when none stays active
+// the system enters state 2 (its last x steps follow in the p update).
 template <typename T>
 __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
 {
@@ -783,34 +797,45 @@ __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0 && !any_active) a.sys_done[sid] = 1;
+    if (threadIdx.x == 0 && !any_active) a.sys_done[sid] = 2;
 }
 
-// (3) p = z + beta p for active right-hand sides, z = D^-1 r formed here
-// (the same product as in the update, so the same bits) instead of being
-// stored by the update and read back: D^-1 has one value per row, z one per
-// (row, right-hand side).
+// (3) x += alpha p for the right-hand sides that took a step this
+// iteration, then p = z + beta p for those still active, z = D^-1 r formed
+// here (the same product as in the update, so the same bits) instead of
+// being stored by the update and read back: D^-1 has one value per row, z
+// one per (row, right-hand side).
 template <typename T>
 __global__ __launch_bounds__(kBB) void batch_direction_kernel(BArgsT<T> a)
 {
     const int w = xcd_block(blockIdx.x, gridDim.x);
     const BTile t = a.tiles[w];
-    if (a.sys_done[t.sys]) return;
+    if (a.sys_done[t.sys] == 1) return;
     const BSysT<T> S = a.sys[t.sys];
     const int j = threadIdx.x % S.K;
     const BScalT<T> c = a.scal[S.scal0 + j];
-    if (!c.active) return;
-    const T beta = c.beta;
+    if (!c.xstep) return;
+    const T alpha = c.alpha, beta = c.beta;
     const int64_t e0 = (int64_t)t.row0 * S.K, e1 = (int64_t)(t.row0 + t.rows) * S.K;
-    if (S.jac) {
+    if (!c.active) {  // finished in this iteration: its last x step only
+#pragma unroll 4
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) S.x[e] = fma_t(alpha, S.p[e], S.x[e]);
+    } else if (S.jac) {
         const int drow = kBB / S.K;
         int row = t.row0 + (int)threadIdx.x / S.K;
 #pragma unroll 4
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB, row += drow)
-            S.p[e] = fma_t(beta, S.p[e], S.dinv[row] * S.r[e]);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB, row += drow) {
+            const T pv = S.p[e];
+            S.x[e] = fma_t(alpha, pv, S.x[e]);
+            S.p[e] = fma_t(beta, pv, S.dinv[row] * S.r[e]);
+        }
     } else {
 #pragma unroll 4
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) S.p[e] = fma_t(beta, S.p[e], S.r[e]);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBB) {
+            const T pv = S.p[e];
+            S.x[e] = fma_t(alpha, pv, S.x[e]);
+            S.p[e] = fma_t(beta, pv, S.r[e]);
+        }
     }
 }
 

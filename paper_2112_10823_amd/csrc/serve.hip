@@ -16,10 +16,10 @@
 // Binary32-refined requests (MIXED) get slots of their own: float64 x and
 // residual, binary32 inner vectors and D^-1.  Their inner CG iterations run
 // in the batched binary32 kernels, all such slots in one launch per phase;
-// each lane's float64 step (fold the inner solution into x, r = b - A x,
-// stopping test, next inner right-hand side r / ||r||) is a short sequence
-// of one-lane kernels the engine issues at the start of the cycle after the
-// lane's inner solve ended.
+// the float64 step of a lane (fold the inner solution into x, r = b - A x,
+// stopping test, next inner right-hand side r / ||r||) is taken at the start
+// of the cycle after its inner solve ended, in one short kernel sequence per
+// slot for all of its lanes that are due.
 //
 // Device memory comes only from the caller's pool: a fixed arena (system
 // tables, lane table, work tables, scalars, reduction partials) at its start
@@ -208,9 +208,12 @@ bool same_group(const Request &a, const Request &b)
 }
 
 // ------------------------------------------------ MIXED slot kernels --
-// One lane j of MIXED slot si; S / F are the slot's float64 / binary32
-// descriptors, a workgroup per tile of trows rows (tile index S.tile0 +
-// blockIdx.x in the partials).
+// Float64 steps of the lanes of MIXED slot si in bit mask `mask` (lane j:
+// bit j), all at once; S / F are the slot's float64 / binary32 descriptors.
+// The tile kernels run a workgroup per tile of trows rows (partials at tile
+// S.tile0 + blockIdx.x) and, as the batched kernels, give thread t the lane
+// t % K.  A lane's arithmetic does not depend on which other lanes are in
+// the mask.
 
 // D^-1 of the slot from val32's diagonal, 1 / a_ii rounded once to binary32
 // from a float64 division (as the float32-refined batch forms it); a
@@ -232,76 +235,71 @@ __global__ __launch_bounds__(kBB) void mixed_setup_kernel(const BSysT<float> *sy
     if (b) bad[si] = 1;  // same value from every writer
 }
 
-// x[:, j] = caller x0 (first step) or fma(||r_prev||, double(d[:, j]),
+// x[:, j] = caller x0 (lanes in `first`) or fma(||r_prev||, double(d[:, j]),
 // x[:, j]): the inner solution folded into the float64 iterate.
-__global__ __launch_bounds__(kBB) void mixed_lane_x_kernel(BArgs a64, BArgsT<float> a32, int si,
-                                                           int j, int first)
+__global__ __launch_bounds__(kBB) void mixed_x_kernel(BArgs a64, BArgsT<float> a32, int si,
+                                                      uint32_t mask, uint32_t first)
 {
     const BSys &S = a64.sys[si];
     const BSysT<float> &F = a32.sys[si];
-    const int row0 = blockIdx.x * S.trows, row1 = min(S.n, row0 + S.trows);
+    const int j = threadIdx.x % S.K;
+    if (!((mask >> j) & 1u)) return;
+    const bool f0 = (first >> j) & 1u;
     const double sigma = sqrt(a64.scal[S.scal0 + j].rr);
     const double *x0 = S.lanes[j].x;
-    for (int row = row0 + threadIdx.x; row < row1; row += kBB) {
-        const int64_t e = (int64_t)row * S.K + j;
-        S.x[e] = first ? x0[row] : __builtin_fma(sigma, (double)F.x[e], S.x[e]);
-    }
-}
-
-// r[:, j] = b - A x[:, j] in float64 (8 lanes per row, each summing entries
-// m, m + 8, ..., then a butterfly) and the tile partials of r.r and b.b.
-__global__ __launch_bounds__(kBB) void mixed_lane_residual_kernel(BArgs a64, int si, int j)
-{
-    constexpr int L = 8;
-    __shared__ double red[2 * (kBB / kWave)];
-    const BSys &S = a64.sys[si];
     const int row0 = blockIdx.x * S.trows, row1 = min(S.n, row0 + S.trows);
-    const int m = threadIdx.x % L;
-    const double *b = S.lanes[j].b;
-    double part[2] = {0.0, 0.0};
-    for (int row = row0 + (int)threadIdx.x / L; row < row1; row += kBB / L) {
-        const int s0 = clampk(S.rp[row], S.nnz), s1 = max(s0, clampk(S.rp[row + 1], S.nnz));
-        double acc = 0.0;
-        for (int k = s0 + m; k < s1; k += L) {
-            const int c = S.ci[k];
-            if ((unsigned)c < (unsigned)S.n_cols) acc += S.val[k] * S.x[(int64_t)c * S.K + j];
-        }
-        acc = group_sum<L>(acc);
-        if (m == 0) {
-            const double bi = b[row];
-            const double ri = bi - acc;
-            S.r[(int64_t)row * S.K + j] = ri;
-            part[0] += ri * ri;
-            part[1] += bi * bi;
-        }
-    }
-    block_sum<2, kBB>(part, red);
-    if (threadIdx.x == 0) {
-        const int64_t t = (int64_t)(S.tile0 + blockIdx.x) * kMaxK + j;
-        a64.part[t] = part[0];
-        a64.part[a64.part_stride + t] = part[1];
-    }
+    const int64_t e1 = (int64_t)row1 * S.K;
+    int row = row0 + (int)threadIdx.x / S.K;
+    for (int64_t e = (int64_t)row0 * S.K + threadIdx.x; e < e1; e += kBB, row += kBB / S.K)
+        S.x[e] = f0 ? x0[row] : __builtin_fma(sigma, (double)F.x[e], S.x[e]);
 }
 
-// One workgroup: ||r||^2 and ||b||^2 of lane j from its tile partials (tile
-// order) and the float64 stopping test: b = 0 or ||r|| <= rtol ||b|| ends
-// it (CGX_OK), a bad Jacobi diagonal ends it (CGX_BREAKDOWN), and so does
-// the step after max_outer inner solves (`last`: CGX_NOT_CONVERGED).
-__global__ __launch_bounds__(kBB) void mixed_lane_outer_kernel(BArgs a64, const int32_t *bad, int si,
-                                                               int j, int last)
+// r = b - A x in float64 for the masked lanes (the row sums of the batched
+// setup pass: K * M lanes per row group, all K lanes gathering each column's
+// line) and the tile partials of r.r and b.b per lane.
+__global__ __launch_bounds__(kBB) void mixed_residual_kernel(BArgs a64, int si, uint32_t mask)
 {
-    __shared__ double red[kBB / kWave];
+    __shared__ double red[kBB];
     const BSys &S = a64.sys[si];
-    double v[2];
-    for (int r = 0; r < 2; ++r) {
-        const double *base = a64.part + r * a64.part_stride;
-        double s = 0.0;
-        for (int q = threadIdx.x; q < S.ntiles; q += kBB) s += base[(int64_t)(S.tile0 + q) * kMaxK + j];
-        v[r] = sum_partials_in_block(s, red);
+    const int M = setup_m(S);
+    const int G = S.K * M, gpw = kWave / G;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
+    const bool on = (mask >> j) & 1u;
+    const double *b = S.lanes[j].b;
+    const int row0 = blockIdx.x * S.trows, row1 = min(S.n, row0 + S.trows);
+    double prr = 0.0, pbb = 0.0;
+    for (int row = row0 + wave * gpw + grp; gpw >= 1 && row < row1; row += (kBB / kWave) * gpw) {
+        double dg;
+        const double ax = row_spmm(S, row, j, m, M, dg, S.x);
+        if (m == 0 && on) {
+            const double bi = b[row];
+            const double ri = bi - ax;
+            S.r[(int64_t)row * S.K + j] = ri;
+            prr += ri * ri;
+            pbb += bi * bi;
+        }
     }
-    if (threadIdx.x == 0) {
+    double *base = a64.part + (int64_t)(S.tile0 + blockIdx.x) * kMaxK;
+    block_sum_by_rhs(prr, S.K, red, base);
+    block_sum_by_rhs(pbb, S.K, red, base + a64.part_stride);
+}
+
+// One workgroup: ||r||^2 and ||b||^2 per masked lane from the tile partials
+// (fixed order) and the float64 stopping test: b = 0 or ||r|| <= rtol ||b||
+// ends the lane (CGX_OK), a bad Jacobi diagonal ends it (CGX_BREAKDOWN), and
+// so does the step after max_outer inner solves (lanes in `last`:
+// CGX_NOT_CONVERGED).
+__global__ __launch_bounds__(kBB) void mixed_outer_kernel(BArgs a64, const int32_t *bad, int si,
+                                                          uint32_t mask, uint32_t last)
+{
+    __shared__ double red[kBB];
+    const BSys &S = a64.sys[si];
+    const double rr = sys_sum(a64, S, 0, red);
+    const double bb = sys_sum(a64, S, 1, red);
+    const int j = threadIdx.x;
+    if (j < S.K && ((mask >> j) & 1u)) {
         BScal &c = a64.scal[S.scal0 + j];
-        const double rr = v[0], bb = v[1];
         c.rr = rr;
         c.bb = bb;
         int status = CGX_PENDING;
@@ -311,71 +309,67 @@ __global__ __launch_bounds__(kBB) void mixed_lane_outer_kernel(BArgs a64, const 
             status = CGX_OK;
         else if (S.jac && bad[si])
             status = CGX_BREAKDOWN;
-        else if (last)
+        else if ((last >> j) & 1u)
             status = CGX_NOT_CONVERGED;
         c.status = status;
         c.active = status == CGX_PENDING;
     }
 }
 
-// Start of lane j's next inner solve (float64 status still pending): c =
-// float(r / ||r||) is its right-hand side and, from d = 0, its residual;
-// z = D^-1 c, p = z; tile partials of c.c and c.z in binary32.
-__global__ __launch_bounds__(kBB) void mixed_lane_start_kernel(BArgs a64, BArgsT<float> a32, int si,
-                                                               int j)
+// Start of the next inner solve of each masked lane whose float64 status is
+// still pending: c = float(r / ||r||) is its right-hand side and, from d =
+// 0, its residual; z = D^-1 c, p = z; tile partials of c.c and c.z in
+// binary32.
+__global__ __launch_bounds__(kBB) void mixed_start_kernel(BArgs a64, BArgsT<float> a32, int si,
+                                                          uint32_t mask)
 {
-    __shared__ float red[2 * (kBB / kWave)];
+    __shared__ float red[kBB];
     const BSys &S = a64.sys[si];
     const BSysT<float> &F = a32.sys[si];
+    const int j = threadIdx.x % S.K;
     const BScal c64 = a64.scal[S.scal0 + j];
-    if (c64.status != CGX_PENDING) return;  // the whole grid returns
-    const double sigma = sqrt(c64.rr);
-    const int row0 = blockIdx.x * S.trows, row1 = min(S.n, row0 + S.trows);
-    float part[2] = {0.0f, 0.0f};
-    for (int row = row0 + threadIdx.x; row < row1; row += kBB) {
-        const int64_t e = (int64_t)row * S.K + j;
-        const float ci = (float)(S.r[e] / sigma);
-        const float zi = F.jac ? F.dinv[row] * ci : ci;
-        F.r[e] = ci;
-        F.x[e] = 0.0f;
-        F.p[e] = zi;
-        part[0] += ci * ci;
-        part[1] += ci * zi;
+    const bool on = ((mask >> j) & 1u) && c64.status == CGX_PENDING;
+    float prr = 0.0f, prz = 0.0f;
+    if (on) {
+        const double sigma = sqrt(c64.rr);
+        const int row0 = blockIdx.x * S.trows, row1 = min(S.n, row0 + S.trows);
+        const int64_t e1 = (int64_t)row1 * S.K;
+        int row = row0 + (int)threadIdx.x / S.K;
+        for (int64_t e = (int64_t)row0 * S.K + threadIdx.x; e < e1; e += kBB, row += kBB / S.K) {
+            const float ci = (float)(S.r[e] / sigma);
+            const float zi = F.jac ? F.dinv[row] * ci : ci;
+            F.r[e] = ci;
+            F.x[e] = 0.0f;
+            F.p[e] = zi;
+            prr += ci * ci;
+            prz += ci * zi;
+        }
     }
-    block_sum<2, kBB>(part, red);
-    if (threadIdx.x == 0) {
-        const int64_t t = (int64_t)(F.tile0 + blockIdx.x) * kMaxK + j;
-        a32.part[t] = part[0];
-        a32.part[a32.part_stride + t] = part[1];
-    }
+    float *base = a32.part + (int64_t)(F.tile0 + blockIdx.x) * kMaxK;
+    block_sum_by_rhs(prr, S.K, red, base);
+    block_sum_by_rhs(prz, S.K, red, base + a32.part_stride);
 }
 
-// One workgroup: lane j's binary32 scalars for its next inner solve (or an
-// inactive lane when its float64 status is final), as batch_r0_kernel sets
-// them for a whole system: stop when ||c - A d|| <= inner_rtol ||c||.
-__global__ __launch_bounds__(kBB) void mixed_lane_inner_r0_kernel(BArgs a64, BArgsT<float> a32,
-                                                                  int si, int j)
+// One workgroup: each masked lane's binary32 scalars for its next inner
+// solve (or an inactive lane when its float64 status is final), as
+// batch_r0_kernel sets them for a whole system: stop when ||c - A d|| <=
+// inner_rtol ||c||.
+__global__ __launch_bounds__(kBB) void mixed_inner_r0_kernel(BArgs a64, BArgsT<float> a32, int si,
+                                                             uint32_t mask)
 {
-    __shared__ float red[kBB / kWave];
+    __shared__ float red[kBB];
     const BSys &S = a64.sys[si];
     const BSysT<float> &F = a32.sys[si];
-    float v[2];
-    for (int r = 0; r < 2; ++r) {
-        const float *base = a32.part + r * a32.part_stride;
-        float s[1] = {0.0f};
-        for (int q = threadIdx.x; q < F.ntiles; q += kBB) s[0] += base[(int64_t)(F.tile0 + q) * kMaxK + j];
-        block_sum<1, kBB>(s, red);
-        v[r] = s[0];
-        __syncthreads();  // red is reused by the next region
-    }
-    if (threadIdx.x == 0) {
+    const float rr = sys_sum(a32, F, 0, red);
+    const float rz = sys_sum(a32, F, 1, red);
+    const int j = threadIdx.x;
+    if (j < S.K && ((mask >> j) & 1u)) {
         BScalT<float> &c = a32.scal[F.scal0 + j];
         c = BScalT<float>{};
         if (a64.scal[S.scal0 + j].status != CGX_PENDING) {
             c.status = CGX_OK;  // no inner solve: the lane is finished
             return;
         }
-        const float rr = v[0], rz = v[1];
         c.rr = rr;
         c.bb = rr;
         c.rho = F.jac ? rz : rr;
@@ -389,7 +383,7 @@ __global__ __launch_bounds__(kBB) void mixed_lane_inner_r0_kernel(BArgs a64, BAr
             status = CGX_BREAKDOWN;
         c.status = status;
         c.active = status == CGX_PENDING;
-        if (c.active) a32.sys_done[si] = 0;
+        if (c.active) a32.sys_done[si] = 0;  // same value from every writer
     }
 }
 
@@ -661,25 +655,30 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
         }
     }
     // float64 steps of MIXED lanes: fold d into x (or take x0), r = b - A x,
-    // stopping test, next inner solve's start
+    // stopping test, next inner solve's start; one pass per slot for all of
+    // its lanes whose inner solve ended
     const int32_t *bad = reinterpret_cast<const int32_t *>(E.pool + E.off_bad);
     for (int i : active) {
         Slot &sl = E.slots[i];
         if (!sl.mixed) continue;
+        uint32_t mask = 0, first = 0, last = 0;
         for (int j = 0; j < sl.K; ++j) {
             if (sl.state[j] != kLaneRunning || !sl.need_outer[j]) continue;
-            const dim3 g(sl.ntiles);
-            hipLaunchKernelGGL(mixed_lane_x_kernel, g, dim3(kBB), 0, s, m, m32, i, j, (int)sl.first[j]);
-            hipLaunchKernelGGL(mixed_lane_residual_kernel, g, dim3(kBB), 0, s, m, i, j);
-            hipLaunchKernelGGL(mixed_lane_outer_kernel, dim3(1), dim3(kBB), 0, s, m, bad, i, j,
-                               (int)(sl.outer[j] >= sl.key.max_outer));
-            hipLaunchKernelGGL(mixed_lane_start_kernel, g, dim3(kBB), 0, s, m, m32, i, j);
-            hipLaunchKernelGGL(mixed_lane_inner_r0_kernel, dim3(1), dim3(kBB), 0, s, m, m32, i, j);
-            ENG_CHECK(hipGetLastError());
+            mask |= 1u << j;
+            if (sl.first[j]) first |= 1u << j;
+            if (sl.outer[j] >= sl.key.max_outer) last |= 1u << j;
             sl.need_outer[j] = 0;
             sl.first[j] = 0;
             sl.outer_ran[j] = 1;
         }
+        if (!mask) continue;
+        const dim3 g(sl.ntiles);
+        hipLaunchKernelGGL(mixed_x_kernel, g, dim3(kBB), 0, s, m, m32, i, mask, first);
+        hipLaunchKernelGGL(mixed_residual_kernel, g, dim3(kBB), 0, s, m, i, mask);
+        hipLaunchKernelGGL(mixed_outer_kernel, dim3(1), dim3(kBB), 0, s, m, bad, i, mask, last);
+        hipLaunchKernelGGL(mixed_start_kernel, g, dim3(kBB), 0, s, m, m32, i, mask);
+        hipLaunchKernelGGL(mixed_inner_r0_kernel, dim3(1), dim3(kBB), 0, s, m, m32, i, mask);
+        ENG_CHECK(hipGetLastError());
     }
     if (E.nlist64 > 0 && E.active_tiles > 0)
         for (int k = 0; k < iters; ++k) launch_batch_iteration(m, s);
