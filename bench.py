@@ -405,7 +405,8 @@ def extra_schwarz(cgx, synth, meter):
         wall, j = _energy_window(solve, meter, min_s=2.0)
         nnz_off = D.arrays()[0].cpu().numpy()
         lrows = D.local_rows
-        it_bytes = 12 * int(nnz_off[-1]) + 4 * (lrows + S) + 88 * lrows
+        # batched iteration: SpMM p, q; update r, q, r; p update p, r, x, p, x
+        it_bytes = 12 * int(nnz_off[-1]) + 4 * (lrows + S) + 80 * lrows
         rows.append({"n_sub": S, "overlap_layers": layers,
                      "inner": f"tau {tau:g}, cap {m}" if tau > 0 else f"{m} iterations",
                      "status": st.status, "outer": st.outer_iters, "inner_iters": st.iters,
@@ -494,7 +495,9 @@ def extra_batched(cgx, synth, meter):
     byts = 0.0
     for (dA, B, X), row in zip(items, st):
         it = max(v.iters for v in row)
-        byts += it * (12 * dA.nnz + 4 * (dA.n_rows + 1) + 88 * 16 * dA.n_rows)
+        # per iteration: the matrix; p, q (SpMM), r, q, r (update), p, r, x,
+        # p, x (p update) for each of the 16 right-hand sides
+        byts += it * (12 * dA.nnz + 4 * (dA.n_rows + 1) + 80 * 16 * dA.n_rows)
     sched = cgx.batch_schedule(items, workspace=ws)
     # one right-hand side at a time with the single-system solver (a sample, scaled)
     sample = list(range(0, 64, 8))

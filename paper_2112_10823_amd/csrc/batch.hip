@@ -414,7 +414,7 @@ int run_batched(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t
 
     // iterations per replay: about 2 ms of work between host checks
     double bytes = 0.0;
-    for (const BSys &S : P.sys) bytes += 12.0 * S.nnz + 88.0 * S.K * S.n;
+    for (const BSys &S : P.sys) bytes += 12.0 * S.nnz + 80.0 * S.K * S.n;
     int K = o->check_every;
     if (K <= 0) {
         const double t_iter = bytes / 4.0e12 + 15.0e-6;
@@ -533,7 +533,7 @@ int run_batched_mixed(Context *c, int32_t nsys, const cgx_system *in, void *ws, 
 
     // binary32 iterations per graph replay: about 2 ms of work between checks
     double bytes = 0.0;
-    for (const BSysT<float> &F : L.P32.sys) bytes += 8.0 * F.nnz + 44.0 * F.K * F.n;
+    for (const BSysT<float> &F : L.P32.sys) bytes += 8.0 * F.nnz + 40.0 * F.K * F.n;
     int K = o->check_every;
     if (K <= 0) {
         const double t_iter = bytes / 4.0e12 + 15.0e-6;

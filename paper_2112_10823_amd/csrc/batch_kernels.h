@@ -988,7 +988,7 @@ int pad_k(int nrhs)
     return K;
 }
 
-int tile_rows_for(int K, bool staged) { return staged && K >= 8 ? 8192 / K : 2048 / K; }
+int tile_rows_for(int K, bool staged) { return staged && K >= 8 ? 4096 / K : 2048 / K; }
 
 // Wave-tile schedules the kernels instantiate: RT rows per wave with
 // RT * K <= 64 (K = 1: any power of two; K > 1: 1, 2 or 4 lanes per

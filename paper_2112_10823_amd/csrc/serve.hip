@@ -840,8 +840,8 @@ void engine_loop(Engine *Ep)
         double bytes = 0.0;
         for (const Slot &sl : E.slots)
             if (sl.used)
-                bytes += sl.mixed ? 8.0 * sl.key.A.nnz + 44.0 * sl.K * sl.key.A.n_rows
-                                  : 12.0 * sl.key.A.nnz + 88.0 * sl.K * sl.key.A.n_rows;
+                bytes += sl.mixed ? 8.0 * sl.key.A.nnz + 40.0 * sl.K * sl.key.A.n_rows
+                                  : 12.0 * sl.key.A.nnz + 80.0 * sl.K * sl.key.A.n_rows;
         int iters = (int)(1.0e-3 / (bytes / 4.0e12 + 25.0e-6));
         iters = iters < 1 ? 1 : (iters > 16 ? 16 : iters);
         if (!device_cycle(E, changed, iters, active)) {
