@@ -423,7 +423,8 @@ def extra_schwarz(cgx, synth, meter):
 
 def extra_mixed(cgx, synth, meter):
     """Q1 192^3 lognormal(0,1.5), uniform RHS, to 1e-10: float64 CG against
-    binary32-inner refinement, each plain and Jacobi-preconditioned."""
+    binary32-inner refinement (restarted) and binary32 CG with float64
+    reliable updates, each plain and Jacobi-preconditioned."""
     import torch
     A = synth.q1cube(192, 1.5, seed=synth.SEED_C3_COEFF)
     b = synth.uniform(synth.SEED_C3_RHS, A.n_rows)
@@ -439,7 +440,12 @@ def extra_mixed(cgx, synth, meter):
             ("mixed_jacobi_tau1e-3", cgx.PRECISION_MIXED, 1, 1e-3, None),
             ("mixed_jacobi_tau1e-4", cgx.PRECISION_MIXED, 1, 1e-4, None),
             ("fp64_jacobi_sell", cgx.PRECISION_FP64, 1, 0.0, S),
-            ("mixed_jacobi_tau1e-2_sell", cgx.PRECISION_MIXED, 1, 1e-2, S)]
+            ("mixed_jacobi_tau1e-2_sell", cgx.PRECISION_MIXED, 1, 1e-2, S),
+            ("ru_plain_delta1e-2", cgx.PRECISION_MIXED_RU, 0, 1e-2, None),
+            ("ru_jacobi_delta1e-1", cgx.PRECISION_MIXED_RU, 1, 1e-1, None),
+            ("ru_jacobi_delta1e-2", cgx.PRECISION_MIXED_RU, 1, 1e-2, None),
+            ("ru_jacobi_delta1e-3", cgx.PRECISION_MIXED_RU, 1, 1e-3, None),
+            ("ru_jacobi_delta1e-2_sell", cgx.PRECISION_MIXED_RU, 1, 1e-2, S)]
     ref = None
     for name, prec, pc, tau, sell in runs:
         opts = cgx.make_opts(rtol=1e-10, precond=pc, precision=prec, inner_rtol=tau,
@@ -462,7 +468,7 @@ def extra_mixed(cgx, synth, meter):
         out[name] = {"status": st.status, "iters": st.iters, "outer": st.outer_iters,
                      "solve_ms": round(wall * 1e3, 1), "solves_per_s": round(1 / wall, 3),
                      "j_per_solve": round(j, 2) if j is not None else None,
-                     "true_relres_host_spmv": tr,
+                     "true_relres_host_spmv": tr, "kappa_est": round(st.kappa_est, 1),
                      "rel_diff_vs_fp64_plain": float(np.linalg.norm(x - ref) / np.linalg.norm(ref))}
         del ws
     return out

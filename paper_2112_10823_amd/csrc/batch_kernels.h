@@ -725,14 +725,83 @@ __global__ __launch_bounds__(kBB) void batch_r1_kernel(BArgsT<T> a)
 // (2) r -= alpha q, z = D^-1 r for active right-hand sides; r.r and r.z
 // partials.  x += alpha p is taken in the p update (3), which reads p
 // anyway, so that p is read once per iteration outside the SpMM.
+// 16-byte accesses of the interleaved vectors: V = 16 / sizeof(T)
+// consecutive right-hand sides of one row per access (used when K >= V; the
+// vectors start 256-byte aligned and K is a multiple of V, so every access
+// is aligned).
+template <typename T>
+using Vec16 = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+
+// Per-right-hand-side sums of V values per thread: value v of thread t
+// belongs to right-hand side (t V + v) mod K (K a multiple of V, K / V
+// dividing kBB); each right-hand side's values are added in index order.
+// `red` holds kBB * V values; the K totals go to out[0..K).
+template <typename T, int V>
+__device__ __forceinline__ void block_sum_by_rhs_vec(const T (&v)[V], int K, T *red, T *out)
+{
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < V; ++u) red[threadIdx.x * V + u] = v[u];
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        T s = T(0);
+        for (int i = threadIdx.x; i < kBB * V; i += K) s += red[i];
+        out[threadIdx.x] = s;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBB) void batch_update_kernel(BArgsT<T> a)
 {
-    __shared__ T red[kBB];
+    constexpr int V = 16 / (int)sizeof(T);
+    __shared__ T red[kBB * V];
     const int w = xcd_block(blockIdx.x, gridDim.x);
     const BTile t = a.tiles[w];
     if (a.sys_done[t.sys]) return;
     const BSysT<T> S = a.sys[t.sys];
+    T *base = a.part + (int64_t)t.tile * kMaxK;
+    if (S.K >= V) {
+        // thread t: right-hand sides j0 .. j0 + V - 1 of every (kBB / KV)-th row
+        const int KV = S.K / V, j0 = ((int)threadIdx.x % KV) * V;
+        T alpha[V], prr[V], prz[V];
+        bool act[V], any = false;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const BScalT<T> c = a.scal[S.scal0 + j0 + v];
+            alpha[v] = c.alpha;
+            act[v] = c.active != 0;
+            any = any || act[v];
+            prr[v] = prz[v] = T(0);
+        }
+        if (any) {
+            Vec16<T> *pr = reinterpret_cast<Vec16<T> *>(S.r);
+            const Vec16<T> *pq = reinterpret_cast<const Vec16<T> *>(S.q);
+            const int64_t g1 = (int64_t)(t.row0 + t.rows) * KV;
+            const int drow = kBB / KV;
+            int row = t.row0 + (int)threadIdx.x / KV;
+#pragma unroll 2
+            for (int64_t g = (int64_t)t.row0 * KV + threadIdx.x; g < g1; g += kBB, row += drow) {
+                const Vec16<T> rv = pr[g], qv = pq[g];
+                T rs[V], qs[V];
+                __builtin_memcpy(rs, &rv, sizeof(rv));
+                __builtin_memcpy(qs, &qv, sizeof(qv));
+                const T di = S.jac ? S.dinv[row] : T(0);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    if (!act[v]) continue;
+                    rs[v] = fma_t(-alpha[v], qs[v], rs[v]);
+                    prr[v] += rs[v] * rs[v];
+                    if (S.jac) prz[v] += rs[v] * (di * rs[v]);
+                }
+                Vec16<T> ro;
+                __builtin_memcpy(&ro, rs, sizeof(ro));
+                pr[g] = ro;
+            }
+        }
+        block_sum_by_rhs_vec<T, V>(prr, S.K, red, base + a.part_stride);
+        block_sum_by_rhs_vec<T, V>(prz, S.K, red, base + 2 * a.part_stride);
+        return;
+    }
     const int j = threadIdx.x % S.K;  // fixed per thread: K divides kBB
     const BScalT<T> c = a.scal[S.scal0 + j];
     T prr = T(0), prz = T(0);
@@ -753,7 +822,6 @@ __global__ __launch_bounds__(kBB) void batch_update_kernel(BArgsT<T> a)
             }
         }
     }
-    T *base = a.part + (int64_t)t.tile * kMaxK;
     block_sum_by_rhs(prr, S.K, red, base + a.part_stride);
     block_sum_by_rhs(prz, S.K, red, base + 2 * a.part_stride);
 }
@@ -812,6 +880,55 @@ __global__ __launch_bounds__(kBB) void batch_direction_kernel(BArgsT<T> a)
     const BTile t = a.tiles[w];
     if (a.sys_done[t.sys] == 1) return;
     const BSysT<T> S = a.sys[t.sys];
+    constexpr int V = 16 / (int)sizeof(T);
+    if (S.K >= V) {  // 16-byte accesses, as in the update
+        const int KV = S.K / V, j0 = ((int)threadIdx.x % KV) * V;
+        T alpha[V], beta[V];
+        bool xs[V], act[V], anyx = false, anyp = false;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const BScalT<T> c = a.scal[S.scal0 + j0 + v];
+            alpha[v] = c.alpha;
+            beta[v] = c.beta;
+            xs[v] = c.xstep != 0;
+            act[v] = xs[v] && c.active != 0;
+            anyx = anyx || xs[v];
+            anyp = anyp || act[v];
+        }
+        if (!anyx) return;
+        Vec16<T> *pp = reinterpret_cast<Vec16<T> *>(S.p), *px = reinterpret_cast<Vec16<T> *>(S.x);
+        const Vec16<T> *pr = reinterpret_cast<const Vec16<T> *>(S.r);
+        const int64_t g1 = (int64_t)(t.row0 + t.rows) * KV;
+        const int drow = kBB / KV;
+        int row = t.row0 + (int)threadIdx.x / KV;
+#pragma unroll 2
+        for (int64_t g = (int64_t)t.row0 * KV + threadIdx.x; g < g1; g += kBB, row += drow) {
+            const Vec16<T> pv = pp[g], xv = px[g];
+            T ps[V], xsv[V], rs[V];
+            __builtin_memcpy(ps, &pv, sizeof(pv));
+            __builtin_memcpy(xsv, &xv, sizeof(xv));
+            T di = T(1);
+            if (anyp) {
+                const Vec16<T> rv = pr[g];
+                __builtin_memcpy(rs, &rv, sizeof(rv));
+                if (S.jac) di = S.dinv[row];
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                if (xs[v]) xsv[v] = fma_t(alpha[v], ps[v], xsv[v]);
+                if (act[v]) ps[v] = fma_t(beta[v], ps[v], S.jac ? di * rs[v] : rs[v]);
+            }
+            Vec16<T> xo;
+            __builtin_memcpy(&xo, xsv, sizeof(xo));
+            px[g] = xo;
+            if (anyp) {
+                Vec16<T> po;
+                __builtin_memcpy(&po, ps, sizeof(po));
+                pp[g] = po;
+            }
+        }
+        return;
+    }
     const int j = threadIdx.x % S.K;
     const BScalT<T> c = a.scal[S.scal0 + j];
     if (!c.xstep) return;
