@@ -548,10 +548,35 @@ def extra_batched(cgx, synth, meter):
              "inner_iters_mean": round(float(np.mean([v.iters for row in mst for v in row])), 1),
              "outer_mean": round(float(np.mean([v.outer_iters for row in mst for v in row])), 2),
              "true_relres_max_sample": max(check)}
+    # the same batch with binary32 CG and float64 reliable updates (delta 1e-2)
+    ropts = cgx.make_opts(rtol=1e-8, precond=1, precision=cgx.PRECISION_MIXED_RU,
+                          inner_rtol=1e-2)
+    rst = None
+
+    def rsolve():
+        nonlocal rst
+        for _, _, X in items:
+            X.zero_()
+        rst = cgx.cg_solve_batched(items, ropts, workspace=mws)
+
+    rsolve()
+    rcheck = []
+    for s in (0, 21, 42, 63):
+        dA, B, X = items[s]
+        for j in (0, 15):
+            rcheck.append(host_relres(mats[s], B[j].cpu().numpy(), X[j].cpu().numpy()))
+    rwall, rjb = _energy_window(rsolve, meter, min_s=2.0)
+    ru = {"solves_per_s": round(1024 / rwall, 1), "batch_s": round(rwall, 3),
+          "converged": sum(v.status == cgx.OK for row in rst for v in row),
+          "j_per_solve": round(rjb / 1024, 4) if rjb is not None else None,
+          "iters_mean": round(float(np.mean([v.iters for row in rst for v in row])), 1),
+          "updates_mean": round(float(np.mean([v.outer_iters for row in rst for v in row])), 2),
+          "true_relres_max_sample": max(rcheck)}
     return {"workload": "64 systems N~U{24..96} 7-point/Q1 lognormal(0,1), 16 RHS each, "
                         "Jacobi CG rtol 1e-8",
-            "float32_refined": mixed,
+            "float32_refined": mixed, "reliable_updates": ru,
             "solves": 1024, "converged": ok, "batch_s": round(wall, 3),
+            "fp64_iters_mean": round(float(np.mean([v.iters for row in st for v in row])), 1),
             "solves_per_s": round(1024 / wall, 1),
             "model_GBs": round(byts / wall / 1e9, 1),
             "j_per_solve": round(jb / 1024, 4) if jb is not None else None,

@@ -293,9 +293,9 @@ typedef struct cgx_system {
  * the solve. */
 size_t cgx_batch_workspace_bytes(int32_t nsys, const cgx_system *systems);
 
-/* Workspace bytes of cgx_cg_solve_batched with opts->precision MIXED (the
- * float64 state, the binary32 inner state and the inner right-hand sides
- * and solutions); 0 for the invalid batches cgx_batch_workspace_bytes
+/* Workspace bytes of cgx_cg_solve_batched with opts->precision MIXED or
+ * MIXED_RU (the float64 state, the binary32 state and the inner right-hand
+ * sides and solutions); 0 for the invalid batches cgx_batch_workspace_bytes
  * rejects. */
 size_t cgx_batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *systems);
 
@@ -323,7 +323,23 @@ size_t cgx_batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *systems);
  * 1e-3) within maxit iterations, and sets x = fma(||r||, double(d), x); at
  * most max_outer (<= 0: 100) steps.  stats: iters = binary32 iterations
  * summed over the steps, outer_iters = refinement steps, relres = the last
- * float64 ||r|| / ||b||. */
+ * float64 ||r|| / ||b||.
+ *
+ * opts->precision MIXED_RU (every A.val32 set; workspace as for MIXED): the
+ * single-system MIXED_RU method for every (system, right-hand side) at
+ * once.  One binary32 CG per right-hand side on A32 (Jacobi from the
+ * binary32 diagonal if asked) whose direction is kept across float64
+ * reliable updates: when the binary32 ||r^|| falls below delta times its
+ * largest value since the last update (delta = inner_rtol, <= 0: 1e-2) or
+ * its estimate of ||r|| reaches rtol ||b||, that right-hand side pauses, x
+ * += ||r|| d and r = b - A x are taken in float64, ||r|| <= rtol ||b|| ends
+ * it, and otherwise it resumes on float(r / ||r||) with beta rescaled by the
+ * ratio of the two norms; the other right-hand sides go on meanwhile.  At
+ * most maxit binary32 iterations (then the pending correction is folded
+ * into x) and max_outer (<= 0: 100) updates per right-hand side, then
+ * CGX_NOT_CONVERGED.  stats: iters =
+ * binary32 iterations, outer_iters = reliable updates, relres = relres_true
+ * = ||b - A x|| / ||b|| of the result in float64. */
 int cgx_cg_solve_batched(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
                          size_t workspace_bytes, const cgx_opts *opts, cgx_stats *stats);
 

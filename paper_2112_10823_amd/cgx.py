@@ -633,10 +633,11 @@ def _systems(items):
 
 
 def batch_workspace_bytes(items, opts: Opts | None = None) -> int:
-    """Workspace bytes of cg_solve_batched (float32-refined with
-    opts.precision == PRECISION_MIXED)."""
+    """Workspace bytes of cg_solve_batched (binary32 with float64
+    refinement or reliable updates when opts.precision is PRECISION_MIXED or
+    PRECISION_MIXED_RU)."""
     arr = _systems(items)
-    if opts is not None and opts.precision == PRECISION_MIXED:
+    if opts is not None and opts.precision in (PRECISION_MIXED, PRECISION_MIXED_RU):
         return int(load_library().cgx_batch_mixed_workspace_bytes(len(items), arr))
     return int(load_library().cgx_batch_workspace_bytes(len(items), arr))
 

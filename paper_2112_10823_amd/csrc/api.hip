@@ -571,9 +571,10 @@ int cgx_cg_solve_batched(cgx_handle h, int32_t nsys, const cgx_system *systems, 
     return guarded([&]() -> int {
         CGX_REQUIRE(opts != nullptr && stats != nullptr, "opts or stats is NULL");
         CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64 ||
-                        opts->precision == CGX_PRECISION_MIXED,
+                        opts->precision == CGX_PRECISION_MIXED ||
+                        opts->precision == CGX_PRECISION_MIXED_RU,
                     "unknown precision");
-        const bool mixed = opts->precision == CGX_PRECISION_MIXED;
+        const bool mixed = opts->precision != CGX_PRECISION_FP64;
         int rc = check_batch(h, nsys, systems, mixed);
         if (rc) return rc;
         CGX_REQUIRE(opts->precond == CGX_PRECOND_NONE || opts->precond == CGX_PRECOND_JACOBI,

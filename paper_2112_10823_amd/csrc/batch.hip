@@ -280,6 +280,255 @@ int ensure_batch_graph(GraphSlot &slot, int K, const BArgsT<T> &a, hipStream_t s
     return CGX_OK;
 }
 
+// ------------------------------------------- reliable-update batch --
+// Binary32 CG with float64 reliable updates for every (system, right-hand
+// side) of the batch (the single-system MIXED_RU method): the binary32
+// plan iterates on r^ = r / sigma with d (its x) the correction in that
+// scale; batch_r2_kernel pauses a right-hand side when its update test
+// fires (system state 3), and these kernels, launched after the p update of
+// every iteration, take the update for the paused ones: x += sigma d, d = 0
+// (fold); r = b - A x in float64 (residual); sigma' = ||r||, the float64
+// stopping test (norm); r^ = float(r / sigma'), z = D^-1 r^ (rescale);
+// beta = (rho' / rho) (sigma' / sigma) and the right-hand side resumes
+// (resume); p = z + beta p (direction).  Systems in another state return at
+// once.  The tiles of the two plans are the same.
+
+__global__ __launch_bounds__(kBB) void ru_fold_kernel(BArgsT<double> a64, BArgsT<float> a32)
+{
+    const BTile t = a32.tiles[blockIdx.x];
+    if (a32.sys_done[t.sys] != 3) return;
+    const BSysT<double> S = a64.sys[t.sys];
+    const BSysT<float> F = a32.sys[t.sys];
+    const int j = threadIdx.x % S.K;
+    if (!a32.scal[F.scal0 + j].ru) return;
+    const double sigma = sqrt(a64.scal[S.scal0 + j].rr);
+    const int64_t e1 = (int64_t)(t.row0 + t.rows) * S.K;
+    for (int64_t e = (int64_t)t.row0 * S.K + threadIdx.x; e < e1; e += kBB) {
+        S.x[e] = __builtin_fma(sigma, (double)F.x[e], S.x[e]);
+        F.x[e] = 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(kBB) void ru_residual_kernel(BArgsT<double> a64, BArgsT<float> a32)
+{
+    __shared__ double red[kBB];
+    const BTile t = a64.tiles[blockIdx.x];
+    if (a32.sys_done[t.sys] != 3) return;
+    const BSysT<double> S = a64.sys[t.sys];
+    const BSysT<float> F = a32.sys[t.sys];
+    const int M = setup_m(S);
+    const int G = S.K * M, gpw = kWave / G;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
+    const bool on = a32.scal[F.scal0 + j].ru != 0;
+    double prr = 0.0;
+    for (int row = t.row0 + wave * gpw + grp; gpw >= 1 && row < t.row0 + t.rows;
+         row += (kBB / kWave) * gpw) {
+        double dg;
+        const double ax = row_spmm(S, row, j, m, M, dg, S.x);
+        if (m == 0 && on) {
+            const double ri = S.B[(int64_t)j * S.n + row] - ax;
+            S.r[(int64_t)row * S.K + j] = ri;
+            prr += ri * ri;
+        }
+    }
+    block_sum_by_rhs(prr, S.K, red, a64.part + (int64_t)t.tile * kMaxK);
+}
+
+__global__ __launch_bounds__(kBB) void ru_norm_kernel(BArgsT<double> a64, BArgsT<float> a32,
+                                                      int max_updates)
+{
+    __shared__ double red[kBB];
+    const int sid = a64.list[blockIdx.x];
+    if (a32.sys_done[sid] != 3) return;
+    const BSysT<double> S = a64.sys[sid];
+    const BSysT<float> F = a32.sys[sid];
+    const double rr = sys_sum(a64, S, 0, red);
+    if (threadIdx.x < S.K) {
+        BScalT<float> &c = a32.scal[F.scal0 + threadIdx.x];
+        if (c.ru) {
+            BScalT<double> &d = a64.scal[S.scal0 + threadIdx.x];
+            d.pq = d.rr;  // sigma^2 of the previous update
+            d.rr = rr;
+            d.iter += 1;  // updates taken
+            int status = CGX_PENDING;
+            if (!isfinite(rr))
+                status = CGX_NONFINITE;
+            else if (rr <= d.stop2)
+                status = CGX_OK;
+            else if (d.iter >= max_updates)
+                status = CGX_NOT_CONVERGED;  // the update cap (x already holds d)
+            if (status != CGX_PENDING) {
+                d.status = status;
+                c.status = status;
+                c.ru = 0;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBB) void ru_rescale_kernel(BArgsT<double> a64, BArgsT<float> a32)
+{
+    __shared__ float red[kBB];
+    const BTile t = a32.tiles[blockIdx.x];
+    if (a32.sys_done[t.sys] != 3) return;
+    const BSysT<double> S = a64.sys[t.sys];
+    const BSysT<float> F = a32.sys[t.sys];
+    const int j = threadIdx.x % S.K;
+    const bool on = a32.scal[F.scal0 + j].ru != 0;
+    float prz = 0.0f, prr = 0.0f;
+    if (on) {
+        const double sigma = sqrt(a64.scal[S.scal0 + j].rr);
+        const int64_t e1 = (int64_t)(t.row0 + t.rows) * S.K;
+        int row = t.row0 + (int)threadIdx.x / S.K;
+        for (int64_t e = (int64_t)t.row0 * S.K + threadIdx.x; e < e1; e += kBB, row += kBB / S.K) {
+            const float ci = (float)(S.r[e] / sigma);
+            const float zi = F.jac ? F.dinv[row] * ci : ci;
+            F.r[e] = ci;
+            prz += ci * zi;
+            prr += ci * ci;
+        }
+    }
+    float *base = a32.part + (int64_t)t.tile * kMaxK;
+    block_sum_by_rhs(prz, S.K, red, base);
+    block_sum_by_rhs(prr, S.K, red, base + a32.part_stride);
+}
+
+__global__ __launch_bounds__(kBB) void ru_resume_kernel(BArgsT<double> a64, BArgsT<float> a32)
+{
+    __shared__ float red[kBB];
+    __shared__ int any_active;
+    const int sid = a32.list[blockIdx.x];
+    if (a32.sys_done[sid] != 3) return;
+    const BSysT<double> S = a64.sys[sid];
+    const BSysT<float> F = a32.sys[sid];
+    if (threadIdx.x == 0) any_active = 0;
+    const float rz = sys_sum(a32, F, 0, red);  // its barriers order the reset above
+    const float rr = sys_sum(a32, F, 1, red);
+    if (threadIdx.x < S.K) {
+        BScalT<float> &c = a32.scal[F.scal0 + threadIdx.x];
+        if (c.ru) {
+            BScalT<double> &d = a64.scal[S.scal0 + threadIdx.x];
+            int status = CGX_PENDING;
+            if (!isfinite(rz) || !isfinite(rr))
+                status = CGX_NONFINITE;
+            else if (!(rz > 0.0f))
+                status = CGX_BREAKDOWN;
+            else if (c.iter >= F.maxit)
+                status = CGX_NOT_CONVERGED;
+            if (status == CGX_PENDING) {
+                c.beta = (rz / c.rho) * (float)(sqrt(d.rr) / sqrt(d.pq));
+                c.rho = rz;
+                c.rr = rr;
+                c.bb = rr;  // the maximum of ||r^||^2 restarts at the update
+                c.stop2 = (float)(d.stop2 / d.rr);
+                c.active = 1;
+                atomicOr(&any_active, 1);
+            } else {
+                c.status = status;
+                c.ru = 0;
+                if (status != CGX_NOT_CONVERGED) d.status = status;
+            }
+        } else if (c.active) {
+            atomicOr(&any_active, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a32.sys_done[sid] = any_active ? 0 : 1;
+}
+
+__global__ __launch_bounds__(kBB) void ru_direction_kernel(BArgsT<float> a32)
+{
+    const BTile t = a32.tiles[blockIdx.x];
+    const BSysT<float> F = a32.sys[t.sys];
+    const int j = threadIdx.x % F.K;
+    const BScalT<float> c = a32.scal[F.scal0 + j];
+    if (!c.ru || !c.active) return;
+    const float beta = c.beta;
+    const int64_t e1 = (int64_t)(t.row0 + t.rows) * F.K;
+    int row = t.row0 + (int)threadIdx.x / F.K;
+    for (int64_t e = (int64_t)t.row0 * F.K + threadIdx.x; e < e1; e += kBB, row += kBB / F.K)
+        F.p[e] = fma_t(beta, F.p[e], F.jac ? F.dinv[row] * F.r[e] : F.r[e]);
+}
+
+// Start of the reliable-update iteration (after the first float64
+// residual and the binary32 setup on float(r / sigma)): the maximum of
+// ||r^||^2 starts at its first value and the stopping test moves into the
+// scale sigma; right-hand sides already done in float64 stay inactive.
+__global__ __launch_bounds__(kBB) void ru_start_kernel(BArgsT<double> a64, BArgsT<float> a32)
+{
+    __shared__ int any_active;
+    const int sid = a32.list[blockIdx.x];
+    const BSysT<double> S = a64.sys[sid];
+    const BSysT<float> F = a32.sys[sid];
+    if (threadIdx.x == 0) any_active = 0;
+    __syncthreads();
+    if (threadIdx.x < S.K) {
+        BScalT<float> &c = a32.scal[F.scal0 + threadIdx.x];
+        const BScalT<double> &d = a64.scal[S.scal0 + threadIdx.x];
+        if (d.status != CGX_PENDING) {
+            c.active = 0;
+            c.status = CGX_OK;
+        } else if (c.active) {
+            c.bb = c.rr;
+            c.stop2 = (float)(d.stop2 / d.rr);
+            atomicOr(&any_active, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a32.sys_done[sid] = any_active ? 0 : 1;
+}
+
+// End: x += sigma d for every right-hand side (d is 0 where the last update
+// folded it; it holds the pending correction where the iteration cap or a
+// breakdown stopped the binary32 iteration).
+__global__ __launch_bounds__(kBB) void ru_final_fold_kernel(BArgsT<double> a64, BArgsT<float> a32)
+{
+    const BTile t = a64.tiles[blockIdx.x];
+    const BSysT<double> S = a64.sys[t.sys];
+    const BSysT<float> F = a32.sys[t.sys];
+    const int j = threadIdx.x % S.K;
+    if (j >= S.nrhs) return;
+    const double sigma = sqrt(a64.scal[S.scal0 + j].rr);
+    const int64_t e1 = (int64_t)(t.row0 + t.rows) * S.K;
+    for (int64_t e = (int64_t)t.row0 * S.K + threadIdx.x; e < e1; e += kBB)
+        S.x[e] = __builtin_fma(sigma, (double)F.x[e], S.x[e]);
+}
+
+void launch_ru_iteration(const BArgsT<double> &a64, const BArgsT<float> &a32, int max_updates,
+                         hipStream_t s)
+{
+    launch_batch_iteration(a32, s);
+    const dim3 g(a32.ntiles), l(a32.nlist), b(kBB);
+    hipLaunchKernelGGL(ru_fold_kernel, g, b, 0, s, a64, a32);
+    hipLaunchKernelGGL(ru_residual_kernel, g, b, 0, s, a64, a32);
+    hipLaunchKernelGGL(ru_norm_kernel, l, b, 0, s, a64, a32, max_updates);
+    hipLaunchKernelGGL(ru_rescale_kernel, g, b, 0, s, a64, a32);
+    hipLaunchKernelGGL(ru_resume_kernel, l, b, 0, s, a64, a32);
+    hipLaunchKernelGGL(ru_direction_kernel, g, b, 0, s, a32);
+}
+
+// K reliable-update iterations captured into `slot` (the binary32 graph
+// slot of the handle, keyed apart from the restarted refinement's graph).
+int ensure_ru_graph(GraphSlot &slot, int K, const BArgsT<double> &a64, const BArgsT<float> &a32,
+                    int max_updates, hipStream_t s)
+{
+    GraphKey key = batch_key<float>(K, a32);
+    key.add(0x5255ull).ptr(a64.sys).ptr(a64.tiles).ptr(a64.list).ptr(a64.scal).ptr(a64.part);
+    key.add((uint64_t)a64.part_stride).add((uint64_t)a64.ntiles).add((uint64_t)a64.nlist);
+    key.add((uint64_t)max_updates);
+    if (slot.matches(key)) return CGX_OK;
+    slot.reset();
+    CGX_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < K; ++k) launch_ru_iteration(a64, a32, max_updates, s);
+    hipGraph_t g = nullptr;
+    CGX_HIP_CHECK(hipStreamEndCapture(s, &g));
+    slot.graph = g;
+    CGX_HIP_CHECK(hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0));
+    slot.key = key.w;
+    return CGX_OK;
+}
+
 // Two timing events destroyed on every exit path.
 struct EventPair {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -474,6 +723,148 @@ size_t batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *in)
     return L.total;
 }
 
+// Binary32 CG with float64 reliable updates for the whole batch (see the
+// reliable-update kernels above): float64 r = b - A x and the stopping test
+// per right-hand side, the binary32 setup on float(r / ||r||) for the
+// others, then graph replays of K iterations (the binary32 phase kernels and
+// the update kernels) until every system is done, a final fold of the
+// pending corrections and a float64 residual pass for the statistics.
+static int run_batched_ru(Context *c, int32_t nsys, const cgx_system *in, void *ws,
+                          size_t ws_bytes, const cgx_opts *o_in, cgx_stats *stats)
+{
+    cgx_opts o = *o_in;
+    if (!(o.inner_rtol > 0.0)) o.inner_rtol = 1e-2;  // delta of the update test
+    hipStream_t s = c->own_stream;
+    CGX_HIP_CHECK(hipEventRecord(c->ev_in, c->stream));
+    CGX_HIP_CHECK(hipStreamWaitEvent(s, c->ev_in, 0));
+    std::vector<int> Ms;
+    int rc = batch_autotune(c, nsys, in, ws, ws_bytes, Ms);
+    if (rc) return rc;
+    MixedLayout L;
+    rc = mixed_layout(nsys, in, Ms.data(), &o, L);
+    if (rc) {
+        set_error("batch too large");
+        return rc;
+    }
+    if (ws_bytes < L.total) {
+        set_error("workspace too small: need " + std::to_string(L.total) + " bytes");
+        return CGX_ENOMEM;
+    }
+    char *w = static_cast<char *>(ws);
+    char *w32 = w + L.base32;
+    float *b32 = reinterpret_cast<float *>(w + L.off_b32);
+    float *d32 = reinterpret_cast<float *>(w + L.off_d32);
+    bind_pointers(L.P64, nsys, in, w);
+    for (int i = 0; i < nsys; ++i) {
+        BSysT<float> &F = L.P32.sys[i];
+        F.rp = in[i].A.row_ptr;
+        F.ci = in[i].A.col_idx;
+        F.val = in[i].A.val32;
+        F.B = b32 + L.sys_off[i];
+        F.X = d32 + L.sys_off[i];
+        F.ru = 1;
+    }
+    bind_vectors(L.P32, nsys, w32);
+    const BArgsT<double> a64 = make_args(L.P64, w);
+    const BArgsT<float> a32 = make_args(L.P32, w32);
+    int maxit = 1;
+    for (const BSysT<float> &F : L.P32.sys) maxit = std::max(maxit, F.maxit);
+
+    CGX_HIP_CHECK(hipEventRecord(c->ev0, s));
+    rc = upload_plan(L.P64, w, s);
+    if (rc) return rc;
+    rc = upload_plan(L.P32, w32, s);
+    if (rc) return rc;
+    const int64_t n64 = std::max<int64_t>(L.P64.nscal, nsys);
+    const int64_t n32 = std::max<int64_t>(L.P32.nscal, nsys);
+    hipLaunchKernelGGL((batch_scal_init_kernel<double>), dim3((unsigned)((n64 + 255) / 256)),
+                       dim3(256), 0, s, a64.scal, L.P64.nscal, a64.sys_done, nsys);
+    hipLaunchKernelGGL((batch_in_kernel<double>), dim3(a64.ntiles), dim3(kBB), 0, s, a64);
+    hipLaunchKernelGGL((batch_init_kernel<double>), dim3(a64.ntiles), dim3(kBB), 0, s, a64);
+    hipLaunchKernelGGL((batch_r0_kernel<double>), dim3(a64.nlist), dim3(kBB), 0, s, a64);
+    hipLaunchKernelGGL(refine_rhs_kernel, dim3(a64.ntiles), dim3(kBB), 0, s, a64, a32, b32);
+    hipLaunchKernelGGL((batch_scal_init_kernel<float>), dim3((unsigned)((n32 + 255) / 256)),
+                       dim3(256), 0, s, a32.scal, L.P32.nscal, a32.sys_done, nsys);
+    hipLaunchKernelGGL((batch_in_kernel<float>), dim3(a32.ntiles), dim3(kBB), 0, s, a32);
+    hipLaunchKernelGGL((batch_init_kernel<float>), dim3(a32.ntiles), dim3(kBB), 0, s, a32);
+    hipLaunchKernelGGL((batch_r0_kernel<float>), dim3(a32.nlist), dim3(kBB), 0, s, a32);
+    hipLaunchKernelGGL(ru_start_kernel, dim3(a32.nlist), dim3(kBB), 0, s, a64, a32);
+    CGX_HIP_CHECK(hipGetLastError());
+
+    // binary32 iterations per graph replay: about 2 ms of work between checks
+    double bytes = 0.0;
+    for (const BSysT<float> &F : L.P32.sys) bytes += 8.0 * F.nnz + 40.0 * F.K * F.n;
+    int K = o.check_every;
+    if (K <= 0) {
+        const double t_iter = bytes / 4.0e12 + 40.0e-6;
+        K = (int)(2.0e-3 / t_iter);
+        K = K < 2 ? 2 : (K > 32 ? 32 : K);
+    }
+    const int max_updates = o.max_outer > 0 ? o.max_outer : 100;
+    rc = ensure_ru_graph(c->graph_batch32, K, a64, a32, max_updates, s);
+    if (rc) return rc;
+    GraphSlot &slot = c->graph_batch32;
+    std::vector<int32_t> done(nsys);
+    const int64_t max_replays = (int64_t)maxit / K + 2;
+    for (int64_t rep = 0; rep < max_replays; ++rep) {
+        CGX_HIP_CHECK(hipMemcpyAsync(done.data(), a32.sys_done, sizeof(int32_t) * nsys,
+                                     hipMemcpyDeviceToHost, s));
+        CGX_HIP_CHECK(hipStreamSynchronize(s));
+        bool all = true;
+        for (int32_t d : done) all = all && d;
+        if (all) break;
+        CGX_HIP_CHECK(hipGraphLaunch(slot.exec, s));
+    }
+    hipLaunchKernelGGL(ru_final_fold_kernel, dim3(a64.ntiles), dim3(kBB), 0, s, a64, a32);
+    CGX_HIP_CHECK(hipGetLastError());
+    std::vector<BScalT<double>> h64(L.P64.nscal);
+    std::vector<BScalT<float>> h32(L.P32.nscal);
+    CGX_HIP_CHECK(hipMemcpyAsync(h64.data(), a64.scal, sizeof(BScalT<double>) * L.P64.nscal,
+                                 hipMemcpyDeviceToHost, s));
+    CGX_HIP_CHECK(hipMemcpyAsync(h32.data(), a32.scal, sizeof(BScalT<float>) * L.P32.nscal,
+                                 hipMemcpyDeviceToHost, s));
+    // float64 residual of the result for the statistics (and x = 0 where b = 0)
+    hipLaunchKernelGGL((batch_init_kernel<double>), dim3(a64.ntiles), dim3(kBB), 0, s, a64);
+    hipLaunchKernelGGL((batch_r0_kernel<double>), dim3(a64.nlist), dim3(kBB), 0, s, a64);
+    hipLaunchKernelGGL((batch_out_kernel<double>), dim3(a64.ntiles), dim3(kBB), 0, s, a64);
+    CGX_HIP_CHECK(hipGetLastError());
+    std::vector<BScalT<double>> hf(L.P64.nscal);
+    CGX_HIP_CHECK(hipMemcpyAsync(hf.data(), a64.scal, sizeof(BScalT<double>) * L.P64.nscal,
+                                 hipMemcpyDeviceToHost, s));
+    CGX_HIP_CHECK(hipEventRecord(c->ev1, s));
+    CGX_HIP_CHECK(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    CGX_HIP_CHECK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    CGX_HIP_CHECK(hipEventRecord(c->ev_out, s));
+    CGX_HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_out, 0));
+
+    int worst = CGX_OK;
+    int64_t k = 0;
+    for (int sidx = 0; sidx < nsys; ++sidx) {
+        const BSysT<double> &S = L.P64.sys[sidx];
+        for (int j = 0; j < S.nrhs; ++j, ++k) {
+            const BScalT<double> &v = h64[S.scal0 + j];
+            const BScalT<float> &f = h32[S.scal0 + j];
+            const BScalT<double> &r = hf[S.scal0 + j];
+            cgx_stats &st = stats[k];
+            st = cgx_stats{};
+            // float64 status when the float64 test ended it, else the
+            // binary32 iteration's (cap, breakdown), else not converged
+            st.status = v.status != CGX_PENDING ? v.status
+                        : (f.status != CGX_PENDING && f.status != CGX_OK) ? f.status
+                                                                          : CGX_NOT_CONVERGED;
+            st.iters = f.iter;
+            st.outer_iters = v.iter;
+            st.path = 3;
+            st.relres = r.bb > 0.0 ? std::sqrt(r.rr / r.bb) : 0.0;
+            st.relres_true = st.relres;
+            st.device_ms = ms;
+            if (st.status != CGX_OK && worst == CGX_OK) worst = st.status;
+        }
+    }
+    return worst;
+}
+
 // Float64 outer refinement around binary32 inner batched CG (the mixed
 // precision of the single-system solve, for every (system, right-hand side)
 // of the batch at once): r = b - A x in float64 with the float64 kernels;
@@ -484,6 +875,8 @@ size_t batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *in)
 int run_batched_mixed(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t ws_bytes,
                       const cgx_opts *o, cgx_stats *stats)
 {
+    if (o->precision == CGX_PRECISION_MIXED_RU)
+        return run_batched_ru(c, nsys, in, ws, ws_bytes, o, stats);
     hipStream_t s = c->own_stream;
     CGX_HIP_CHECK(hipEventRecord(c->ev_in, c->stream));
     CGX_HIP_CHECK(hipStreamWaitEvent(s, c->ev_in, 0));

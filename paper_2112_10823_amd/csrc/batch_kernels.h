@@ -37,6 +37,8 @@ struct BSysT {
     int n_cols, jac;     // jac: Jacobi preconditioning for this system
     int maxit;
     int staged;          // SpMM wave tiles for K >= 8 staged per wave (batch call; see below)
+    int ru;              // binary32 system of a reliable-update batch: the stopping test of
+                         // R2 becomes the update test (rtol2 = delta^2, see batch_r2_kernel)
     double rtol2;        // squared relative tolerance of this system
 };
 using BSys = BSysT<double>;
@@ -49,7 +51,8 @@ template <typename T>
 struct BScalT {
     T rho, rho_used, alpha, beta, rr, bb, stop2, pq;
     int32_t iter, status, active, pad;  // pad: a diagonal entry <= 0 met at setup
-    int32_t xstep, pad2;                // xstep: x += alpha p due in this iteration's p update
+    int32_t xstep;                      // x += alpha p due in this iteration's p update
+    int32_t ru;                         // reliable update due after this iteration's p update
 };
 using BScal = BScalT<double>;
 
@@ -60,7 +63,8 @@ struct BArgsT {
     const int32_t *list;    // systems the per-system kernels cover (one workgroup each)
     BScalT<T> *scal;
     int32_t *sys_done;      // per system: 0 running; 2 all right-hand sides finished, the
-                            // last x steps pending in this iteration's p update; 1 done
+                            // last x steps pending in this iteration's p update; 1 done;
+                            // 3 (reliable-update batch) updates due after the p update
     T *part;                // 3 regions of part_stride values
     int64_t part_stride;    // (tiles of the whole table) * 16
     int ntiles;
@@ -704,6 +708,7 @@ __global__ __launch_bounds__(kBB) void batch_r1_kernel(BArgsT<T> a)
     if (threadIdx.x < S.K) {
         BScalT<T> &c = a.scal[S.scal0 + threadIdx.x];
         c.xstep = 0;
+        c.ru = 0;
         if (c.active) {
             c.pq = pq;
             if (!isfinite(pq) || !(pq > T(0))) {
@@ -828,17 +833,25 @@ __global__ __launch_bounds__(kBB) void batch_update_kernel(BArgsT<T> a)
 
 // (R2) stopping test and beta per right-hand side; when none stays active
 // the system enters state 2 (its last x steps follow in the p update).
+// Reliable-update systems (S.ru; binary32 iteration scaled by sigma = ||r||
+// of the last float64 update, Sleijpen and van der Vorst's scheme as in
+// mixed-precision CG): the test is the update test instead, ||r^||^2 <=
+// stop2 (the tolerance in the scale of the last update) or ||r^||^2 <
+// delta^2 max ||r^||^2 since the last update (c.bb holds that maximum); a
+// right-hand side that passes it pauses (no beta, no p update; its x step
+// still runs) and the system enters state 3, after which the update
+// kernels of the batch call take over.
 template <typename T>
 __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
 {
     __shared__ T red[kBB];
-    __shared__ int any_active;
+    __shared__ int any_active, any_ru;
     const int sid = a.list[blockIdx.x];
     if (a.sys_done[sid]) return;
     const BSysT<T> S = a.sys[sid];
     const T rr = sys_sum(a, S, 1, red);
     const T rz0 = sys_sum(a, S, 2, red);
-    if (threadIdx.x == 0) any_active = 0;
+    if (threadIdx.x == 0) any_active = any_ru = 0;
     __syncthreads();
     if (threadIdx.x < S.K) {
         BScalT<T> &c = a.scal[S.scal0 + threadIdx.x];
@@ -846,15 +859,28 @@ __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
             const T rz = S.jac ? rz0 : rr;
             c.rr = rr;
             int status = CGX_PENDING;
-            if (!isfinite(rr) || !isfinite(rz))
+            bool pause = false;
+            if (!isfinite(rr) || !isfinite(rz)) {
                 status = CGX_NONFINITE;
-            else if (rr <= c.stop2)
+            } else if (S.ru) {
+                if (rr > c.bb) c.bb = rr;
+                pause = rr <= c.stop2 || (double)rr < S.rtol2 * (double)c.bb;
+                if (!pause && !(rz > T(0)))
+                    status = CGX_BREAKDOWN;
+                else if (!pause && c.iter >= S.maxit)
+                    status = CGX_NOT_CONVERGED;
+            } else if (rr <= c.stop2) {
                 status = CGX_OK;
-            else if (!(rz > T(0)))
+            } else if (!(rz > T(0))) {
                 status = CGX_BREAKDOWN;
-            else if (c.iter >= S.maxit)
+            } else if (c.iter >= S.maxit) {
                 status = CGX_NOT_CONVERGED;
-            if (status == CGX_PENDING) {
+            }
+            if (pause) {
+                c.ru = 1;
+                c.active = 0;
+                atomicOr(&any_ru, 1);
+            } else if (status == CGX_PENDING) {
                 c.beta = rz / c.rho_used;
                 c.rho = rz;
                 atomicOr(&any_active, 1);
@@ -865,7 +891,12 @@ __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0 && !any_active) a.sys_done[sid] = 2;
+    if (threadIdx.x == 0) {
+        if (any_ru)
+            a.sys_done[sid] = 3;
+        else if (!any_active)
+            a.sys_done[sid] = 2;
+    }
 }
 
 // (3) x += alpha p for the right-hand sides that took a step this
