@@ -640,7 +640,8 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5, full=Tr
         lat.sort()
         return {"qps": round(qps, 2) if qps else "burst", "max_group": max_group,
                 "precond": "jacobi" if opts.precond else "none",
-                "precision": "mixed" if opts.precision == cgx.PRECISION_MIXED else "fp64",
+                "precision": {cgx.PRECISION_MIXED: "mixed",
+                              cgx.PRECISION_MIXED_RU: "mixed_ru"}.get(opts.precision, "fp64"),
                 "solves_per_s": round(n_req / wall, 2),
                 "p50_ms": round(lat[len(lat) // 2], 2),
                 "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 2),
@@ -683,6 +684,11 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5, full=Tr
                         inner_rtol=1e-2)
     msat = run(0, opts=mix)
     rows += [msat, run(0.8 * msat["solves_per_s"], opts=mix)]
+    # binary32 CG with float64 reliable updates (delta 1e-2)
+    rmix = cgx.make_opts(rtol=1e-8, precond=cgx.PRECOND_JACOBI,
+                         precision=cgx.PRECISION_MIXED_RU, inner_rtol=1e-2)
+    rsat = run(0, opts=rmix)
+    rows += [rsat, run(0.8 * rsat["solves_per_s"], opts=rmix)]
     return {"workload": f"{n_req} Poisson-arrival requests on {pool_systems} resident Q1 systems "
                         f"(rows lognormal in [1e4, 4e6]), lognormal(0,1), rtol 1e-8",
             "rows": rows, "one_at_a_time_fp64_cg": sequential(),

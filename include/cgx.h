@@ -392,7 +392,11 @@ size_t cgx_serve_request_bytes(int64_t n_rows);
  * ends it, else binary32 CG on A->val32 (Jacobi from val32's diagonal with
  * precond) from 0 on float(r / ||r||) to inner_rtol (default 1e-3) or maxit
  * iterations, then x += ||r|| d in float64; at most max_outer (default 100)
- * inner solves, then CGX_NOT_CONVERGED.  The inner solves of all MIXED
+ * inner solves, then CGX_NOT_CONVERGED.  MIXED_RU (needs A->val32): the
+ * reliable-update method of cgx_cg_solve_batched's MIXED_RU for the
+ * request (delta = inner_rtol, default 1e-2; at most max_outer updates,
+ * default 100, and maxit binary32 iterations), its updates taken inside the
+ * iteration sequence.  The inner solves of all MIXED
  * requests advance together in the batched binary32 kernels; each request
  * takes its float64 steps on its own.  Non-blocking; *ticket identifies the
  * request.  CGX_ENOMEM at once if the request can never fit the pool. */

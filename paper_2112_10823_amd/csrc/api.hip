@@ -649,9 +649,10 @@ int cgx_submit(cgx_handle h, const cgx_csr *A, const double *b, double *x, const
     return guarded([&]() -> int {
         CGX_REQUIRE(h != nullptr, "handle is NULL");
         CGX_REQUIRE(opts != nullptr && ticket != nullptr, "opts or ticket is NULL");
-        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64 || opts->precision == CGX_PRECISION_MIXED,
-                    "served solves are float64 or MIXED");
-        const bool mixed = opts->precision == CGX_PRECISION_MIXED;
+        CGX_REQUIRE(opts->precision == CGX_PRECISION_FP64 || opts->precision == CGX_PRECISION_MIXED ||
+                        opts->precision == CGX_PRECISION_MIXED_RU,
+                    "served solves are float64, MIXED or MIXED_RU");
+        const bool mixed = opts->precision != CGX_PRECISION_FP64;
         int rc = check_csr(A, true, mixed);
         if (rc) return rc;
         CGX_REQUIRE(A->n_rows == A->n_cols && A->n_rows >= 1, "matrix must be square, n >= 1");

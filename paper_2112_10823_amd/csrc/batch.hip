@@ -280,234 +280,6 @@ int ensure_batch_graph(GraphSlot &slot, int K, const BArgsT<T> &a, hipStream_t s
     return CGX_OK;
 }
 
-// ------------------------------------------- reliable-update batch --
-// Binary32 CG with float64 reliable updates for every (system, right-hand
-// side) of the batch (the single-system MIXED_RU method): the binary32
-// plan iterates on r^ = r / sigma with d (its x) the correction in that
-// scale; batch_r2_kernel pauses a right-hand side when its update test
-// fires (system state 3), and these kernels, launched after the p update of
-// every iteration, take the update for the paused ones: x += sigma d, d = 0
-// (fold); r = b - A x in float64 (residual); sigma' = ||r||, the float64
-// stopping test (norm); r^ = float(r / sigma'), z = D^-1 r^ (rescale);
-// beta = (rho' / rho) (sigma' / sigma) and the right-hand side resumes
-// (resume); p = z + beta p (direction).  Systems in another state return at
-// once.  The tiles of the two plans are the same.
-
-__global__ __launch_bounds__(kBB) void ru_fold_kernel(BArgsT<double> a64, BArgsT<float> a32)
-{
-    const BTile t = a32.tiles[blockIdx.x];
-    if (a32.sys_done[t.sys] != 3) return;
-    const BSysT<double> S = a64.sys[t.sys];
-    const BSysT<float> F = a32.sys[t.sys];
-    const int j = threadIdx.x % S.K;
-    if (!a32.scal[F.scal0 + j].ru) return;
-    const double sigma = sqrt(a64.scal[S.scal0 + j].rr);
-    const int64_t e1 = (int64_t)(t.row0 + t.rows) * S.K;
-    for (int64_t e = (int64_t)t.row0 * S.K + threadIdx.x; e < e1; e += kBB) {
-        S.x[e] = __builtin_fma(sigma, (double)F.x[e], S.x[e]);
-        F.x[e] = 0.0f;
-    }
-}
-
-__global__ __launch_bounds__(kBB) void ru_residual_kernel(BArgsT<double> a64, BArgsT<float> a32)
-{
-    __shared__ double red[kBB];
-    const BTile t = a64.tiles[blockIdx.x];
-    if (a32.sys_done[t.sys] != 3) return;
-    const BSysT<double> S = a64.sys[t.sys];
-    const BSysT<float> F = a32.sys[t.sys];
-    const int M = setup_m(S);
-    const int G = S.K * M, gpw = kWave / G;
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
-    const bool on = a32.scal[F.scal0 + j].ru != 0;
-    double prr = 0.0;
-    for (int row = t.row0 + wave * gpw + grp; gpw >= 1 && row < t.row0 + t.rows;
-         row += (kBB / kWave) * gpw) {
-        double dg;
-        const double ax = row_spmm(S, row, j, m, M, dg, S.x);
-        if (m == 0 && on) {
-            const double ri = S.B[(int64_t)j * S.n + row] - ax;
-            S.r[(int64_t)row * S.K + j] = ri;
-            prr += ri * ri;
-        }
-    }
-    block_sum_by_rhs(prr, S.K, red, a64.part + (int64_t)t.tile * kMaxK);
-}
-
-__global__ __launch_bounds__(kBB) void ru_norm_kernel(BArgsT<double> a64, BArgsT<float> a32,
-                                                      int max_updates)
-{
-    __shared__ double red[kBB];
-    const int sid = a64.list[blockIdx.x];
-    if (a32.sys_done[sid] != 3) return;
-    const BSysT<double> S = a64.sys[sid];
-    const BSysT<float> F = a32.sys[sid];
-    const double rr = sys_sum(a64, S, 0, red);
-    if (threadIdx.x < S.K) {
-        BScalT<float> &c = a32.scal[F.scal0 + threadIdx.x];
-        if (c.ru) {
-            BScalT<double> &d = a64.scal[S.scal0 + threadIdx.x];
-            d.pq = d.rr;  // sigma^2 of the previous update
-            d.rr = rr;
-            d.iter += 1;  // updates taken
-            int status = CGX_PENDING;
-            if (!isfinite(rr))
-                status = CGX_NONFINITE;
-            else if (rr <= d.stop2)
-                status = CGX_OK;
-            else if (d.iter >= max_updates)
-                status = CGX_NOT_CONVERGED;  // the update cap (x already holds d)
-            if (status != CGX_PENDING) {
-                d.status = status;
-                c.status = status;
-                c.ru = 0;
-            }
-        }
-    }
-}
-
-__global__ __launch_bounds__(kBB) void ru_rescale_kernel(BArgsT<double> a64, BArgsT<float> a32)
-{
-    __shared__ float red[kBB];
-    const BTile t = a32.tiles[blockIdx.x];
-    if (a32.sys_done[t.sys] != 3) return;
-    const BSysT<double> S = a64.sys[t.sys];
-    const BSysT<float> F = a32.sys[t.sys];
-    const int j = threadIdx.x % S.K;
-    const bool on = a32.scal[F.scal0 + j].ru != 0;
-    float prz = 0.0f, prr = 0.0f;
-    if (on) {
-        const double sigma = sqrt(a64.scal[S.scal0 + j].rr);
-        const int64_t e1 = (int64_t)(t.row0 + t.rows) * S.K;
-        int row = t.row0 + (int)threadIdx.x / S.K;
-        for (int64_t e = (int64_t)t.row0 * S.K + threadIdx.x; e < e1; e += kBB, row += kBB / S.K) {
-            const float ci = (float)(S.r[e] / sigma);
-            const float zi = F.jac ? F.dinv[row] * ci : ci;
-            F.r[e] = ci;
-            prz += ci * zi;
-            prr += ci * ci;
-        }
-    }
-    float *base = a32.part + (int64_t)t.tile * kMaxK;
-    block_sum_by_rhs(prz, S.K, red, base);
-    block_sum_by_rhs(prr, S.K, red, base + a32.part_stride);
-}
-
-__global__ __launch_bounds__(kBB) void ru_resume_kernel(BArgsT<double> a64, BArgsT<float> a32)
-{
-    __shared__ float red[kBB];
-    __shared__ int any_active;
-    const int sid = a32.list[blockIdx.x];
-    if (a32.sys_done[sid] != 3) return;
-    const BSysT<double> S = a64.sys[sid];
-    const BSysT<float> F = a32.sys[sid];
-    if (threadIdx.x == 0) any_active = 0;
-    const float rz = sys_sum(a32, F, 0, red);  // its barriers order the reset above
-    const float rr = sys_sum(a32, F, 1, red);
-    if (threadIdx.x < S.K) {
-        BScalT<float> &c = a32.scal[F.scal0 + threadIdx.x];
-        if (c.ru) {
-            BScalT<double> &d = a64.scal[S.scal0 + threadIdx.x];
-            int status = CGX_PENDING;
-            if (!isfinite(rz) || !isfinite(rr))
-                status = CGX_NONFINITE;
-            else if (!(rz > 0.0f))
-                status = CGX_BREAKDOWN;
-            else if (c.iter >= F.maxit)
-                status = CGX_NOT_CONVERGED;
-            if (status == CGX_PENDING) {
-                c.beta = (rz / c.rho) * (float)(sqrt(d.rr) / sqrt(d.pq));
-                c.rho = rz;
-                c.rr = rr;
-                c.bb = rr;  // the maximum of ||r^||^2 restarts at the update
-                c.stop2 = (float)(d.stop2 / d.rr);
-                c.active = 1;
-                atomicOr(&any_active, 1);
-            } else {
-                c.status = status;
-                c.ru = 0;
-                if (status != CGX_NOT_CONVERGED) d.status = status;
-            }
-        } else if (c.active) {
-            atomicOr(&any_active, 1);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) a32.sys_done[sid] = any_active ? 0 : 1;
-}
-
-__global__ __launch_bounds__(kBB) void ru_direction_kernel(BArgsT<float> a32)
-{
-    const BTile t = a32.tiles[blockIdx.x];
-    const BSysT<float> F = a32.sys[t.sys];
-    const int j = threadIdx.x % F.K;
-    const BScalT<float> c = a32.scal[F.scal0 + j];
-    if (!c.ru || !c.active) return;
-    const float beta = c.beta;
-    const int64_t e1 = (int64_t)(t.row0 + t.rows) * F.K;
-    int row = t.row0 + (int)threadIdx.x / F.K;
-    for (int64_t e = (int64_t)t.row0 * F.K + threadIdx.x; e < e1; e += kBB, row += kBB / F.K)
-        F.p[e] = fma_t(beta, F.p[e], F.jac ? F.dinv[row] * F.r[e] : F.r[e]);
-}
-
-// Start of the reliable-update iteration (after the first float64
-// residual and the binary32 setup on float(r / sigma)): the maximum of
-// ||r^||^2 starts at its first value and the stopping test moves into the
-// scale sigma; right-hand sides already done in float64 stay inactive.
-__global__ __launch_bounds__(kBB) void ru_start_kernel(BArgsT<double> a64, BArgsT<float> a32)
-{
-    __shared__ int any_active;
-    const int sid = a32.list[blockIdx.x];
-    const BSysT<double> S = a64.sys[sid];
-    const BSysT<float> F = a32.sys[sid];
-    if (threadIdx.x == 0) any_active = 0;
-    __syncthreads();
-    if (threadIdx.x < S.K) {
-        BScalT<float> &c = a32.scal[F.scal0 + threadIdx.x];
-        const BScalT<double> &d = a64.scal[S.scal0 + threadIdx.x];
-        if (d.status != CGX_PENDING) {
-            c.active = 0;
-            c.status = CGX_OK;
-        } else if (c.active) {
-            c.bb = c.rr;
-            c.stop2 = (float)(d.stop2 / d.rr);
-            atomicOr(&any_active, 1);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) a32.sys_done[sid] = any_active ? 0 : 1;
-}
-
-// End: x += sigma d for every right-hand side (d is 0 where the last update
-// folded it; it holds the pending correction where the iteration cap or a
-// breakdown stopped the binary32 iteration).
-__global__ __launch_bounds__(kBB) void ru_final_fold_kernel(BArgsT<double> a64, BArgsT<float> a32)
-{
-    const BTile t = a64.tiles[blockIdx.x];
-    const BSysT<double> S = a64.sys[t.sys];
-    const BSysT<float> F = a32.sys[t.sys];
-    const int j = threadIdx.x % S.K;
-    if (j >= S.nrhs) return;
-    const double sigma = sqrt(a64.scal[S.scal0 + j].rr);
-    const int64_t e1 = (int64_t)(t.row0 + t.rows) * S.K;
-    for (int64_t e = (int64_t)t.row0 * S.K + threadIdx.x; e < e1; e += kBB)
-        S.x[e] = __builtin_fma(sigma, (double)F.x[e], S.x[e]);
-}
-
-void launch_ru_iteration(const BArgsT<double> &a64, const BArgsT<float> &a32, int max_updates,
-                         hipStream_t s)
-{
-    launch_batch_iteration(a32, s);
-    const dim3 g(a32.ntiles), l(a32.nlist), b(kBB);
-    hipLaunchKernelGGL(ru_fold_kernel, g, b, 0, s, a64, a32);
-    hipLaunchKernelGGL(ru_residual_kernel, g, b, 0, s, a64, a32);
-    hipLaunchKernelGGL(ru_norm_kernel, l, b, 0, s, a64, a32, max_updates);
-    hipLaunchKernelGGL(ru_rescale_kernel, g, b, 0, s, a64, a32);
-    hipLaunchKernelGGL(ru_resume_kernel, l, b, 0, s, a64, a32);
-    hipLaunchKernelGGL(ru_direction_kernel, g, b, 0, s, a32);
-}
-
 // K reliable-update iterations captured into `slot` (the binary32 graph
 // slot of the handle, keyed apart from the restarted refinement's graph).
 int ensure_ru_graph(GraphSlot &slot, int K, const BArgsT<double> &a64, const BArgsT<float> &a32,

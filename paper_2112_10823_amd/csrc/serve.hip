@@ -60,9 +60,9 @@ struct Request {
     double *x = nullptr;
     int jac = 0, maxit = 0;
     double rtol = 0.0;
-    int mixed = 0;            // binary32 inner solves inside float64 refinement
-    double inner_rtol = 0.0;  // MIXED: inner stopping tolerance
-    int max_outer = 0;        // MIXED: inner solves at most
+    int mixed = 0;            // 1: restarted refinement (MIXED); 2: reliable updates (MIXED_RU)
+    double inner_rtol = 0.0;  // MIXED: inner stopping tolerance; MIXED_RU: update trigger delta
+    int max_outer = 0;        // MIXED: inner solves at most; MIXED_RU: updates at most
     double t_submit = 0.0;
     size_t bytes = 0;  // heap bytes: Krylov vectors plus a one-system tuning plan
 };
@@ -78,11 +78,13 @@ struct Slot {
     std::vector<int> sharing;       // per lane: requests in the slot when it started
     // MIXED slots, per lane: float64 step due at the next cycle, first step
     // (x = caller x0), step issued this cycle, inner solves started, inner
-    // iterations so far
-    std::vector<uint8_t> need_outer, first, outer_ran;
-    std::vector<int> outer, inner_sum;
+    // iterations so far; MIXED_RU lanes: the status of a stopped binary32
+    // iteration (its last float64 step is due), and the update cap
+    std::vector<uint8_t> need_outer, first, outer_ran, last;
+    std::vector<int> outer, inner_sum, final_status;
     size_t off = 0, bytes = 0;      // heap block of the slot's vectors
-    bool mixed = false;
+    bool mixed = false;             // binary32 slot (MIXED or MIXED_RU)
+    bool ru = false;                // MIXED_RU: reliable updates inside the iteration
     int M = 1;
     int K = 1;
     int ntiles = 0;
@@ -302,6 +304,7 @@ __global__ __launch_bounds__(kBB) void mixed_outer_kernel(BArgs a64, const int32
         BScal &c = a64.scal[S.scal0 + j];
         c.rr = rr;
         c.bb = bb;
+        c.stop2 = S.rtol2 * bb;
         int status = CGX_PENDING;
         if (!isfinite(bb) || !isfinite(rr))
             status = CGX_NONFINITE;
@@ -370,14 +373,17 @@ __global__ __launch_bounds__(kBB) void mixed_inner_r0_kernel(BArgs a64, BArgsT<f
             c.status = CGX_OK;  // no inner solve: the lane is finished
             return;
         }
+        const BScal &d = a64.scal[S.scal0 + j];
         c.rr = rr;
-        c.bb = rr;
+        c.bb = rr;  // reliable updates: the largest ||r^||^2 since the last update
         c.rho = F.jac ? rz : rr;
-        c.stop2 = (float)F.rtol2 * rr;
+        // restarted refinement: stop at inner_rtol ||c||; reliable updates:
+        // the float64 stopping test in the scale ||r|| (update when reached)
+        c.stop2 = F.ru ? (float)(d.stop2 / d.rr) : (float)F.rtol2 * rr;
         int status = CGX_PENDING;
         if (!isfinite(rr) || !isfinite(rz))
             status = CGX_NONFINITE;
-        else if (rr == 0.0f || rr <= c.stop2)
+        else if (rr == 0.0f || (!F.ru && rr <= c.stop2))
             status = CGX_OK;
         else if (F.jac && !(rz > 0.0f))
             status = CGX_BREAKDOWN;
@@ -430,7 +436,7 @@ BSys slot_sys(const Engine &E, int si, int tile0)
     S.ntiles = s.ntiles;
     S.scal0 = si * kMaxK;
     S.jac = q.jac;
-    S.maxit = q.maxit;
+    S.maxit = q.mixed == 2 ? q.max_outer : q.maxit;  // MIXED_RU: the update cap
     S.rtol2 = q.rtol * q.rtol;
     return S;
 }
@@ -465,6 +471,7 @@ BSysT<float> slot_sys32(const Engine &E, int si, int tile0)
     F.jac = q.jac;
     F.maxit = q.maxit;
     F.rtol2 = q.inner_rtol * q.inner_rtol;
+    F.ru = q.mixed == 2;
     return F;
 }
 
@@ -666,7 +673,7 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
             if (sl.state[j] != kLaneRunning || !sl.need_outer[j]) continue;
             mask |= 1u << j;
             if (sl.first[j]) first |= 1u << j;
-            if (sl.outer[j] >= sl.key.max_outer) last |= 1u << j;
+            if (sl.ru ? sl.last[j] != 0 : sl.outer[j] >= sl.key.max_outer) last |= 1u << j;
             sl.need_outer[j] = 0;
             sl.first[j] = 0;
             sl.outer_ran[j] = 1;
@@ -682,8 +689,16 @@ bool device_cycle(Engine &E, bool changed, int iters, std::vector<int> &active)
     }
     if (E.nlist64 > 0 && E.active_tiles > 0)
         for (int k = 0; k < iters; ++k) launch_batch_iteration(m, s);
-    if (E.nlist32 > 0 && E.active_tiles32 > 0)
-        for (int k = 0; k < iters; ++k) launch_batch_iteration(m32, s);
+    if (E.nlist32 > 0 && E.active_tiles32 > 0) {
+        bool any_ru = false;
+        for (int i : active) any_ru = any_ru || (E.slots[i].used && E.slots[i].ru);
+        for (int k = 0; k < iters; ++k) {
+            if (any_ru)
+                launch_ru_iteration(m, m32, 0, s);  // the update caps in the slots' descriptors
+            else
+                launch_batch_iteration(m32, s);
+        }
+    }
     ENG_CHECK(hipGetLastError());
     ENG_CHECK(hipMemcpyAsync(E.h_done, E.pool + E.off_done, sizeof(int32_t) * E.max_slots,
                              hipMemcpyDeviceToHost, s));
@@ -725,8 +740,9 @@ bool admit(Engine &E, int &ntiles_active)
             sl.state[j] = kLaneJoining;
             sl.t_start[j] = t;
             sl.sharing[j] = sl.running();
-            sl.need_outer[j] = sl.first[j] = sl.outer_ran[j] = 0;
+            sl.need_outer[j] = sl.first[j] = sl.outer_ran[j] = sl.last[j] = 0;
             sl.outer[j] = sl.inner_sum[j] = 0;
+            sl.final_status[j] = CGX_PENDING;
             taken[h] = 1;
             joined = true;
             break;
@@ -772,6 +788,7 @@ bool admit(Engine &E, int &ntiles_active)
         sl.K = K;
         sl.key = pending[h];
         sl.mixed = pending[h].mixed != 0;
+        sl.ru = pending[h].mixed == 2;
         sl.lane.assign(K, Request{});
         sl.state.assign(K, kLaneFree);
         sl.t_start.assign(K, t);
@@ -779,8 +796,10 @@ bool admit(Engine &E, int &ntiles_active)
         sl.need_outer.assign(K, 0);
         sl.first.assign(K, 0);
         sl.outer_ran.assign(K, 0);
+        sl.last.assign(K, 0);
         sl.outer.assign(K, 0);
         sl.inner_sum.assign(K, 0);
+        sl.final_status.assign(K, CGX_PENDING);
         for (size_t q = 0; q < members.size(); ++q) {
             sl.lane[q] = pending[members[q]];
             sl.state[q] = kLaneJoining;
@@ -877,7 +896,31 @@ void engine_loop(Engine *Ep)
         for (int i : active) {
             Slot &sl = E.slots[i];
             if (!sl.used) continue;
-            if (sl.mixed) {
+            if (sl.ru) {
+                // reliable updates: a lane is finished when a float64 test
+                // (start, an update, or its last step) gave a final status;
+                // a lane whose binary32 iteration stopped otherwise (cap,
+                // breakdown) takes a last float64 step (fold, residual) first
+                for (int j = 0; j < sl.K; ++j) {
+                    if (sl.state[j] != kLaneRunning) continue;
+                    BScal v = E.h_scal[(size_t)i * kMaxK + j];
+                    const BScalT<float> &f = E.h_scal32[(size_t)i * kMaxK + j];
+                    const bool ran = sl.outer_ran[j] != 0;
+                    sl.outer_ran[j] = 0;
+                    if (v.status != CGX_PENDING) {
+                        if (sl.last[j] && v.status != CGX_OK) v.status = sl.final_status[j];
+                        retire(i, j, v, sl.last[j] ? sl.inner_sum[j] : (ran ? 0 : f.iter), v.iter);
+                        continue;
+                    }
+                    if (!ran && !f.active) {
+                        sl.final_status[j] = f.status;
+                        sl.inner_sum[j] = f.iter;
+                        sl.last[j] = 1;
+                        sl.need_outer[j] = 1;
+                    }
+                }
+                if (sl.running() > 0) continue;
+            } else if (sl.mixed) {
                 // a lane whose float64 step ran this cycle is finished if its
                 // status is final; a lane whose inner solve ended takes its
                 // next float64 step at the next cycle
@@ -1055,8 +1098,8 @@ int serve_submit(Context *c, const cgx_csr *A, const double *b, double *x, const
     q.jac = o->precond == CGX_PRECOND_JACOBI ? 1 : 0;
     q.maxit = o->maxit > 0 ? o->maxit : std::max(A->n_rows, 1);
     q.rtol = o->rtol;
-    q.mixed = o->precision == CGX_PRECISION_MIXED ? 1 : 0;
-    q.inner_rtol = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-3;
+    q.mixed = o->precision == CGX_PRECISION_MIXED ? 1 : o->precision == CGX_PRECISION_MIXED_RU ? 2 : 0;
+    q.inner_rtol = o->inner_rtol > 0.0 ? o->inner_rtol : (q.mixed == 2 ? 1e-2 : 1e-3);
     q.max_outer = o->max_outer > 0 ? o->max_outer : 100;
     q.bytes = request_bytes(A->n_rows);
     std::lock_guard<std::mutex> lk(E->mu);

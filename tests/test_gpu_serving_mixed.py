@@ -1,6 +1,8 @@
-"""GPU tests of binary32-refined (MIXED) requests in the solve server: float64
-residual, update and stopping test per request, binary32 inner CG of all
-such requests in the batched kernels.
+"""GPU tests of binary32 requests in the solve server: restarted refinement
+(MIXED: float64 residual, update and stopping test per request, binary32
+inner CG of all such requests in the batched kernels) and reliable updates
+(MIXED_RU: one binary32 CG per request, float64 updates inside the
+iteration; bars at the end of the file).
 
 Bars, as for the float32-refined batch: the float64 true residual (the
 oracle's SpMV on the served solution) <= rtol; the solution within 1e-6 of
@@ -217,3 +219,143 @@ def test_served_mixed_million_rows_in_a_mix():
             assert true_relres(S, bs, xs.cpu().numpy()) <= 1e-8 * 1.01
     assert st.status == cgx.OK and st.outer_iters >= 2
     assert true_relres(A, b, x.cpu().numpy()) <= 1e-8 * 1.01
+
+
+# ---------------------------------------------------------------- MIXED_RU --
+# Served requests with reliable updates: each against the oracle's mixed_ru
+# of it alone, with the bars of the single-system reliable-update tests (true
+# residual, the kappa * rtol bound against float64, updates within 2, the
+# stopping step in the band of the oracle's history).
+
+def ru_opts(rtol=1e-10, jacobi=True, delta=1e-2, **kw):
+    return cgx.make_opts(rtol=rtol, precond=int(jacobi), precision=cgx.PRECISION_MIXED_RU,
+                         inner_rtol=delta, **kw)
+
+
+def check_ru_against_oracle(A, b, x, st, rtol, jacobi, delta, gate_stop=False):
+    info = st.as_dict()
+    ref = oracle.mixed_ru(A, A.val.astype(np.float32), b, rtol=rtol, delta=delta, jacobi=jacobi)
+    assert ref.status == oracle.OK
+    assert st.status == cgx.OK and st.path == 4, info
+    tr = true_relres(A, b, x)
+    assert tr <= rtol, info
+    assert abs(st.relres - tr) <= 1e-3 * tr + 1e-16, info
+    assert abs(st.outer_iters - ref.outer_iters) <= 2, (info, ref.outer_iters)
+    xs = oracle.cg(A, b, rtol=1e-13, jacobi=True, maxit=20000).x
+    assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs), info
+    if gate_stop:
+        from cg_gates import assert_stop_in_band, residual_band
+        h, F = residual_band(A, b, rtol, solve=lambda M, w, t: oracle.mixed_ru(
+            M, M.val.astype(np.float32), w, rtol=t, delta=delta, jacobi=jacobi,
+            history=True).relres_hist)
+        assert_stop_in_band(h, F, st.iters, rtol, (st.iters, ref.iters))
+
+
+@pytest.mark.parametrize("jacobi", [False, True], ids=["plain", "jacobi"])
+def test_served_ru_matches_oracle(resident, jacobi):
+    mats, dmats = resident
+    opts = ru_opts(jacobi=jacobi)
+    print(f"[served ru] oracle parity jacobi={jacobi}", flush=True)
+    with cgx.Server(pool(1 << 28), max_slots=6) as srv:
+        reqs = []
+        for i in range(8):
+            k = i % 4
+            b = synth.uniform(5200 + i, mats[k].n_rows)
+            x = torch.zeros(mats[k].n_rows, dtype=torch.float64, device="cuda")
+            reqs.append((k, b, x, srv.submit(dmats[k], dev(b), x, opts)))
+        for i, (k, b, x, t) in enumerate(reqs):
+            st = srv.wait(t)
+            check_ru_against_oracle(mats[k], b, x.cpu().numpy(), st, 1e-10, jacobi, 1e-2,
+                                    gate_stop=i < 4)
+
+
+def test_served_ru_alone_equals_mix(resident):
+    """Ungrouped, a MIXED_RU request gets the same bits alone and among
+    float64, MIXED and MIXED_RU requests."""
+    mats, dmats = resident
+    opts = ru_opts()
+    b = dev(synth.uniform(5300, mats[2].n_rows))
+    h = cgx.Handle()
+    x_alone = torch.zeros_like(b)
+    print("[served ru] alone", flush=True)
+    with cgx.Server(pool(1 << 28), max_slots=8, handle=h, max_group=1) as srv:
+        st_alone = srv.wait(srv.submit(dmats[2], b, x_alone, opts))
+    x_mix = torch.zeros_like(b)
+    others = []
+    kinds = [cgx.make_opts(rtol=1e-10, precond=1), mixed_opts(), opts]
+    print("[served ru] in a mix", flush=True)
+    with cgx.Server(pool(1 << 28), max_slots=8, handle=h, max_group=1) as srv:
+        for i in range(6):
+            k = i % 4
+            bo = dev(synth.uniform(5400 + i, mats[k].n_rows))
+            xo = torch.zeros_like(bo)
+            others.append(srv.submit(dmats[k], bo, xo, kinds[i % 3]))
+        time.sleep(0.002)
+        t = srv.submit(dmats[2], b, x_mix, opts)
+        for i in range(4):
+            k = (i + 1) % 4
+            bo = dev(synth.uniform(5500 + i, mats[k].n_rows))
+            xo = torch.zeros_like(bo)
+            others.append(srv.submit(dmats[k], bo, xo, kinds[(i + 1) % 3]))
+        st_mix = srv.wait(t)
+        for to in others:
+            assert srv.wait(to).status == cgx.OK
+    assert st_alone.status == st_mix.status == cgx.OK
+    assert (st_alone.iters, st_alone.outer_iters) == (st_mix.iters, st_mix.outer_iters)
+    assert torch.equal(x_alone, x_mix)
+
+
+def test_served_ru_grouped_and_initial_guess(resident):
+    """MIXED_RU requests on one matrix sharing a slot, one with an initial
+    guess, one with b = 0."""
+    mats, dmats = resident
+    big = synth.q1cube(50, 1.0, 5600)
+    dbig = cgx.DeviceCSR.from_host(big, with_f32=True)
+    A, dA = mats[1], dmats[1]
+    opts = ru_opts()
+    bs = [synth.uniform(5700 + i, A.n_rows) for i in range(4)]
+    x0 = synth.uniform(5710, A.n_rows)
+    xs = [dev(x0)] + [torch.zeros(A.n_rows, dtype=torch.float64, device="cuda") for _ in bs[1:]]
+    xz = dev(synth.uniform(5711, A.n_rows))
+    print("[served ru] grouped", flush=True)
+    with cgx.Server(pool(1 << 30), max_slots=1, max_group=16) as srv:
+        bb = synth.uniform(5701, big.n_rows)
+        xb = torch.zeros(big.n_rows, dtype=torch.float64, device="cuda")
+        tb = srv.submit(dbig, dev(bb), xb, opts)  # holds the only slot
+        ts = [srv.submit(dA, dev(b), x, opts) for b, x in zip(bs, xs)]
+        tz = srv.submit(dA, torch.zeros_like(xz), xz, opts)
+        stb = srv.wait(tb)
+        sts = [srv.wait(t) for t in ts]
+        stz = srv.wait(tz)
+    check_ru_against_oracle(big, bb, xb.cpu().numpy(), stb, 1e-10, True, 1e-2)
+    for j, (b, x, st) in enumerate(zip(bs, xs, sts)):
+        assert st.slot_requests == 5
+        info = st.as_dict()
+        assert st.status == cgx.OK, info
+        assert true_relres(A, b, x.cpu().numpy()) <= 1e-10, info
+        ref = oracle.mixed_ru(A, A.val.astype(np.float32), b, x0=x0 if j == 0 else None,
+                              rtol=1e-10, delta=1e-2, jacobi=True)
+        assert abs(st.outer_iters - ref.outer_iters) <= 2, (info, ref.outer_iters)
+    assert stz.status == cgx.OK and stz.outer_iters == 0 and not xz.any()
+
+
+def test_served_ru_caps_and_errors(resident):
+    mats, dmats = resident
+    A, dA = mats[0], dmats[0]
+    b = synth.uniform(5800, A.n_rows)
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    print("[served ru] caps", flush=True)
+    with cgx.Server(pool(1 << 26), max_slots=2) as srv:
+        st = srv.wait(srv.submit(dA, dev(b), x, ru_opts(rtol=1e-15, jacobi=False, maxit=7)))
+        assert st.status == cgx.NOT_CONVERGED and st.iters == 7, st.as_dict()
+        tr = true_relres(A, b, x.cpu().numpy())
+        assert abs(st.relres - tr) <= 1e-6 * tr and tr < 0.9
+        x.zero_()
+        st = srv.wait(srv.submit(dA, dev(b), x, ru_opts(rtol=1e-15, jacobi=False, max_outer=2)))
+        assert st.status == cgx.NOT_CONVERGED and st.outer_iters == 2, st.as_dict()
+        neg = synth.CSR(A.n_rows, A.n_cols, A.row_ptr, A.col_idx, -A.val)
+        dneg = cgx.DeviceCSR.from_host(neg, with_f32=True)
+        st = srv.wait(srv.submit(dneg, dev(b), torch.zeros_like(x), ru_opts()))
+        assert st.status == cgx.BREAKDOWN, st.as_dict()
+        with pytest.raises(cgx.CgxError):
+            srv.submit(cgx.DeviceCSR.from_host(A), dev(b), torch.zeros_like(x), ru_opts())
