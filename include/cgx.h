@@ -386,7 +386,7 @@ size_t cgx_serve_request_bytes(int64_t n_rows);
 /* Queue a solve of A x = b (A resident and square, b / x device float64[n],
  * x holds x0 and receives the solution; all must stay valid until the
  * request completes).  opts: rtol, maxit, precond, precision are used, and
- * for CGX_PRECISION_MIXED inner_rtol and max_outer.  FP64: CG (Section 5.3)
+ * for CGX_PRECISION_MIXED and MIXED_RU inner_rtol and max_outer.  FP64: CG (Section 5.3)
  * in float64.  MIXED (needs A->val32): the refinement of cgx_cg_solve's
  * MIXED, step by step per request: float64 r = b - A x, ||r|| <= rtol ||b||
  * ends it, else binary32 CG on A->val32 (Jacobi from val32's diagonal with
