@@ -19,7 +19,11 @@
 // the float64 step of a lane (fold the inner solution into x, r = b - A x,
 // stopping test, next inner right-hand side r / ||r||) is taken at the start
 // of the cycle after its inner solve ended, in one short kernel sequence per
-// slot for all of its lanes that are due.
+// slot for all of its lanes that are due.  Requests with reliable updates
+// (MIXED_RU) use the same slots, start and finish the same way, but take
+// their float64 updates inside the iteration sequence (the update kernels of
+// batch_kernels.h run after every binary32 iteration while such a slot is
+// active), so between start and finish they need no host step.
 //
 // Device memory comes only from the caller's pool: a fixed arena (system
 // tables, lane table, work tables, scalars, reduction partials) at its start
