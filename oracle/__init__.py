@@ -89,6 +89,11 @@ def _load(path: str = _LIB_PATH):
             fn.argtypes = [i64, i32p, i32p, f64p, lp, f64p, f64p, dbl, dbl, i32, i32,
                            ctypes.POINTER(_Stats), ctypes.c_void_p]
             fn.restype = ctypes.c_int
+        for name, lp in (("oracle_mixed_ru_block", f32p), ("oracle_mixed_ru_block_f64", f64p)):
+            fn = getattr(lib, name)
+            fn.argtypes = [i64, i32p, i32p, f64p, lp, i32, f64p, f64p, dbl, dbl, i32, i32,
+                           ctypes.POINTER(_Stats)]
+            fn.restype = ctypes.c_int
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
         _libs[path] = lib
@@ -256,6 +261,28 @@ def mixed_ir(A, val32, b, x0=None, rtol=1e-10, tau=1e-3, inner_maxit=0, max_oute
                             b, x, float(rtol), float(tau), int(inner_maxit), int(max_outer),
                             int(bool(jacobi)), ctypes.byref(st))
     return SolveResult(x, st.status, st.iters, st.outer_iters, st.relres, st.relres_true)
+
+
+def mixed_ru_block(A, val32, B, X0=None, rtol=1e-10, delta=0.1, maxit=0, jacobi=False,
+                   inner_f64=False):
+    """mixed_ru for the k rows of B (right-hand sides of A) in step, an
+    update of one taken by all (see mixed_ru_block.inc).  Returns one
+    SolveResult per right-hand side (outer_iters = reliable updates)."""
+    B = np.ascontiguousarray(np.atleast_2d(B), dtype=np.float64)
+    k, n = B.shape
+    X = np.zeros((k, n)) if X0 is None else np.ascontiguousarray(X0, dtype=np.float64).copy()
+    st = (_Stats * k)()
+    lib = _load()
+    if inner_f64:
+        lib.oracle_mixed_ru_block_f64(A.n_rows, _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val),
+                                      _f64(A.val), int(k), B, X, float(rtol), float(delta),
+                                      int(maxit), int(bool(jacobi)), st)
+    else:
+        lib.oracle_mixed_ru_block(A.n_rows, _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val),
+                                  _f32(val32), int(k), B, X, float(rtol), float(delta),
+                                  int(maxit), int(bool(jacobi)), st)
+    return [SolveResult(X[j], s.status, s.iters, s.outer_iters, s.relres, s.relres_true)
+            for j, s in enumerate(st)]
 
 
 def lanczos_extremes(alpha, beta):

@@ -462,3 +462,33 @@ int oracle_mixed_ir(int64_t n, const int32_t *rp, const int32_t *ci, const doubl
 #undef RU_SPMV
 #undef RU_FMA
 #undef RU_SQRT
+
+/* oracle_mixed_ru_block (binary32 iteration) and oracle_mixed_ru_block_f64
+ * (float64 iteration, for the tests): k right-hand sides of one matrix in
+ * step, an update of one being taken by all (mixed_ru_block.inc). */
+#define RU_T float
+#define RUB_NAME oracle_mixed_ru_block
+#define RU_DOT oracle_dot_f32
+#define RU_SPMV oracle_spmv_f32
+#define RU_FMA fmaf
+#define RU_SQRT sqrtf
+#include "mixed_ru_block.inc"
+#undef RU_T
+#undef RUB_NAME
+#undef RU_DOT
+#undef RU_SPMV
+#undef RU_FMA
+#undef RU_SQRT
+#define RU_T double
+#define RUB_NAME oracle_mixed_ru_block_f64
+#define RU_DOT oracle_dot
+#define RU_SPMV oracle_spmv
+#define RU_FMA fma
+#define RU_SQRT sqrt
+#include "mixed_ru_block.inc"
+#undef RU_T
+#undef RUB_NAME
+#undef RU_DOT
+#undef RU_SPMV
+#undef RU_FMA
+#undef RU_SQRT

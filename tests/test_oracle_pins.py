@@ -658,3 +658,112 @@ def test_mixed_ru_status_cases():
     # the correction of the unfinished cycle is kept: reported residual = true residual
     true = np.linalg.norm(b - oracle.spmv(A, cap.x)) / np.linalg.norm(b)
     assert abs(cap.relres - true) <= 1e-12 * true and true < 0.5
+
+
+# ------------------------------------------- reliable updates, k in step --
+
+@pytest.mark.parametrize("case", ["fd7_plain", "q1_jacobi", "q1s_plain"])
+def test_ru_block_of_one_is_mixed_ru(case):
+    """One right-hand side: the block method is the single method, bit for
+    bit (iterates, counts, status), in binary32 and in float64."""
+    A = {"fd7_plain": lambda: synth.fd7(9), "q1_jacobi": lambda: synth.q1cube(10, 1.0, 5),
+         "q1s_plain": lambda: synth.q1cube(9, 1.5, 6)}[case]()
+    jacobi = case.endswith("jacobi")
+    b = synth.uniform(31, A.n_rows)
+    v32 = A.val.astype(np.float32)
+    for f64 in (False, True):
+        one = oracle.mixed_ru(A, v32, b, rtol=1e-10, delta=0.01, jacobi=jacobi, inner_f64=f64)
+        blk = oracle.mixed_ru_block(A, v32, b[None], rtol=1e-10, delta=0.01, jacobi=jacobi,
+                                    inner_f64=f64)[0]
+        assert (blk.status, blk.iters, blk.outer_iters) == (one.status, one.iters, one.outer_iters)
+        assert np.array_equal(blk.x, one.x) and blk.relres == one.relres
+
+
+@pytest.mark.parametrize("case", ["fd7_plain", "q1_jacobi", "fd7var_jacobi"])
+def test_ru_block_float64_steps_are_cg(case):
+    """Updates taken because another right-hand side fired are exact in
+    exact arithmetic too: in float64 every right-hand side of the block
+    follows float64 CG (iteration count, solution), whatever the others do."""
+    A = {"fd7_plain": lambda: synth.fd7(12), "q1_jacobi": lambda: synth.q1cube(12, 1.0, 4),
+         "fd7var_jacobi": lambda: synth.fd7_var(12, 1.0, 4)}[case]()
+    jacobi = case.endswith("jacobi")
+    B = np.stack([synth.uniform(40 + j, A.n_rows) for j in range(4)])
+    B[2] *= np.linspace(0.1, 3.0, A.n_rows)  # a right-hand side of another spectrum mix
+    res = oracle.mixed_ru_block(A, None, B, rtol=1e-10, delta=0.1, jacobi=jacobi,
+                                inner_f64=True)
+    for j, r in enumerate(res):
+        ref = oracle.cg(A, B[j], rtol=1e-10, jacobi=jacobi)
+        assert r.status == oracle.OK and r.outer_iters >= 3, j
+        assert abs(r.iters - ref.iters) <= 1, (j, r.iters, ref.iters)
+        assert np.linalg.norm(r.x - ref.x) / np.linalg.norm(ref.x) <= 1e-8, j
+
+
+def test_ru_block_updates_are_shared():
+    """Every active right-hand side takes every update event: those still
+    running have equal counts, each at least as many as alone less rounding
+    slack; duplicates of one right-hand side reproduce its solo run; a zero
+    right-hand side is inert (the others equal the block without it)."""
+    A = synth.q1cube(11, 1.0, 8)
+    v32 = A.val.astype(np.float32)
+    B = np.stack([synth.uniform(50 + j, A.n_rows) for j in range(3)])
+    res = oracle.mixed_ru_block(A, v32, B, rtol=1e-10, delta=0.01, jacobi=True)
+    solo = [oracle.mixed_ru(A, v32, B[j], rtol=1e-10, delta=0.01, jacobi=True) for j in range(3)]
+    assert all(r.status == oracle.OK for r in res)
+    last = max(r.iters for r in res)
+    # the right-hand sides that ran to the end saw every event
+    runners = [r for r in res if r.iters == last]
+    assert len({r.outer_iters for r in runners}) == 1
+    for r, s in zip(res, solo):
+        assert r.outer_iters >= s.outer_iters - 1
+        assert np.linalg.norm(r.x - s.x) <= 1e-8 * np.linalg.norm(s.x)
+    dup = oracle.mixed_ru_block(A, v32, np.stack([B[0], B[0]]), rtol=1e-10, delta=0.01,
+                                jacobi=True)
+    for r in dup:
+        assert (r.iters, r.outer_iters) == (solo[0].iters, solo[0].outer_iters)
+        assert np.array_equal(r.x, solo[0].x)
+    Bz = np.stack([B[0], np.zeros(A.n_rows), B[1]])
+    rz = oracle.mixed_ru_block(A, v32, Bz, rtol=1e-10, delta=0.01, jacobi=True)
+    r2 = oracle.mixed_ru_block(A, v32, np.stack([B[0], B[1]]), rtol=1e-10, delta=0.01,
+                               jacobi=True)
+    assert rz[1].status == oracle.OK and rz[1].iters == 0 and not rz[1].x.any()
+    for a, c in zip((rz[0], rz[2]), r2):
+        assert (a.iters, a.outer_iters) == (c.iters, c.outer_iters) and np.array_equal(a.x, c.x)
+
+
+def test_ru_block_status_cases():
+    A = synth.fd7(6)
+    v32 = A.val.astype(np.float32)
+    n = A.n_rows
+    B = np.stack([synth.uniform(4, n), synth.uniform(5, n)])
+    cap = oracle.mixed_ru_block(A, v32, B, rtol=1e-14, maxit=5)
+    for j, c in enumerate(cap):
+        assert c.status == oracle.NOT_CONVERGED and c.iters == 5
+        true = np.linalg.norm(B[j] - oracle.spmv(A, c.x)) / np.linalg.norm(B[j])
+        assert abs(c.relres - true) <= 1e-12 * true and true < 0.5
+    neg = CSR(n, n, A.row_ptr, A.col_idx, -A.val)
+    assert all(r.status == oracle.BREAKDOWN
+               for r in oracle.mixed_ru_block(neg, -v32, B, jacobi=True))
+    assert all(r.status == oracle.BREAKDOWN for r in oracle.mixed_ru_block(neg, -v32, B))
+
+
+def test_ru_block_sibling_event_reaches_every_rhs():
+    """A discrete eigenvector of the 7-point operator converges in one binary32
+    step and fires an update there; in the block the other right-hand side
+    takes that update too (its run then differs from its solo run and counts
+    at least as many updates), while each lane alone keeps its solo result."""
+    N = 9
+    A = synth.fd7(N)
+    v32 = A.val.astype(np.float32)
+    i = np.arange(1, N + 1)
+    vs = [np.sin(jj * math.pi * i / (N + 1)) for jj in (2, 5, 7)]
+    v = np.einsum("k,j,i->kji", vs[2], vs[1], vs[0]).ravel()
+    lam = sum(4 * math.sin(jj * math.pi / (2 * (N + 1))) ** 2 for jj in (2, 5, 7))
+    b_eig, b_rnd = lam * v, synth.uniform(60, A.n_rows)
+    solo_eig = oracle.mixed_ru(A, v32, b_eig, rtol=1e-6, delta=0.01)
+    solo_rnd = oracle.mixed_ru(A, v32, b_rnd, rtol=1e-6, delta=0.01)
+    assert solo_eig.iters == 1 and solo_eig.outer_iters == 1
+    assert solo_rnd.iters > 3
+    blk = oracle.mixed_ru_block(A, v32, np.stack([b_rnd, b_eig]), rtol=1e-6, delta=0.01)
+    assert blk[1].iters == 1 and np.array_equal(blk[1].x, solo_eig.x)
+    assert blk[0].status == oracle.OK and blk[0].outer_iters >= solo_rnd.outer_iters
+    assert not np.array_equal(blk[0].x, solo_rnd.x)  # the update at step 1 was taken
