@@ -51,3 +51,37 @@ def assert_stop_in_band(h, F, k, rtol, what=""):
     assert 1 <= k < len(h), (what, k, len(h))
     assert h[k] <= F * rtol, (what, k, h[k] / rtol, F)
     assert h[k - 1] > rtol / F, (what, k, h[k - 1] / rtol, F)
+
+
+def ru_block_refs(A, B, rtol, delta, jacobi, X0=None):
+    """The oracle's reliable-update run of the right-hand sides B (k x n) of
+    A with updates shared by all of them, and the slack it implies for the
+    update count of another correct run.
+
+    An update event of the block is the union of every right-hand side's
+    trigger, the final ones (each right-hand side's own convergence test)
+    included, so a stopping step moved by one iteration merges or splits an
+    event of every right-hand side still running: the count is far more
+    sensitive to rounding than a single right-hand side's.  The oracle
+    measures that sensitivity as D, the largest per-right-hand-side
+    difference of the count between its run and the same run on the
+    reversed-order system; a third run is allowed max(2, 2 D)."""
+    v32 = np.asarray(A.val).astype(np.float32)
+    refs = oracle.mixed_ru_block(A, v32, B, X0=X0, rtol=rtol, delta=delta, jacobi=jacobi)
+    Ar, _ = reversed_system(A, B[0])
+    Br = np.ascontiguousarray(np.asarray(B)[:, ::-1])
+    X0r = None if X0 is None else np.ascontiguousarray(np.asarray(X0)[:, ::-1])
+    rev = oracle.mixed_ru_block(Ar, np.asarray(Ar.val).astype(np.float32), Br, X0=X0r,
+                                rtol=rtol, delta=delta, jacobi=jacobi)
+    D = max(abs(a.outer_iters - b.outer_iters) for a, b in zip(refs, rev))
+    return refs, max(2, 2 * D)
+
+
+def assert_updates_shared(runs, what=""):
+    """runs: (iters, updates) of the right-hand sides of one matrix that
+    started together and converged.  With shared updates each stops at an
+    event and has taken every event up to it, so the update count is a
+    strictly increasing function of the stopping step."""
+    runs = sorted(runs)
+    for (i0, u0), (i1, u1) in zip(runs, runs[1:]):
+        assert (u1 == u0) if i1 == i0 else (u1 > u0), (what, runs)

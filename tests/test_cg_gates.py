@@ -1,9 +1,11 @@
 """CPU checks of the stopping-step gate used by the GPU tests (cg_gates)."""
 import numpy as np
+import pytest
 
 import oracle
 import synth
-from cg_gates import assert_stop_in_band, residual_band, reversed_system
+from cg_gates import (assert_stop_in_band, assert_updates_shared, residual_band,
+                      reversed_system, ru_block_refs)
 
 
 def dense(A):
@@ -44,3 +46,23 @@ def test_band_accepts_the_oracle_and_its_reversal_and_rejects_shifts():
         except AssertionError:
             continue
         raise AssertionError(f"stop at {bad} (oracle {k}) accepted")
+
+
+def test_shared_update_gates_accept_the_oracle_and_reject_solo_updates():
+    """The reversed-order block run is within the slack and satisfies the
+    shared-update invariant; per-right-hand-side (solo) updates break it."""
+    A = synth.fd7_var(10, 1.0, 7)
+    B = np.stack([synth.uniform(70 + j, A.n_rows) for j in range(6)])
+    refs, slack = ru_block_refs(A, B, 1e-10, 1e-2, False)
+    assert 2 <= slack <= 8
+    assert all(r.status == oracle.OK for r in refs)
+    assert_updates_shared([(r.iters, r.outer_iters) for r in refs])
+    Ar, _ = reversed_system(A, B[0])
+    rev = oracle.mixed_ru_block(Ar, Ar.val.astype(np.float32), B[:, ::-1].copy(), rtol=1e-10,
+                                delta=1e-2)
+    assert_updates_shared([(r.iters, r.outer_iters) for r in rev])
+    for a, b in zip(refs, rev):
+        assert abs(a.outer_iters - b.outer_iters) <= slack
+    solo = [oracle.mixed_ru(A, A.val.astype(np.float32), b, rtol=1e-10, delta=1e-2) for b in B]
+    with pytest.raises(AssertionError):
+        assert_updates_shared([(r.iters, r.outer_iters) for r in solo])
