@@ -839,8 +839,9 @@ __global__ __launch_bounds__(kBB) void batch_update_kernel(BArgsT<T> a)
 // stop2 (the tolerance in the scale of the last update) or ||r^||^2 <
 // delta^2 max ||r^||^2 since the last update (c.bb holds that maximum); a
 // right-hand side that passes it pauses (no beta, no p update; its x step
-// still runs) and the system enters state 3, after which the update
-// kernels of the batch call take over.
+// still runs), with it every other right-hand side of the system that
+// would go on, and the system enters state 3, after which the update
+// kernels take over.
 template <typename T>
 __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
 {
@@ -853,41 +854,49 @@ __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
     const T rz0 = sys_sum(a, S, 2, red);
     if (threadIdx.x == 0) any_active = any_ru = 0;
     __syncthreads();
-    if (threadIdx.x < S.K) {
+    const bool mine = threadIdx.x < S.K && a.scal[S.scal0 + threadIdx.x].active;
+    T rz = T(0);
+    int status = CGX_PENDING;
+    bool pause = false;
+    if (mine) {
         BScalT<T> &c = a.scal[S.scal0 + threadIdx.x];
-        if (c.active) {
-            const T rz = S.jac ? rz0 : rr;
-            c.rr = rr;
-            int status = CGX_PENDING;
-            bool pause = false;
-            if (!isfinite(rr) || !isfinite(rz)) {
-                status = CGX_NONFINITE;
-            } else if (S.ru) {
-                if (rr > c.bb) c.bb = rr;
-                pause = rr <= c.stop2 || (double)rr < S.rtol2 * (double)c.bb;
-                if (!pause && !(rz > T(0)))
-                    status = CGX_BREAKDOWN;
-                else if (!pause && c.iter >= S.maxit)
-                    status = CGX_NOT_CONVERGED;
-            } else if (rr <= c.stop2) {
-                status = CGX_OK;
-            } else if (!(rz > T(0))) {
+        rz = S.jac ? rz0 : rr;
+        c.rr = rr;
+        if (!isfinite(rr) || !isfinite(rz)) {
+            status = CGX_NONFINITE;
+        } else if (S.ru) {
+            if (rr > c.bb) c.bb = rr;
+            pause = rr <= c.stop2 || (double)rr < S.rtol2 * (double)c.bb;
+            if (!pause && !(rz > T(0)))
                 status = CGX_BREAKDOWN;
-            } else if (c.iter >= S.maxit) {
+            else if (!pause && c.iter >= S.maxit)
                 status = CGX_NOT_CONVERGED;
-            }
-            if (pause) {
-                c.ru = 1;
-                c.active = 0;
-                atomicOr(&any_ru, 1);
-            } else if (status == CGX_PENDING) {
-                c.beta = rz / c.rho_used;
-                c.rho = rz;
-                atomicOr(&any_active, 1);
-            } else {
-                c.status = status;
-                c.active = 0;
-            }
+        } else if (rr <= c.stop2) {
+            status = CGX_OK;
+        } else if (!(rz > T(0))) {
+            status = CGX_BREAKDOWN;
+        } else if (c.iter >= S.maxit) {
+            status = CGX_NOT_CONVERGED;
+        }
+        if (pause) atomicOr(&any_ru, 1);
+    }
+    __syncthreads();
+    if (mine) {
+        BScalT<T> &c = a.scal[S.scal0 + threadIdx.x];
+        // the float64 residual of an update is a pass over the whole system
+        // for all its right-hand sides: those that would go on take the
+        // update too (exact in exact arithmetic, like any reliable update)
+        if (S.ru && any_ru && status == CGX_PENDING) pause = true;
+        if (pause) {
+            c.ru = 1;
+            c.active = 0;
+        } else if (status == CGX_PENDING) {
+            c.beta = rz / c.rho_used;
+            c.rho = rz;
+            atomicOr(&any_active, 1);
+        } else {
+            c.status = status;
+            c.active = 0;
         }
     }
     __syncthreads();

@@ -1,21 +1,26 @@
 """GPU parity of the batched reliable-update solve (binary32 CG per (system,
 right-hand side) whose direction is kept across float64 updates of x, the
-true residual and the stopping test, all right-hand sides advanced together)
-against the oracle's mixed_ru run on each (system, right-hand side) alone.
+true residual and the stopping test, all right-hand sides advanced together,
+an update of one right-hand side taken by all of its system) against the
+oracle's mixed_ru_block run on each system's right-hand sides.
 
 Bars, as for the single-system reliable-update solve: the true residual
 (the oracle's float64 SpMV on the GPU solution) below the tolerance; the
 solution within the kappa * rtol bound of the float64 oracle; the step where
 the run stopped inside the band of the oracle's own residual history and its
-rounding sensitivity (tests/cg_gates.py); the update count within 2; and a
-system's result bit-identical alone and inside the batch."""
+rounding sensitivity (tests/cg_gates.py; in exact arithmetic the history of a
+right-hand side does not depend on where updates are taken); the update
+count within the slack of the oracle's own reordered run (cg_gates.
+ru_block_refs) and, exactly, a strictly increasing function of the stopping
+step over a system's right-hand sides (each takes every event up to its
+stop); and a system's result bit-identical alone and inside the batch."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import synth
-from cg_gates import assert_stop_in_band, residual_band
+from cg_gates import assert_stop_in_band, assert_updates_shared, residual_band, ru_block_refs
 from paper_2112_10823_amd import cgx
 
 pytestmark = pytest.mark.gpu
@@ -60,7 +65,9 @@ def test_batched_ru_vs_oracle(jacobi, delta):
     st = cgx.cg_solve_batched(items, ru_opts(rtol, jacobi, delta))
     for s, (A, (dA, dB, dX)) in enumerate(zip(mats, items)):
         X = dX.cpu().numpy()
-        v32 = A.val.astype(np.float32)
+        refs, slack = ru_block_refs(A, hostB[s], rtol, delta, jacobi)
+        assert_updates_shared([(v.iters, v.outer_iters) for v, b in zip(st[s], hostB[s])
+                               if b.any()], (s, jacobi, delta))
         for j in range(NRHS[s]):
             b = hostB[s][j]
             v = st[s][j]
@@ -69,12 +76,12 @@ def test_batched_ru_vs_oracle(jacobi, delta):
             if not b.any():
                 assert not X[j].any() and v.iters == 0, info
                 continue
-            ref = oracle.mixed_ru(A, v32, b, rtol=rtol, delta=delta, jacobi=jacobi)
+            ref = refs[j]
             assert ref.status == oracle.OK
             tr = true_relres(A, b, X[j])
             assert tr <= rtol, info
             assert abs(v.relres - tr) <= 1e-3 * tr + 1e-16, info
-            assert abs(v.outer_iters - ref.outer_iters) <= 2, (info, ref.outer_iters)
+            assert abs(v.outer_iters - ref.outer_iters) <= slack, (info, ref.outer_iters, slack)
             xs = oracle.cg(A, b, rtol=1e-13, jacobi=True, maxit=20000).x
             assert np.linalg.norm(X[j] - xs) <= 1e-6 * np.linalg.norm(xs), info
             if j == 0:  # the stopping step, gated by the oracle's own history

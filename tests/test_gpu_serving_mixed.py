@@ -19,6 +19,7 @@ import torch
 
 import oracle
 import synth
+from cg_gates import assert_updates_shared, ru_block_refs
 from paper_2112_10823_amd import cgx
 
 pytestmark = pytest.mark.gpu
@@ -222,10 +223,11 @@ def test_served_mixed_million_rows_in_a_mix():
 
 
 # ---------------------------------------------------------------- MIXED_RU --
-# Served requests with reliable updates: each against the oracle's mixed_ru
-# of it alone, with the bars of the single-system reliable-update tests (true
-# residual, the kappa * rtol bound against float64, updates within 2, the
-# stopping step in the band of the oracle's history).
+# Served requests with reliable updates: ungrouped, each against the oracle's
+# mixed_ru of it alone, with the bars of the single-system reliable-update
+# tests (true residual, the kappa * rtol bound against float64, updates within
+# 2, the stopping step in the band of the oracle's history); requests grouped
+# in one slot share update events, against the oracle's mixed_ru_block.
 
 def ru_opts(rtol=1e-10, jacobi=True, delta=1e-2, **kw):
     return cgx.make_opts(rtol=rtol, precond=int(jacobi), precision=cgx.PRECISION_MIXED_RU,
@@ -256,7 +258,8 @@ def test_served_ru_matches_oracle(resident, jacobi):
     mats, dmats = resident
     opts = ru_opts(jacobi=jacobi)
     print(f"[served ru] oracle parity jacobi={jacobi}", flush=True)
-    with cgx.Server(pool(1 << 28), max_slots=6) as srv:
+    # ungrouped: each request alone in its slot, as the oracle runs it
+    with cgx.Server(pool(1 << 28), max_slots=6, max_group=1) as srv:
         reqs = []
         for i in range(8):
             k = i % 4
@@ -328,14 +331,18 @@ def test_served_ru_grouped_and_initial_guess(resident):
         sts = [srv.wait(t) for t in ts]
         stz = srv.wait(tz)
     check_ru_against_oracle(big, bb, xb.cpu().numpy(), stb, 1e-10, True, 1e-2)
+    X0 = np.zeros((len(bs), A.n_rows))
+    X0[0] = x0
+    # the four requests started together: one update event serves all
+    refs, slack = ru_block_refs(A, np.stack(bs), 1e-10, 1e-2, True, X0=X0)
+    assert_updates_shared([(st.iters, st.outer_iters) for st in sts])
     for j, (b, x, st) in enumerate(zip(bs, xs, sts)):
         assert st.slot_requests == 5
         info = st.as_dict()
         assert st.status == cgx.OK, info
         assert true_relres(A, b, x.cpu().numpy()) <= 1e-10, info
-        ref = oracle.mixed_ru(A, A.val.astype(np.float32), b, x0=x0 if j == 0 else None,
-                              rtol=1e-10, delta=1e-2, jacobi=True)
-        assert abs(st.outer_iters - ref.outer_iters) <= 2, (info, ref.outer_iters)
+        assert refs[j].status == oracle.OK
+        assert abs(st.outer_iters - refs[j].outer_iters) <= slack, (info, refs[j].outer_iters)
     assert stz.status == cgx.OK and stz.outer_iters == 0 and not xz.any()
 
 
