@@ -767,3 +767,10 @@ def test_ru_block_sibling_event_reaches_every_rhs():
     assert blk[1].iters == 1 and np.array_equal(blk[1].x, solo_eig.x)
     assert blk[0].status == oracle.OK and blk[0].outer_iters >= solo_rnd.outer_iters
     assert not np.array_equal(blk[0].x, solo_rnd.x)  # the update at step 1 was taken
+    # capped at that step: the sibling still takes the update (then stops at
+    # the cap with its correction in x), as it does when rho <= 0 would stop it
+    cap = oracle.mixed_ru_block(A, v32, np.stack([b_rnd, b_eig]), rtol=1e-6, delta=0.01, maxit=1)
+    assert (cap[1].status, cap[1].iters, cap[1].outer_iters) == (oracle.OK, 1, 1)
+    assert (cap[0].status, cap[0].iters, cap[0].outer_iters) == (oracle.NOT_CONVERGED, 1, 1)
+    alone = oracle.mixed_ru(A, v32, b_rnd, rtol=1e-6, delta=0.01, maxit=1)
+    assert alone.outer_iters == 0 and np.array_equal(cap[0].x, alone.x)
