@@ -884,9 +884,12 @@ __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
     if (mine) {
         BScalT<T> &c = a.scal[S.scal0 + threadIdx.x];
         // the float64 residual of an update is a pass over the whole system
-        // for all its right-hand sides: those that would go on take the
-        // update too (exact in exact arithmetic, like any reliable update)
-        if (S.ru && any_ru && status == CGX_PENDING) pause = true;
+        // for all its right-hand sides: every one still active after this
+        // step takes the update too (exact in exact arithmetic, like any
+        // reliable update), also one that the iteration cap or rho <= 0 would
+        // stop here: the update restarts rho from the true residual and the
+        // resume applies the cap; a non-finite one stops
+        if (S.ru && any_ru && status != CGX_NONFINITE) pause = true;
         if (pause) {
             c.ru = 1;
             c.active = 0;

@@ -14,6 +14,8 @@ count within the slack of the oracle's own reordered run (cg_gates.
 ru_block_refs) and, exactly, a strictly increasing function of the stopping
 step over a system's right-hand sides (each takes every event up to its
 stop); and a system's result bit-identical alone and inside the batch."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -126,6 +128,42 @@ def test_batched_ru_keeps_krylov_space():
     for j in range(4):
         assert counts["ru"][j] <= 1.1 * counts["fp64"][j] + 2, counts
     assert sum(counts["ir"]) >= 1.15 * sum(counts["ru"]), counts
+
+
+def test_batched_ru_sibling_event_and_cap():
+    """A discrete eigenvector of the 7-point operator converges in one binary32
+    step and fires an update there: its sibling takes that update, also when
+    the iteration cap stops it at that step (status, counts and the folded
+    correction as in the oracle's block method)."""
+    N = 9
+    A = synth.fd7(N)
+    i = np.arange(1, N + 1)
+    vs = [np.sin(jj * math.pi * i / (N + 1)) for jj in (2, 5, 7)]
+    v = np.einsum("k,j,i->kji", vs[2], vs[1], vs[0]).ravel()
+    lam = sum(4 * math.sin(jj * math.pi / (2 * (N + 1))) ** 2 for jj in (2, 5, 7))
+    B = np.stack([synth.uniform(60, A.n_rows), lam * v])
+    dA = cgx.DeviceCSR.from_host(A, with_f32=True)
+    v32 = A.val.astype(np.float32)
+    print("[batched ru] sibling event, uncapped and capped at it", flush=True)
+    for maxit in (0, 1):
+        X = torch.zeros(2, A.n_rows, dtype=torch.float64, device="cuda")
+        st = cgx.cg_solve_batched([(dA, dev(B), X)], ru_opts(rtol=1e-6, jacobi=False,
+                                                              maxit=maxit))[0]
+        refs = oracle.mixed_ru_block(A, v32, B, rtol=1e-6, delta=1e-2, maxit=maxit)
+        Xh = X.cpu().numpy()
+        assert (st[1].status, st[1].iters, st[1].outer_iters) == (cgx.OK, 1, 1), st[1].as_dict()
+        assert true_relres(A, B[1], Xh[1]) <= 1e-6
+        if maxit == 1:
+            assert (refs[0].status, refs[0].outer_iters) == (oracle.NOT_CONVERGED, 1)
+            assert (st[0].status, st[0].iters, st[0].outer_iters) == \
+                (cgx.NOT_CONVERGED, 1, 1), st[0].as_dict()
+            tr = true_relres(A, B[0], Xh[0])
+            assert abs(st[0].relres - tr) <= 1e-6 * tr
+            # the step's correction is in x: the oracle's x within binary32 rounding
+            assert np.linalg.norm(Xh[0] - refs[0].x) <= 1e-4 * np.linalg.norm(refs[0].x)
+        else:
+            assert st[0].status == cgx.OK and true_relres(A, B[0], Xh[0]) <= 1e-6
+            assert st[0].outer_iters >= 2  # the event at step 1, then its own
 
 
 def test_batched_ru_caps_and_errors():
