@@ -133,6 +133,53 @@ def cpu_baseline_all_cores(A, b, n, nnz, iters=20):
                       f"system, {dt:.1f} s on {threads} threads"}
 
 
+def batch_sample():
+    """Systems of the 64-system batch measured one at a time: eight, both
+    stencils (the stencil alternates with the system index) and sizes across
+    the range."""
+    return [8 * k + (k % 2) for k in range(8)]
+
+
+def cpu_baseline_batched(mats):
+    """The oracle solving the batch's sample one (system, right-hand side) at
+    a time, Jacobi-CG to 1e-8 from 0 on each sampled system's first
+    right-hand side: solves/s of the sample, on one core (the plain C
+    oracle) and on all cores (its OpenMP timing build)."""
+    import oracle
+    import synth
+    pick = batch_sample()
+    rhs = [synth.uniform(1000 + s * 16, mats[s].n_rows) for s in pick]
+    desc = (f"systems {pick} of the batch (mean {np.mean([mats[s].nnz for s in pick]) / 1e6:.2f} M "
+            f"nnz against {np.mean([A.nnz for A in mats]) / 1e6:.2f} M for all 64), first "
+            "right-hand side each, Jacobi-CG to 1e-8 one at a time")
+    out = {}
+    for key, solve, cores, kind in (
+            ("cpu_baseline", oracle.cg, 1, "oracle"),
+            ("cpu_baseline_all_cores", oracle.cg_timing, oracle.timing_threads(),
+             "oracle (OpenMP timing build)")):
+        t0 = time.perf_counter()
+        for s, b in zip(pick, rhs):
+            solve(mats[s], b, rtol=1e-8, jacobi=True)
+        dt = time.perf_counter() - t0
+        out[key] = {"value": round(len(pick) / dt, 3), "unit": "solves/s", "cores": cores,
+                    "kind": kind, "sample": f"{desc}, {dt:.1f} s"}
+    return out
+
+
+def cpu_baseline_mixed(A, b, iters=40):
+    """The oracle's binary32 CG with float64 reliable updates (delta 1e-2,
+    Jacobi) for `iters` iterations on the full mixed-precision system, setup
+    and final residual included: binary32 iterations per second."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.mixed_ru(A, np.asarray(A.val).astype(np.float32), b, rtol=1e-10, delta=1e-2,
+                    maxit=iters, jacobi=True)
+    dt = time.perf_counter() - t0
+    return {"value": round(iters / dt, 3), "unit": "binary32 iterations/s", "cores": 1,
+            "kind": "oracle", "sample": f"{iters} iterations of the reliable-update method "
+                                       f"(setup, updates and final residual included), {dt:.1f} s"}
+
+
 def calib_gather_matrix(n):
     """Permutation matrix of n rows (n a multiple of 16) moving 16-entry
     blocks of x (one 128-byte line) to a seeded random order: row i reads
@@ -145,7 +192,7 @@ def calib_gather_matrix(n):
     return synth.CSR(n, n, np.arange(n + 1, dtype=np.int32), col, np.ones(n))
 
 
-def mixed_path(cgx, synth, meter, reps=3):
+def mixed_path(cgx, synth, meter, reps=3, cpu=True):
     """The mixed-precision configuration beside the headline: Q1 192^3
     (7,077,888 rows, 189,119,224 nnz), lognormal(0, 1.5), uniform RHS,
     Jacobi, to 1e-10: float64 Jacobi-CG against binary32 CG with float64
@@ -188,6 +235,9 @@ def mixed_path(cgx, synth, meter, reps=3):
             out["mixed_ru_updates"] = st.outer_iters
         del ws
     out["time_ratio"] = round(out["mixed_ru_ms"] / out["fp64_jacobi_ms"], 4)
+    out["mixed_ru_iters_per_s"] = round(out["mixed_ru_iters"] / (out["mixed_ru_ms"] * 1e-3), 1)
+    if cpu:
+        out["cpu_baseline"] = cpu_baseline_mixed(A, b)
     out["mixed_vs_fp64_rel_error"] = float(torch.linalg.norm(sol["mixed_ru"] - sol["fp64_jacobi"])
                                            / torch.linalg.norm(sol["fp64_jacobi"]))
     return out
@@ -506,7 +556,7 @@ def extra_batched(cgx, synth, meter):
         byts += it * (12 * dA.nnz + 4 * (dA.n_rows + 1) + 80 * 16 * dA.n_rows)
     sched = cgx.batch_schedule(items, workspace=ws)
     # one right-hand side at a time with the single-system solver (a sample, scaled)
-    sample = list(range(0, 64, 8))
+    sample = batch_sample()
     t_single = 0.0
     for s in sample:
         dA, B, _ = items[s]
@@ -582,7 +632,9 @@ def extra_batched(cgx, synth, meter):
             "j_per_solve": round(jb / 1024, 4) if jb is not None else None,
             "one_at_a_time_est_s": round(t_single, 3),
             "one_at_a_time_solves_per_s": round(1024 / t_single, 1),
-            "schedule_M": {"fd7": sched[0], "q1": sched[1]}}
+            "one_at_a_time_sample": sample,
+            "schedule_M": {"fd7": sched[0], "q1": sched[1]},
+            **cpu_baseline_batched(mats)}
 
 
 def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5, full=True):
@@ -1083,7 +1135,7 @@ def main():
     del ws
     mixed = None
     if not args.no_mixed:
-        mixed = mixed_path(cgx, synth, meter)
+        mixed = mixed_path(cgx, synth, meter, cpu=not args.no_cpu_baseline)
         print(f"# mixed path {mixed['mixed_ru_ms']} ms vs float64 {mixed['fp64_jacobi_ms']} ms",
               file=sys.stderr, flush=True)
 

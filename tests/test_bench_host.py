@@ -70,8 +70,9 @@ def test_host_residual_matches_the_oracle():
 
 
 def test_only_the_cpu_baseline_uses_the_oracle():
-    """Apart from the CPU baselines (one core, all cores), no part of the
-    benchmark imports the oracle."""
+    """Apart from the CPU baselines (one core, all cores; headline, batched
+    and mixed-precision samples), no part of the benchmark imports the
+    oracle."""
     import ast
     tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
     users = set()
@@ -82,7 +83,16 @@ def test_only_the_cpu_baseline_uses_the_oracle():
                     names = [a.name for a in node.names] + [getattr(node, "module", None) or ""]
                     if any(n == "oracle" or n.startswith("oracle.") for n in names):
                         users.add(fn.name)
-    assert users == {"cpu_baseline", "cpu_baseline_all_cores"}
+    assert users == {"cpu_baseline", "cpu_baseline_all_cores", "cpu_baseline_batched",
+                     "cpu_baseline_mixed"}
+
+
+def test_batch_sample_spans_both_stencils():
+    """The one-at-a-time sample of the batch holds both stencils (the stencil
+    alternates with the system index) and distinct systems."""
+    pick = bench.batch_sample()
+    assert len(set(pick)) == len(pick) == 8 and all(0 <= s < 64 for s in pick)
+    assert {s % 2 for s in pick} == {0, 1}
 
 
 def test_oracle_timing_build_matches_the_oracle():
