@@ -287,7 +287,8 @@ int ensure_ru_graph(GraphSlot &slot, int K, const BArgsT<double> &a64, const BAr
 {
     GraphKey key = batch_key<float>(K, a32);
     key.add(0x5255ull).ptr(a64.sys).ptr(a64.tiles).ptr(a64.list).ptr(a64.scal).ptr(a64.part);
-    key.add((uint64_t)a64.part_stride).add((uint64_t)a64.ntiles).add((uint64_t)a64.nlist);
+    key.ptr(a64.sys_done).add((uint64_t)a64.part_stride).add((uint64_t)a64.ntiles);
+    key.add((uint64_t)a64.nlist).add((uint64_t)a64.wave_lds);
     key.add((uint64_t)max_updates);
     if (slot.matches(key)) return CGX_OK;
     slot.reset();
