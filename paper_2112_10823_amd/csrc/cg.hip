@@ -44,7 +44,6 @@ constexpr int kMinTilesPerRed = 512; // tile partials per reduction workgroup, a
 constexpr int kPB = 512;             // threads per workgroup of the other phase kernels
 constexpr int kPhaseBlocksPerCu = 4;
 constexpr int kMaxPhaseBlocks = 2048;
-constexpr int kRowsPerGroup = 4;     // vector-CSR rows per lane group (setup passes)
 constexpr int kSmallBlock = 1024;
 
 // Partials of the grid-wide sums, one slot per workgroup of the phase grid.
@@ -156,27 +155,46 @@ __device__ __forceinline__ void tile_range(int ntiles, int tiles_per_block, int 
 
 // ------------------------------------------------ phase kernels (large n) --
 
-// Setup: r0 = b - A x0 (vector-CSR rows, diagonal read on the way), z0, p0,
+// Float64 row passes of the setup and the mixed solver's residual: the
+// workgroup's contiguous range of wave tiles of RT rows (die-contiguous as
+// in the phase kernels), wave w of the workgroup taking tiles w, w + W, ...
+// (W waves per workgroup), each tile computed by wave_rows with the row's
+// stored diagonal captured on the way.  f(row, A x row, a_ii) runs on the
+// first lane of every row.  sm: the workgroup's W staging areas.
+template <int RT>
+using SetupSmem = WaveSmem<wave_e<double>(), RT, double>;
+
+template <int RT, bool kDiagA, typename F>
+__device__ __forceinline__ void setup_rows(int n, int n_cols, int64_t nnz,
+                                           const int32_t *__restrict__ rp,
+                                           const int32_t *__restrict__ ci,
+                                           const double *__restrict__ val,
+                                           const double *__restrict__ x, SetupSmem<RT> *sm, F f)
+{
+    constexpr int W = kPB / kWave;
+    const int nt = (n + RT - 1) / RT;
+    const int per = (nt + gridDim.x - 1) / gridDim.x;
+    int t0, t1;
+    tile_range(nt, per, t0, t1);
+    const int w = threadIdx.x / kWave;
+    for (int t = t0 + w; t < t1; t += W) {
+        int row;
+        double dg = 0.0;
+        const double acc = wave_rows<wave_e<double>(), RT, 4, double, false, kDiagA>(
+            t * RT, n, n_cols, nnz, rp, ci, val, x, sm[w], row, nullptr, nullptr, &dg);
+        if (threadIdx.x % (kWave / RT) == 0 && row < n) f(row, acc, dg);
+    }
+}
+
+// Setup: r0 = b - A x0 (the row's stored diagonal read on the way), z0, p0,
 // and the partials of r.r, r.z, b.b.
-template <int L, bool kJac>
+template <int RT, bool kJac>
 __global__ __launch_bounds__(kPB) void cg_init_kernel(CgArgs<double> a)
 {
-    constexpr int R = kRowsPerGroup, RPB = (kPB / L) * R;
-    const int ntiles = (a.n + RPB - 1) / RPB;
-    const int per = (ntiles + gridDim.x - 1) / gridDim.x;
-    int t0, t1;
-    tile_range(ntiles, per, t0, t1);
+    __shared__ SetupSmem<RT> sm[kPB / kWave];
     double part[3] = {0.0, 0.0, 0.0};
-    for (int t = t0; t < t1; ++t) {
-        double acc[R], dg[R];
-        int rows[R];
-        vector_rows<L, R, kPB, double, kJac>(t * RPB, a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val, a.x,
-                                             acc, dg, rows);
-        if (threadIdx.x % L == 0)
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (rows[r] < a.n) init_row<kJac>(a, rows[r], acc[r], dg[r], part);
-    }
+    setup_rows<RT, kJac>(a.n, a.n_cols, a.nnz, a.rp, a.ci, a.val, a.x, sm,
+                         [&](int row, double ax, double dg) { init_row<kJac>(a, row, ax, dg, part); });
     __shared__ double red[3 * (kPB / kWave)];
     block_sum<3, kPB>(part, red);
     if (threadIdx.x == 0)
@@ -630,43 +648,30 @@ struct MxArgs {
 
 // r = b - A x in float64 and the partials of ||r||^2 (and ||b||^2 and the
 // inverse diagonal on the first step).
-template <int L, bool kFirst, bool kJac>
+template <int RT, bool kFirst, bool kJac>
 __global__ __launch_bounds__(kPB) void mx_residual_kernel(MxArgs m)
 {
+    __shared__ SetupSmem<RT> sm[kPB / kWave];
     if (m.ost->done) return;
-    constexpr int R = kRowsPerGroup, RPB = (kPB / L) * R;
-    const int ntiles = (m.n + RPB - 1) / RPB;
-    const int per = (ntiles + gridDim.x - 1) / gridDim.x;
-    int t0, t1;
-    tile_range(ntiles, per, t0, t1);
     double part[2] = {0.0, 0.0};
-    for (int t = t0; t < t1; ++t) {
-        double acc[R], dg[R];
-        int rows[R];
-        vector_rows<L, R, kPB, double, kFirst && kJac>(t * RPB, m.n, m.n_cols, m.nnz, m.rp, m.ci,
-                                                       m.val, m.x, acc, dg, rows);
-        if (threadIdx.x % L == 0)
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int row = rows[r];
-                if (row >= m.n) continue;
-                const double bi = m.b[row];
-                const double ri = bi - acc[r];
-                m.r[row] = ri;
-                part[0] += ri * ri;
-                if (kFirst) {
-                    part[1] += bi * bi;
-                    if (kJac) {
-                        double d = dg[r];
-                        if (!(d > 0.0)) {
-                            m.ost->bad = 1;
-                            d = 1.0;
-                        }
-                        m.dinv32[row] = (float)(1.0 / d);
-                    }
+    setup_rows<RT, kFirst && kJac>(m.n, m.n_cols, m.nnz, m.rp, m.ci, m.val, m.x, sm,
+                                   [&](int row, double ax, double dg) {
+        const double bi = m.b[row];
+        const double ri = bi - ax;
+        m.r[row] = ri;
+        part[0] += ri * ri;
+        if (kFirst) {
+            part[1] += bi * bi;
+            if (kJac) {
+                double d = dg;
+                if (!(d > 0.0)) {
+                    m.ost->bad = 1;
+                    d = 1.0;
                 }
+                m.dinv32[row] = (float)(1.0 / d);
             }
-    }
+        }
+    });
     __shared__ double red[2 * (kPB / kWave)];
     block_sum<2, kPB>(part, red);
     if (threadIdx.x == 0) {
@@ -886,31 +891,21 @@ Layout make_layout(int64_t n, int64_t nnz, bool jac, bool mixed)
     return L;
 }
 
-#define CGX_LANE_SWITCH(L, EXPR_T)       \
-    switch (L) {                         \
-        case 2: EXPR_T(2); break;        \
-        case 4: EXPR_T(4); break;        \
-        case 8: EXPR_T(8); break;        \
-        case 16: EXPR_T(16); break;      \
-        case 32: EXPR_T(32); break;      \
-        default: EXPR_T(64); break;      \
-    }
-
 struct Grids {
-    int L;              // lanes per row of the vector-CSR setup passes
+    int RT64;           // rows per wave tile of the float64 setup passes
     int RT;             // rows per wave tile of the SpMV phase
     int ntiles;         // wave tiles (= workgroups) of the SpMV phase
     int grid_red;       // workgroups of the p.q reduction, 0 when the tiles write region kPPq
     int tiles_per_red;  // tile partials per reduction workgroup
     int n_pq;           // p.q partials the update phase adds
     int grid_ew;        // workgroups of the elementwise phases
-    int grid_vr;        // workgroups of the vector-CSR setup passes
+    int grid_vr;        // workgroups of the float64 setup passes
 };
 
 Grids make_grids(const Context *c, int64_t n, int64_t nnz, bool mixed, bool sell)
 {
     Grids g{};
-    g.L = lanes_per_row(n, nnz);
+    g.RT64 = wave_tile_rows(n, nnz, wave_e<double>());
     // sliced ELL: one 64-row slice per SpMV workgroup (never more tiles than
     // the wave tiles the workspace is sized for)
     g.RT = sell ? kWave : wave_tile_rows(n, nnz, mixed ? wave_e<float>() : wave_e<double>());
@@ -928,9 +923,10 @@ Grids make_grids(const Context *c, int64_t n, int64_t nnz, bool mixed, bool sell
     const int cap = std::min(c->num_cu * kPhaseBlocksPerCu, kMaxPhaseBlocks);
     const int64_t ew_need = (n + kPB - 1) / kPB;
     g.grid_ew = (int)std::max<int64_t>(1, std::min<int64_t>(cap, ew_need));
-    const int RPB = (kPB / g.L) * kRowsPerGroup;
-    const int64_t vr_tiles = (n + RPB - 1) / RPB;
-    g.grid_vr = (int)std::max<int64_t>(1, std::min<int64_t>(cap, vr_tiles));
+    // at least one wave tile per wave of a setup workgroup
+    const int64_t vr_tiles = (n + g.RT64 - 1) / g.RT64;
+    const int64_t vr_need = (vr_tiles + kPB / kWave - 1) / (kPB / kWave);
+    g.grid_vr = (int)std::max<int64_t>(1, std::min<int64_t>(cap, vr_need));
     return g;
 }
 
@@ -952,7 +948,7 @@ void launch_init(const Grids &g, bool jac, hipStream_t s, const CgArgs<double> &
         hipLaunchKernelGGL((cg_init_kernel<LL, true>), dim3(g.grid_vr), dim3(kPB), 0, s, a);      \
     else                                                                                         \
         hipLaunchKernelGGL((cg_init_kernel<LL, false>), dim3(g.grid_vr), dim3(kPB), 0, s, a)
-    CGX_LANE_SWITCH(g.L, CGX_INIT)
+    CGX_WRT_SWITCH(g.RT64, CGX_INIT)
 #undef CGX_INIT
     hipLaunchKernelGGL(cg_init_finish_kernel, dim3(1), dim3(kPB), 0, s, a, g.grid_vr, rtol2,
                        jac ? 1 : 0);
@@ -1049,7 +1045,7 @@ void launch_mx_residual(const Grids &g, bool first, bool jac, hipStream_t s, con
     else                                                                                       \
         hipLaunchKernelGGL((mx_residual_kernel<LL, false, false>), dim3(g.grid_vr), dim3(kPB),  \
                            0, s, m)
-    CGX_LANE_SWITCH(g.L, CGX_MX)
+    CGX_WRT_SWITCH(g.RT64, CGX_MX)
 #undef CGX_MX
     hipLaunchKernelGGL(mx_residual_finish_kernel, dim3(1), dim3(kPB), 0, s, m, g.grid_vr,
                        first ? 1 : 0, rtol2);

@@ -80,77 +80,6 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
     e = (a - (s - bb)) + (b - bb);
 }
 
-// ------------------------------------------------------- vector CSR rows --
-
-// One workgroup of BS threads covers GPB = BS / L row-groups of L lanes;
-// for a tile starting at row0, group g handles rows row0 + g + GPB * r,
-// r < R, so that at each r the groups of a wave read one contiguous stretch
-// of col_idx / val.  Lane k of a group takes entries start + k, + k + L, ...
-// Every index read is clamped: row_ptr values to [0, nnz], columns to
-// [0, n_cols) (out-of-range columns contribute nothing).  acc[r] ends with
-// the row sum in every lane of the group; with kDiag, dg[r] gets the
-// diagonal entry (0 if absent).
-template <int L, int R, int BS, typename T, bool kDiag>
-__device__ __forceinline__ void vector_rows(int row0, int n_rows, int n_cols, int64_t nnz,
-                                            const int32_t *__restrict__ rp,
-                                            const int32_t *__restrict__ ci,
-                                            const T *__restrict__ val, const T *__restrict__ x,
-                                            T (&acc)[R], T (&dg)[R], int (&rows)[R])
-{
-    constexpr int GPB = BS / L;
-    const int lane = threadIdx.x % L;
-    const int g = threadIdx.x / L;
-    int k[R], e[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int row = row0 + g + GPB * r;
-        rows[r] = row;
-        int s = 0, t = 0;
-        if (row < n_rows) {
-            s = rp[row];
-            t = rp[row + 1];
-            s = s < 0 ? 0 : (s > nnz ? (int)nnz : s);
-            t = t < s ? s : (t > nnz ? (int)nnz : t);
-        }
-        k[r] = s + lane;
-        e[r] = t;
-        acc[r] = T(0);
-        dg[r] = T(0);
-    }
-    bool more = true;
-    while (more) {
-        int c[R];
-        T a[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            c[r] = -1;
-            a[r] = T(0);
-            if (k[r] < e[r]) {
-                c[r] = ci[k[r]];
-                a[r] = val[k[r]];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if ((unsigned)c[r] < (unsigned)n_cols) {
-                acc[r] += a[r] * x[c[r]];
-                if (kDiag && c[r] == rows[r]) dg[r] = a[r];
-            }
-        }
-        more = false;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            k[r] += L;
-            more |= k[r] < e[r];
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        acc[r] = group_sum<L>(acc[r]);
-        if (kDiag) dg[r] = group_sum<L>(dg[r]);
-    }
-}
-
 // ---------------------------------------------------------- wave CSR rows --
 
 // Wave-local barrier for LDS data exchanged between the lanes of one wave:
@@ -181,21 +110,26 @@ struct WaveSmem {
 // fall on a few cache lines instead of one line per row.  The TPR lanes then
 // combine by butterfly.  A tile with more than 64 * E entries is processed in
 // several chunks.  Returns the row sum in all TPR lanes of the row's group;
-// `row` receives the row index (>= n_rows for idle groups).  Indices are
-// clamped as in vector_rows.  Must be reached by all 64 lanes of the wave.
+// `row` receives the row index (>= n_rows for idle groups).  Every index
+// read is clamped: row_ptr values to [0, nnz], columns to [0, n_cols)
+// (out-of-range columns contribute nothing).  Must be reached by all 64
+// lanes of the wave.
 // With a non-null `stop`, *stop is read together with the row starts (its
 // latency hidden behind theirs); if nonzero the tile is skipped: returns 0
 // with row = -1 in every lane.
 // kDiag: *xdiag receives x[row] in all TPR lanes of the row, taken from the
 // gather of the row's diagonal entry (no load of its own), or loaded when
 // the row stores no diagonal.
-template <int E, int RT, int U, typename T, bool kDiag = false>
+// kDiagA: *adiag receives the row's stored diagonal a_ii in all TPR lanes of
+// the row (0 when the row stores none).
+template <int E, int RT, int U, typename T, bool kDiag = false, bool kDiagA = false>
 __device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t nnz,
                                        const int32_t *__restrict__ rp,
                                        const int32_t *__restrict__ ci,
                                        const T *__restrict__ val, const T *__restrict__ x,
                                        WaveSmem<E, RT, T> &sm, int &row,
-                                       const int *stop = nullptr, T *xdiag = nullptr)
+                                       const int *stop = nullptr, T *xdiag = nullptr,
+                                       T *adiag = nullptr)
 {
     constexpr int TPR = kWave / RT;
     constexpr int C = kWave * E;
@@ -223,7 +157,7 @@ __device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t
         s = max(sm.rp[g], k0);
         e = min(max(sm.rp[g + 1], s), k1);
     }
-    T acc = T(0), xd = T(0);
+    T acc = T(0), xd = T(0), ad = T(0);
     int seen = 0;
     for (int c0 = k0; c0 < k1; c0 += C) {
         int col[E];
@@ -268,9 +202,11 @@ __device__ __forceinline__ T wave_rows(int row0, int n_rows, int n_cols, int64_t
                     xd = xv[u];
                     seen = 1;
                 }
+                if (kDiagA && cc[u] == row) ad = vv[u];
             }
         }
     }
+    if (kDiagA) *adiag = group_sum<TPR>(ad);  // one lane of the row holds it, the others 0
     if (kDiag) {
         // one lane of the row holds the diagonal's value, the others 0
         xd = group_sum<TPR>(xd);

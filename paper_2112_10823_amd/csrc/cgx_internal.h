@@ -219,6 +219,5 @@ int serve_submit(Context *c, const cgx_csr *A, const double *b, double *x, const
 int serve_poll(Context *c, uint64_t ticket, cgx_stats *st, bool wait);
 
 // Lanes per row for the vector CSR kernel, from the mean row length.
-int lanes_per_row(int64_t n_rows, int64_t nnz);
 
 }  // namespace cgx

@@ -92,14 +92,6 @@ int wave_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_lane)
     return rt;
 }
 
-int lanes_per_row(int64_t n_rows, int64_t nnz)
-{
-    const double mean = n_rows > 0 ? (double)nnz / (double)n_rows : 1.0;
-    int L = 2;
-    while (L < 64 && L < mean) L *= 2;
-    return L;
-}
-
 int launch_spmv(Context *c, const cgx_csr *A, const double *x, double *y)
 {
     return launch_spmv_t<double>(c, A, A->val, x, y);
