@@ -79,6 +79,11 @@ namespace {  // internal linkage: each translation unit keeps its own copy
 constexpr int kBB = 256;  // threads per workgroup of the batched kernels
 constexpr int kMaxK = 16;
 
+// Sixteen bytes of an interleaved vector: V = 16 / sizeof(T) consecutive
+// right-hand sides of one row.
+template <typename T>
+using Vec16 = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+
 __device__ __forceinline__ int clampk(int v, int64_t nnz)
 {
     return v < 0 ? 0 : (v > nnz ? (int)nnz : v);
@@ -327,8 +332,12 @@ __global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgsT<T> a)
 // schedules keep their occupancy.
 constexpr int kWaveStageBytes = (kBB / kWave) * (kWave * 8 * 12 + 65 * 4 + 8);
 
-template <int RT, int K, typename T, bool kStaged>
-__device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, double *lds)
+// src: the interleaved vector multiplied (p in the SpMM phase); fin(row, j,
+// sum, part) consumes the sum of a (row, right-hand side) in the lane that
+// holds it, part being the lane's running partial (returned at the end).
+template <int RT, int K, typename T, bool kStaged, typename Fin>
+__device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, double *lds,
+                                             const T *__restrict__ src, Fin fin)
 {
     using Sm = WaveSmem<8, kWave, T>;  // row starts of up to 64 rows
     static_assert((kBB / kWave) * sizeof(Sm) <= kWaveStageBytes, "wave staging");
@@ -343,7 +352,7 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
     const int per = ((t.rows + NW - 1) / NW + RT - 1) / RT * RT;  // rows per wave (kContig)
     const int wr0 = kContig ? t.row0 + w * per : t.row0 + w * RT;
     const int wend = kContig ? min(t.row0 + t.rows, wr0 + per) : t.row0 + t.rows;
-    const T *__restrict__ p = S.p;
+    const T *__restrict__ p = src;
     T ppq = T(0);
 
     // rows [row0 + r_lo, row0 + r_hi) of the staged range (entries [k0, k1)
@@ -394,11 +403,7 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
     auto finish = [&](int row, bool valid, T acc) {
 #pragma unroll
         for (int off = TL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off * K);
-        if (sl == 0 && valid) {
-            const int64_t ei = (int64_t)row * K + j;
-            S.q[ei] = acc;
-            ppq += p[ei] * acc;
-        }
+        if (sl == 0 && valid) fin(row, j, acc, ppq);
     };
 
     for (int r0 = wr0; r0 < wend;) {
@@ -459,9 +464,12 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
 // hand side) still sums its entries in the same order.  The p.q partials
 // come back per lane and right-hand side: pp[v] for right-hand side
 // (lane % (K / V)) V + v.
-template <int RT, int K, typename T>
+// src and finv as for spmm_wave_tiles: finv(row, j0, sums, pp) takes the V
+// sums of right-hand sides j0 .. j0 + V - 1 of a row.
+template <int RT, int K, typename T, typename FinV>
 __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTile &t,
-                                                    double *lds, T (&pp)[16 / sizeof(T)])
+                                                    double *lds, T (&pp)[16 / sizeof(T)],
+                                                    const T *__restrict__ src, FinV finv)
 {
     constexpr int V = 16 / (int)sizeof(T), KV = K / V;
     using Sm = WaveSmem<8, kWave, T>;
@@ -470,14 +478,14 @@ __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTi
     constexpr int RTV = RT * V;           // rows per pass
     static_assert(TL >= 1 && RTV * KV * TL == kWave, "lanes per row");
     constexpr int C = kWave * 8, U = 8, NW = kBB / kWave;
-    using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    using VT = Vec16<T>;
     Sm &sm = reinterpret_cast<Sm *>(lds)[threadIdx.x / kWave];
     const int lane = threadIdx.x % kWave;
     const int g = lane / (KV * TL), sl = (lane / KV) % TL, j0 = (lane % KV) * V;
     const int per = ((t.rows + NW - 1) / NW + RTV - 1) / RTV * RTV;  // rows per wave
     const int wr0 = t.row0 + (threadIdx.x / kWave) * per;
     const int wend = min(t.row0 + t.rows, wr0 + per);
-    const T *__restrict__ p = S.p;
+    const T *__restrict__ p = src;
 #pragma unroll
     for (int v = 0; v < V; ++v) pp[v] = T(0);
 
@@ -538,17 +546,7 @@ __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTi
         for (int v = 0; v < V; ++v)
 #pragma unroll
             for (int off = TL / 2; off > 0; off >>= 1) acc[v] += __shfl_xor(acc[v], off * KV);
-        if (sl == 0 && valid) {
-            const int64_t ei = (int64_t)row * K + j0;
-            VT qv;
-            __builtin_memcpy(&qv, acc, sizeof(VT));
-            *reinterpret_cast<VT *>(S.q + ei) = qv;
-            const VT pvv = *reinterpret_cast<const VT *>(p + ei);
-            T ps[V];
-            __builtin_memcpy(ps, &pvv, sizeof(VT));
-#pragma unroll
-            for (int v = 0; v < V; ++v) pp[v] += ps[v] * acc[v];
-        }
+        if (sl == 0 && valid) finv(row, j0, acc, pp);
     };
 
     for (int r0 = wr0; r0 < wend;) {
@@ -606,25 +604,26 @@ __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTi
 // Returns the number of p.q values in pp: 1 (pp[0], right-hand side
 // threadIdx.x % K) or V = 16 / sizeof(T) (the vector-gather form, see
 // spmm_wave_tiles_vec).
-template <typename T>
+template <typename T, typename Fin, typename FinV>
 __device__ __forceinline__ int spmm_wave_dispatch(const BSysT<T> &S, const BTile &t, double *lds,
-                                                  T (&pp)[16 / sizeof(T)])
+                                                  T (&pp)[16 / sizeof(T)], const T *src, Fin fin,
+                                                  FinV finv)
 {
     const int rt = -S.M;
-#define CGX_WT(R, KK)                                                          \
-    if (rt == R && S.K == KK) {                                                \
-        pp[0] = S.staged ? spmm_wave_tiles<R, KK, T, true>(S, t, lds)          \
-                         : spmm_wave_tiles<R, KK, T, false>(S, t, lds);        \
-        return 1;                                                              \
+#define CGX_WT(R, KK)                                                                 \
+    if (rt == R && S.K == KK) {                                                       \
+        pp[0] = S.staged ? spmm_wave_tiles<R, KK, T, true>(S, t, lds, src, fin)       \
+                         : spmm_wave_tiles<R, KK, T, false>(S, t, lds, src, fin);     \
+        return 1;                                                                     \
     }
-#define CGX_WV(R, KK)                                                          \
-    if (rt == R && S.K == KK) {                                                \
-        if (S.staged) {                                                        \
-            spmm_wave_tiles_vec<R, KK, T>(S, t, lds, pp);                      \
-            return 16 / (int)sizeof(T);                                        \
-        }                                                                      \
-        pp[0] = spmm_wave_tiles<R, KK, T, false>(S, t, lds);                   \
-        return 1;                                                              \
+#define CGX_WV(R, KK)                                                                 \
+    if (rt == R && S.K == KK) {                                                       \
+        if (S.staged) {                                                               \
+            spmm_wave_tiles_vec<R, KK, T>(S, t, lds, pp, src, finv);                  \
+            return 16 / (int)sizeof(T);                                               \
+        }                                                                             \
+        pp[0] = spmm_wave_tiles<R, KK, T, false>(S, t, lds, src, fin);                \
+        return 1;                                                                     \
     }
     CGX_WT(1, 1) CGX_WT(2, 1) CGX_WT(4, 1) CGX_WT(8, 1) CGX_WT(16, 1) CGX_WT(32, 1) CGX_WT(64, 1)
     CGX_WT(8, 2) CGX_WT(16, 2) CGX_WT(32, 2)
@@ -635,6 +634,32 @@ __device__ __forceinline__ int spmm_wave_dispatch(const BSysT<T> &S, const BTile
 #undef CGX_WV
     pp[0] = T(0);  // not reached: schedules are validated on the host
     return 1;
+}
+
+// Per-right-hand-side sums of the wave-tile partials pp (nv values per
+// thread, see spmm_wave_dispatch) into out[0..K).  With nv = V, thread t's
+// value v belongs to right-hand side (t V + v) mod K: the staging LDS (free
+// by then) holds them in that order, and each right-hand side's values are
+// added in index order.
+template <typename T>
+__device__ __forceinline__ void wave_partials_out(const T (&pp)[16 / sizeof(T)], int nv, int K,
+                                                  double *stage, T *red, T *out)
+{
+    constexpr int V = 16 / (int)sizeof(T);
+    if (nv == 1) {
+        block_sum_by_rhs(pp[0], K, red, out);
+        return;
+    }
+    __syncthreads();
+    T *vred = reinterpret_cast<T *>(stage);
+#pragma unroll
+    for (int v = 0; v < V; ++v) vred[threadIdx.x * V + v] = pp[v];
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        T sum = T(0);
+        for (int i = threadIdx.x; i < kBB * V; i += K) sum += vred[i];
+        out[threadIdx.x] = sum;
+    }
 }
 
 // (1) q = A p for every active system, p.q partials per right-hand side.
@@ -653,24 +678,27 @@ __global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgsT<T> a)
     if (S.M < 0) {
         constexpr int V = 16 / (int)sizeof(T);
         T pp[V];
-        const int nv = spmm_wave_dispatch(S, t, stage, pp);
-        if (nv > 1) {
-            // thread t's value v belongs to right-hand side (t V + v) mod K:
-            // the staging LDS (free now) holds them in that order, and each
-            // right-hand side's values are added in index order
-            __syncthreads();
-            T *vred = reinterpret_cast<T *>(stage);
+        // q = A p and the p.q partials
+        auto fin = [&](int row, int j, T acc, T &part) {
+            const int64_t ei = (int64_t)row * S.K + j;
+            S.q[ei] = acc;
+            part += S.p[ei] * acc;
+        };
+        auto finv = [&](int row, int j0, T (&acc)[V], T (&part)[V]) {
+            using VT = Vec16<T>;
+            const int64_t ei = (int64_t)row * S.K + j0;
+            VT qv;
+            __builtin_memcpy(&qv, acc, sizeof(VT));
+            *reinterpret_cast<VT *>(S.q + ei) = qv;
+            const VT pvv = *reinterpret_cast<const VT *>(S.p + ei);
+            T ps[V];
+            __builtin_memcpy(ps, &pvv, sizeof(VT));
 #pragma unroll
-            for (int v = 0; v < V; ++v) vred[threadIdx.x * V + v] = pp[v];
-            __syncthreads();
-            if (threadIdx.x < S.K) {
-                T sum = T(0);
-                for (int i = threadIdx.x; i < kBB * V; i += S.K) sum += vred[i];
-                a.part[(int64_t)t.tile * kMaxK + threadIdx.x] = sum;
-            }
-            return;
-        }
-        ppq = pp[0];
+            for (int v = 0; v < V; ++v) part[v] += ps[v] * acc[v];
+        };
+        const int nv = spmm_wave_dispatch(S, t, stage, pp, (const T *)S.p, fin, finv);
+        wave_partials_out(pp, nv, S.K, stage, red, a.part + (int64_t)t.tile * kMaxK);
+        return;
     } else {
         const int G = S.K * S.M, gpw = kWave / G;
         const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -730,12 +758,10 @@ __global__ __launch_bounds__(kBB) void batch_r1_kernel(BArgsT<T> a)
 // (2) r -= alpha q, z = D^-1 r for active right-hand sides; r.r and r.z
 // partials.  x += alpha p is taken in the p update (3), which reads p
 // anyway, so that p is read once per iteration outside the SpMM.
-// 16-byte accesses of the interleaved vectors: V = 16 / sizeof(T)
+// 16-byte accesses of the interleaved vectors (Vec16): V = 16 / sizeof(T)
 // consecutive right-hand sides of one row per access (used when K >= V; the
 // vectors start 256-byte aligned and K is a multiple of V, so every access
 // is aligned).
-template <typename T>
-using Vec16 = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
 
 // Per-right-hand-side sums of V values per thread: value v of thread t
 // belongs to right-hand side (t V + v) mod K (K a multiple of V, K / V
@@ -1173,13 +1199,37 @@ __global__ __launch_bounds__(kBB) void ru_fold_kernel(BArgsT<double> a64, BArgsT
     }
 }
 
+// The residual runs on the SpMM's wave tiles (the tile's rows times x) for
+// systems of the batch call on that schedule, when the launch carries the
+// staging LDS (a64.wave_lds); otherwise, and in the solve server, as a
+// vector-CSR pass.
 __global__ __launch_bounds__(kBB) void ru_residual_kernel(BArgsT<double> a64, BArgsT<float> a32)
 {
     __shared__ double red[kBB];
+    extern __shared__ double stage[];  // a64.wave_lds bytes
     const BTile t = a32.tiles[blockIdx.x];
     if (a32.sys_done[t.sys] != 3) return;
     const BSysT<double> S = a64.sys[t.sys];
     const BSysT<float> F = a32.sys[t.sys];
+    if (S.M < 0 && S.staged && a64.wave_lds >= kWaveStageBytes) {
+        constexpr int V = 2;
+        const BScalT<float> *fs = a32.scal + F.scal0;
+        auto fin = [&](int row, int j, double acc, double &part) {
+            if (!fs[j].ru) return;
+            const double bi = S.lanes ? S.lanes[j].b[row] : S.B[(int64_t)j * S.n + row];
+            const double ri = bi - acc;
+            S.r[(int64_t)row * S.K + j] = ri;
+            part += ri * ri;
+        };
+        auto finv = [&](int row, int j0, double (&acc)[V], double (&part)[V]) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) fin(row, j0 + v, acc[v], part[v]);
+        };
+        double pp[V];
+        const int nv = spmm_wave_dispatch(S, t, stage, pp, (const double *)S.x, fin, finv);
+        wave_partials_out(pp, nv, S.K, stage, red, a64.part + (int64_t)t.tile * kMaxK);
+        return;
+    }
     const int M = setup_m(S);
     const int G = S.K * M, gpw = kWave / G;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -1367,7 +1417,7 @@ void launch_ru_iteration(const BArgsT<double> &a64, const BArgsT<float> &a32, in
     launch_batch_iteration(a32, s);
     const dim3 g(a32.ntiles), l(a32.nlist), b(kBB);
     hipLaunchKernelGGL(ru_fold_kernel, g, b, 0, s, a64, a32);
-    hipLaunchKernelGGL(ru_residual_kernel, g, b, 0, s, a64, a32);
+    hipLaunchKernelGGL(ru_residual_kernel, g, b, a64.wave_lds, s, a64, a32);
     hipLaunchKernelGGL(ru_norm_kernel, l, b, 0, s, a64, a32, max_updates);
     hipLaunchKernelGGL(ru_rescale_kernel, g, b, 0, s, a64, a32);
     hipLaunchKernelGGL(ru_resume_kernel, l, b, 0, s, a64, a32);
