@@ -430,7 +430,7 @@ int run_batched(Context *c, int32_t nsys, const cgx_system *in, void *ws, size_t
     hipLaunchKernelGGL((batch_scal_init_kernel<double>), dim3((unsigned)((init_n + 255) / 256)), dim3(256), 0,
                        s, a.scal, P.nscal, a.sys_done, nsys);
     hipLaunchKernelGGL((batch_in_kernel<double>), dim3(a.ntiles), dim3(kBB), 0, s, a);
-    hipLaunchKernelGGL((batch_init_kernel<double>), dim3(a.ntiles), dim3(kBB), 0, s, a);
+    hipLaunchKernelGGL((batch_init_kernel<double>), dim3(a.ntiles), dim3(kBB), a.wave_lds, s, a);
     hipLaunchKernelGGL((batch_r0_kernel<double>), dim3(a.nlist), dim3(kBB), 0, s, a);
     CGX_HIP_CHECK(hipGetLastError());
 
@@ -553,13 +553,15 @@ static int run_batched_ru(Context *c, int32_t nsys, const cgx_system *in, void *
     hipLaunchKernelGGL((batch_scal_init_kernel<double>), dim3((unsigned)((n64 + 255) / 256)),
                        dim3(256), 0, s, a64.scal, L.P64.nscal, a64.sys_done, nsys);
     hipLaunchKernelGGL((batch_in_kernel<double>), dim3(a64.ntiles), dim3(kBB), 0, s, a64);
-    hipLaunchKernelGGL((batch_init_kernel<double>), dim3(a64.ntiles), dim3(kBB), 0, s, a64);
+    hipLaunchKernelGGL((batch_init_kernel<double>), dim3(a64.ntiles), dim3(kBB), a64.wave_lds, s,
+                       a64);
     hipLaunchKernelGGL((batch_r0_kernel<double>), dim3(a64.nlist), dim3(kBB), 0, s, a64);
     hipLaunchKernelGGL(refine_rhs_kernel, dim3(a64.ntiles), dim3(kBB), 0, s, a64, a32, b32);
     hipLaunchKernelGGL((batch_scal_init_kernel<float>), dim3((unsigned)((n32 + 255) / 256)),
                        dim3(256), 0, s, a32.scal, L.P32.nscal, a32.sys_done, nsys);
     hipLaunchKernelGGL((batch_in_kernel<float>), dim3(a32.ntiles), dim3(kBB), 0, s, a32);
-    hipLaunchKernelGGL((batch_init_kernel<float>), dim3(a32.ntiles), dim3(kBB), 0, s, a32);
+    hipLaunchKernelGGL((batch_init_kernel<float>), dim3(a32.ntiles), dim3(kBB), a32.wave_lds, s,
+                       a32);
     hipLaunchKernelGGL((batch_r0_kernel<float>), dim3(a32.nlist), dim3(kBB), 0, s, a32);
     hipLaunchKernelGGL(ru_start_kernel, dim3(a32.nlist), dim3(kBB), 0, s, a64, a32);
     CGX_HIP_CHECK(hipGetLastError());
@@ -597,7 +599,8 @@ static int run_batched_ru(Context *c, int32_t nsys, const cgx_system *in, void *
     CGX_HIP_CHECK(hipMemcpyAsync(h32.data(), a32.scal, sizeof(BScalT<float>) * L.P32.nscal,
                                  hipMemcpyDeviceToHost, s));
     // float64 residual of the result for the statistics (and x = 0 where b = 0)
-    hipLaunchKernelGGL((batch_init_kernel<double>), dim3(a64.ntiles), dim3(kBB), 0, s, a64);
+    hipLaunchKernelGGL((batch_init_kernel<double>), dim3(a64.ntiles), dim3(kBB), a64.wave_lds, s,
+                       a64);
     hipLaunchKernelGGL((batch_r0_kernel<double>), dim3(a64.nlist), dim3(kBB), 0, s, a64);
     hipLaunchKernelGGL((batch_out_kernel<double>), dim3(a64.ntiles), dim3(kBB), 0, s, a64);
     CGX_HIP_CHECK(hipGetLastError());
@@ -716,7 +719,8 @@ int run_batched_mixed(Context *c, int32_t nsys, const cgx_system *in, void *ws, 
     const int64_t n32 = std::max<int64_t>(L.P32.nscal, nsys);
     for (int step = 0;; ++step) {
         // float64 residual r = b - A x and its norms; rr <= rtol^2 bb -> done
-        hipLaunchKernelGGL((batch_init_kernel<double>), dim3(a64.ntiles), dim3(kBB), 0, s, a64);
+        hipLaunchKernelGGL((batch_init_kernel<double>), dim3(a64.ntiles), dim3(kBB), a64.wave_lds,
+                           s, a64);
         hipLaunchKernelGGL((batch_r0_kernel<double>), dim3(a64.nlist), dim3(kBB), 0, s, a64);
         CGX_HIP_CHECK(hipGetLastError());
         CGX_HIP_CHECK(hipMemcpyAsync(h64.data(), a64.scal, sizeof(BScalT<double>) * L.P64.nscal,
@@ -731,7 +735,8 @@ int run_batched_mixed(Context *c, int32_t nsys, const cgx_system *in, void *ws, 
         hipLaunchKernelGGL((batch_scal_init_kernel<float>), dim3((unsigned)((n32 + 255) / 256)),
                            dim3(256), 0, s, a32.scal, L.P32.nscal, a32.sys_done, nsys);
         hipLaunchKernelGGL((batch_in_kernel<float>), dim3(a32.ntiles), dim3(kBB), 0, s, a32);
-        hipLaunchKernelGGL((batch_init_kernel<float>), dim3(a32.ntiles), dim3(kBB), 0, s, a32);
+        hipLaunchKernelGGL((batch_init_kernel<float>), dim3(a32.ntiles), dim3(kBB), a32.wave_lds,
+                           s, a32);
         hipLaunchKernelGGL((batch_r0_kernel<float>), dim3(a32.nlist), dim3(kBB), 0, s, a32);
         CGX_HIP_CHECK(hipGetLastError());
         const int64_t max_replays = (int64_t)maxit / K + 2;

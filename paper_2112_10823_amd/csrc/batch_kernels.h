@@ -182,57 +182,6 @@ __global__ __launch_bounds__(kBB) void batch_in_kernel(BArgsT<T> a)
     }
 }
 
-// r0 = b - A x0, D^-1, z0, p0 and the partials of r.r, r.z, b.b.  D^-1 is
-// 1 / a_ii rounded once to T from a float64 division.
-template <typename T>
-__global__ __launch_bounds__(kBB) void batch_init_kernel(BArgsT<T> a)
-{
-    __shared__ T red[kBB];
-    const int w = xcd_block(blockIdx.x, gridDim.x);
-    const BTile t = a.tiles[w];
-    const BSysT<T> S = a.sys[t.sys];
-    const int M = setup_m(S);
-    const int G = S.K * M, gpw = kWave / G;
-    if (gpw < 1) return;  // not reached: K * M <= 64 is validated on the host
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
-    T prr = T(0), prz = T(0), pbb = T(0);
-    for (int row = t.row0 + wave * gpw + grp; row < t.row0 + t.rows; row += (kBB / kWave) * gpw) {
-        T dg;
-        const T ax = row_spmm(S, row, j, m, M, dg, S.x);
-        if (m == 0) {
-            const int64_t e = (int64_t)row * S.K + j;
-            T bi = T(0);
-            if (j < S.nrhs) {
-                if (!S.lanes)
-                    bi = S.B[(int64_t)j * S.n + row];
-                else if (S.lanes[j].b)
-                    bi = S.lanes[j].b[row];
-            }
-            const T ri = bi - ax;
-            T zi = ri;
-            S.r[e] = ri;
-            if (S.jac) {
-                const T d = dg > T(0) ? dg : T(1);
-                if (!(dg > T(0))) a.scal[S.scal0 + j].pad = 1;  // same value from every writer
-                const T di = (T)(1.0 / (double)d);
-                if (j == 0) S.dinv[row] = di;
-                zi = di * ri;
-                S.z[e] = zi;
-            }
-            S.p[e] = zi;
-            prr += ri * ri;
-            prz += ri * zi;
-            pbb += bi * bi;
-        }
-    }
-    // lanes with m > 0 hold zeros; the lane of (grp, j, m = 0) is lane % K == j
-    T *base = a.part + (int64_t)t.tile * kMaxK;
-    block_sum_by_rhs(prr, S.K, red, base);
-    block_sum_by_rhs(prz, S.K, red, base + a.part_stride);
-    block_sum_by_rhs(pbb, S.K, red, base + 2 * a.part_stride);
-}
-
 // Block sum of one value per thread in a fixed order (wave butterflies, then
 // the waves in order); the result is valid in thread 0.  `red` holds
 // kBB / 64 values.
@@ -333,9 +282,11 @@ __global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgsT<T> a)
 constexpr int kWaveStageBytes = (kBB / kWave) * (kWave * 8 * 12 + 65 * 4 + 8);
 
 // src: the interleaved vector multiplied (p in the SpMM phase); fin(row, j,
-// sum, part) consumes the sum of a (row, right-hand side) in the lane that
-// holds it, part being the lane's running partial (returned at the end).
-template <int RT, int K, typename T, bool kStaged, typename Fin>
+// sum, part, diag) consumes the sum of a (row, right-hand side) in the lane
+// that holds it, part being the lane's running partial (returned at the
+// end); with kDiag, diag is the row's stored diagonal (0 if it stores none),
+// otherwise 0.
+template <int RT, int K, typename T, bool kStaged, bool kDiag, typename Fin>
 __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, double *lds,
                                              const T *__restrict__ src, Fin fin)
 {
@@ -357,7 +308,7 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
 
     // rows [row0 + r_lo, row0 + r_hi) of the staged range (entries [k0, k1)
     // of the current chunk c0) for this lane's (row, right-hand side, slice)
-    auto walk = [&](int s, int e, int c0, T &acc) {
+    auto walk = [&](int s, int e, int c0, T &acc, int row, T &dg) {
         const int lo = s - c0, hi = e - c0;
         for (int k = lo + sl; k < hi; k += U * TL) {
             int cc[U];
@@ -376,7 +327,10 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
             for (int u = 0; u < U; ++u)
                 xv[u] = (unsigned)cc[u] < (unsigned)S.n_cols ? p[(int64_t)cc[u] * K + j] : T(0);
 #pragma unroll
-            for (int u = 0; u < U; ++u) acc += vv[u] * xv[u];
+            for (int u = 0; u < U; ++u) {
+                acc += vv[u] * xv[u];
+                if (kDiag && cc[u] == row) dg = vv[u];
+            }
         }
     };
     auto stage = [&](int c0, int k1) {
@@ -400,10 +354,13 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
         }
         wave_lds_sync();
     };
-    auto finish = [&](int row, bool valid, T acc) {
+    auto finish = [&](int row, bool valid, T acc, T dg) {
 #pragma unroll
-        for (int off = TL / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off * K);
-        if (sl == 0 && valid) fin(row, j, acc, ppq);
+        for (int off = TL / 2; off > 0; off >>= 1) {
+            acc += __shfl_xor(acc, off * K);
+            if (kDiag) dg += __shfl_xor(dg, off * K);  // one slice holds it, the others 0
+        }
+        if (sl == 0 && valid) fin(row, j, acc, ppq, dg);
     };
 
     for (int r0 = wr0; r0 < wend;) {
@@ -431,9 +388,9 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
                     s = max(sm.rp[gr], k0);
                     e = min(max(sm.rp[gr + 1], s), k1);
                 }
-                T acc = T(0);
-                walk(s, e, k0, acc);
-                finish(r0 + gr, gr < rs, acc);
+                T acc = T(0), dg = T(0);
+                walk(s, e, k0, acc, r0 + gr, dg);
+                finish(r0 + gr, gr < rs, acc, dg);
             }
             r0 += kContig ? rs : NW * RT;
         } else {  // one group of RT rows longer than a chunk
@@ -444,12 +401,12 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
                 s = max(sm.rp[g], k0);
                 e = min(max(sm.rp[g + 1], s), k1);
             }
-            T acc = T(0);
+            T acc = T(0), dg = T(0);
             for (int c0 = k0; c0 < k1; c0 += C) {
                 stage(c0, k1);
-                walk(max(s, c0), min(e, c0 + C), c0, acc);
+                walk(max(s, c0), min(e, c0 + C), c0, acc, r0 + g, dg);
             }
-            finish(r0 + g, g < nr, acc);
+            finish(r0 + g, g < nr, acc, dg);
             r0 += kContig ? nr : NW * RT;
         }
     }
@@ -464,9 +421,9 @@ __device__ __forceinline__ T spmm_wave_tiles(const BSysT<T> &S, const BTile &t, 
 // hand side) still sums its entries in the same order.  The p.q partials
 // come back per lane and right-hand side: pp[v] for right-hand side
 // (lane % (K / V)) V + v.
-// src and finv as for spmm_wave_tiles: finv(row, j0, sums, pp) takes the V
-// sums of right-hand sides j0 .. j0 + V - 1 of a row.
-template <int RT, int K, typename T, typename FinV>
+// src, kDiag and finv as for spmm_wave_tiles: finv(row, j0, sums, pp, diag)
+// takes the V sums of right-hand sides j0 .. j0 + V - 1 of a row.
+template <int RT, int K, typename T, bool kDiag, typename FinV>
 __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTile &t,
                                                     double *lds, T (&pp)[16 / sizeof(T)],
                                                     const T *__restrict__ src, FinV finv)
@@ -489,7 +446,7 @@ __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTi
 #pragma unroll
     for (int v = 0; v < V; ++v) pp[v] = T(0);
 
-    auto walk = [&](int s, int e, int c0, T (&acc)[V]) {
+    auto walk = [&](int s, int e, int c0, T (&acc)[V], int row, T &dg) {
         const int lo = s - c0, hi = e - c0;
         for (int k = lo + sl; k < hi; k += U * TL) {
             int cc[U];
@@ -517,6 +474,7 @@ __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTi
                 __builtin_memcpy(xs, &xv[u], sizeof(VT));
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc[v] += vv[u] * xs[v];
+                if (kDiag && cc[u] == row) dg = vv[u];
             }
         }
     };
@@ -541,12 +499,15 @@ __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTi
         }
         wave_lds_sync();
     };
-    auto finish = [&](int row, bool valid, T (&acc)[V]) {
+    auto finish = [&](int row, bool valid, T (&acc)[V], T dg) {
 #pragma unroll
         for (int v = 0; v < V; ++v)
 #pragma unroll
             for (int off = TL / 2; off > 0; off >>= 1) acc[v] += __shfl_xor(acc[v], off * KV);
-        if (sl == 0 && valid) finv(row, j0, acc, pp);
+        if (kDiag)
+#pragma unroll
+            for (int off = TL / 2; off > 0; off >>= 1) dg += __shfl_xor(dg, off * KV);
+        if (sl == 0 && valid) finv(row, j0, acc, pp, dg);
     };
 
     for (int r0 = wr0; r0 < wend;) {
@@ -572,11 +533,11 @@ __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTi
                     s = max(sm.rp[gr], k0);
                     e = min(max(sm.rp[gr + 1], s), k1);
                 }
-                T acc[V];
+                T acc[V], dg = T(0);
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc[v] = T(0);
-                walk(s, e, k0, acc);
-                finish(r0 + gr, gr < rs, acc);
+                walk(s, e, k0, acc, r0 + gr, dg);
+                finish(r0 + gr, gr < rs, acc, dg);
             }
             r0 += rs;
         } else {  // one group of RTV rows longer than a chunk
@@ -587,14 +548,14 @@ __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTi
                 s = max(sm.rp[g], k0);
                 e = min(max(sm.rp[g + 1], s), k1);
             }
-            T acc[V];
+            T acc[V], dg = T(0);
 #pragma unroll
             for (int v = 0; v < V; ++v) acc[v] = T(0);
             for (int c0 = k0; c0 < k1; c0 += C) {
                 stage(c0, k1);
-                walk(max(s, c0), min(e, c0 + C), c0, acc);
+                walk(max(s, c0), min(e, c0 + C), c0, acc, r0 + g, dg);
             }
-            finish(r0 + g, g < nr, acc);
+            finish(r0 + g, g < nr, acc, dg);
             r0 += nr;
         }
     }
@@ -603,8 +564,9 @@ __device__ __forceinline__ void spmm_wave_tiles_vec(const BSysT<T> &S, const BTi
 // Wave-tile schedule (M < 0: RT = -M rows per wave tile) for K = S.K.
 // Returns the number of p.q values in pp: 1 (pp[0], right-hand side
 // threadIdx.x % K) or V = 16 / sizeof(T) (the vector-gather form, see
-// spmm_wave_tiles_vec).
-template <typename T, typename Fin, typename FinV>
+// spmm_wave_tiles_vec).  kDiag: the epilogues receive the row's stored
+// diagonal.
+template <typename T, bool kDiag = false, typename Fin, typename FinV>
 __device__ __forceinline__ int spmm_wave_dispatch(const BSysT<T> &S, const BTile &t, double *lds,
                                                   T (&pp)[16 / sizeof(T)], const T *src, Fin fin,
                                                   FinV finv)
@@ -612,17 +574,17 @@ __device__ __forceinline__ int spmm_wave_dispatch(const BSysT<T> &S, const BTile
     const int rt = -S.M;
 #define CGX_WT(R, KK)                                                                 \
     if (rt == R && S.K == KK) {                                                       \
-        pp[0] = S.staged ? spmm_wave_tiles<R, KK, T, true>(S, t, lds, src, fin)       \
-                         : spmm_wave_tiles<R, KK, T, false>(S, t, lds, src, fin);     \
+        pp[0] = S.staged ? spmm_wave_tiles<R, KK, T, true, kDiag>(S, t, lds, src, fin)   \
+                         : spmm_wave_tiles<R, KK, T, false, kDiag>(S, t, lds, src, fin); \
         return 1;                                                                     \
     }
 #define CGX_WV(R, KK)                                                                 \
     if (rt == R && S.K == KK) {                                                       \
         if (S.staged) {                                                               \
-            spmm_wave_tiles_vec<R, KK, T>(S, t, lds, pp, src, finv);                  \
+            spmm_wave_tiles_vec<R, KK, T, kDiag>(S, t, lds, pp, src, finv);           \
             return 16 / (int)sizeof(T);                                               \
         }                                                                             \
-        pp[0] = spmm_wave_tiles<R, KK, T, false>(S, t, lds, src, fin);                \
+        pp[0] = spmm_wave_tiles<R, KK, T, false, kDiag>(S, t, lds, src, fin);         \
         return 1;                                                                     \
     }
     CGX_WT(1, 1) CGX_WT(2, 1) CGX_WT(4, 1) CGX_WT(8, 1) CGX_WT(16, 1) CGX_WT(32, 1) CGX_WT(64, 1)
@@ -662,6 +624,79 @@ __device__ __forceinline__ void wave_partials_out(const T (&pp)[16 / sizeof(T)],
     }
 }
 
+// r0 = b - A x0, D^-1, z0, p0 and the partials of r.r, r.z, b.b.  D^-1 is
+// 1 / a_ii rounded once to T from a float64 division.
+template <typename T>
+__global__ __launch_bounds__(kBB) void batch_init_kernel(BArgsT<T> a)
+{
+    __shared__ T red[kBB];
+    extern __shared__ double stage[];  // a.wave_lds bytes
+    const int w = xcd_block(blockIdx.x, gridDim.x);
+    const BTile t = a.tiles[w];
+    const BSysT<T> S = a.sys[t.sys];
+    // the row's residual, preconditioned residual, direction and partials
+    auto init_row = [&](int row, int j, T ax, T dg, T &prr, T &prz, T &pbb) {
+        const int64_t e = (int64_t)row * S.K + j;
+        T bi = T(0);
+        if (j < S.nrhs) {
+            if (!S.lanes)
+                bi = S.B[(int64_t)j * S.n + row];
+            else if (S.lanes[j].b)
+                bi = S.lanes[j].b[row];
+        }
+        const T ri = bi - ax;
+        T zi = ri;
+        S.r[e] = ri;
+        if (S.jac) {
+            const T d = dg > T(0) ? dg : T(1);
+            if (!(dg > T(0))) a.scal[S.scal0 + j].pad = 1;  // same value from every writer
+            const T di = (T)(1.0 / (double)d);
+            if (j == 0) S.dinv[row] = di;
+            zi = di * ri;
+            S.z[e] = zi;
+        }
+        S.p[e] = zi;
+        prr += ri * ri;
+        prz += ri * zi;
+        pbb += bi * bi;
+    };
+    T *base = a.part + (int64_t)t.tile * kMaxK;
+    if (S.M < 0 && S.staged && a.wave_lds >= kWaveStageBytes) {
+        // on the SpMM's wave tiles, the stored diagonal read on the way
+        constexpr int V = 16 / (int)sizeof(T);
+        T prr[V], prz[V], pbb[V], pp[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) prr[v] = prz[v] = pbb[v] = T(0);
+        auto fin = [&](int row, int j, T acc, T &, T dg) {
+            init_row(row, j, acc, dg, prr[0], prz[0], pbb[0]);
+        };
+        auto finv = [&](int row, int j0, T (&acc)[V], T (&)[V], T dg) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) init_row(row, j0 + v, acc[v], dg, prr[v], prz[v], pbb[v]);
+        };
+        const int nv = spmm_wave_dispatch<T, true>(S, t, stage, pp, (const T *)S.x, fin, finv);
+        wave_partials_out(prr, nv, S.K, stage, red, base);
+        wave_partials_out(prz, nv, S.K, stage, red, base + a.part_stride);
+        wave_partials_out(pbb, nv, S.K, stage, red, base + 2 * a.part_stride);
+        return;
+    }
+    const int M = setup_m(S);
+    const int G = S.K * M, gpw = kWave / G;
+    if (gpw < 1) return;  // not reached: K * M <= 64 is validated on the host
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int grp = lane / G, sub = lane % G, j = sub % S.K, m = sub / S.K;
+    T prr = T(0), prz = T(0), pbb = T(0);
+    for (int row = t.row0 + wave * gpw + grp; row < t.row0 + t.rows; row += (kBB / kWave) * gpw) {
+        T dg;
+        const T ax = row_spmm(S, row, j, m, M, dg, S.x);
+        if (m == 0) init_row(row, j, ax, dg, prr, prz, pbb);
+    }
+    // lanes with m > 0 hold zeros; the lane of (grp, j, m = 0) is lane % K == j
+    block_sum_by_rhs(prr, S.K, red, base);
+    block_sum_by_rhs(prz, S.K, red, base + a.part_stride);
+    block_sum_by_rhs(pbb, S.K, red, base + 2 * a.part_stride);
+}
+
 // (1) q = A p for every active system, p.q partials per right-hand side.
 // Systems with M > 0 use K * M lanes per row (vector CSR over the
 // interleaved vectors), systems with M < 0 wave tiles of -M rows.
@@ -679,12 +714,12 @@ __global__ __launch_bounds__(kBB) void batch_spmm_kernel(BArgsT<T> a)
         constexpr int V = 16 / (int)sizeof(T);
         T pp[V];
         // q = A p and the p.q partials
-        auto fin = [&](int row, int j, T acc, T &part) {
+        auto fin = [&](int row, int j, T acc, T &part, T) {
             const int64_t ei = (int64_t)row * S.K + j;
             S.q[ei] = acc;
             part += S.p[ei] * acc;
         };
-        auto finv = [&](int row, int j0, T (&acc)[V], T (&part)[V]) {
+        auto finv = [&](int row, int j0, T (&acc)[V], T (&part)[V], T) {
             using VT = Vec16<T>;
             const int64_t ei = (int64_t)row * S.K + j0;
             VT qv;
@@ -1214,16 +1249,16 @@ __global__ __launch_bounds__(kBB) void ru_residual_kernel(BArgsT<double> a64, BA
     if (S.M < 0 && S.staged && a64.wave_lds >= kWaveStageBytes) {
         constexpr int V = 2;
         const BScalT<float> *fs = a32.scal + F.scal0;
-        auto fin = [&](int row, int j, double acc, double &part) {
+        auto fin = [&](int row, int j, double acc, double &part, double) {
             if (!fs[j].ru) return;
             const double bi = S.lanes ? S.lanes[j].b[row] : S.B[(int64_t)j * S.n + row];
             const double ri = bi - acc;
             S.r[(int64_t)row * S.K + j] = ri;
             part += ri * ri;
         };
-        auto finv = [&](int row, int j0, double (&acc)[V], double (&part)[V]) {
+        auto finv = [&](int row, int j0, double (&acc)[V], double (&part)[V], double) {
 #pragma unroll
-            for (int v = 0; v < V; ++v) fin(row, j0 + v, acc[v], part[v]);
+            for (int v = 0; v < V; ++v) fin(row, j0 + v, acc[v], part[v], 0.0);
         };
         double pp[V];
         const int nv = spmm_wave_dispatch(S, t, stage, pp, (const double *)S.x, fin, finv);
