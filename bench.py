@@ -166,6 +166,24 @@ def cpu_baseline_batched(mats):
     return out
 
 
+def cpu_baseline_small(A, xs, min_s=2.0):
+    """The oracle's plain CG (one core) on the whole 7-point 16^3 solve to
+    1e-10 (b = A x* by the oracle's SpMV), repeated for about min_s seconds:
+    solves per second."""
+    import oracle
+    b = oracle.spmv(A, xs)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.cg(A, b, rtol=1e-10)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s:
+            break
+    return {"value": round(n / dt, 1), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} whole solves, {dt:.1f} s"}
+
+
 def cpu_baseline_mixed(A, b, iters=40):
     """The oracle's binary32 CG with float64 reliable updates (delta 1e-2,
     Jacobi) for `iters` iterations on the full mixed-precision system, setup
@@ -336,7 +354,8 @@ def extra_small_cg(cgx, synth, meter):
             "j_per_solve": round(jsolve, 5) if jsolve is not None else None,
             "blas1_n4096_us": {"add": round(t_add * 1e6, 2), "xmul": round(t_mul * 1e6, 2),
                                "dot": round(t_dot * 1e6, 2)},
-            "bound": "latency (whole problem on chip)"}
+            "bound": "latency (whole problem on chip)",
+            "cpu_baseline": cpu_baseline_small(A, xs)}
 
 
 def extra_blas1_sweep(cgx, synth):
