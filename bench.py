@@ -184,6 +184,25 @@ def cpu_baseline_small(A, xs, min_s=2.0):
             "sample": f"{n} whole solves, {dt:.1f} s"}
 
 
+def cpu_baseline_blas1(x, y, min_s=1.0):
+    """The oracle's add (24 bytes per element) and compensated dot (16) on
+    one core, each repeated for about min_s seconds: GB/s."""
+    import oracle
+    out = {}
+    for name, fn, bpe in (("add", lambda: oracle.add(x, y), 24), ("dot", lambda: oracle.dot(x, y), 16)):
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            fn()
+            k += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_s:
+                break
+        out[name + "_GBs"] = round(bpe * x.size * k / dt / 1e9, 2)
+    return {"value": out, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"n = {x.size} float64, add then dot, about {min_s:g} s each"}
+
+
 def cpu_baseline_mixed(A, b, iters=40):
     """The oracle's binary32 CG with float64 reliable updates (delta 1e-2,
     Jacobi) for `iters` iterations on the full mixed-precision system, setup
@@ -381,7 +400,10 @@ def extra_blas1_sweep(cgx, synth):
                      "dot_GBs": round(16 * n / t_dot / 1e9, 1),
                      "mall_resident": 24 * n < 256e6})
         del x, y, z
-    return {"workload": "BLAS-1 add / xmul / axpy / dot, float64 U[-1,1]", "rows": rows}
+    n = 1 << 24
+    cpu = cpu_baseline_blas1(synth.uniform(synth.SEED_VEC_X, n), synth.uniform(synth.SEED_VEC_Y, n))
+    return {"workload": "BLAS-1 add / xmul / axpy / dot, float64 U[-1,1]", "rows": rows,
+            "cpu_baseline": cpu}
 
 
 def extra_spmv_and_cg(cgx, synth, meter):

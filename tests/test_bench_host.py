@@ -71,8 +71,8 @@ def test_host_residual_matches_the_oracle():
 
 def test_only_the_cpu_baseline_uses_the_oracle():
     """Apart from the CPU baselines (one core, all cores; headline, small
-    system, batched and mixed-precision samples), no part of the benchmark
-    imports the oracle."""
+    system, BLAS-1, batched and mixed-precision samples), no part of the
+    benchmark imports the oracle."""
     import ast
     tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
     users = set()
@@ -84,7 +84,7 @@ def test_only_the_cpu_baseline_uses_the_oracle():
                     if any(n == "oracle" or n.startswith("oracle.") for n in names):
                         users.add(fn.name)
     assert users == {"cpu_baseline", "cpu_baseline_all_cores", "cpu_baseline_batched",
-                     "cpu_baseline_mixed", "cpu_baseline_small"}
+                     "cpu_baseline_mixed", "cpu_baseline_small", "cpu_baseline_blas1"}
 
 
 def test_batch_sample_spans_both_stencils():
