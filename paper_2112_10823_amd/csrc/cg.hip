@@ -1479,17 +1479,26 @@ int run_mixed(Context *c, const cgx_csr *A, const cgx_sell *S, const double *b, 
 
 // Sturm count: eigenvalues of the symmetric tridiagonal (diagonal d,
 // off-diagonal squares e2) below x.
-static int sturm_below(const double *d, const double *e2, int k, double x, double pivmin)
+// The Sturm counts at NX points at once: the NX recurrences are independent,
+// so their divisions overlap instead of waiting on one another.
+template <int NX>
+static void sturm_below_n(const double *d, const double *e2, int k, const double (&x)[NX],
+                          double pivmin, int (&c)[NX])
 {
-    int c = 0;
-    double q = d[0] - x;
-    for (int i = 0;; ++i) {
-        if (std::fabs(q) < pivmin) q = -pivmin;
-        if (q < 0.0) ++c;
-        if (i + 1 == k) break;
-        q = d[i + 1] - x - e2[i] / q;
+    double q[NX];
+    for (int t = 0; t < NX; ++t) {
+        c[t] = 0;
+        q[t] = d[0] - x[t];
     }
-    return c;
+    for (int i = 0;; ++i) {
+        for (int t = 0; t < NX; ++t) {
+            if (std::fabs(q[t]) < pivmin) q[t] = -pivmin;
+            if (q[t] < 0.0) ++c[t];
+        }
+        if (i + 1 == k) break;
+        const double di = d[i + 1], ei = e2[i];
+        for (int t = 0; t < NX; ++t) q[t] = di - x[t] - ei / q[t];
+    }
 }
 
 bool lanczos_extremes_ws(const double *coef, int k, double *work, double &lo, double &hi)
@@ -1522,21 +1531,36 @@ bool lanczos_extremes_ws(const double *coef, int k, double *work, double &lo, do
     const double pivmin = std::max(1e-300, 1e-290 * std::max(1.0, emax2));
     g0 -= 1e-15 * span + pivmin;
     g1 += 1e-15 * span + pivmin;
-    auto bisect = [&](int target) {  // smallest x with sturm_below(x) >= target
-        double a = g0, b = g1;
-        for (int it = 0; it < 200; ++it) {
-            const double m = 0.5 * (a + b);
-            if (m <= a || m >= b) break;
-            if (sturm_below(d, e2, k, m, pivmin) >= target)
-                b = m;
-            else
-                a = m;
-            if (b - a <= 2e-16 * std::max(std::fabs(a), std::fabs(b))) break;
+    // Both ends at once by quadrisection: each pass counts at the quarter
+    // points of the two intervals [a, b] (Sturm count below a < target <=
+    // count below b, target 1 for the smallest Ritz value, k for the
+    // largest) and keeps the quarter holding the target.
+    double a[2] = {g0, g0}, b[2] = {g1, g1};
+    const int target[2] = {1, k};
+    bool done[2] = {false, false};
+    for (int pass = 0; pass < 200 && !(done[0] && done[1]); ++pass) {
+        double x[6];
+        for (int t = 0; t < 2; ++t)
+            for (int i = 0; i < 3; ++i) x[3 * t + i] = a[t] + (b[t] - a[t]) * (0.25 * (i + 1));
+        int c[6];
+        sturm_below_n<6>(d, e2, k, x, pivmin, c);
+        for (int t = 0; t < 2; ++t) {
+            if (done[t]) continue;
+            int i = 0;
+            while (i < 3 && c[3 * t + i] < target[t]) ++i;
+            const double na = i > 0 ? x[3 * t + i - 1] : a[t];
+            const double nb = i < 3 ? x[3 * t + i] : b[t];
+            if (!(na > a[t]) && !(nb < b[t])) {  // the quarter points no longer split it
+                done[t] = true;
+                continue;
+            }
+            a[t] = na;
+            b[t] = nb;
+            if (b[t] - a[t] <= 2e-16 * std::max(std::fabs(a[t]), std::fabs(b[t]))) done[t] = true;
         }
-        return 0.5 * (a + b);
-    };
-    lo = bisect(1);
-    hi = bisect(k);
+    }
+    lo = 0.5 * (a[0] + b[0]);
+    hi = 0.5 * (a[1] + b[1]);
     return std::isfinite(lo) && std::isfinite(hi);
 }
 
