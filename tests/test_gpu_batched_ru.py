@@ -93,6 +93,35 @@ def test_batched_ru_vs_oracle(jacobi, delta):
                 assert_stop_in_band(h, F, v.iters, rtol, (v.iters, ref.iters))
 
 
+@pytest.mark.parametrize("nrhs,schedule", [(16, -4), (16, -1), (8, -8), (4, -16), (1, -64),
+                                           (3, -8), (16, 1)])
+def test_batched_ru_schedules_vs_oracle(nrhs, schedule):
+    """Reliable updates with each SpMM schedule forced (the float64 setup and
+    the update residual then run on the SpMM's wave tiles of that shape, or
+    on vector CSR for the positive schedule): the bars of the test above."""
+    mats = [synth.q1cube(11, 1.0, 31), synth.fd7_var(15, 1.0, 32)]
+    items, hostB = make_items(mats, [nrhs, nrhs], seed=720)
+    items = [it + (schedule,) for it in items]
+    rtol = 1e-10
+    print(f"[batched ru] nrhs={nrhs} schedule={schedule}", flush=True)
+    st = cgx.cg_solve_batched(items, ru_opts(rtol, True, 1e-2))
+    for s, (A, it) in enumerate(zip(mats, items)):
+        X = it[2].cpu().numpy()
+        refs, slack = ru_block_refs(A, hostB[s], rtol, 1e-2, True)
+        assert_updates_shared([(v.iters, v.outer_iters) for v in st[s]], (s, nrhs, schedule))
+        for j in range(nrhs):
+            v = st[s][j]
+            info = (s, j, v.as_dict())
+            assert v.status == cgx.OK, info
+            b = hostB[s][j]
+            tr = true_relres(A, b, X[j])
+            assert tr <= rtol, info
+            assert abs(v.relres - tr) <= 1e-3 * tr + 1e-16, info
+            assert abs(v.outer_iters - refs[j].outer_iters) <= slack, (info, refs[j].outer_iters)
+            xs = oracle.cg(A, b, rtol=1e-13, jacobi=True, maxit=20000).x
+            assert np.linalg.norm(X[j] - xs) <= 1e-6 * np.linalg.norm(xs), info
+
+
 def test_batched_ru_alone_equals_in_batch():
     mats = [f() for f in MATS]
     items, _ = make_items(mats, NRHS, seed=950)
