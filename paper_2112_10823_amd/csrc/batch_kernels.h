@@ -100,7 +100,7 @@ __device__ __forceinline__ void block_sum_by_rhs(T v, int K, T *red, T *out)
     __syncthreads();
     red[threadIdx.x] = v;
     __syncthreads();
-    if (threadIdx.x < K) {
+    if ((int)threadIdx.x < K) {
         T s = T(0);
         for (int i = threadIdx.x; i < kBB; i += K) s += red[i];
         out[threadIdx.x] = s;
@@ -213,7 +213,7 @@ __device__ __forceinline__ T sys_sum(const BArgsT<T> &a, const BSysT<T> &S, int 
     red[threadIdx.x] = s;
     __syncthreads();
     T tot = T(0);
-    if (threadIdx.x < K)
+    if ((int)threadIdx.x < K)
         for (int i = 0; i < nsl; ++i) tot += red[i * K + threadIdx.x];
     return tot;  // valid in threads 0..K-1
 }
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kBB) void batch_r0_kernel(BArgsT<T> a)
     __shared__ int any_active;
     if (threadIdx.x == 0) any_active = 0;
     __syncthreads();
-    if (threadIdx.x < S.K) {
+    if ((int)threadIdx.x < S.K) {
         const int j = threadIdx.x;
         BScalT<T> &c = a.scal[S.scal0 + j];
         const bool badd = c.pad != 0;
@@ -768,7 +768,7 @@ __global__ __launch_bounds__(kBB) void batch_r1_kernel(BArgsT<T> a)
     const BSysT<T> S = a.sys[sid];
     if (threadIdx.x == 0) any_active = 0;
     const T pq = sys_sum(a, S, 0, red);  // its barriers order any_active's reset
-    if (threadIdx.x < S.K) {
+    if ((int)threadIdx.x < S.K) {
         BScalT<T> &c = a.scal[S.scal0 + threadIdx.x];
         c.xstep = 0;
         c.ru = 0;
@@ -915,7 +915,7 @@ __global__ __launch_bounds__(kBB) void batch_r2_kernel(BArgsT<T> a)
     const T rz0 = sys_sum(a, S, 2, red);
     if (threadIdx.x == 0) any_active = any_ru = 0;
     __syncthreads();
-    const bool mine = threadIdx.x < S.K && a.scal[S.scal0 + threadIdx.x].active;
+    const bool mine = (int)threadIdx.x < S.K && a.scal[S.scal0 + threadIdx.x].active;
     T rz = T(0);
     int status = CGX_PENDING;
     bool pause = false;
@@ -1295,7 +1295,7 @@ __global__ __launch_bounds__(kBB) void ru_norm_kernel(BArgsT<double> a64, BArgsT
     const BSysT<double> S = a64.sys[sid];
     const BSysT<float> F = a32.sys[sid];
     const double rr = sys_sum(a64, S, 0, red);
-    if (threadIdx.x < S.K) {
+    if ((int)threadIdx.x < S.K) {
         BScalT<float> &c = a32.scal[F.scal0 + threadIdx.x];
         if (c.ru) {
             BScalT<double> &d = a64.scal[S.scal0 + threadIdx.x];
@@ -1356,7 +1356,7 @@ __global__ __launch_bounds__(kBB) void ru_resume_kernel(BArgsT<double> a64, BArg
     if (threadIdx.x == 0) any_active = 0;
     const float rz = sys_sum(a32, F, 0, red);  // its barriers order the reset above
     const float rr = sys_sum(a32, F, 1, red);
-    if (threadIdx.x < S.K) {
+    if ((int)threadIdx.x < S.K) {
         BScalT<float> &c = a32.scal[F.scal0 + threadIdx.x];
         if (c.ru) {
             BScalT<double> &d = a64.scal[S.scal0 + threadIdx.x];
@@ -1414,7 +1414,7 @@ __global__ __launch_bounds__(kBB) void ru_start_kernel(BArgsT<double> a64, BArgs
     const BSysT<float> F = a32.sys[sid];
     if (threadIdx.x == 0) any_active = 0;
     __syncthreads();
-    if (threadIdx.x < S.K) {
+    if ((int)threadIdx.x < S.K) {
         BScalT<float> &c = a32.scal[F.scal0 + threadIdx.x];
         const BScalT<double> &d = a64.scal[S.scal0 + threadIdx.x];
         if (d.status != CGX_PENDING) {

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kSB) void scan_apply_kernel(int64_t m, int64_t *v,
     __syncthreads();
     // Hillis-Steele inclusive scan of the thread totals
     for (int off = 1; off < kSB; off <<= 1) {
-        const int64_t add = threadIdx.x >= off ? pre[threadIdx.x - off] : 0;
+        const int64_t add = (int)threadIdx.x >= off ? pre[threadIdx.x - off] : 0;
         __syncthreads();
         pre[threadIdx.x] += add;
         __syncthreads();
