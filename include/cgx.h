@@ -329,15 +329,17 @@ size_t cgx_batch_mixed_workspace_bytes(int32_t nsys, const cgx_system *systems);
  * single-system MIXED_RU method for every (system, right-hand side) at
  * once.  One binary32 CG per right-hand side on A32 (Jacobi from the
  * binary32 diagonal if asked) whose direction is kept across float64
- * reliable updates: when the binary32 ||r^|| falls below delta times its
- * largest value since the last update (delta = inner_rtol, <= 0: 1e-2) or
- * its estimate of ||r|| reaches rtol ||b||, that right-hand side pauses, x
+ * reliable updates: when the binary32 ||r^|| of a right-hand side falls
+ * below delta times its largest value since its last update (delta =
+ * inner_rtol, <= 0: 1e-2) or its estimate of ||r|| reaches rtol ||b||, every
+ * right-hand side of that system still active after the step pauses (the
+ * float64 residual is one pass over the system's matrix for all of them): x
  * += ||r|| d and r = b - A x are taken in float64, ||r|| <= rtol ||b|| ends
- * it, and otherwise it resumes on float(r / ||r||) with beta rescaled by the
- * ratio of the two norms; the other right-hand sides go on meanwhile.  At
- * most maxit binary32 iterations (then the pending correction is folded
- * into x) and max_outer (<= 0: 100) updates per right-hand side, then
- * CGX_NOT_CONVERGED.  stats: iters =
+ * a right-hand side, and otherwise it resumes on float(r / ||r||) with beta
+ * rescaled by the ratio of the two norms; the other systems go on
+ * meanwhile.  At most maxit binary32 iterations (then the pending
+ * correction is folded into x) and max_outer (<= 0: 100) updates per
+ * right-hand side, then CGX_NOT_CONVERGED.  stats: iters =
  * binary32 iterations, outer_iters = reliable updates, relres = relres_true
  * = ||b - A x|| / ||b|| of the result in float64. */
 int cgx_cg_solve_batched(cgx_handle h, int32_t nsys, const cgx_system *systems, void *workspace,
@@ -396,7 +398,8 @@ size_t cgx_serve_request_bytes(int64_t n_rows);
  * reliable-update method of cgx_cg_solve_batched's MIXED_RU for the
  * request (delta = inner_rtol, default 1e-2; at most max_outer updates,
  * default 100, and maxit binary32 iterations), its updates taken inside the
- * iteration sequence.  The inner solves of all MIXED
+ * iteration sequence and shared by the requests of its slot (one matrix,
+ * one update event for all of them).  The inner solves of all MIXED
  * requests advance together in the batched binary32 kernels; each request
  * takes its float64 steps on its own.  Non-blocking; *ticket identifies the
  * request.  CGX_ENOMEM at once if the request can never fit the pool. */
