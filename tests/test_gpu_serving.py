@@ -134,16 +134,27 @@ def test_late_requests_join_a_running_slot():
     opts = cgx.make_opts(rtol=1e-11)
     bs = [synth.uniform(900 + i, A.n_rows) for i in range(4)]
     xs = [torch.zeros(A.n_rows, dtype=torch.float64, device="cuda") for _ in bs]
+    dbs = [dev(b) for b in bs]
     with cgx.Server(pool(1 << 30), max_slots=1, max_group=16) as srv:
-        t0 = srv.submit(dA, dev(bs[0]), xs[0], opts)
+        c0 = time.perf_counter()
+        t0 = srv.submit(dA, dbs[0], xs[0], opts)
         time.sleep(0.002)  # the first request now holds the only slot (one spare lane)
-        ts = [t0] + [srv.submit(dA, dev(b), x, opts) for b, x in zip(bs[1:], xs[1:])]
+        c1 = time.perf_counter()
+        ts = [t0] + [srv.submit(dA, b, x, opts) for b, x in zip(dbs[1:], xs[1:])]
         sts = [srv.wait(t) for t in ts]
-    assert sts[0].outer_iters == 1
-    # the second request took the spare lane while the first was running; the
-    # other two waited for the slot and then ran as one group
-    assert sts[1].outer_iters == 2 and sts[1].queue_ms < sts[0].latency_ms
-    assert sts[2].outer_iters == sts[3].outer_iters == 2
+    if sts[0].queue_ms * 1e-3 < c1 - c0:
+        # the first request was running when the others arrived (the recorded
+        # times say so): the second took the spare lane of its slot, the
+        # other two waited for the slot and then ran as one group
+        assert sts[0].outer_iters == 1
+        assert sts[1].outer_iters == 2 and sts[1].queue_ms < sts[0].latency_ms
+        assert sts[2].outer_iters == sts[3].outer_iters == 2
+    else:
+        # admitted only while or after the others arrived: how they grouped
+        # depends on that moment; each still shared a slot of at most four
+        print("[serving] first request admitted late:", [st.outer_iters for st in sts],
+              flush=True)
+        assert all(1 <= st.outer_iters <= 4 for st in sts), [st.as_dict() for st in sts]
     for b, x, st in zip(bs, xs, sts):
         ref = oracle.cg(A, b, rtol=1e-11)
         xg = x.cpu().numpy()
