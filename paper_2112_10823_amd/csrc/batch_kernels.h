@@ -625,7 +625,10 @@ __device__ __forceinline__ void wave_partials_out(const T (&pp)[16 / sizeof(T)],
 }
 
 // r0 = b - A x0, D^-1, z0, p0 and the partials of r.r, r.z, b.b.  D^-1 is
-// 1 / a_ii rounded once to T from a float64 division.
+// 1 / a_ii rounded once to T from a float64 division.  On the SpMM's wave
+// tiles (the stored diagonal read on the way) for systems of the batch call
+// on that schedule when the launch carries the staging LDS (a.wave_lds);
+// otherwise, and in the solve server, a vector-CSR pass.
 template <typename T>
 __global__ __launch_bounds__(kBB) void batch_init_kernel(BArgsT<T> a)
 {
