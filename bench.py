@@ -682,8 +682,10 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5, full=Tr
     """Poisson arrivals of solve requests on resident Q1 systems whose row
     counts follow ln(rows) ~ N(mu, sigma) truncated to [1e4, 4e6] (pool of
     `pool_systems` resident systems, bounded from the 256 of the full
-    workload), lognormal(0,1), uniform RHS, rtol 1e-8.  full=False runs only
-    the burst and one Poisson rate at 0.8 of it (the long stream)."""
+    workload), lognormal(0,1), uniform RHS, rtol 1e-8.  full=False (the long
+    stream) runs, for plain float64 CG, float64 Jacobi-CG and binary32
+    Jacobi-CG with float64 reliable updates, the burst and one Poisson rate
+    at 0.8 of it."""
     import torch
     rng = np.random.default_rng(seed)
     mu = 0.5 * (math.log(1e4) + math.log(4e6))
@@ -696,7 +698,7 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5, full=Tr
                 break
         N = max(2, round(r ** (1 / 3)))
         A = synth.q1cube(N, 1.0, 2000 + i)
-        mats.append((A, cgx.DeviceCSR.from_host(A, with_f32=full)))
+        mats.append((A, cgx.DeviceCSR.from_host(A, with_f32=True)))
     opts = cgx.make_opts(rtol=1e-8)
     picks = rng.integers(0, pool_systems, n_req)
     max_n = max(A.n_rows for A, _ in mats)
@@ -761,12 +763,17 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5, full=Tr
                 "j_per_solve": round(p * wall / n_req, 3) if p is not None else None}
 
     jac = cgx.make_opts(rtol=1e-8, precond=cgx.PRECOND_JACOBI)
+    rmix = cgx.make_opts(rtol=1e-8, precond=cgx.PRECOND_JACOBI,
+                         precision=cgx.PRECISION_MIXED_RU, inner_rtol=1e-2)
     sat = run(0)  # all requests at once: saturation throughput
     if not full:
+        rows = [sat, run(0.8 * sat["solves_per_s"])]
+        for o in (jac, rmix):
+            osat = run(0, opts=o)
+            rows += [osat, run(0.8 * osat["solves_per_s"], opts=o)]
         return {"workload": f"{n_req} Poisson-arrival requests on {pool_systems} resident Q1 "
                             f"systems (rows lognormal in [1e4, 4e6]), lognormal(0,1), rtol 1e-8",
-                "rows": [sat, run(0.8 * sat["solves_per_s"])],
-                "pool_rows": sorted(A.n_rows for A, _ in mats)}
+                "rows": rows, "pool_rows": sorted(A.n_rows for A, _ in mats)}
     rows = [sat, run(0, max_group=1)]
     for f in (0.5, 0.8, 0.95):
         rows.append(run(f * sat["solves_per_s"]))
@@ -778,8 +785,6 @@ def extra_serving(cgx, synth, meter, n_req=300, pool_systems=24, seed=5, full=Tr
     msat = run(0, opts=mix)
     rows += [msat, run(0.8 * msat["solves_per_s"], opts=mix)]
     # binary32 CG with float64 reliable updates (delta 1e-2)
-    rmix = cgx.make_opts(rtol=1e-8, precond=cgx.PRECOND_JACOBI,
-                         precision=cgx.PRECISION_MIXED_RU, inner_rtol=1e-2)
     rsat = run(0, opts=rmix)
     rows += [rsat, run(0.8 * rsat["solves_per_s"], opts=rmix)]
     return {"workload": f"{n_req} Poisson-arrival requests on {pool_systems} resident Q1 systems "
