@@ -43,6 +43,7 @@ constexpr int kRB = 256;             // threads per workgroup of the p.q tile-pa
 constexpr int kMinTilesPerRed = 512; // tile partials per reduction workgroup, at least
 constexpr int kPB = 512;             // threads per workgroup of the other phase kernels
 constexpr int kPhaseBlocksPerCu = 4;
+constexpr int kPre = 4;              // rows per thread an elementwise phase loads before its scalar
 constexpr int kMaxPhaseBlocks = 2048;
 constexpr int kSmallBlock = 1024;
 
@@ -275,8 +276,28 @@ template <bool kJac, typename T>
 __global__ __launch_bounds__(kPB) void cg_update_kernel(CgArgs<T> a)
 {
     CgState *st = a.st;
+    T *__restrict__ x = a.x;
+    T *__restrict__ r = a.r;
+    T *__restrict__ z = a.z;
+    const T *__restrict__ p = a.p;
+    const T *__restrict__ q = a.q;
+    const T *__restrict__ dinv = a.dinv;
+    const int64_t i0 = (int64_t)blockIdx.x * kPB + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kPB;
+    // The thread's first kPre rows are loaded before alpha is known, so that
+    // their loads are in flight with those of the partials and state fields
+    // (rows past the end load row n - 1, n >= 1, and are not used).
+    T xv[kPre], pv[kPre], rv[kPre], qv[kPre], dv[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int64_t i = min(i0 + u * stride, (int64_t)a.n - 1);
+        xv[u] = x[i];
+        pv[u] = p[i];
+        rv[u] = r[i];
+        qv[u] = q[i];
+        dv[u] = kJac ? dinv[i] : T(0);
+    }
     __shared__ T red[kPB / kWave];
-    // the partials' loads are in flight with those of the state fields
     const T pq = sum_partials<kPB>(region(a, kPPq), a.n_pq, red);
     if (st->done) return;
     const T rho = (T)st->rho;
@@ -298,16 +319,25 @@ __global__ __launch_bounds__(kPB) void cg_update_kernel(CgArgs<T> a)
         st->rho_used = rho;
         st->iter = it + 1;
     }
-    T *__restrict__ x = a.x;
-    T *__restrict__ r = a.r;
-    T *__restrict__ z = a.z;
-    const T *__restrict__ p = a.p;
-    const T *__restrict__ q = a.q;
-    const T *__restrict__ dinv = a.dinv;
     T part[2] = {T(0), T(0)};
-    const int64_t stride = (int64_t)gridDim.x * kPB;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int64_t i = i0 + u * stride;
+        if (i < a.n) {
+            const T xi = __builtin_fma(alpha, pv[u], xv[u]);
+            const T ri = __builtin_fma(-alpha, qv[u], rv[u]);
+            x[i] = xi;
+            r[i] = ri;
+            part[0] += ri * ri;
+            if (kJac) {
+                const T zi = dv[u] * ri;
+                z[i] = zi;
+                part[1] += ri * zi;
+            }
+        }
+    }
 #pragma unroll 4
-    for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < a.n; i += stride) {
+    for (int64_t i = i0 + kPre * stride; i < a.n; i += stride) {
         const T xi = __builtin_fma(alpha, p[i], x[i]);
         const T ri = __builtin_fma(-alpha, q[i], r[i]);
         x[i] = xi;
@@ -337,9 +367,31 @@ template <bool kJac, typename T>
 __global__ __launch_bounds__(kPB) void cg_direction_kernel(CgArgs<T> a)
 {
     CgState *st = a.st;
+    T *__restrict__ p = a.p;
+    const T *__restrict__ z = a.z;
+    const int64_t i0 = (int64_t)blockIdx.x * kPB + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kPB;
+    // the thread's first kPre rows, loaded before beta is known (rows past
+    // the end load row n - 1, n >= 1, and are not used)
+    T pv[kPre], zv[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int64_t i = min(i0 + u * stride, (int64_t)a.n - 1);
+        pv[u] = p[i];
+        zv[u] = z[i];
+    }
     __shared__ T red[kPB / kWave];
-    const T rr = sum_partials<kPB>(region(a, kPRr), a.grid_ew, red);
-    const T rz = kJac ? sum_partials<kPB>(region(a, kPRz), a.grid_ew, red) : rr;
+    T rr, rz;
+    if constexpr (kJac) {
+        // the loads of both partial arrays in flight together
+        const T *const pa[2] = {region(a, kPRr), region(a, kPRz)};
+        T ts[2];
+        thread_partials<kPB>(pa, a.grid_ew, ts);
+        rr = block_total<kPB>(ts[0], red);
+        rz = block_total<kPB>(ts[1], red);
+    } else {
+        rr = rz = sum_partials<kPB>(region(a, kPRr), a.grid_ew, red);
+    }
     if (st->done) return;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     const double rmax2 = fmax(st->rmax2, (double)rr);
@@ -369,11 +421,13 @@ __global__ __launch_bounds__(kPB) void cg_direction_kernel(CgArgs<T> a)
         st->beta = beta;
         st->rmax2 = rmax2;
     }
-    T *__restrict__ p = a.p;
-    const T *__restrict__ z = a.z;
-    const int64_t stride = (int64_t)gridDim.x * kPB;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int64_t i = i0 + u * stride;
+        if (i < a.n) p[i] = __builtin_fma(beta, pv[u], zv[u]);
+    }
 #pragma unroll 4
-    for (int64_t i = (int64_t)blockIdx.x * kPB + threadIdx.x; i < a.n; i += stride)
+    for (int64_t i = i0 + kPre * stride; i < a.n; i += stride)
         p[i] = __builtin_fma(beta, p[i], z[i]);
 }
 

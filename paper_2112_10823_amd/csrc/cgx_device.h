@@ -289,14 +289,39 @@ __device__ __forceinline__ T sell_rows(int s, int n_rows, int n_cols,
     return acc;
 }
 
-// Sum of `count` partials in index order (strided per thread, then a fixed
-// block tree); every thread of the block receives the same bits.  `red` is
+// Per-thread part of a sum of partials: thread t adds partials t, t + BS,
+// t + 2 BS, ... in that order, two loads in flight at a time, for NA arrays
+// of `count` partials each at once (their loads in flight together).
+template <int BS, int NA, typename T>
+__device__ __forceinline__ void thread_partials(const T *const (&pa)[NA], int count, T (&s)[NA])
+{
+#pragma unroll
+    for (int k = 0; k < NA; ++k) s[k] = T(0);
+    int i = threadIdx.x;
+    for (; i + BS < count; i += 2 * BS) {
+        T v0[NA], v1[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            v0[k] = pa[k][i];
+            v1[k] = pa[k][i + BS];
+        }
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            s[k] += v0[k];
+            s[k] += v1[k];
+        }
+    }
+    if (i < count)
+#pragma unroll
+        for (int k = 0; k < NA; ++k) s[k] += pa[k][i];
+}
+
+// The block's total of the threads' values s: a wave sum, then the waves'
+// sums in wave order; every thread receives the same bits.  `red` is
 // __shared__ scratch of BS / 64 values.
 template <int BS, typename T>
-__device__ __forceinline__ T sum_partials(const T *partials, int count, T *red)
+__device__ __forceinline__ T block_total(T s, T *red)
 {
-    T s = T(0);
-    for (int i = threadIdx.x; i < count; i += BS) s += partials[i];
     s = wave_sum(s);
     constexpr int W = BS / kWave;
     const int w = threadIdx.x / kWave;
@@ -307,6 +332,18 @@ __device__ __forceinline__ T sum_partials(const T *partials, int count, T *red)
 #pragma unroll
     for (int i = 0; i < W; ++i) t += red[i];
     return t;
+}
+
+// Sum of `count` partials in index order (strided per thread, then a fixed
+// block tree); every thread of the block receives the same bits.  `red` is
+// __shared__ scratch of BS / 64 values.
+template <int BS, typename T>
+__device__ __forceinline__ T sum_partials(const T *partials, int count, T *red)
+{
+    const T *const pa[1] = {partials};
+    T s[1];
+    thread_partials<BS>(pa, count, s);
+    return block_total<BS>(s[0], red);
 }
 
 }  // namespace cgx
