@@ -217,11 +217,15 @@ __global__ __launch_bounds__(kPB) void cg_init_finish_kernel(CgArgs<double> a, i
 template <int RT, typename T>
 __global__ __launch_bounds__(kWave) void cg_spmv_kernel(CgArgs<T> a)
 {
+    // gathers in flight per lane: 8 in float64 (all of a Q1 row's share at 4
+    // lanes per row), 16 in binary32 (2 lanes per row); measured in the solve
+    // against 4, bit-identical
+    constexpr int U = sizeof(T) == sizeof(double) ? 8 : 16;
     __shared__ WaveSmem<wave_e<T>(), RT, T> sm;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     int row;
     T prow;  // p[row], from the gather of the diagonal entry
-    const T acc = wave_rows<wave_e<T>(), RT, 4, T, true>(tile * RT, a.n, a.n_cols, a.nnz, a.rp,
+    const T acc = wave_rows<wave_e<T>(), RT, U, T, true>(tile * RT, a.n, a.n_cols, a.nnz, a.rp,
                                                          a.ci, a.val, a.p, sm, row, &a.st->done,
                                                          &prow);
     if (row < 0) return;  // the solve has stopped
