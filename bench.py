@@ -68,10 +68,10 @@ class EnergyMeter:
 
 def wave_tile_rows(n, nnz, entries_per_lane=8):
     """Rows per SpMV wave tile the library picks: the largest power of two in
-    [1, 64] whose expected entries fill at most 90% of 64 * entries_per_lane."""
+    [1, 64] whose expected entries fill at most 97% of 64 * entries_per_lane."""
     mean = max(nnz / n, 1.0) if n else 1.0
     rt = 64
-    while rt > 1 and rt * mean > 0.9 * 64 * entries_per_lane:
+    while rt > 1 and rt * mean > 0.97 * 64 * entries_per_lane:
         rt //= 2
     return rt
 

@@ -44,13 +44,16 @@ constexpr int kReduceBlocks = 1024; // fixed grid of the standalone reductions
 constexpr int kProfWindow = 32;     // profile mode: iterations launched between host checks
 
 // Wave tiles (one wavefront per tile, 64 * E entries per chunk): E = 8
-// float64 or 16 binary32 entries per lane (64 bytes of values in flight per
-// lane either way).
+// float64 or 14 binary32 entries per lane.  14 is the fewest that hold 32
+// rows of 27 entries (a Q1 tile) in one chunk; the smaller staging area
+// (7.3 KB against 8.3 KB at 16) admits more waves per compute unit, which
+// measured 88.2 against 91-92 us for the binary32 SpMV of the Q1 128^3
+// matrix (float64 at 7 entries, 5.4 KB: no change).
 template <typename T>
-constexpr int wave_e() { return 64 / (int)sizeof(T); }
+constexpr int wave_e() { return sizeof(T) == sizeof(double) ? 8 : 14; }
 
 // Rows per wave tile: the largest power of two in [1, 64] whose expected
-// entries fill at most 90% of one chunk of 64 * entries_per_lane entries.
+// entries fill at most 97% of one chunk of 64 * entries_per_lane entries.
 int wave_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_lane);
 
 #define CGX_WRT_SWITCH(RT, EXPR_T)    \

@@ -4,8 +4,8 @@
 //
 // Wave-tile layout: each 64-thread workgroup (one wavefront) owns a tile of
 // RT consecutive rows, RT from the mean row length so that a tile's entries
-// fill one chunk of 64 x 8 float64 (64 x 16 binary32) entries.  The tile's
-// col_idx / val are read as one contiguous stream with eight (sixteen)
+// fill one chunk of 64 x 8 float64 (64 x 14 binary32) entries.  The tile's
+// col_idx / val are read as one contiguous stream with eight (fourteen)
 // independent coalesced non-temporal loads per lane and staged in LDS; then
 // 64 / RT lanes per row walk the row's entries in step, so that the x gathers
 // of neighbouring rows coalesce.  One tile per workgroup and many small
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void csr_validate_kernel(int n_rows, int n_
 int wave_tile_rows(int64_t n_rows, int64_t nnz, int entries_per_lane)
 {
     const double mean = n_rows > 0 ? (double)nnz / (double)n_rows : 1.0;
-    const double budget = 0.9 * kWave * entries_per_lane;
+    const double budget = 0.97 * kWave * entries_per_lane;
     int rt = kWave;
     while (rt > 1 && rt * (mean > 1.0 ? mean : 1.0) > budget) rt /= 2;
     return rt;

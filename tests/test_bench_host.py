@@ -31,13 +31,13 @@ def test_byte_models_count_the_arrays(make):
 
 def test_wave_tile_rows_rule():
     """The largest power of two up to 64 whose expected entries fill at most
-    90 % of 64 x 8: 16 rows for the 27-point Q1 rows, 64 for the 7-point
+    97 % of 64 x 8: 16 rows for the 27-point Q1 rows, 64 for the 7-point
     rows, one row when a mean row exceeds the chunk."""
     assert bench.wave_tile_rows(2_097_152, 55_742_968) == 16
     assert bench.wave_tile_rows(4096, 27136) == 64
     assert bench.wave_tile_rows(100, 100 * 600) == 1
     for rt in (1, 2, 4, 8, 16, 32, 64):
-        mean = 0.9 * 64 * 8 / rt
+        mean = 0.97 * 64 * 8 / rt
         assert bench.wave_tile_rows(1000, int(1000 * mean)) == rt
 
 
